@@ -1,0 +1,247 @@
+/*
+ * idmrg.h -- C-ABI of the MI355X (gfx950) hot path of the parallel
+ * infinite-size DMRG of H. Ueda, "Infinite-Size Density Matrix
+ * Renormalization Group with Parallel Hida's Algorithm" (arXiv 1606.06790).
+ *
+ * Five calls follow the paper's statement of the per-superblock problem:
+ *   heff_apply            apply the superblock Hamiltonian H^(n)_i
+ *                         (Sec. 2, Step 3; Fig. 2(b))
+ *   lanczos_solve_batch   solve H^(n)_i Psi = e Psi from a start vector for
+ *                         the l/2 superblocks of one iteration (Steps 3, 3')
+ *   truncate_twosite      Psi = U Lambda V^dagger and keep the largest states
+ *                         (Steps 4, 6; Eqs. (13), (14))
+ *   update_env            block-spin transformation of the expanded blocks
+ *                         (Step 6, Eqs. (4), (5), with Step 2' folded in)
+ *   predict_wavefunction  start vector of the next iteration (Eq. (10))
+ * Every call is batch-first: it takes nprob >= 1 independent problems and
+ * runs them in one set of grouped launches.
+ *
+ * ---------------------------------------------------------------------------
+ * Data conventions (all floating point data is IEEE FP64 unless stated).
+ *
+ * Charges are 2*S^z (integers) in the left-flux convention: the charge of a
+ * bond sector is the total charge of everything to the left of that bond.
+ * A dense (no symmetry) problem is the special case where every charge is 0.
+ *
+ * A leg (idmrg_leg) lists sectors with strictly ascending charge q[k] and
+ * dimension dim[k] >= 1.  Local states have charges qp[0..d-1].
+ *
+ * An MPO tensor W[w][w'][s][s'] (idmrg_mpo) is dense, row-major, on the host,
+ * with channel charges ql (rows, the cut to the left of the site) and qr
+ * (columns).  W[w][w'][s][s'] may be nonzero only if
+ * qp[s] - qp[s'] == qr[w'] - ql[w].  Channel 0 is "complete" and channel D-1
+ * is "identity"; W[0][0] and W[dl-1][dr-1] must be the identity (the paper's
+ * lower-triangular form whose last row and first column are the boundary
+ * vectors, Sec. 2 after Eq. (1)).
+ *
+ * Device tensors are flat FP64 arrays in these orders (k ascending everywhere):
+ *   two-site state Psi[alpha,s1,s2,beta], legs A (alpha), B (beta):
+ *       blocks for b in B, a in A, s1, s2 with q_a+qp[s1]+qp[s2] == q_b,
+ *       each block [dim_a x dim_b] row-major.
+ *   left environment L[alpha,w,alpha'] (leg A, channels = rows of W1):
+ *       for a' in A, for w = 0..dl-2, if q_a'+ql[w] is a sector a of A:
+ *       block [dim_a x dim_a'] row-major.  Channel dl-1 (identity) is not stored.
+ *   right environment R[beta,w,beta'] (leg B, channels = columns of W2):
+ *       for b in B, one row-major [dim_b x K_b] matrix whose columns run over
+ *       w = 1..dr-1 and the sector b' with q_b' = q_b - qr[w] (if present).
+ *       Channel 0 (identity) is not stored.
+ *   left isometry U[(alpha,s),gamma] (new leg C):
+ *       for c in C, a row-major [r_c x k_c] matrix, rows over a in A, s with
+ *       q_a + qp[s] == q_c.
+ *   right isometry V[(s,beta),gamma] (new leg C):
+ *       for c in C, a row-major [r'_c x k_c] matrix, rows over s, b in B with
+ *       q_b - qp[s] == q_c.
+ *   singular values lambda: for c in C, k_c values (descending, then zeros).
+ *
+ * Ownership: the caller allocates every input and output buffer.  The library
+ * owns only its internal scratch memory (allocated on first use with
+ * hipMalloc, grown when needed, freed by idmrg_destroy) and keeps no pointer
+ * to caller memory after a call returns.
+ *
+ * Streams: all device work of a context is enqueued on its stream.  Calls
+ * that return host results (lanczos_solve_batch, truncate_twosite) and every
+ * call that uploads a work plan synchronise that stream before returning.
+ *
+ * Errors: 0 = success; > 0 = warning (IDMRG_WARN_NOCONV); < 0 = error, with a
+ * message from idmrg_last_error().  No C++ exception crosses this boundary.
+ * Every shape, charge and capacity is validated on the host before any
+ * kernel is launched; an invalid argument returns IDMRG_EINVAL and launches
+ * nothing.
+ */
+#ifndef IDMRG_H
+#define IDMRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IDMRG_OK 0
+#define IDMRG_WARN_NOCONV 1
+#define IDMRG_EINVAL (-1)
+#define IDMRG_ENOMEM (-2)
+#define IDMRG_EHIP (-3)
+#define IDMRG_ENUMERIC (-4)
+#define IDMRG_EUNSUPPORTED (-5)
+
+/* arithmetic policies of the H_eff contractions */
+#define IDMRG_PREC_F64 0      /* FP64 MFMA */
+#define IDMRG_PREC_F32 1      /* operands rounded to FP32, FP32 MFMA, FP32 accumulate */
+#define IDMRG_PREC_BF16X3 2   /* operands split a = hi + lo (bf16), hi*hi + hi*lo + lo*hi, FP32 accumulate */
+
+#define IDMRG_LEFT 0
+#define IDMRG_RIGHT 1
+
+typedef struct idmrg_ctx idmrg_ctx;
+
+typedef struct {
+    int32_t nsec;
+    const int32_t* q;    /* host [nsec], strictly ascending */
+    const int32_t* dim;  /* host [nsec], each >= 1 */
+} idmrg_leg;
+
+typedef struct {
+    int32_t dl, dr, d;
+    const double* w;     /* host [dl][dr][d][d] */
+    const int32_t* ql;   /* host [dl] */
+    const int32_t* qr;   /* host [dr] */
+    const int32_t* qp;   /* host [d] */
+} idmrg_mpo;
+
+/* One superblock Hamiltonian H^(n)_i = {L W1 W2 R} (Sec. 2, Step 3). */
+typedef struct {
+    idmrg_leg left;           /* alpha leg = leg of L */
+    idmrg_leg right;          /* beta leg = leg of R */
+    const idmrg_mpo* w1;      /* W_{f(2i+n-1)}: rows = channels of L */
+    const idmrg_mpo* w2;      /* W_{f(2i+n)}: columns = channels of R; w1->dr == w2->dl */
+    const double* L;          /* device, left-environment layout */
+    const double* R;          /* device, right-environment layout */
+} idmrg_heff;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+int idmrg_create(idmrg_ctx** ctx, int device, void* hip_stream);
+int idmrg_destroy(idmrg_ctx* ctx);
+int idmrg_set_stream(idmrg_ctx* ctx, void* hip_stream);
+const char* idmrg_last_error(const idmrg_ctx* ctx);
+
+/* Element counts of the flat layouts above (host only; no device work). */
+int64_t idmrg_psi_size(idmrg_leg A, idmrg_leg B, int32_t d, const int32_t* qp);
+int64_t idmrg_envL_size(idmrg_leg A, int32_t dl, const int32_t* ql);
+int64_t idmrg_envR_size(idmrg_leg B, int32_t dr, const int32_t* qr);
+int64_t idmrg_U_size(idmrg_leg A, int32_t d, const int32_t* qp, idmrg_leg C);
+int64_t idmrg_V_size(idmrg_leg B, int32_t d, const int32_t* qp, idmrg_leg C);
+
+/* Algorithmic work of one heff_apply of H (host only): flops of the two
+ * environment GEMM stages plus the W mixing, counted from the block lists
+ * (identity channels and symmetry-forbidden blocks excluded), and the bytes
+ * that the matvec must move at least once (environments, input, output). */
+int idmrg_heff_work(const idmrg_heff* H, double* flops, double* bytes);
+
+/* ------------------------------------------------------------------ calls */
+
+/* y_p = H_p x_p for p < nprob (Sec. 2, Step 3; Fig. 2(b)):
+ *   y[a,s1,s2,b] = sum L[a,w,a'] W1[w,w',s1,t1] W2[w',w'',s2,t2] R[b,w'',b'] x[a',t1,t2,b'].
+ * x[p], y[p]: device pointers (host array of nprob pointers) in the Psi
+ * layout of H[p].left/right; x and y must not overlap.  prec selects the
+ * arithmetic (IDMRG_PREC_*); FP64 inputs and outputs in every case. */
+int heff_apply(idmrg_ctx* ctx, int nprob, const idmrg_heff* H,
+               const double* const* x, double* const* y, int prec);
+
+typedef struct {
+    double tol_E;       /* stop when |theta_k - theta_{k-1}| <= tol_E ... */
+    double tol_res;     /* ... and the residual estimate beta_k |y_k| <= tol_res */
+    int32_t k_max;      /* at most min(k_max, N) Lanczos vectors */
+    int32_t prec;       /* IDMRG_PREC_* of the matvec inside the iteration */
+    int32_t chunk;      /* iterations between host checks of the device stop flags */
+    int32_t refine;     /* mixed precision only: FP64 residual refinement after the iteration */
+} idmrg_lanczos_opts;
+
+typedef struct {
+    int32_t iters;        /* Lanczos vectors used (k) */
+    int32_t converged;    /* 1 if a stop rule other than k = k_max fired */
+    int32_t fp64_matvecs; /* FP64 matvecs of the refinement (mixed precision) */
+    int32_t flags;        /* bit 0: invariant subspace (beta ~ 0) */
+    double residual;      /* |H psi - e psi| (FP64 matvec) after the solve */
+    double overlap0;      /* |<start/|start|, psi>|, so 1 - overlap0 is the fidelity error of Eq. (12) */
+} idmrg_lanczos_info;
+
+/* Lowest eigenpair of each H_p by Lanczos with full FP64 re-orthogonalisation
+ * (classical Gram-Schmidt applied twice), FP64 tridiagonal eigensolver and
+ * Ritz vector, all on the device (Step 3; Step 3' for the start vector).
+ * psi[p]: device, in: start vector (any nonzero norm), out: normalised ground
+ * state.  energy[p], info[p]: host outputs.  Synchronises the stream.
+ * Returns IDMRG_WARN_NOCONV if any problem stopped at k = k_max. */
+int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* H, double* const* psi,
+                        const idmrg_lanczos_opts* opts, double* energy, idmrg_lanczos_info* info);
+
+typedef struct {
+    /* inputs */
+    idmrg_leg left, right;     /* legs of psi */
+    const double* psi;         /* device, normalised two-site state */
+    int32_t cap_sec;           /* capacity of q_out/dim_out */
+    int32_t* q_out;            /* host out: new leg charges */
+    int32_t* dim_out;          /* host out: new leg dims */
+    double* U;                 /* device out, U layout of the new leg; capacity cap_U doubles */
+    double* V;                 /* device out, V layout; capacity cap_V doubles */
+    double* lambda;            /* device out; capacity cap_lam doubles */
+    int64_t cap_U, cap_V, cap_lam;
+    /* outputs */
+    int32_t nsec_out;
+    int32_t m_kept;
+    double eps;                /* discarded weight, Eq. (14) */
+    double eps_prime;          /* best fidelity error, Eq. (13) */
+    double cut_gap;            /* relative gap at the cut (-1 if no nonzero value was cut) */
+} idmrg_trunc;
+
+/* Psi = U Lambda V^dagger per centre charge (FP64 one-sided Jacobi SVD on the
+ * device), keep the largest min(m_max, ...) states (Steps 4, 6).  Readings:
+ * values <= lam_floor count as zero; when more states are kept than nonzero
+ * values exist, zero-weight states fill in ascending charge order; the cut is
+ * moved up past values within deg_rel (relative) of the last kept one.
+ * lambda is normalised over the full spectrum (sum lambda^2 = 1) and the
+ * kept values are not renormalised.  Synchronises the stream. */
+int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp, int32_t m_max,
+                     double lam_floor, double deg_rel, idmrg_trunc* t);
+
+typedef struct {
+    idmrg_leg old_leg;         /* leg of env_old (alpha for LEFT, beta for RIGHT) */
+    idmrg_leg new_leg;         /* leg of the isometry's new index */
+    const idmrg_mpo* w;        /* W1 (LEFT: rows = channels of env_old) or W2 (RIGHT: columns) */
+    const double* env_old;     /* device */
+    const double* iso;         /* device: U (LEFT) or V (RIGHT) */
+    double* env_new;           /* device out: L layout with channels = columns of W (LEFT),
+                                  R layout with channels = rows of W (RIGHT) */
+} idmrg_env_update;
+
+/* Block-spin transformation (Step 6):
+ *   LEFT  (Eq. (4)): L'[w'](c,c') = sum u[(a,s),c] L[w](a,a') W[w,w',s,s'] u[(a',s'),c']
+ *   RIGHT (Eq. (5)): R'[w](c,c') = sum v[(s,b),c] W[w,w'',s,s'] R[w''](b,b') v[(s',b'),c']
+ * Environments stay FP64 in every mode. */
+int update_env(idmrg_ctx* ctx, int nprob, int side, const idmrg_env_update* u);
+
+typedef struct {
+    idmrg_leg leg_a;           /* leg of lam_i = alpha leg of the prediction */
+    idmrg_leg leg_beta;        /* leg of lam_prev = the contracted index */
+    idmrg_leg leg_b;           /* leg of lam_ip1 = beta leg of the prediction */
+    const double* lam_i;       /* device: lambda^(n-1)_i */
+    const double* V_i;         /* device: V^(n-1)_i, V layout (B = leg_beta, C = leg_a) */
+    const double* lam_prev;    /* device: lambda^(n-2)_{i+1} */
+    const double* U_ip1;       /* device: U^(n-1)_{i+1}, U layout (A = leg_beta, C = leg_b) */
+    const double* lam_ip1;     /* device: lambda^(n-1)_{i+1} */
+    double* psi;               /* device out: Psi layout with legs (leg_a, leg_b) */
+} idmrg_predict;
+
+/* Eq. (10): psi[a,s,s',a'] = sum_b lam_i[a] v_i[(s,b),a] u~[b,s',a'],
+ *           u~[b,s',a'] = u_{i+1}[(b,s'),a'] lam_ip1[a'] / lam_prev[b] (0 if lam_prev[b] <= lam_floor). */
+int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp, double lam_floor,
+                         const idmrg_predict* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IDMRG_H */

@@ -1,0 +1,841 @@
+// C-ABI entry points (idmrg.h): validation, workspace, plan upload and the
+// launch sequences of the five calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "idmrg.h"
+#include "internal.h"
+#include "plan.h"
+
+using namespace idmrg;
+
+// ------------------------------------------------------------------ context
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct idmrg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  DevBuf plan;                 // uploaded task lists and base tables
+  void* pinned = nullptr;      // host staging for uploads
+  size_t pinned_n = 0;
+  DevBuf ws[12];               // scratch, by purpose (see WS_*)
+};
+
+namespace {
+
+enum {
+  WS_T1 = 0, WS_T3, WS_LOWENV, WS_LOWVEC, WS_LZ, WS_LZSMALL, WS_SVD, WS_SEL, WS_ENV, WS_PRED, WS_READ, WS_MISC
+};
+
+void sync(idmrg_ctx* c) { IDMRG_HIP(hipStreamSynchronize(c->stream)); }
+
+void* ensure(idmrg_ctx* c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.n >= bytes) return b.p;
+  sync(c);
+  if (b.p) IDMRG_HIP(hipFree(b.p));
+  b.p = nullptr;
+  b.n = 0;
+  size_t want = std::max(bytes, b.n + b.n / 4);
+  want = (want + 4095) / 4096 * 4096;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  b.n = want;
+  return b.p;
+}
+
+// Collects host arrays into one upload; offsets aligned to 256 bytes.
+struct Packer {
+  std::vector<char> host;
+  size_t add(const void* p, size_t bytes) {
+    const size_t off = (host.size() + 255) / 256 * 256;
+    host.resize(off + std::max<size_t>(bytes, 8));
+    if (bytes) std::memcpy(host.data() + off, p, bytes);
+    return off;
+  }
+  template <typename T>
+  size_t add(const std::vector<T>& v) { return add(v.data(), v.size() * sizeof(T)); }
+};
+
+char* upload(idmrg_ctx* c, const Packer& pk) {
+  sync(c);   // previous work may still read the plan buffer and the staging area
+  char* dev = (char*)ensure(c, c->plan, pk.host.size());
+  if (c->pinned_n < pk.host.size()) {
+    if (c->pinned) IDMRG_HIP(hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    c->pinned_n = 0;
+    size_t want = std::max(pk.host.size(), (size_t)1 << 20);
+    IDMRG_HIP(hipHostMalloc(&c->pinned, want, hipHostMallocDefault));
+    c->pinned_n = want;
+  }
+  std::memcpy(c->pinned, pk.host.data(), pk.host.size());
+  IDMRG_HIP(hipMemcpyAsync(dev, c->pinned, pk.host.size(), hipMemcpyHostToDevice, c->stream));
+  return dev;
+}
+
+template <typename F>
+int guarded(idmrg_ctx* c, F&& f) {
+  if (!c) return IDMRG_EINVAL;
+  try {
+    c->err.clear();
+    IDMRG_HIP(hipSetDevice(c->device));
+    return f();
+  } catch (const InvalidArg& e) {
+    c->err = e.what;
+    return IDMRG_EINVAL;
+  } catch (const HipFailure& e) {
+    c->err = e.what;
+    return IDMRG_EHIP;
+  } catch (const std::bad_alloc&) {
+    c->err = "device or host allocation failed";
+    return IDMRG_ENOMEM;
+  } catch (...) {
+    c->err = "unexpected internal error";
+    return IDMRG_EUNSUPPORTED;
+  }
+}
+
+// The caller's buffer at p must hold n elements of esize bytes inside one device allocation.
+void check_dev(const void* p, int64_t n, size_t esize, const std::string& what) {
+  if (!p) throw InvalidArg(what + ": null pointer");
+  if (n <= 0) return;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+    (void)hipGetLastError();
+    throw InvalidArg(what + ": not a device allocation of this context's device");
+  }
+  if ((const char*)p + (size_t)n * esize > (const char*)base + size) throw InvalidArg(what + ": buffer too small");
+}
+
+// ------------------------------------------------------------------ H_eff execution
+
+struct HeffExec {
+  HeffPlan plan;
+  int P = 0;
+  Prec prec = Prec::F64;
+  GemmTask *g1 = nullptr, *g2 = nullptr;
+  MixTask *mY = nullptr, *mT = nullptr;
+  MixSrc *sY = nullptr, *sT = nullptr;
+  void** bases = nullptr;      // device [P][8]
+  // per-problem buffers of the low-precision policies
+  std::vector<void*> xlow, xmix, ylow;
+  std::vector<int64_t> npsi;
+};
+
+size_t elem_size_operand(Prec p) { return p == Prec::F64 ? 8 : 4; }
+
+// Build plans for P problems, allocate scratch, convert environments for the
+// low-precision policies, and upload.  x/y are the FP64 input/output vectors.
+void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const std::vector<double*>& x,
+                const std::vector<double*>& y, int prec) {
+  if (prec < 0 || prec > 2) throw InvalidArg("unknown precision policy");
+  ex.P = P;
+  ex.prec = (Prec)prec;
+  std::vector<Leg> A(P), B(P);
+  std::vector<Mpo> W1(P), W2(P);
+  for (int p = 0; p < P; ++p) {
+    if (!H[p].w1 || !H[p].w2 || !H[p].L || !H[p].R) throw InvalidArg("null field in idmrg_heff");
+    A[p] = make_leg(H[p].left, "heff.left");
+    B[p] = make_leg(H[p].right, "heff.right");
+    W1[p] = make_mpo(H[p].w1, "heff.w1");
+    W2[p] = make_mpo(H[p].w2, "heff.w2");
+    if (W1[p].dr != W2[p].dl || W1[p].qr != W2[p].ql) throw InvalidArg("w1 columns and w2 rows differ");
+    if (W1[p].qp != W2[p].qp) throw InvalidArg("w1 and w2 local charges differ");
+    build_heff(ex.plan, p, A[p], B[p], W1[p], W2[p]);
+    if (ex.plan.n_psi[p] == 0) throw InvalidArg("two-site state has no allowed block");
+  }
+  ex.npsi = ex.plan.n_psi;
+  {
+    std::vector<int64_t> sz((size_t)P * kNumBases, -1);
+    for (int p = 0; p < P; ++p) {
+      int64_t* z = &sz[(size_t)p * kNumBases];
+      z[0] = ex.plan.n_L[p]; z[1] = ex.plan.n_R[p]; z[2] = z[3] = z[6] = ex.plan.n_psi[p];
+      z[4] = ex.plan.n_T1[p]; z[5] = ex.plan.n_T3[p];
+      check_dev(H[p].L, ex.plan.n_L[p], 8, "heff.L");
+      check_dev(H[p].R, ex.plan.n_R[p], 8, "heff.R");
+      check_dev(x[p], ex.plan.n_psi[p], 8, "x");
+      check_dev(y[p], ex.plan.n_psi[p], 8, "y");
+    }
+    check_gemm(ex.plan.g1, 0, sz, "heff gemm1");
+    check_mix(ex.plan.mixY, sz, "heff mixY");
+    check_mix(ex.plan.mixT, sz, "heff mixT");
+    check_gemm(ex.plan.g2, 1, sz, "heff gemm2");
+  }
+  const size_t es = ex.prec == Prec::F64 ? 8 : 4;   // accumulator / T1 element size
+  int64_t nT1 = 0, nT3 = 0;
+  std::vector<int64_t> o1(P), o3(P);
+  for (int p = 0; p < P; ++p) {
+    o1[p] = nT1;
+    o3[p] = nT3;
+    nT1 += ex.plan.n_T1[p] + 64;
+    nT3 += ex.plan.n_T3[p] + 64;
+  }
+  char* T1 = (char*)ensure(c, c->ws[WS_T1], nT1 * es);
+  char* T3 = (char*)ensure(c, c->ws[WS_T3], nT3 * 4 * (ex.prec == Prec::F64 ? 2 : 1));
+  std::vector<void*> hb((size_t)P * kNumBases, nullptr);
+  ex.xlow.assign(P, nullptr);
+  ex.xmix.assign(P, nullptr);
+  ex.ylow.assign(P, nullptr);
+  if (ex.prec == Prec::F64) {
+    for (int p = 0; p < P; ++p) {
+      void** b = &hb[(size_t)p * kNumBases];
+      b[0] = (void*)H[p].L;
+      b[1] = (void*)H[p].R;
+      b[2] = x[p];
+      b[3] = y[p];
+      b[4] = T1 + o1[p] * 8;
+      b[5] = T3 + o3[p] * 8;
+      b[6] = x[p];
+    }
+  } else {
+    int64_t nenv = 0, nvec = 0;
+    for (int p = 0; p < P; ++p) {
+      nenv += ex.plan.n_L[p] + ex.plan.n_R[p] + 128;
+      nvec += 3 * (ex.npsi[p] + 64);
+    }
+    char* env = (char*)ensure(c, c->ws[WS_LOWENV], nenv * 4);
+    char* vec = (char*)ensure(c, c->ws[WS_LOWVEC], nvec * 4);
+    int64_t oe = 0, ov = 0;
+    const int kind = ex.prec == Prec::F32 ? 0 : 1;
+    for (int p = 0; p < P; ++p) {
+      void** b = &hb[(size_t)p * kNumBases];
+      void* Ll = env + oe * 4;
+      oe += ex.plan.n_L[p] + 64;
+      void* Rl = env + oe * 4;
+      oe += ex.plan.n_R[p] + 64;
+      launch_convert(kind, H[p].L, Ll, ex.plan.n_L[p], c->stream);
+      launch_convert(kind, H[p].R, Rl, ex.plan.n_R[p], c->stream);
+      ex.xlow[p] = vec + ov * 4;
+      ov += ex.npsi[p] + 64;
+      ex.xmix[p] = ex.prec == Prec::F32 ? ex.xlow[p] : (void*)(vec + ov * 4);
+      ov += ex.npsi[p] + 64;
+      ex.ylow[p] = vec + ov * 4;
+      ov += ex.npsi[p] + 64;
+      b[0] = Ll;
+      b[1] = Rl;
+      b[2] = ex.xlow[p];
+      b[3] = ex.ylow[p];
+      b[4] = T1 + o1[p] * 4;
+      b[5] = T3 + o3[p] * 4;
+      b[6] = ex.xmix[p];
+    }
+  }
+  Packer pk;
+  const size_t a1 = pk.add(ex.plan.g1.t), a2 = pk.add(ex.plan.g2.t), a3 = pk.add(ex.plan.mixY.t),
+               a4 = pk.add(ex.plan.mixY.src), a5 = pk.add(ex.plan.mixT.t), a6 = pk.add(ex.plan.mixT.src),
+               a7 = pk.add(hb);
+  char* dev = upload(c, pk);
+  ex.g1 = (GemmTask*)(dev + a1);
+  ex.g2 = (GemmTask*)(dev + a2);
+  ex.mY = (MixTask*)(dev + a3);
+  ex.sY = (MixSrc*)(dev + a4);
+  ex.mT = (MixTask*)(dev + a5);
+  ex.sT = (MixSrc*)(dev + a6);
+  ex.bases = (void**)(dev + a7);
+}
+
+// y = H x for every problem (x, y: the FP64 vectors given at setup).
+void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const std::vector<double*>& y,
+              const int32_t* active) {
+  hipStream_t s = c->stream;
+  if (ex.prec != Prec::F64) {
+    for (int p = 0; p < ex.P; ++p) {
+      launch_convert(ex.prec == Prec::F32 ? 0 : 1, x[p], ex.xlow[p], ex.npsi[p], s);
+      if (ex.prec == Prec::BF16X3) launch_convert(0, x[p], ex.xmix[p], ex.npsi[p], s);
+    }
+  }
+  const int tin = ex.prec == Prec::F64 ? 0 : 1;
+  const int toutT = ex.prec == Prec::F64 ? 0 : (ex.prec == Prec::F32 ? 1 : 2);
+  const int toutY = ex.prec == Prec::F64 ? 0 : 1;
+  launch_gemm(ex.prec, 0, ex.g1, (int)ex.plan.g1.t.size(), ex.plan.g1.tiles, ex.bases, active, s);
+  launch_mix(tin, toutY, ex.mY, ex.sY, (int)ex.plan.mixY.t.size(), ex.plan.mixY.tiles, ex.bases, active, s);
+  launch_mix(tin, toutT, ex.mT, ex.sT, (int)ex.plan.mixT.t.size(), ex.plan.mixT.tiles, ex.bases, active, s);
+  launch_gemm(ex.prec, 1, ex.g2, (int)ex.plan.g2.t.size(), ex.plan.g2.tiles, ex.bases, active, s);
+  if (ex.prec != Prec::F64)
+    for (int p = 0; p < ex.P; ++p) launch_convert(2, ex.ylow[p], y[p], ex.npsi[p], s);
+  IDMRG_HIP(hipGetLastError());
+}
+
+void check_nprob(int nprob) {
+  if (nprob < 1 || nprob > 64) throw InvalidArg("nprob must be 1..64");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context API
+
+extern "C" int idmrg_create(idmrg_ctx** ctx, int device, void* hip_stream) {
+  if (!ctx) return IDMRG_EINVAL;
+  *ctx = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return IDMRG_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return IDMRG_EHIP;
+  auto* c = new (std::nothrow) idmrg_ctx();
+  if (!c) return IDMRG_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *ctx = c;
+  return IDMRG_OK;
+}
+
+extern "C" int idmrg_destroy(idmrg_ctx* c) {
+  if (!c) return IDMRG_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->plan.p) (void)hipFree(c->plan.p);
+  for (auto& b : c->ws)
+    if (b.p) (void)hipFree(b.p);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+  return IDMRG_OK;
+}
+
+extern "C" int idmrg_set_stream(idmrg_ctx* c, void* hip_stream) {
+  if (!c) return IDMRG_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  c->stream = (hipStream_t)hip_stream;
+  return IDMRG_OK;
+}
+
+extern "C" const char* idmrg_last_error(const idmrg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int64_t idmrg_psi_size(idmrg_leg A, idmrg_leg B, int32_t d, const int32_t* qp) {
+  try {
+    return psi_layout(make_leg(A, "A"), make_leg(B, "B"), make_qp(d, qp)).size;
+  } catch (...) {
+    return -1;
+  }
+}
+
+extern "C" int64_t idmrg_envL_size(idmrg_leg A, int32_t dl, const int32_t* ql) {
+  try {
+    if (dl < 2 || !ql) return -1;
+    return envL_layout(make_leg(A, "A"), std::vector<int>(ql, ql + dl)).size;
+  } catch (...) {
+    return -1;
+  }
+}
+
+extern "C" int64_t idmrg_envR_size(idmrg_leg B, int32_t dr, const int32_t* qr) {
+  try {
+    if (dr < 2 || !qr) return -1;
+    return envR_layout(make_leg(B, "B"), std::vector<int>(qr, qr + dr)).size;
+  } catch (...) {
+    return -1;
+  }
+}
+
+extern "C" int64_t idmrg_U_size(idmrg_leg A, int32_t d, const int32_t* qp, idmrg_leg C) {
+  try {
+    return U_layout(make_leg(A, "A"), make_qp(d, qp), make_leg(C, "C")).size;
+  } catch (...) {
+    return -1;
+  }
+}
+
+extern "C" int64_t idmrg_V_size(idmrg_leg B, int32_t d, const int32_t* qp, idmrg_leg C) {
+  try {
+    return V_layout(make_leg(B, "B"), make_qp(d, qp), make_leg(C, "C")).size;
+  } catch (...) {
+    return -1;
+  }
+}
+
+extern "C" int idmrg_heff_work(const idmrg_heff* H, double* flops, double* bytes) {
+  if (!H || !flops || !bytes) return IDMRG_EINVAL;
+  try {
+    const Mpo W1 = make_mpo(H->w1, "w1"), W2 = make_mpo(H->w2, "w2");
+    heff_work(make_leg(H->left, "left"), make_leg(H->right, "right"), W1, W2, *flops, *bytes);
+    return IDMRG_OK;
+  } catch (...) {
+    return IDMRG_EINVAL;
+  }
+}
+
+// ------------------------------------------------------------------ heff_apply
+
+extern "C" int heff_apply(idmrg_ctx* ctx, int nprob, const idmrg_heff* H, const double* const* x, double* const* y,
+                          int prec) {
+  return guarded(ctx, [&]() {
+    check_nprob(nprob);
+    if (!H || !x || !y) throw InvalidArg("null argument");
+    std::vector<double*> xs(nprob), ys(nprob);
+    for (int p = 0; p < nprob; ++p) {
+      if (!x[p] || !y[p] || x[p] == y[p]) throw InvalidArg("x and y must be distinct device pointers");
+      xs[p] = const_cast<double*>(x[p]);
+      ys[p] = y[p];
+    }
+    HeffExec ex;
+    heff_setup(ctx, ex, nprob, H, xs, ys, prec);
+    heff_run(ctx, ex, xs, ys, nullptr);
+    return IDMRG_OK;
+  });
+}
+
+// ------------------------------------------------------------------ lanczos_solve_batch
+
+extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* H, double* const* psi,
+                                   const idmrg_lanczos_opts* o, double* energy, idmrg_lanczos_info* info) {
+  return guarded(ctx, [&]() {
+    check_nprob(nprob);
+    if (!H || !psi || !o || !energy || !info) throw InvalidArg("null argument");
+    if (o->k_max < 1 || o->k_max > kLzMaxK) throw InvalidArg("k_max must be 1..1024");
+    if (!(o->tol_E >= 0) || !(o->tol_res >= 0)) throw InvalidArg("tolerances must be >= 0");
+    const int P = nprob;
+    const int kmax = o->k_max;
+    const int chunk = std::max(1, o->chunk > 0 ? o->chunk : 8);
+    hipStream_t s = ctx->stream;
+    // sizes first (plan building validates everything)
+    std::vector<int64_t> N(P);
+    for (int p = 0; p < P; ++p) {
+      if (!psi[p]) throw InvalidArg("null psi");
+      N[p] = psi_layout(make_leg(H[p].left, "left"), make_leg(H[p].right, "right"),
+                        make_mpo(H[p].w1, "w1").qp).size;
+      if (N[p] == 0) throw InvalidArg("empty two-site space");
+      check_dev(psi[p], N[p], 8, "psi");
+    }
+    // vectors: Q [kcap x N], w, v
+    std::vector<int64_t> kcap(P), qoff(P), woff(P), voff(P);
+    int64_t tot = 0;
+    for (int p = 0; p < P; ++p) {
+      kcap[p] = std::min<int64_t>(kmax, N[p]);
+      qoff[p] = tot;
+      tot += kcap[p] * N[p] + 32;
+      woff[p] = tot;
+      tot += N[p] + 32;
+      voff[p] = tot;
+      tot += N[p] + 32;
+    }
+    double* V = (double*)ensure(ctx, ctx->ws[WS_LZ], tot * 8);
+    // small arrays
+    const size_t nsm = (size_t)P * kmax;
+    const size_t small_bytes = (size_t)P * kmax * kLzBlocks * 8 + 4 * nsm * 8 + P * sizeof(LzCtrl) + P * 4 + 4096;
+    char* sm = (char*)ensure(ctx, ctx->ws[WS_LZSMALL], small_bytes);
+    double* partial = (double*)sm;
+    double* alpha = partial + (size_t)P * kmax * kLzBlocks;
+    double* beta = alpha + nsm;
+    double* ritz = beta + nsm;
+    double* coef = ritz + nsm;
+    LzCtrl* ctrl = (LzCtrl*)(coef + nsm);
+    int32_t* active = (int32_t*)(ctrl + P);
+    std::vector<double*> vv(P), ww(P);
+    std::vector<LzProblem> probs(P);
+    std::vector<LzCtrl> hctrl(P);
+    std::vector<int32_t> hact(P, 1);
+    for (int p = 0; p < P; ++p) {
+      vv[p] = V + voff[p];
+      ww[p] = V + woff[p];
+      probs[p] = LzProblem{N[p], V + qoff[p], ww[p], vv[p], psi[p]};
+      LzCtrl z{};
+      z.active = 1;
+      z.kcap = (int32_t)kcap[p];
+      hctrl[p] = z;
+    }
+    // low-precision stage (if any), then FP64
+    const bool mixed = o->prec != IDMRG_PREC_F64;
+    int total_fp64 = 0;
+    std::vector<LzCtrl> out(P);
+    for (int stage = mixed ? 0 : 1; stage < 2; ++stage) {
+      const int prec = stage == 0 ? o->prec : IDMRG_PREC_F64;
+      double tolE = o->tol_E, tolR = o->tol_res;
+      if (stage == 0) {   // the low-precision iteration stops at its own noise floor
+        tolE = std::max(tolE, prec == IDMRG_PREC_F32 ? 1e-9 : 1e-6);
+        tolR = std::max(tolR, prec == IDMRG_PREC_F32 ? 1e-4 : 1e-3);
+      }
+      HeffExec ex;
+      heff_setup(ctx, ex, P, H, vv, ww, prec);
+      Packer pk;
+      const size_t a1 = pk.add(probs), a2 = pk.add(hctrl), a3 = pk.add(hact);
+      char* dev = (char*)ensure(ctx, ctx->ws[WS_MISC], pk.host.size());
+      sync(ctx);
+      IDMRG_HIP(hipMemcpy(dev, pk.host.data(), pk.host.size(), hipMemcpyHostToDevice));
+      LzProblem* dprobs = (LzProblem*)(dev + a1);
+      IDMRG_HIP(hipMemcpyAsync(ctrl, dev + a2, P * sizeof(LzCtrl), hipMemcpyDeviceToDevice, s));
+      IDMRG_HIP(hipMemcpyAsync(active, dev + a3, P * 4, hipMemcpyDeviceToDevice, s));
+      lz_init(P, dprobs, ctrl, partial, kmax, s);
+      {
+        std::vector<LzCtrl> chk(P);
+        IDMRG_HIP(hipMemcpyAsync(chk.data(), ctrl, P * sizeof(LzCtrl), hipMemcpyDeviceToHost, s));
+        sync(ctx);
+        for (int p = 0; p < P; ++p)
+          if (!(chk[p].norm0 > 0.0) || !std::isfinite(chk[p].norm0))
+            throw InvalidArg("start vector has zero or non-finite norm (problem " + std::to_string(p) + ")");
+      }
+      int64_t maxk = 0;
+      for (int p = 0; p < P; ++p) maxk = std::max(maxk, kcap[p]);
+      std::vector<int32_t> act(P);
+      for (int64_t it = 0; it < maxk;) {
+        for (int k = 0; k < chunk && it < maxk; ++k, ++it) {
+          heff_run(ctx, ex, vv, ww, active);
+          lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, kmax, tolE, tolR, s);
+        }
+        IDMRG_HIP(hipMemcpyAsync(act.data(), active, P * 4, hipMemcpyDeviceToHost, s));
+        sync(ctx);
+        if (std::all_of(act.begin(), act.end(), [](int32_t a) { return a == 0; })) break;
+      }
+      lz_finish(P, dprobs, ctrl, ritz, partial, kmax, s);
+      if (stage == 1) {
+        // FP64 residual of the result: w = H psi (v holds psi)
+        heff_run(ctx, ex, vv, ww, nullptr);
+        lz_residual(P, dprobs, ctrl, partial, kmax, s);
+      }
+      IDMRG_HIP(hipMemcpyAsync(out.data(), ctrl, P * sizeof(LzCtrl), hipMemcpyDeviceToHost, s));
+      sync(ctx);
+      if (stage == 1)
+        for (int p = 0; p < P; ++p) total_fp64 += out[p].iters + 1;
+      if (stage == 0) {
+        for (int p = 0; p < P; ++p) info[p].overlap0 = out[p].overlap0;
+      }
+    }
+    int rc = IDMRG_OK;
+    for (int p = 0; p < P; ++p) {
+      energy[p] = out[p].theta;
+      if (!mixed) info[p].overlap0 = out[p].overlap0;
+      info[p].iters = out[p].iters;
+      info[p].converged = out[p].converged;
+      info[p].fp64_matvecs = mixed ? out[p].iters + 1 : 0;
+      info[p].flags = out[p].flags;
+      info[p].residual = out[p].residual;
+      if (!std::isfinite(out[p].theta) || !std::isfinite(out[p].residual)) {
+        ctx->err = "non-finite energy or residual (problem " + std::to_string(p) + ")";
+        return IDMRG_ENUMERIC;
+      }
+      if (!out[p].converged) rc = IDMRG_WARN_NOCONV;
+    }
+    (void)total_fp64;
+    return rc;
+  });
+}
+
+// ------------------------------------------------------------------ truncate_twosite
+
+extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp_in, int32_t m_max,
+                                double lam_floor, double deg_rel, idmrg_trunc* t) {
+  return guarded(ctx, [&]() {
+    check_nprob(nprob);
+    if (!t || m_max < 1 || !(lam_floor >= 0) || !(deg_rel >= 0)) throw InvalidArg("bad truncation arguments");
+    const std::vector<int> qp = make_qp(d, qp_in);
+    const int P = nprob;
+    hipStream_t s = ctx->stream;
+    struct Sec { int q, r, c; std::vector<std::tuple<int, int, int>> rows, cols; int64_t m, x, g, u, v, sv; };
+    std::vector<std::vector<Sec>> secs(P);
+    std::vector<Leg> A(P), B(P);
+    std::vector<PsiLayout> X(P);
+    int64_t nM = 0, nX = 0, nG = 0, nU = 0, nV = 0, nS = 0;
+    MixList gather;
+    std::vector<SvdTask> svd;
+    std::vector<SelTask> sel;
+    std::vector<SelSector> ssec;
+    int ncand_tot = 0;
+    for (int p = 0; p < P; ++p) {
+      if (!t[p].psi) throw InvalidArg("null psi");
+      A[p] = make_leg(t[p].left, "trunc.left");
+      B[p] = make_leg(t[p].right, "trunc.right");
+      X[p] = psi_layout(A[p], B[p], qp);
+      std::map<int, Sec> byq;
+      for (int a = 0; a < A[p].n(); ++a)
+        for (int s1 = 0; s1 < d; ++s1) {
+          Sec& S = byq[A[p].q[a] + qp[s1]];
+          S.rows.emplace_back(a, s1, S.r);
+          S.r += A[p].dim[a];
+        }
+      for (int s2 = 0; s2 < d; ++s2)
+        for (int b = 0; b < B[p].n(); ++b) {
+          Sec& S = byq[B[p].q[b] - qp[s2]];
+          S.cols.emplace_back(s2, b, S.c);
+          S.c += B[p].dim[b];
+        }
+      SelTask st{};
+      st.sec0 = (int)ssec.size();
+      st.cand0 = ncand_tot;
+      st.m_max = m_max;
+      st.prob = p;
+      st.lam_floor = lam_floor;
+      st.deg_rel = deg_rel;
+      for (auto& kv : byq) {
+        Sec S = kv.second;
+        S.q = kv.first;
+        if (S.r == 0 || S.c == 0) continue;
+        const int n = std::min(S.r, S.c), pp = std::max(S.r, S.c);
+        if (n > 4096) throw InvalidArg("centre sector larger than 4096 states is not supported");
+        S.m = nM; nM += (int64_t)S.r * S.c;
+        S.x = nX; nX += (int64_t)n * pp;
+        S.g = nG; nG += (int64_t)n * n;
+        S.u = nU; nU += (int64_t)S.r * n;
+        S.v = nV; nV += (int64_t)S.c * n;
+        S.sv = nS; nS += n;
+        for (auto& rw : S.rows)
+          for (auto& cl : S.cols) {
+            const int a = std::get<0>(rw), s1 = std::get<1>(rw), ro = std::get<2>(rw);
+            const int s2 = std::get<0>(cl), b = std::get<1>(cl), co = std::get<2>(cl);
+            const int xi = X[p].find(a, s1, s2);
+            if (xi < 0 || X[p].blk[xi].b != b) throw InvalidArg("internal: truncation block bookkeeping");
+            MixTask m{};
+            m.rows = A[p].dim[a]; m.cols = B[p].dim[b]; m.ldd = S.c; m.prob = p; m.dbase = 1;
+            m.doff = S.m + (int64_t)ro * S.c + co;
+            MixSrc sr{};
+            sr.coef = 1.0; sr.base = 0; sr.off = X[p].blk[xi].off; sr.ld = B[p].dim[b];
+            gather.add(m, {sr});
+          }
+        SvdTask sv{};
+        sv.r = S.r; sv.c = S.c; sv.prob = p;
+        sv.m_off = S.m; sv.x_off = S.x; sv.g_off = S.g; sv.u_off = S.u; sv.v_off = S.v; sv.s_off = S.sv;
+        svd.push_back(sv);
+        SelSector se{};
+        se.charge = S.q; se.n = n; se.cand0 = ncand_tot; se.s_off = S.sv;
+        ssec.push_back(se);
+        ncand_tot += n;
+        st.ncand += n;
+        st.nsec += 1;
+        secs[p].push_back(S);
+      }
+      if (st.ncand > 8192) throw InvalidArg("more than 8192 singular values per problem is not supported");
+      if (st.ncand == 0) throw InvalidArg("two-site state has no centre sector");
+      sel.push_back(st);
+    }
+    // S values of all problems live in one array: make s_off global
+    // (each problem's sectors were given offsets into its own region; regions are disjoint)
+    char* ws = (char*)ensure(ctx, ctx->ws[WS_SVD], (nM + nX + nG + nU + nV + nS + 6 * 64) * 8);
+    double* dM = (double*)ws;
+    double* dX = dM + nM + 64;
+    double* dG = dX + nX + 64;
+    double* dU = dG + nG + 64;
+    double* dV = dU + nU + 64;
+    double* dS = dV + nV + 64;
+    const size_t selb = (size_t)ncand_tot * (4 + 8) + ssec.size() * 4 + P * 32 + 4096;
+    char* sw = (char*)ensure(ctx, ctx->ws[WS_SEL], selb);
+    int32_t* colmap = (int32_t*)sw;
+    double* lam_sel = (double*)(sw + ((size_t)ncand_tot * 4 + 255) / 256 * 256);
+    int32_t* kept = (int32_t*)((char*)lam_sel + ((size_t)ncand_tot * 8 + 255) / 256 * 256);
+    double* scal = (double*)((char*)kept + (ssec.size() * 4 + 255) / 256 * 256);
+    {
+      std::vector<int64_t> sz((size_t)P * kNumBases, -1);
+      for (int p = 0; p < P; ++p) {
+        sz[(size_t)p * kNumBases + 0] = X[p].size;
+        sz[(size_t)p * kNumBases + 1] = nM;
+        check_dev(t[p].psi, X[p].size, 8, "psi");
+      }
+      check_mix(gather, sz, "truncation gather");
+    }
+    std::vector<void*> hb((size_t)P * kNumBases, nullptr);
+    for (int p = 0; p < P; ++p) {
+      void** b = &hb[(size_t)p * kNumBases];
+      b[0] = (void*)t[p].psi; b[1] = dM; b[2] = dX; b[3] = dG; b[4] = dU; b[5] = dV; b[6] = dS;
+    }
+    std::vector<int32_t> sweeps(svd.size(), 0);
+    Packer pk;
+    const size_t a1 = pk.add(gather.t), a2 = pk.add(gather.src), a3 = pk.add(svd), a4 = pk.add(sel),
+                 a5 = pk.add(ssec), a6 = pk.add(hb), a7 = pk.add(sweeps);
+    char* dev = upload(ctx, pk);
+    launch_mix(0, 0, (MixTask*)(dev + a1), (MixSrc*)(dev + a2), (int)gather.t.size(), gather.tiles,
+               (void**)(dev + a6), nullptr, s);
+    launch_svd((SvdTask*)(dev + a3), (int)svd.size(), (void**)(dev + a6), (int32_t*)(dev + a7), s);
+    launch_select((SelTask*)(dev + a4), (int)sel.size(), (SelSector*)(dev + a5), dS, kept, colmap, lam_sel, scal, s);
+    IDMRG_HIP(hipGetLastError());
+    std::vector<int32_t> hkept(ssec.size());
+    std::vector<double> hscal(4 * (size_t)P);
+    IDMRG_HIP(hipMemcpyAsync(hkept.data(), kept, hkept.size() * 4, hipMemcpyDeviceToHost, s));
+    IDMRG_HIP(hipMemcpyAsync(hscal.data(), scal, hscal.size() * 8, hipMemcpyDeviceToHost, s));
+    sync(ctx);
+    // outputs
+    ScaleList outl;
+    std::vector<void*> ob((size_t)P * kNumBases, nullptr);
+    for (int p = 0; p < P; ++p) {
+      const SelTask& st = sel[p];
+      Leg C;
+      std::vector<int> which;
+      for (int k = 0; k < st.nsec; ++k)
+        if (hkept[st.sec0 + k] > 0) {
+          C.q.push_back(ssec[st.sec0 + k].charge);
+          C.dim.push_back(hkept[st.sec0 + k]);
+          which.push_back(k);
+        }
+      if (C.n() > t[p].cap_sec || !t[p].q_out || !t[p].dim_out) throw InvalidArg("new-leg capacity too small");
+      const IsoLayout U = U_layout(A[p], qp, C), Vl = V_layout(B[p], qp, C);
+      if (U.size > t[p].cap_U || Vl.size > t[p].cap_V || C.total() > t[p].cap_lam)
+        throw InvalidArg("output capacity too small (U, V or lambda)");
+      if (!t[p].U || !t[p].V || !t[p].lambda) throw InvalidArg("null output buffer");
+      void** b = &ob[(size_t)p * kNumBases];
+      b[0] = dU; b[1] = dV; b[2] = lam_sel; b[3] = t[p].U; b[4] = t[p].V; b[5] = t[p].lambda;
+      int64_t loff = 0;
+      for (int ci = 0; ci < C.n(); ++ci) {
+        const Sec& S = secs[p][which[ci]];
+        const SelSector& se = ssec[st.sec0 + which[ci]];
+        const int n = se.n, k = C.dim[ci];
+        if (U.rows[ci] != S.r || Vl.rows[ci] != S.c) throw InvalidArg("internal: isometry row mismatch");
+        ScaleTask a{};
+        a.rows = S.r; a.cols = k; a.lds = n; a.ldd = k; a.prob = p; a.sbase = 0; a.dbase = 3; a.rbase = -1;
+        a.cbase = -1; a.colmap = se.cand0; a.soff = S.u; a.doff = U.off[ci];
+        outl.add(a);
+        ScaleTask v = a;
+        v.rows = S.c; v.sbase = 1; v.dbase = 4; v.soff = S.v; v.doff = Vl.off[ci];
+        outl.add(v);
+        ScaleTask l{};
+        l.rows = 1; l.cols = k; l.lds = k; l.ldd = k; l.prob = p; l.sbase = 2; l.dbase = 5; l.rbase = -1;
+        l.cbase = -1; l.colmap = -1; l.soff = se.cand0; l.doff = loff;
+        outl.add(l);
+        loff += k;
+        t[p].q_out[ci] = C.q[ci];
+        t[p].dim_out[ci] = k;
+      }
+      t[p].nsec_out = C.n();
+      t[p].eps = hscal[4 * p + 0];
+      t[p].eps_prime = hscal[4 * p + 1];
+      t[p].cut_gap = hscal[4 * p + 2];
+      t[p].m_kept = (int32_t)hscal[4 * p + 3];
+    }
+    {
+      std::vector<int64_t> sz((size_t)P * kNumBases, -1);
+      for (int p = 0; p < P; ++p) {
+        int64_t* z = &sz[(size_t)p * kNumBases];
+        z[0] = nU; z[1] = nV; z[2] = ncand_tot; z[3] = t[p].cap_U; z[4] = t[p].cap_V; z[5] = t[p].cap_lam;
+        check_dev(t[p].U, t[p].cap_U, 8, "U");
+        check_dev(t[p].V, t[p].cap_V, 8, "V");
+        check_dev(t[p].lambda, t[p].cap_lam, 8, "lambda");
+      }
+      check_scale(outl, sz, "truncation output", ncand_tot);
+    }
+    Packer pk2;
+    const size_t b1 = pk2.add(outl.t), b2 = pk2.add(ob);
+    char* dev2 = upload(ctx, pk2);
+    launch_scale((ScaleTask*)(dev2 + b1), colmap, (int)outl.t.size(), outl.tiles, 0.0, (void**)(dev2 + b2), s);
+    IDMRG_HIP(hipGetLastError());
+    sync(ctx);
+    for (int p = 0; p < P; ++p)
+      if (!std::isfinite(t[p].eps)) {
+        ctx->err = "non-finite singular values";
+        return IDMRG_ENUMERIC;
+      }
+    return IDMRG_OK;
+  });
+}
+
+// ------------------------------------------------------------------ update_env
+
+extern "C" int update_env(idmrg_ctx* ctx, int nprob, int side, const idmrg_env_update* u) {
+  return guarded(ctx, [&]() {
+    check_nprob(nprob);
+    if (!u || (side != IDMRG_LEFT && side != IDMRG_RIGHT)) throw InvalidArg("bad update_env arguments");
+    const int P = nprob;
+    EnvPlan plan;
+    std::vector<int64_t> sz((size_t)P * kNumBases, -1);
+    for (int p = 0; p < P; ++p) {
+      if (!u[p].env_old || !u[p].iso || !u[p].env_new) throw InvalidArg("null buffer in idmrg_env_update");
+      const Leg O = make_leg(u[p].old_leg, "env.old_leg"), C = make_leg(u[p].new_leg, "env.new_leg");
+      const Mpo W = make_mpo(u[p].w, "env.w");
+      int64_t* z = &sz[(size_t)p * kNumBases];
+      if (side == IDMRG_LEFT) {
+        build_envL(plan, p, O, C, W);
+        z[0] = envL_layout(O, W.ql).size; z[1] = U_layout(O, W.qp, C).size; z[2] = envL_layout(C, W.qr).size;
+      } else {
+        build_envR(plan, p, O, C, W);
+        z[0] = envR_layout(O, W.qr).size; z[1] = V_layout(O, W.qp, C).size; z[2] = envR_layout(C, W.ql).size;
+      }
+      z[3] = plan.n_T1[p]; z[4] = plan.n_T2[p];
+      check_dev(u[p].env_old, z[0], 8, "env_old");
+      check_dev(u[p].iso, z[1], 8, "iso");
+      check_dev(u[p].env_new, z[2], 8, "env_new");
+    }
+    check_gemm(plan.ga, side == IDMRG_LEFT ? 0 : 2, sz, "env stage a");
+    check_mix(plan.mix, sz, "env mix");
+    check_gemm(plan.gc, side == IDMRG_LEFT ? 2 : 0, sz, "env stage c");
+    int64_t n1 = 0, n2 = 0;
+    std::vector<int64_t> o1(P), o2(P);
+    for (int p = 0; p < P; ++p) {
+      o1[p] = n1; n1 += plan.n_T1[p] + 64;
+      o2[p] = n2; n2 += plan.n_T2[p] + 64;
+    }
+    double* ws = (double*)ensure(ctx, ctx->ws[WS_ENV], (n1 + n2) * 8);
+    std::vector<void*> hb((size_t)P * kNumBases, nullptr);
+    for (int p = 0; p < P; ++p) {
+      void** b = &hb[(size_t)p * kNumBases];
+      b[0] = (void*)u[p].env_old; b[1] = (void*)u[p].iso; b[2] = u[p].env_new;
+      b[3] = ws + o1[p]; b[4] = ws + n1 + o2[p];
+    }
+    Packer pk;
+    const size_t a1 = pk.add(plan.ga.t), a2 = pk.add(plan.mix.t), a3 = pk.add(plan.mix.src), a4 = pk.add(plan.gc.t),
+                 a5 = pk.add(hb);
+    char* dev = upload(ctx, pk);
+    void** bases = (void**)(dev + a5);
+    hipStream_t s = ctx->stream;
+    launch_gemm(Prec::F64, side == IDMRG_LEFT ? 0 : 2, (GemmTask*)(dev + a1), (int)plan.ga.t.size(), plan.ga.tiles,
+                bases, nullptr, s);
+    launch_mix(0, 0, (MixTask*)(dev + a2), (MixSrc*)(dev + a3), (int)plan.mix.t.size(), plan.mix.tiles, bases,
+               nullptr, s);
+    launch_gemm(Prec::F64, side == IDMRG_LEFT ? 2 : 0, (GemmTask*)(dev + a4), (int)plan.gc.t.size(), plan.gc.tiles,
+                bases, nullptr, s);
+    IDMRG_HIP(hipGetLastError());
+    return IDMRG_OK;
+  });
+}
+
+// ------------------------------------------------------------------ predict_wavefunction
+
+extern "C" int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp_in, double lam_floor,
+                                    const idmrg_predict* pr) {
+  return guarded(ctx, [&]() {
+    check_nprob(nprob);
+    if (!pr || !(lam_floor >= 0)) throw InvalidArg("bad predict arguments");
+    const std::vector<int> qp = make_qp(d, qp_in);
+    const int P = nprob;
+    PredictPlan plan;
+    std::vector<int64_t> sz((size_t)P * kNumBases, -1);
+    for (int p = 0; p < P; ++p) {
+      if (!pr[p].lam_i || !pr[p].V_i || !pr[p].lam_prev || !pr[p].U_ip1 || !pr[p].lam_ip1 || !pr[p].psi)
+        throw InvalidArg("null buffer in idmrg_predict");
+      const Leg Aa = make_leg(pr[p].leg_a, "leg_a"), Bt = make_leg(pr[p].leg_beta, "leg_beta"),
+                Bb = make_leg(pr[p].leg_b, "leg_b");
+      build_predict(plan, p, Aa, Bt, Bb, qp);
+      int64_t* z = &sz[(size_t)p * kNumBases];
+      z[0] = Aa.total(); z[1] = z[6] = V_layout(Bt, qp, Aa).size; z[2] = Bt.total();
+      z[3] = z[7] = U_layout(Bt, qp, Bb).size; z[4] = Bb.total(); z[5] = psi_layout(Aa, Bb, qp).size;
+      check_dev(pr[p].lam_i, z[0], 8, "lam_i");
+      check_dev(pr[p].V_i, z[1], 8, "V_i");
+      check_dev(pr[p].lam_prev, z[2], 8, "lam_prev");
+      check_dev(pr[p].U_ip1, z[3], 8, "U_ip1");
+      check_dev(pr[p].lam_ip1, z[4], 8, "lam_ip1");
+      check_dev(pr[p].psi, z[5], 8, "psi");
+    }
+    check_scale(plan.scale, sz, "predict scale", 0);
+    check_gemm(plan.g, 2, sz, "predict gemm");
+    int64_t n = 0;
+    std::vector<int64_t> ov(P), ou(P);
+    for (int p = 0; p < P; ++p) {
+      ov[p] = n; n += plan.n_Vs[p] + 64;
+      ou[p] = n; n += plan.n_Us[p] + 64;
+    }
+    double* ws = (double*)ensure(ctx, ctx->ws[WS_PRED], n * 8);
+    std::vector<void*> hb((size_t)P * kNumBases, nullptr);
+    for (int p = 0; p < P; ++p) {
+      void** b = &hb[(size_t)p * kNumBases];
+      b[0] = (void*)pr[p].lam_i; b[1] = (void*)pr[p].V_i; b[2] = (void*)pr[p].lam_prev; b[3] = (void*)pr[p].U_ip1;
+      b[4] = (void*)pr[p].lam_ip1; b[5] = pr[p].psi; b[6] = ws + ov[p]; b[7] = ws + ou[p];
+    }
+    Packer pk;
+    const size_t a1 = pk.add(plan.scale.t), a2 = pk.add(plan.g.t), a3 = pk.add(hb);
+    char* dev = upload(ctx, pk);
+    void** bases = (void**)(dev + a3);
+    launch_scale((ScaleTask*)(dev + a1), nullptr, (int)plan.scale.t.size(), plan.scale.tiles, lam_floor, bases,
+                 ctx->stream);
+    launch_gemm(Prec::F64, 2, (GemmTask*)(dev + a2), (int)plan.g.t.size(), plan.g.tiles, bases, nullptr, ctx->stream);
+    IDMRG_HIP(hipGetLastError());
+    return IDMRG_OK;
+  });
+}

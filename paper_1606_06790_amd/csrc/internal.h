@@ -1,0 +1,159 @@
+// Internal declarations of the idmrg library: work-plan records shared by the
+// host plan builders and the gfx950 kernels, and the host-side launchers.
+//
+// Every device operand is addressed as bases[prob * kNumBases + base] + off,
+// so one plan (a list of tasks with element offsets) serves any set of buffers
+// and any element type (FP64 masters, FP32 copies, packed bf16 hi/lo pairs).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace idmrg {
+
+constexpr int kNumBases = 8;
+
+// C[M x N] (+)= op(A) op(B); A is [M x K] row-major (or [K x M] when transposed),
+// B is [K x N] row-major (or [N x K] when transposed).  beta is 0 or 1.
+struct GemmTask {
+  int32_t M, N, K;
+  int32_t lda, ldb, ldc;
+  int32_t prob, beta;
+  int32_t abase, bbase, cbase;
+  int32_t tile0;      // first global tile of this task (exclusive prefix sum)
+  int32_t tiles_n;    // tiles along N
+  int32_t pad;
+  int64_t aoff, boff, coff;
+};
+
+// D[rows x cols] = sum_k coef_k * S_k   (S_k[r][c] at off + r*ld + c, or off + c*ld + r if trans)
+struct MixTask {
+  int32_t rows, cols, ldd, prob;
+  int32_t dbase, nsrc, src0, tile0;
+  int32_t tiles_c, pad;
+  int64_t doff;
+};
+
+struct MixSrc {
+  double coef;
+  int64_t off;
+  int32_t ld, base;
+  int32_t trans, pad;
+};
+
+// D[r][c] = S[r][colmap[c]] * rowscale[r] * colscale[c]; absent scales are 1.
+// rowscale may be replaced by 1/x (0 for x <= floor) when invert_row is set.
+struct ScaleTask {
+  int32_t rows, cols, lds, ldd;
+  int32_t prob, sbase, dbase, rbase;
+  int32_t cbase, invert_row, colmap, tile0;   // colmap < 0: identity map
+  int32_t tiles_c, pad;
+  int64_t soff, doff, roff, coff;
+};
+
+// One-sided Jacobi SVD of M[r x c] (row-major); n = min(r, c), p = max(r, c).
+struct SvdTask {
+  int32_t r, c, prob, pad;
+  int64_t m_off, x_off, g_off, u_off, v_off, s_off;
+};
+
+// Selection of kept singular values for one problem (all its centre sectors).
+struct SelTask {
+  int32_t nsec, sec0;       // sectors [sec0, sec0 + nsec) in the sector arrays
+  int32_t ncand, cand0;     // candidates [cand0, cand0 + ncand)
+  int32_t m_max, prob;
+  double lam_floor, deg_rel;
+};
+
+// Per-sector record of the selection (device).
+struct SelSector {
+  int32_t charge, n;        // centre charge, number of singular values
+  int32_t cand0, pad;       // offset of its candidates in the candidate arrays
+  int64_t s_off;            // singular values in the S workspace
+};
+
+// ---------------------------------------------------------------- host errors
+
+struct Status {
+  int code = 0;
+  std::string msg;
+};
+
+#define IDMRG_HIP(call)                                                          \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      throw ::idmrg::HipFailure(std::string(#call) + ": " + hipGetErrorString(e_)); \
+    }                                                                            \
+  } while (0)
+
+struct HipFailure {
+  std::string what;
+  explicit HipFailure(std::string w) : what(std::move(w)) {}
+};
+struct InvalidArg {
+  std::string what;
+  explicit InvalidArg(std::string w) : what(std::move(w)) {}
+};
+
+// ---------------------------------------------------------------- launchers
+
+enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
+
+// Grouped GEMM over `ntask` tasks with `ntiles` total tiles (tile 64 x 64).
+// mode: 0 = NN, 1 = NT, 2 = TN.  Element type chosen by prec:
+//   F64: double A, B, C;  F32: float A, B, C;  BF16X3: packed (hi,lo) bf16 A, B, float C.
+// `active` (nullable) holds one flag per problem; tasks of inactive problems exit at once.
+void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntiles,
+                 void* const* bases, const int32_t* active, hipStream_t s);
+
+// Mix over tasks; tin/tout element types: 0 = double, 1 = float, 2 = packed bf16 pair (output only).
+void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int ntask, int ntiles,
+                void* const* bases, const int32_t* active, hipStream_t s);
+
+void launch_scale(const ScaleTask* tasks, const int32_t* colmaps, int ntask, int ntiles,
+                  double lam_floor, void* const* bases, hipStream_t s);
+
+// element conversions (n elements): double -> float, double -> packed bf16 pair, float -> double
+void launch_convert(int kind, const void* src, void* dst, int64_t n, hipStream_t s);
+
+void launch_svd(const SvdTask* tasks, int ntask, void* const* bases, int32_t* sweeps_out, hipStream_t s);
+void launch_select(const SelTask* tasks, int ntask, const SelSector* secs, const double* S,
+                   int32_t* kept_per_sec, int32_t* colmap, double* lam_sel, double* scal,
+                   hipStream_t s);
+
+// Lanczos vector kernels (batched over problems), see lanczos.hip
+struct LzProblem {
+  int64_t N;
+  double* Q;        // [kcap x N]
+  double* w;        // [N]
+  double* v;        // [N] current vector (matvec input)
+  double* psi;      // [N] caller's vector
+};
+
+struct LzCtrl {     // device, one per problem
+  int32_t j;        // index of the current Lanczos vector
+  int32_t active;
+  int32_t iters;
+  int32_t converged;
+  int32_t flags;
+  int32_t kcap;
+  int32_t pad0, pad1;
+  double theta, theta_prev, beta_j, residual, norm0, overlap0, ynorm, pad2;
+};
+
+constexpr int kLzBlocks = 128;   // partial-sum blocks per problem
+constexpr int kLzMaxK = 1024;    // upper bound of k_max (tridiagonal kept in LDS)
+
+// ctrl[] and active[] are initialised by the host before lz_init.
+void lz_init(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s);
+void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* active, double* alpha, double* beta,
+                       double* ritz, double* coef, double* partial, int kmax, double tol_E, double tol_res,
+                       hipStream_t s);
+void lz_finish(int P, const LzProblem* probs, LzCtrl* ctrl, double* ritz, double* partial, int kmax, hipStream_t s);
+void lz_residual(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s);
+
+}  // namespace idmrg

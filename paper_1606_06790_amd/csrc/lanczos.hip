@@ -1,0 +1,392 @@
+// Lanczos iteration kernels, batched over the problems of one call.
+//
+// All per-problem control lives on the device (LzCtrl): the current Krylov
+// index j, the stop flag, the Ritz value history.  The host only launches a
+// fixed sequence of kernels per iteration and reads the stop flags once per
+// chunk of iterations, so the sequence is the same for every iteration.
+//
+// Reductions are two-stage and deterministic: kLzBlocks partial sums per
+// problem in fixed positions, then one workgroup adds them in a fixed tree.
+//
+// Iteration j (current vector v = q_j, w = H q_j on entry):
+//   alpha_j = <q_j, w>;  w -= alpha_j q_j + beta_{j-1} q_{j-1}
+//   two passes of classical Gram-Schmidt against q_0..q_j (CGS2)
+//   beta_j = |w|; lowest Ritz pair (theta, y) of T_{j+1}; stop test;
+//   otherwise q_{j+1} = w / beta_j.
+#include "internal.h"
+
+namespace idmrg {
+namespace {
+
+constexpr int TB = 256;
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Deterministic block sum of one value per thread (TB threads): fixed tree.
+__device__ double block_sum(double x, double* sh) {
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void range_of(int64_t N, int b, int64_t& lo, int64_t& hi) {
+  const int64_t per = (N + kLzBlocks - 1) / kLzBlocks;
+  lo = per * b;
+  hi = lo + per;
+  if (hi > N) hi = N;
+  if (lo > N) lo = N;
+}
+
+// which: 0 = v, 1 = w, 2 = psi
+__device__ __forceinline__ double* vec_of(const LzProblem& p, int which) {
+  return which == 0 ? p.v : (which == 1 ? p.w : p.psi);
+}
+
+// partial[p][0][b] = sum_{n in range b} x[n] * y[n]
+__global__ __launch_bounds__(TB) void k_dot_partial(const LzProblem* probs, const int32_t* active, int wx, int wy,
+                                                    double* partial, int kmax) {
+  __shared__ double sh[TB];
+  const int p = blockIdx.y, b = blockIdx.x;
+  if (active && !active[p]) return;
+  const LzProblem pr = probs[p];
+  const double* x = vec_of(pr, wx);
+  const double* y = vec_of(pr, wy);
+  int64_t lo, hi;
+  range_of(pr.N, b, lo, hi);
+  double acc = 0.0;
+  for (int64_t n = lo + threadIdx.x; n < hi; n += TB) acc += x[n] * y[n];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[((int64_t)p * kmax) * kLzBlocks + b] = acc;
+}
+
+// Sum kLzBlocks partials of slot i of each problem in a fixed tree.
+__device__ double sum_partials(const double* partial, int p, int i, int kmax, double* sh) {
+  double x = 0.0;
+  for (int b = threadIdx.x; b < kLzBlocks; b += TB) x += partial[((int64_t)p * kmax + i) * kLzBlocks + b];
+  return block_sum(x, sh);
+}
+
+// mode 0: alpha_j = sum;  mode 1: beta_j = sqrt(sum);  mode 2: norm0 = sqrt(sum);  mode 3: residual = sqrt(sum)
+__global__ __launch_bounds__(TB) void k_finalize(LzCtrl* ctrl, const int32_t* active, const double* partial,
+                                                 double* alpha, int kmax, int mode) {
+  __shared__ double sh[TB];
+  const int p = blockIdx.x;
+  if (active && !active[p]) return;
+  const double s = sum_partials(partial, p, 0, kmax, sh);
+  if (threadIdx.x == 0) {
+    if (mode == 0) alpha[(int64_t)p * kmax + ctrl[p].j] = s;
+    else if (mode == 1) ctrl[p].beta_j = sqrt(s);
+    else if (mode == 2) ctrl[p].norm0 = sqrt(s);
+    else ctrl[p].residual = sqrt(s);
+  }
+}
+
+// v = Q[0] = psi / norm0
+__global__ __launch_bounds__(TB) void k_start(const LzProblem* probs, const LzCtrl* ctrl) {
+  const int p = blockIdx.y;
+  const LzProblem pr = probs[p];
+  const double inv = 1.0 / ctrl[p].norm0;
+  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
+    const double x = pr.psi[n] * inv;
+    pr.v[n] = x;
+    pr.Q[n] = x;
+  }
+}
+
+// w -= alpha_j v + beta_{j-1} Q[j-1]
+__global__ __launch_bounds__(TB) void k_three_term(const LzProblem* probs, const LzCtrl* ctrl, const int32_t* active,
+                                                   const double* alpha, const double* beta, int kmax) {
+  const int p = blockIdx.y;
+  if (!active[p]) return;
+  const LzProblem pr = probs[p];
+  const int j = ctrl[p].j;
+  const double a = alpha[(int64_t)p * kmax + j];
+  const double bm = j > 0 ? beta[(int64_t)p * kmax + j - 1] : 0.0;
+  const double* qm = j > 0 ? pr.Q + (int64_t)(j - 1) * pr.N : pr.Q;
+  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB)
+    pr.w[n] -= a * pr.v[n] + bm * qm[n];
+}
+
+// partial[p][i][b] = sum_{n in range b} Q[i][n] w[n], i = 0..j; one wave per i.
+__global__ __launch_bounds__(TB) void k_multidot_partial(const LzProblem* probs, const LzCtrl* ctrl,
+                                                         const int32_t* active, double* partial, int kmax) {
+  const int p = blockIdx.y, b = blockIdx.x;
+  if (!active[p]) return;
+  const LzProblem pr = probs[p];
+  const int j = ctrl[p].j;
+  int64_t lo, hi;
+  range_of(pr.N, b, lo, hi);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = wave; i <= j; i += TB / 64) {
+    const double* q = pr.Q + (int64_t)i * pr.N;
+    double acc = 0.0;
+    for (int64_t n = lo + lane; n < hi; n += 64) acc += q[n] * pr.w[n];
+    acc = wave_sum(acc);
+    if (lane == 0) partial[((int64_t)p * kmax + i) * kLzBlocks + b] = acc;
+  }
+}
+
+// coef[p][i] = sum_b partial[p][i][b], i = 0..j; one block per (i, p).
+__global__ __launch_bounds__(TB) void k_multidot_finalize(const LzCtrl* ctrl, const int32_t* active,
+                                                          const double* partial, double* coef, int kmax) {
+  __shared__ double sh[TB];
+  const int p = blockIdx.y, i = blockIdx.x;
+  if (!active[p] || i > ctrl[p].j) return;
+  const double s = sum_partials(partial, p, i, kmax, sh);
+  if (threadIdx.x == 0) coef[(int64_t)p * kmax + i] = s;
+}
+
+// w -= sum_{i<=j} coef[i] Q[i]
+__global__ __launch_bounds__(TB) void k_gs_update(const LzProblem* probs, const LzCtrl* ctrl, const int32_t* active,
+                                                  const double* coef, int kmax) {
+  const int p = blockIdx.y;
+  if (!active[p]) return;
+  const LzProblem pr = probs[p];
+  const int j = ctrl[p].j;
+  const double* c = coef + (int64_t)p * kmax;
+  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
+    double s = 0.0;
+    for (int i = 0; i <= j; ++i) s += c[i] * pr.Q[(int64_t)i * pr.N + n];
+    pr.w[n] -= s;
+  }
+}
+
+// Number of eigenvalues of the tridiagonal (a, b) below x (Sturm sequence).
+__device__ int sturm_count(const double* a, const double* b, int k, double x, double pivmin) {
+  int cnt = 0;
+  double d = a[0] - x;
+  if (fabs(d) < pivmin) d = -pivmin;
+  cnt += d < 0.0;
+  for (int i = 1; i < k; ++i) {
+    d = (a[i] - x) - b[i - 1] * b[i - 1] / d;
+    if (fabs(d) < pivmin) d = -pivmin;
+    cnt += d < 0.0;
+  }
+  return cnt;
+}
+
+// Lowest eigenpair of T_{j+1}, stop test, advance.  One wave per problem.
+// Eigenvalue: multisection with Sturm counts (64 points per round).
+// Eigenvector: inverse iteration with the shift just below the eigenvalue,
+// where T - sigma I is positive definite and its LDL^T needs no pivoting.
+__global__ __launch_bounds__(64) void k_tridiag(LzCtrl* ctrl, int32_t* active, const double* alpha, double* beta,
+                                                double* ritz, int kmax, double tol_E, double tol_res) {
+  __shared__ double a[1024], b[1024], dd[1024], ll[1024], y[1024];
+  __shared__ double s_lo, s_hi;
+  const int p = blockIdx.x;
+  if (!active[p]) return;
+  const int lane = threadIdx.x;
+  const int j = ctrl[p].j;
+  const int k = j + 1;
+  const double bnew = ctrl[p].beta_j;
+  for (int i = lane; i < k; i += 64) {
+    a[i] = alpha[(int64_t)p * kmax + i];
+    b[i] = i < k - 1 ? beta[(int64_t)p * kmax + i] : 0.0;
+  }
+  __syncthreads();
+  // Gershgorin interval
+  double lo = 1e300, hi = -1e300, bmax = 0.0;
+  for (int i = lane; i < k; i += 64) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < k - 1 ? fabs(b[i]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
+    if (i < k - 1) bmax = fmax(bmax, fabs(b[i]));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+    bmax = fmax(bmax, __shfl_xor(bmax, o, 64));
+  }
+  const double pivmin = fmax(1e-300, 1e-290 * bmax * bmax);
+  double theta;
+  if (k == 1) {
+    theta = a[0];
+  } else {
+    const double pad = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+    lo -= pad;
+    hi += pad;
+    for (int round = 0; round < 40; ++round) {
+      const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+      const int c = sturm_count(a, b, k, x, pivmin);
+      const unsigned long long m = __ballot(c >= 1);
+      // first lane whose point has at least one eigenvalue below it
+      int first = m ? __ffsll((long long)m) - 1 : 64;
+      const double nlo = first == 0 ? lo : lo + (hi - lo) * (double)first / 65.0;
+      const double nhi = first == 64 ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
+      lo = nlo;
+      hi = nhi;
+      if (hi - lo <= 2.5e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    }
+    theta = 0.5 * (lo + hi);
+  }
+  if (lane == 0) {
+    if (k == 1) {
+      y[0] = 1.0;
+    } else {
+      const double sigma = theta - (1e-10 * fabs(theta) + 1e-13 * (fabs(lo) + fabs(hi)) + 1e-300);
+      dd[0] = a[0] - sigma;
+      for (int i = 1; i < k; ++i) {
+        ll[i] = b[i - 1] / dd[i - 1];
+        dd[i] = (a[i] - sigma) - ll[i] * b[i - 1];
+      }
+      for (int i = 0; i < k; ++i) y[i] = 1.0;
+      for (int it = 0; it < 4; ++it) {
+        for (int i = 1; i < k; ++i) y[i] -= ll[i] * y[i - 1];     // L z = y
+        for (int i = 0; i < k; ++i) y[i] /= dd[i];                // D
+        for (int i = k - 2; i >= 0; --i) y[i] -= ll[i + 1] * y[i + 1];  // L^T
+        double nrm = 0.0;
+        for (int i = 0; i < k; ++i) nrm += y[i] * y[i];
+        nrm = 1.0 / sqrt(nrm);
+        for (int i = 0; i < k; ++i) y[i] *= nrm;
+      }
+    }
+    if (y[0] < 0.0)
+      for (int i = 0; i < k; ++i) y[i] = -y[i];
+    LzCtrl& c = ctrl[p];
+    const double res = bnew * fabs(y[k - 1]);
+    const bool have_prev = k > 1;
+    const bool stop_dtheta = have_prev && fabs(theta - c.theta_prev) <= tol_E && res <= tol_res;
+    const bool stop_inv = bnew <= 1e-14 * fabs(theta);
+    c.theta = theta;
+    for (int i = 0; i < k; ++i) ritz[(int64_t)p * kmax + i] = y[i];
+    if (stop_dtheta || stop_inv || k >= c.kcap) {
+      c.active = 0;
+      active[p] = 0;
+      c.iters = k;
+      c.converged = (stop_dtheta || stop_inv) ? 1 : 0;
+      c.flags |= stop_inv ? 1 : 0;
+      c.residual = res;
+      c.overlap0 = fabs(y[0]);
+    } else {
+      beta[(int64_t)p * kmax + j] = bnew;
+      c.theta_prev = theta;
+      c.j = k;
+    }
+  }
+}
+
+// Q[j] = v = w / beta_{j-1}  (j already advanced)
+__global__ __launch_bounds__(TB) void k_next(const LzProblem* probs, const LzCtrl* ctrl, const int32_t* active,
+                                             const double* beta, int kmax) {
+  const int p = blockIdx.y;
+  if (!active[p]) return;
+  const LzProblem pr = probs[p];
+  const int j = ctrl[p].j;
+  const double inv = 1.0 / beta[(int64_t)p * kmax + j - 1];
+  double* q = pr.Q + (int64_t)j * pr.N;
+  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
+    const double x = pr.w[n] * inv;
+    q[n] = x;
+    pr.v[n] = x;
+  }
+}
+
+// psi = sum_{i < iters} y_i Q[i]
+__global__ __launch_bounds__(TB) void k_ritz(const LzProblem* probs, const LzCtrl* ctrl, const double* ritz, int kmax) {
+  const int p = blockIdx.y;
+  const LzProblem pr = probs[p];
+  const int k = ctrl[p].iters;
+  const double* y = ritz + (int64_t)p * kmax;
+  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += y[i] * pr.Q[(int64_t)i * pr.N + n];
+    pr.psi[n] = s;
+  }
+}
+
+// psi /= norm0 ; v = psi (input of the residual matvec)
+__global__ __launch_bounds__(TB) void k_normalize_psi(const LzProblem* probs, const LzCtrl* ctrl) {
+  const int p = blockIdx.y;
+  const LzProblem pr = probs[p];
+  const double inv = 1.0 / ctrl[p].norm0;
+  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
+    const double x = pr.psi[n] * inv;
+    pr.psi[n] = x;
+    pr.v[n] = x;
+  }
+}
+
+// partial[p][0][b] = sum |w - theta psi|^2
+__global__ __launch_bounds__(TB) void k_residual_partial(const LzProblem* probs, const LzCtrl* ctrl, double* partial,
+                                                         int kmax) {
+  __shared__ double sh[TB];
+  const int p = blockIdx.y, b = blockIdx.x;
+  const LzProblem pr = probs[p];
+  const double th = ctrl[p].theta;
+  int64_t lo, hi;
+  range_of(pr.N, b, lo, hi);
+  double acc = 0.0;
+  for (int64_t n = lo + threadIdx.x; n < hi; n += TB) {
+    const double r = pr.w[n] - th * pr.psi[n];
+    acc += r * r;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[((int64_t)p * kmax) * kLzBlocks + b] = acc;
+}
+
+dim3 vec_grid(int P) { return dim3(512, P); }
+
+}  // namespace
+
+void lz_init(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)nullptr, 2, 2,
+                     partial, kmax);
+  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, partial, (double*)nullptr,
+                     kmax, 2);
+  hipLaunchKernelGGL(k_start, vec_grid(P), dim3(TB), 0, s, probs, ctrl);
+}
+
+void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* active, double* alpha, double* beta,
+                       double* ritz, double* coef, double* partial, int kmax, double tol_E, double tol_res,
+                       hipStream_t s) {
+  // alpha_j = <v, w>
+  hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)active, 0, 1,
+                     partial, kmax);
+  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)active, partial, alpha, kmax, 0);
+  hipLaunchKernelGGL(k_three_term, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, (const int32_t*)active,
+                     (const double*)alpha, (const double*)beta, kmax);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_multidot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl,
+                       (const int32_t*)active, partial, kmax);
+    hipLaunchKernelGGL(k_multidot_finalize, dim3(kmax, P), dim3(TB), 0, s, (const LzCtrl*)ctrl,
+                       (const int32_t*)active, (const double*)partial, coef, kmax);
+    hipLaunchKernelGGL(k_gs_update, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, (const int32_t*)active,
+                       (const double*)coef, kmax);
+  }
+  hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)active, 1, 1, partial,
+                     kmax);
+  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)active, partial, alpha, kmax, 1);
+  hipLaunchKernelGGL(k_tridiag, dim3(P), dim3(64), 0, s, ctrl, active, (const double*)alpha, beta, ritz, kmax, tol_E,
+                     tol_res);
+  hipLaunchKernelGGL(k_next, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, (const int32_t*)active,
+                     (const double*)beta, kmax);
+}
+
+void lz_finish(int P, const LzProblem* probs, LzCtrl* ctrl, double* ritz, double* partial, int kmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_ritz, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, (const double*)ritz, kmax);
+  hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)nullptr, 2, 2,
+                     partial, kmax);
+  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, partial, (double*)nullptr,
+                     kmax, 2);
+  hipLaunchKernelGGL(k_normalize_psi, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl);
+}
+
+void lz_residual(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, partial,
+                     kmax);
+  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, partial, (double*)nullptr,
+                     kmax, 3);
+}
+
+}  // namespace idmrg

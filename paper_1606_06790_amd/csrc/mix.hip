@@ -1,0 +1,153 @@
+// Bandwidth-bound kernels of the plans: the MPO channel mixing between the two
+// environment GEMMs (and plain block copies), diagonal scalings with column
+// selection, and element conversions for the mixed-precision policies.
+//
+// A mix tile is 32 rows x 64 columns; 256 threads each produce 8 outputs of
+// one column, so every row segment is read and written as 512 contiguous bytes.
+#include "internal.h"
+
+namespace idmrg {
+namespace {
+
+constexpr int MR = 32, MC = 64;
+
+template <typename T>
+__device__ __forceinline__ double ld_as_double(const void* base, int64_t idx) {
+  return (double)reinterpret_cast<const T*>(base)[idx];
+}
+
+__device__ __forceinline__ uint32_t split_bf16(float x) {
+  // hi = round-to-nearest-even bf16 of x; lo = bf16(x - hi)
+  uint32_t u = __float_as_uint(x);
+  uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  uint32_t hi = r & 0xffff0000u;
+  float rem = x - __uint_as_float(hi);
+  uint32_t v = __float_as_uint(rem);
+  uint32_t r2 = v + 0x7fffu + ((v >> 16) & 1u);
+  return (hi >> 16) | (r2 & 0xffff0000u);
+}
+
+__device__ __forceinline__ int find_tile(const int32_t* tile0, int stride_words, int ntask, int tile) {
+  int lo = 0, hi = ntask - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tile0[(int64_t)mid * stride_words] <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename TIN, typename TOUT>
+__global__ __launch_bounds__(256) void mix_kernel(const MixTask* __restrict__ tasks, const MixSrc* __restrict__ srcs,
+                                                  int ntask, void* const* __restrict__ bases,
+                                                  const int32_t* __restrict__ active) {
+  const int tile = blockIdx.x;
+  const int ti = find_tile(&tasks[0].tile0, sizeof(MixTask) / 4, ntask, tile);
+  const MixTask& tk = tasks[ti];
+  if (active && !active[tk.prob]) return;
+  const int local = tile - tk.tile0;
+  const int r0 = (local / tk.tiles_c) * MR;
+  const int c = (local % tk.tiles_c) * MC + (threadIdx.x & 63);
+  const int rbase = r0 + (threadIdx.x >> 6);
+  if (c >= tk.cols) return;
+  float acc32[8];
+  double acc[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) acc[e] = 0.0;
+  for (int k = 0; k < tk.nsrc; ++k) {
+    const MixSrc& s = srcs[tk.src0 + k];
+    const TIN* base = reinterpret_cast<const TIN*>(bases[tk.prob * kNumBases + s.base]) + s.off;
+    const double coef = s.coef;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = rbase + 4 * e;
+      if (r < tk.rows) {
+        const int64_t idx = s.trans ? ((int64_t)c * s.ld + r) : ((int64_t)r * s.ld + c);
+        acc[e] += coef * (double)base[idx];
+      }
+    }
+  }
+  (void)acc32;
+  TOUT* dst = reinterpret_cast<TOUT*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int r = rbase + 4 * e;
+    if (r < tk.rows) {
+      if constexpr (std::is_same<TOUT, uint32_t>::value) {
+        dst[(int64_t)r * tk.ldd + c] = split_bf16((float)acc[e]);
+      } else {
+        dst[(int64_t)r * tk.ldd + c] = (TOUT)acc[e];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void scale_kernel(const ScaleTask* __restrict__ tasks, const int32_t* __restrict__ colmaps,
+                                                    int ntask, double lam_floor, void* const* __restrict__ bases) {
+  const int tile = blockIdx.x;
+  const int ti = find_tile(&tasks[0].tile0, sizeof(ScaleTask) / 4, ntask, tile);
+  const ScaleTask& tk = tasks[ti];
+  const int local = tile - tk.tile0;
+  const int r0 = (local / tk.tiles_c) * MR;
+  const int c = (local % tk.tiles_c) * MC + (threadIdx.x & 63);
+  if (c >= tk.cols) return;
+  const double* S = reinterpret_cast<const double*>(bases[tk.prob * kNumBases + tk.sbase]) + tk.soff;
+  double* D = reinterpret_cast<double*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff;
+  const int sc = tk.colmap >= 0 ? colmaps[tk.colmap + c] : c;
+  double cs = 1.0;
+  if (tk.cbase >= 0) cs = reinterpret_cast<const double*>(bases[tk.prob * kNumBases + tk.cbase])[tk.coff + c];
+  const double* rs = tk.rbase >= 0 ? reinterpret_cast<const double*>(bases[tk.prob * kNumBases + tk.rbase]) + tk.roff
+                                   : nullptr;
+  for (int e = 0; e < 8; ++e) {
+    const int r = r0 + (threadIdx.x >> 6) + 4 * e;
+    if (r >= tk.rows) break;
+    double f = cs;
+    if (rs) {
+      const double x = rs[r];
+      f *= tk.invert_row ? (x > lam_floor ? 1.0 / x : 0.0) : x;
+    }
+    D[(int64_t)r * tk.ldd + c] = S[(int64_t)r * tk.lds + sc] * f;
+  }
+}
+
+__global__ void convert_kernel(int kind, const void* __restrict__ src, void* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (kind == 0) {
+      reinterpret_cast<float*>(dst)[i] = (float)reinterpret_cast<const double*>(src)[i];
+    } else if (kind == 1) {
+      reinterpret_cast<uint32_t*>(dst)[i] = split_bf16((float)reinterpret_cast<const double*>(src)[i]);
+    } else {
+      reinterpret_cast<double*>(dst)[i] = (double)reinterpret_cast<const float*>(src)[i];
+    }
+  }
+}
+
+}  // namespace
+
+void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int ntask, int ntiles,
+                void* const* bases, const int32_t* active, hipStream_t s) {
+  if (ntask == 0 || ntiles == 0) return;
+  dim3 grid(ntiles), block(256);
+  if (tin == 0 && tout == 0)
+    hipLaunchKernelGGL((mix_kernel<double, double>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
+  else if (tin == 1 && tout == 1)
+    hipLaunchKernelGGL((mix_kernel<float, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
+  else if (tin == 1 && tout == 2)
+    hipLaunchKernelGGL((mix_kernel<float, uint32_t>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
+  else if (tin == 0 && tout == 1)
+    hipLaunchKernelGGL((mix_kernel<double, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
+}
+
+void launch_scale(const ScaleTask* tasks, const int32_t* colmaps, int ntask, int ntiles, double lam_floor,
+                  void* const* bases, hipStream_t s) {
+  if (ntask == 0 || ntiles == 0) return;
+  hipLaunchKernelGGL(scale_kernel, dim3(ntiles), dim3(256), 0, s, tasks, colmaps, ntask, lam_floor, bases);
+}
+
+void launch_convert(int kind, const void* src, void* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, s, kind, src, dst, n);
+}
+
+}  // namespace idmrg

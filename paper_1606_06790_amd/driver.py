@@ -1,0 +1,158 @@
+"""Parallel infinite-size DMRG on one GPU (host control flow).
+
+Follows Sec. 3 of the paper: Hida's iDMRG with Steps 2, 3 and 5 replaced by
+their parallel versions.  At iteration n the l/2 superblocks i = 1..l/2 each
+consist of L^(n-1)_{2i-1}, the centre sites 2i+n-1 and 2i+n with W_{f(.)},
+and R^(n-1)_{2(i+1)} from the neighbour (R_{l+2} = R_2) (Step 2', Eqs. (8),
+(9)).  All of them go through the library together: one batched prediction
+(Eq. (10), Step 3'), one batched Lanczos solve (Step 3), one batched
+truncation (Step 4), two batched environment updates (Step 6, Eqs. (4),
+(5)).  The neighbour hand-off is a swap of device tensors.  Step 5' forms
+e_g = (e^(n)_1 - e^(n-l)_1) / (2l) whenever mod(n+1, l) = 0.
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import numpy as np
+
+import workloads
+
+from . import lib, models
+
+
+class IDMRG:
+    def __init__(self, cfg, device=0, prec=None, dense=False, predict=True, chunk=8, log=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.ell = cfg["ell"]
+        self.half = self.ell // 2
+        self.dev = torch.device("cuda", device)
+        self.prec = prec or cfg.get("prec", "f64")
+        self.predict = predict
+        self.chunk = chunk
+        self.log = log
+        self.W = models.heisenberg_mpo(cfg["bonds"], self.ell, dense=dense)
+        self.qp = self.W[0].qp
+        self.ctx = lib.Context(device)
+        self.n = 0
+        self.energies = {}
+        self.steps = []
+        self.e_g = {}
+        # Step 1: L^(0)_{2i-1} = last row of W_{2i-1}, R^(0)_{2i} = first column of W_{2i}
+        self.L, self.R = {}, {}
+        for i in range(1, self.half + 1):
+            leg, x = models.initial_left(self.Wsite(2 * i - 1))
+            self.L[i] = (leg, self._dev(x))
+            leg, x = models.initial_right(self.Wsite(2 * i))
+            self.R[i] = (leg, self._dev(x))
+        self.prev, self.lam2 = {}, {}
+
+    def _dev(self, x):
+        return self.torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(self.dev)
+
+    def Wsite(self, k):
+        return self.W[(k - 1) % self.ell]
+
+    def problems(self, n):
+        """Superblock Hamiltonians of iteration n (Step 2'): pointers only."""
+        out = []
+        for i in range(1, self.half + 1):
+            ip1 = i % self.half + 1
+            (A, Lt), (B, Rt) = self.L[i], self.R[ip1]
+            out.append(dict(left=A, right=B, w1=self.Wsite(2 * i + n - 1), w2=self.Wsite(2 * i + n), L=Lt, R=Rt,
+                            i=i, ip1=ip1))
+        return out
+
+    def start_vectors(self, n, H):
+        """Step 3': random for n <= 2 (seeded, drawn on the host), Eq. (10) otherwise."""
+        if n <= 2 or not self.predict:
+            return [self._dev(workloads.start_vector(lib.psi_size(h["left"], h["right"], self.qp), n, h["i"]))
+                    for h in H]
+        items = []
+        for h in H:
+            i, ip1 = h["i"], h["ip1"]
+            pi, pn = self.prev[i], self.prev[ip1]
+            items.append(dict(leg_a=pi["C"], leg_beta=self.lam2[ip1][0], leg_b=pn["C"], lam_i=pi["lam"],
+                              V_i=pi["V"], lam_prev=self.lam2[ip1][1], U_ip1=pn["U"], lam_ip1=pn["lam"]))
+        guesses = lib.predict_wavefunction(self.ctx, items, self.qp, self.cfg["lam_floor"])
+        return guesses
+
+    def step(self):
+        """One unit-cell step: iteration n for all l/2 superblocks."""
+        torch = self.torch
+        n = self.n + 1
+        cfg = self.cfg
+        t0 = time.perf_counter()
+        H = self.problems(n)
+        psis = self.start_vectors(n, H)
+        if n > 2 and self.predict:
+            # a start vector that is exactly zero cannot seed Lanczos; fall back to the random rule
+            norms = [float(torch.linalg.vector_norm(p)) for p in psis]
+            for j, nr in enumerate(norms):
+                if nr == 0.0:
+                    psis[j] = self._dev(workloads.start_vector(psis[j].numel(), n, H[j]["i"]))
+        t1 = time.perf_counter()
+        es, infos = lib.lanczos_solve_batch(self.ctx, H, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"],
+                                            self.prec, self.chunk)
+        t2 = time.perf_counter()
+        trs = lib.truncate_twosite(self.ctx, [dict(left=h["left"], right=h["right"], psi=p) for h, p in zip(H, psis)],
+                                   self.qp, cfg["m"], cfg["lam_floor"], cfg["deg_rel"])
+        t3 = time.perf_counter()
+        newL = lib.update_env(self.ctx, lib.LEFT, [dict(old_leg=h["left"], new_leg=tr["C"], w=h["w1"], env_old=h["L"],
+                                                        iso=tr["U"]) for h, tr in zip(H, trs)])
+        newR = lib.update_env(self.ctx, lib.RIGHT, [dict(old_leg=h["right"], new_leg=tr["C"], w=h["w2"],
+                                                         env_old=h["R"], iso=tr["V"]) for h, tr in zip(H, trs)])
+        torch.cuda.synchronize(self.dev)
+        t4 = time.perf_counter()
+        for h, e, inf, tr, Ln, Rn in zip(H, es, infos, trs, newL, newR):
+            i = h["i"]
+            self.energies[(n, i)] = e
+            rec = dict(n=n, i=i, energy=e, e_site=e / (2 * n + 2), iters=inf["iters"], residual=inf["residual"],
+                       fidelity=1.0 - inf["overlap0"], eps=tr["eps"], eps_prime=tr["eps_prime"],
+                       m_kept=tr["m_kept"], cut_gap=tr["cut_gap"], fp64_matvecs=inf["fp64_matvecs"],
+                       N=int(psis[h["i"] - 1].numel()))
+            self.steps.append(rec)
+            if self.log:
+                self.log(rec)
+        # hand-off: new environments and decompositions replace the old ones (pointer swap)
+        self.lam2 = {i: (self.prev[i]["C"], self.prev[i]["lam"]) for i in self.prev}
+        self.prev = {h["i"]: tr for h, tr in zip(H, trs)}
+        self.L = {h["i"]: (tr["C"], Ln) for h, tr, Ln in zip(H, trs, newL)}
+        self.R = {h["i"]: (tr["C"], Rn) for h, tr, Rn in zip(H, trs, newR)}
+        self.n = n
+        if (n + 1) % self.ell == 0:       # Step 5'
+            e_old = self.energies[(n - self.ell, 1)] if n - self.ell >= 1 else 0.0
+            self.e_g[n] = (self.energies[(n, 1)] - e_old) / (2 * self.ell)
+        return dict(n=n, seconds=t4 - t0, t_predict=t1 - t0, t_lanczos=t2 - t1, t_truncate=t3 - t2,
+                    t_env=t4 - t3, iters=[inf["iters"] for inf in infos])
+
+    def run(self, n_max):
+        out = []
+        while self.n < n_max:
+            out.append(self.step())
+        return out
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser(description="parallel iDMRG on one GPU")
+    ap.add_argument("--workload", default="chain")
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--prec", default=None)
+    ap.add_argument("--dense", action="store_true")
+    a = ap.parse_args()
+    over = {}
+    if a.m:
+        over["m"] = a.m
+    cfg = workloads.workload(a.workload, **over)
+    d = IDMRG(cfg, prec=a.prec, dense=a.dense, log=lambda r: print(json.dumps(r), flush=True))
+    d.run(a.n or cfg["n_max"])
+    print(json.dumps(dict(e_g=d.e_g)))
+
+
+if __name__ == "__main__":
+    main()

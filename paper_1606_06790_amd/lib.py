@@ -1,0 +1,356 @@
+"""Thin ctypes binding of libidmrg.so (the C-ABI in include/idmrg.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  Device memory comes from PyTorch tensors (float64, on the GPU);
+the calls enqueue on the current PyTorch stream of the tensors' device.
+
+The library must be built (``python -m paper_1606_06790_amd.build`` or
+``__graft_entry__.build()``); importing this module on a machine without it
+raises an error instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libidmrg.so")
+
+OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
+PREC = {"f64": 0, "f32": 1, "bf16x3": 2}
+LEFT, RIGHT = 0, 1
+
+EXPORTS = ["idmrg_create", "idmrg_destroy", "idmrg_set_stream", "idmrg_last_error", "idmrg_psi_size",
+           "idmrg_envL_size", "idmrg_envR_size", "idmrg_U_size", "idmrg_V_size", "idmrg_heff_work",
+           "heff_apply", "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction"]
+
+
+class IdmrgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"idmrg error {code}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------- C structs
+
+class Leg_t(C.Structure):
+    _fields_ = [("nsec", C.c_int32), ("q", C.POINTER(C.c_int32)), ("dim", C.POINTER(C.c_int32))]
+
+
+class Mpo_t(C.Structure):
+    _fields_ = [("dl", C.c_int32), ("dr", C.c_int32), ("d", C.c_int32), ("w", C.POINTER(C.c_double)),
+                ("ql", C.POINTER(C.c_int32)), ("qr", C.POINTER(C.c_int32)), ("qp", C.POINTER(C.c_int32))]
+
+
+class Heff_t(C.Structure):
+    _fields_ = [("left", Leg_t), ("right", Leg_t), ("w1", C.POINTER(Mpo_t)), ("w2", C.POINTER(Mpo_t)),
+                ("L", C.c_void_p), ("R", C.c_void_p)]
+
+
+class LanczosOpts_t(C.Structure):
+    _fields_ = [("tol_E", C.c_double), ("tol_res", C.c_double), ("k_max", C.c_int32), ("prec", C.c_int32),
+                ("chunk", C.c_int32), ("refine", C.c_int32)]
+
+
+class LanczosInfo_t(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("fp64_matvecs", C.c_int32), ("flags", C.c_int32),
+                ("residual", C.c_double), ("overlap0", C.c_double)]
+
+
+class Trunc_t(C.Structure):
+    _fields_ = [("left", Leg_t), ("right", Leg_t), ("psi", C.c_void_p), ("cap_sec", C.c_int32),
+                ("q_out", C.POINTER(C.c_int32)), ("dim_out", C.POINTER(C.c_int32)), ("U", C.c_void_p),
+                ("V", C.c_void_p), ("lambda_", C.c_void_p), ("cap_U", C.c_int64), ("cap_V", C.c_int64),
+                ("cap_lam", C.c_int64), ("nsec_out", C.c_int32), ("m_kept", C.c_int32), ("eps", C.c_double),
+                ("eps_prime", C.c_double), ("cut_gap", C.c_double)]
+
+
+class EnvUpdate_t(C.Structure):
+    _fields_ = [("old_leg", Leg_t), ("new_leg", Leg_t), ("w", C.POINTER(Mpo_t)), ("env_old", C.c_void_p),
+                ("iso", C.c_void_p), ("env_new", C.c_void_p)]
+
+
+class Predict_t(C.Structure):
+    _fields_ = [("leg_a", Leg_t), ("leg_beta", Leg_t), ("leg_b", Leg_t), ("lam_i", C.c_void_p), ("V_i", C.c_void_p),
+                ("lam_prev", C.c_void_p), ("U_ip1", C.c_void_p), ("lam_ip1", C.c_void_p), ("psi", C.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load libidmrg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    lib.idmrg_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]
+    lib.idmrg_destroy.argtypes = [C.c_void_p]
+    lib.idmrg_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+    lib.idmrg_last_error.argtypes = [C.c_void_p]
+    lib.idmrg_last_error.restype = C.c_char_p
+    lib.idmrg_psi_size.argtypes = [Leg_t, Leg_t, C.c_int32, C.POINTER(C.c_int32)]
+    lib.idmrg_psi_size.restype = C.c_int64
+    lib.idmrg_envL_size.argtypes = [Leg_t, C.c_int32, C.POINTER(C.c_int32)]
+    lib.idmrg_envL_size.restype = C.c_int64
+    lib.idmrg_envR_size.argtypes = [Leg_t, C.c_int32, C.POINTER(C.c_int32)]
+    lib.idmrg_envR_size.restype = C.c_int64
+    lib.idmrg_U_size.argtypes = [Leg_t, C.c_int32, C.POINTER(C.c_int32), Leg_t]
+    lib.idmrg_U_size.restype = C.c_int64
+    lib.idmrg_V_size.argtypes = [Leg_t, C.c_int32, C.POINTER(C.c_int32), Leg_t]
+    lib.idmrg_V_size.restype = C.c_int64
+    lib.idmrg_heff_work.argtypes = [C.POINTER(Heff_t), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.heff_apply.argtypes = [C.c_void_p, C.c_int, C.POINTER(Heff_t), C.POINTER(C.c_void_p),
+                               C.POINTER(C.c_void_p), C.c_int]
+    lib.lanczos_solve_batch.argtypes = [C.c_void_p, C.c_int, C.POINTER(Heff_t), C.POINTER(C.c_void_p),
+                                        C.POINTER(LanczosOpts_t), C.POINTER(C.c_double),
+                                        C.POINTER(LanczosInfo_t)]
+    lib.truncate_twosite.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                     C.c_double, C.c_double, C.POINTER(Trunc_t)]
+    lib.update_env.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(EnvUpdate_t)]
+    lib.predict_wavefunction.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_int32), C.c_double,
+                                         C.POINTER(Predict_t)]
+    for name in ["idmrg_create", "idmrg_destroy", "idmrg_set_stream", "idmrg_heff_work", "heff_apply",
+                 "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction"]:
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------- marshalling helpers
+
+class _Keep:
+    """Holds ctypes arrays alive for the duration of one call."""
+
+    def __init__(self):
+        self.items = []
+
+    def ints(self, seq):
+        a = (C.c_int32 * max(1, len(seq)))(*[int(x) for x in seq])
+        self.items.append(a)
+        return a
+
+    def doubles(self, arr):
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        self.items.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+
+    def leg(self, leg):
+        q = [int(x) for x, _ in leg]
+        d = [int(x) for _, x in leg]
+        return Leg_t(len(q), self.ints(q), self.ints(d))
+
+    def mpo(self, W):
+        m = Mpo_t(W.dl, W.dr, W.d, self.doubles(W.w), self.ints(W.ql), self.ints(W.qr), self.ints(W.qp))
+        self.items.append(m)
+        return C.pointer(m)
+
+
+class Mpo:
+    """One MPO tensor W[w, w', s, s'] with channel and local charges."""
+
+    def __init__(self, w, ql, qr, qp):
+        self.w = np.ascontiguousarray(w, dtype=np.float64)
+        self.dl, self.dr, self.d, _ = self.w.shape
+        self.ql, self.qr, self.qp = [int(x) for x in ql], [int(x) for x in qr], [int(x) for x in qp]
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != _torch().float64 or not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous float64 CUDA tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(ctx, rc):
+    if rc < 0:
+        raise IdmrgError(rc, load().idmrg_last_error(ctx.handle).decode())
+    return rc
+
+
+class Context:
+    """Library context bound to a device and PyTorch's current stream on it."""
+
+    def __init__(self, device=0):
+        torch = _torch()
+        self.device = device
+        self.lib = load()
+        h = C.c_void_p()
+        stream = torch.cuda.current_stream(device).cuda_stream
+        rc = self.lib.idmrg_create(C.byref(h), device, C.c_void_p(stream))
+        if rc != 0:
+            raise IdmrgError(rc, "idmrg_create failed")
+        self.handle = h
+
+    def sync_stream(self):
+        torch = _torch()
+        self.lib.idmrg_set_stream(self.handle, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def close(self):
+        if self.handle:
+            self.lib.idmrg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- sizes
+
+def psi_size(A, B, qp):
+    k = _Keep()
+    return int(load().idmrg_psi_size(k.leg(A), k.leg(B), len(qp), k.ints(qp)))
+
+
+def envL_size(A, ql):
+    k = _Keep()
+    return int(load().idmrg_envL_size(k.leg(A), len(ql), k.ints(ql)))
+
+
+def envR_size(B, qr):
+    k = _Keep()
+    return int(load().idmrg_envR_size(k.leg(B), len(qr), k.ints(qr)))
+
+
+def U_size(A, qp, Cleg):
+    k = _Keep()
+    return int(load().idmrg_U_size(k.leg(A), len(qp), k.ints(qp), k.leg(Cleg)))
+
+
+def V_size(B, qp, Cleg):
+    k = _Keep()
+    return int(load().idmrg_V_size(k.leg(B), len(qp), k.ints(qp), k.leg(Cleg)))
+
+
+def _heff_structs(k, problems):
+    arr = (Heff_t * len(problems))()
+    for j, h in enumerate(problems):
+        arr[j] = Heff_t(k.leg(h["left"]), k.leg(h["right"]), k.mpo(h["w1"]), k.mpo(h["w2"]), _ptr(h["L"]),
+                        _ptr(h["R"]))
+    k.items.append(arr)
+    return arr
+
+
+def heff_work(h):
+    """(flops, bytes) of one heff_apply of problem h."""
+    k = _Keep()
+    arr = _heff_structs(k, [h])
+    f, b = C.c_double(), C.c_double()
+    rc = load().idmrg_heff_work(arr, C.byref(f), C.byref(b))
+    if rc != 0:
+        raise IdmrgError(rc, "idmrg_heff_work failed")
+    return f.value, b.value
+
+
+# ---------------------------------------------------------------- the five calls
+
+def heff_apply(ctx, problems, xs, ys, prec="f64"):
+    """ys[p] = H_p xs[p] (Sec. 2, Step 3)."""
+    k = _Keep()
+    arr = _heff_structs(k, problems)
+    xp = (C.c_void_p * len(xs))(*[_ptr(x) for x in xs])
+    yp = (C.c_void_p * len(ys))(*[_ptr(y) for y in ys])
+    _check(ctx, ctx.lib.heff_apply(ctx.handle, len(problems), arr, xp, yp, PREC[prec]))
+
+
+def lanczos_solve_batch(ctx, problems, psis, tol_E=1e-12, tol_res=1e-8, k_max=300, prec="f64", chunk=8,
+                        refine=True):
+    """Lowest eigenpairs; psis are overwritten with the ground states.  Returns (energies, infos)."""
+    k = _Keep()
+    arr = _heff_structs(k, problems)
+    P = len(problems)
+    pp = (C.c_void_p * P)(*[_ptr(x) for x in psis])
+    opts = LanczosOpts_t(tol_E, tol_res, k_max, PREC[prec], chunk, 1 if refine else 0)
+    e = (C.c_double * P)()
+    inf = (LanczosInfo_t * P)()
+    rc = _check(ctx, ctx.lib.lanczos_solve_batch(ctx.handle, P, arr, pp, C.byref(opts), e, inf))
+    infos = [dict(iters=x.iters, converged=x.converged, fp64_matvecs=x.fp64_matvecs, flags=x.flags,
+                  residual=x.residual, overlap0=x.overlap0, warn=rc) for x in inf]
+    return [float(x) for x in e], infos
+
+
+def truncate_twosite(ctx, items, qp, m_max, lam_floor=1e-14, deg_rel=1e-5):
+    """items: list of dict(left, right, psi).  Returns list of dict(C, U, V, lam, eps, eps_prime,
+    m_kept, cut_gap) with U, V, lam as new float64 device tensors."""
+    torch = _torch()
+    k = _Keep()
+    P = len(items)
+    arr = (Trunc_t * P)()
+    bufs = []
+    d = len(qp)
+    for j, it in enumerate(items):
+        A, B = it["left"], it["right"]
+        rows = sum(x for _, x in A) * d
+        cols = sum(x for _, x in B) * d
+        cap_sec = len(A) * d + len(B) * d + 2
+        kmax = min(m_max, rows, cols)
+        dev = it["psi"].device
+        U = torch.empty(rows * kmax + 1, dtype=torch.float64, device=dev)
+        V = torch.empty(cols * kmax + 1, dtype=torch.float64, device=dev)
+        lam = torch.empty(kmax + 1, dtype=torch.float64, device=dev)
+        qo = (C.c_int32 * cap_sec)()
+        do = (C.c_int32 * cap_sec)()
+        bufs.append((U, V, lam, qo, do))
+        arr[j] = Trunc_t(k.leg(A), k.leg(B), _ptr(it["psi"]), cap_sec, qo, do, C.c_void_p(U.data_ptr()),
+                         C.c_void_p(V.data_ptr()), C.c_void_p(lam.data_ptr()), U.numel(), V.numel(),
+                         lam.numel(), 0, 0, 0.0, 0.0, 0.0)
+    _check(ctx, ctx.lib.truncate_twosite(ctx.handle, P, d, k.ints(qp), m_max, lam_floor, deg_rel, arr))
+    out = []
+    for j, it in enumerate(items):
+        U, V, lam, qo, do = bufs[j]
+        t = arr[j]
+        Cleg = [(int(qo[s]), int(do[s])) for s in range(t.nsec_out)]
+        nU, nV = U_size(it["left"], qp, Cleg), V_size(it["right"], qp, Cleg)
+        m = sum(x for _, x in Cleg)
+        out.append(dict(C=Cleg, U=U[:nU].clone(), V=V[:nV].clone(), lam=lam[:m].clone(), eps=t.eps,
+                        eps_prime=t.eps_prime, m_kept=t.m_kept, cut_gap=(None if t.cut_gap < 0 else t.cut_gap)))
+    return out
+
+
+def update_env(ctx, side, items):
+    """items: list of dict(old_leg, new_leg, w (Mpo), env_old, iso).  Returns new env tensors."""
+    torch = _torch()
+    k = _Keep()
+    P = len(items)
+    arr = (EnvUpdate_t * P)()
+    outs = []
+    for j, it in enumerate(items):
+        W = it["w"]
+        n = envL_size(it["new_leg"], W.qr) if side == LEFT else envR_size(it["new_leg"], W.ql)
+        o = torch.empty(max(n, 1), dtype=torch.float64, device=it["env_old"].device)
+        outs.append(o[:n])
+        arr[j] = EnvUpdate_t(k.leg(it["old_leg"]), k.leg(it["new_leg"]), k.mpo(W), _ptr(it["env_old"]),
+                             _ptr(it["iso"]), C.c_void_p(o.data_ptr()))
+    _check(ctx, ctx.lib.update_env(ctx.handle, P, side, arr))
+    return outs
+
+
+def predict_wavefunction(ctx, items, qp, lam_floor=1e-14):
+    """items: list of dict(leg_a, leg_beta, leg_b, lam_i, V_i, lam_prev, U_ip1, lam_ip1).  Returns psi tensors."""
+    torch = _torch()
+    k = _Keep()
+    P = len(items)
+    arr = (Predict_t * P)()
+    outs = []
+    for j, it in enumerate(items):
+        n = psi_size(it["leg_a"], it["leg_b"], qp)
+        o = torch.empty(n, dtype=torch.float64, device=it["V_i"].device)
+        outs.append(o)
+        arr[j] = Predict_t(k.leg(it["leg_a"]), k.leg(it["leg_beta"]), k.leg(it["leg_b"]), _ptr(it["lam_i"]),
+                           _ptr(it["V_i"]), _ptr(it["lam_prev"]), _ptr(it["U_ip1"]), _ptr(it["lam_ip1"]),
+                           C.c_void_p(o.data_ptr()))
+    _check(ctx, ctx.lib.predict_wavefunction(ctx.handle, P, len(qp), k.ints(qp), lam_floor, arr))
+    return outs

@@ -1,0 +1,249 @@
+"""GPU parity of the five C-ABI calls against the FP64 oracle (needs an MI355X).
+
+Every call is fed the same seeded inputs as the oracle.  FP64 results must
+agree elementwise to 1e-13 relative to the largest output magnitude (the
+rounding of FP64 sums of at most a few thousand terms), energies to 1e-12,
+trajectories (per-site energies) to 1e-10.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense as odense
+from oracle import idmrg as oidmrg
+from oracle import layout, u1
+
+from gpu_common import QP, H, T, mpo_pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+lib = pytest.importorskip("paper_1606_06790_amd.lib")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lib.Context(0)
+
+
+LEGS = {
+    "small": ([(-1, 3), (1, 2)], [(-1, 2), (1, 3)]),
+    "ragged": ([(-3, 20), (-1, 70), (1, 65), (3, 15)], [(-3, 12), (-1, 67), (1, 80), (3, 30)]),
+    "wide": ([(-5, 8), (-3, 33), (-1, 66), (1, 70), (3, 40), (5, 9)],
+             [(-5, 5), (-3, 41), (-1, 72), (1, 61), (3, 30), (5, 11)]),
+}
+
+
+def _heff_case(name, legs, key):
+    (W1, W2, dl, dm, dr), (M1, M2) = mpo_pair(name, 4)
+    A, B = LEGS[legs]
+    nL, nR, nx = layout.envL_size(A, dl), layout.envR_size(B, dr), layout.psi_size(A, B, QP)
+    Lf, Rf, x = workloads.gaussian(nL, key, 1), workloads.gaussian(nR, key, 2), workloads.gaussian(nx, key, 3)
+    y = layout.psi_to_flat(u1.heff_apply(layout.flat_to_envL(Lf, A, dl), W1, W2, layout.flat_to_envR(Rf, B, dr),
+                                         layout.flat_to_psi(x, A, B, QP), A, B, QP, dl, dr), A, B, QP)
+    prob = dict(left=A, right=B, w1=M1, w2=M2, L=T(Lf), R=T(Rf))
+    return prob, x, y
+
+
+def test_heff_apply_batched_u1(ctx):
+    cases = [_heff_case("chain", "small", 11), _heff_case("chain", "ragged", 12), _heff_case("yc8", "wide", 13),
+             _heff_case("yc4", "ragged", 14)]
+    probs = [c[0] for c in cases]
+    xs = [T(c[1]) for c in cases]
+    ys = [T(np.full(len(c[2]), np.nan)) for c in cases]
+    lib.heff_apply(ctx, probs, xs, ys, "f64")
+    for (p, x, y), yg in zip(cases, ys):
+        assert rel_err(H(yg), y) <= 1e-13
+
+
+@pytest.mark.parametrize("m", [40, 96, 256])
+def test_heff_apply_dense(ctx, m):
+    """No symmetry blocks (all charges 0): one block per (s1, s2)."""
+    from paper_1606_06790_amd.lib import Mpo
+    (W1, W2, dl, dm, dr), _ = mpo_pair("chain", 1)
+    D = W1.shape[0]
+    z = lambda k: [0] * k
+    M1, M2 = Mpo(W1, z(D), z(D), [0, 0]), Mpo(W2, z(D), z(D), [0, 0])
+    Lf = workloads.gaussian((D - 1) * m * m, 20, m, 1)
+    Rf = workloads.gaussian(m * (D - 1) * m, 20, m, 2)
+    x = workloads.gaussian(4 * m * m, 20, m, 3)
+    L = np.zeros((m, D, m))
+    L[:, :D - 1, :] = Lf.reshape(D - 1, m, m).transpose(1, 0, 2)
+    L[:, D - 1, :] = np.eye(m)
+    R = np.zeros((m, D, m))
+    R[:, 1:, :] = Rf.reshape(m, D - 1, m)
+    R[:, 0, :] = np.eye(m)
+    y = odense.psi_to_flat(odense.heff_apply(L, W1, W2, R, odense.psi_from_flat(x, m, 2, m)))
+    yg = T(np.zeros(4 * m * m))
+    lib.heff_apply(ctx, [dict(left=[(0, m)], right=[(0, m)], w1=M1, w2=M2, L=T(Lf), R=T(Rf))], [T(x)], [yg], "f64")
+    assert rel_err(H(yg), y) <= 1e-13
+
+
+def _iso_size(rows_fn, leg, Cl):
+    return sum(sum(r[2] for r in rows_fn(leg, QP, q)) * k for q, k in Cl)
+
+
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_update_env(ctx, side):
+    (W1, W2, dl, dm, dr), (M1, M2) = mpo_pair("yc8", 3)
+    A = LEGS["wide"][0]
+    Cl = [(-4, 17), (-2, 60), (0, 90), (2, 55), (4, 21)]
+    if side == "left":
+        Lf = workloads.gaussian(layout.envL_size(A, dl), 30, 1)
+        Uf = workloads.gaussian(_iso_size(layout.U_rows, A, Cl), 30, 2)
+        L = layout.flat_to_envL(Lf, A, dl)
+        U = layout.flat_to_U(Uf, A, QP, Cl)
+        ref = u1.update_env_left(L, W1, U, A, QP, Cl, dl, dm)
+        out = lib.update_env(ctx, lib.LEFT, [dict(old_leg=A, new_leg=Cl, w=M1, env_old=T(Lf), iso=T(Uf))])[0]
+        ref_flat = layout.envL_to_flat(ref, Cl, dm)
+    else:
+        B = LEGS["wide"][1]
+        Rf = workloads.gaussian(layout.envR_size(B, dr), 31, 1)
+        Vf = workloads.gaussian(_iso_size(layout.V_rows, B, Cl), 31, 2)
+        R = layout.flat_to_envR(Rf, B, dr)
+        V = layout.flat_to_V(Vf, B, QP, Cl)
+        ref = u1.update_env_right(R, W2, V, B, QP, Cl, dm, dr)
+        out = lib.update_env(ctx, lib.RIGHT, [dict(old_leg=B, new_leg=Cl, w=M2, env_old=T(Rf), iso=T(Vf))])[0]
+        ref_flat = layout.envR_to_flat(ref, Cl, dm)
+    assert rel_err(H(out), ref_flat) <= 1e-13
+
+
+def test_predict_wavefunction(ctx):
+    Aa = [(-2, 30), (0, 70), (2, 33)]
+    Bt = [(-3, 20), (-1, 66), (1, 64), (3, 18)]
+    Bb = [(-2, 25), (0, 81), (2, 28)]
+    Vf = workloads.gaussian(_iso_size(layout.V_rows, Bt, Aa), 40, 1)
+    Uf = workloads.gaussian(_iso_size(layout.U_rows, Bt, Bb), 40, 2)
+    la = np.abs(workloads.gaussian(sum(k for _, k in Aa), 40, 3))
+    lt = np.abs(workloads.gaussian(sum(k for _, k in Bt), 40, 4))
+    lt[::7] = 0.0                       # zero Schmidt values take the 0 branch of Eq. (10)
+    lb = np.abs(workloads.gaussian(sum(k for _, k in Bb), 40, 5))
+    ref = u1.predict_wavefunction(layout.flat_to_lam(la, Aa), layout.flat_to_V(Vf, Bt, QP, Aa),
+                                  layout.flat_to_lam(lt, Bt), layout.flat_to_U(Uf, Bt, QP, Bb),
+                                  layout.flat_to_lam(lb, Bb), Aa, Bb, QP, 1e-14)
+    out = lib.predict_wavefunction(ctx, [dict(leg_a=Aa, leg_beta=Bt, leg_b=Bb, lam_i=T(la), V_i=T(Vf), lam_prev=T(lt),
+                                              U_ip1=T(Uf), lam_ip1=T(lb))], QP, 1e-14)[0]
+    assert rel_err(H(out), layout.psi_to_flat(ref, Aa, Bb, QP)) <= 1e-13
+
+
+def _oracle_states(name, m, n_max, **over):
+    cfg = workloads.workload(name, m=m, **over)
+    return cfg, oidmrg.run(cfg, mode="u1", n_max=n_max, keep_states=True)
+
+
+def test_truncate_twosite(ctx):
+    """Singular values, kept legs, eps and eps' equal the oracle's; the kept
+    subspaces agree (projectors) and the isometries are orthonormal."""
+    cfg, r = _oracle_states("random_chain", 24, 7)
+    sts = [st for st in r["states"] if st["n"] in (3, 5, 6, 7)][:8]
+    items = [dict(left=st["A"], right=st["B"], psi=T(st["psi"])) for st in sts]
+    out = lib.truncate_twosite(ctx, items, QP, cfg["m"], cfg["lam_floor"], cfg["deg_rel"])
+    for st, o in zip(sts, out):
+        tr = st["tr"]
+        assert o["C"] == tr["C"]
+        assert o["m_kept"] == tr["m_kept"]
+        assert abs(o["eps"] - tr["eps"]) <= 1e-14 + 1e-10 * tr["eps"]
+        assert abs(o["eps_prime"] - tr["eps_prime"]) <= 1e-14 + 1e-10 * tr["eps_prime"]
+        lam = layout.flat_to_lam(H(o["lam"]), o["C"])
+        for q, _ in o["C"]:
+            assert np.abs(lam[q] - tr["lam"][q]).max() <= 1e-13
+        U = layout.flat_to_U(H(o["U"]), st["A"], QP, o["C"])
+        V = layout.flat_to_V(H(o["V"]), st["B"], QP, o["C"])
+        for q, k in o["C"]:
+            rows = layout.U_rows(st["A"], QP, q)
+            Ug = np.concatenate([U[(a, s, q)] for (a, s, _) in rows])
+            Uo = np.concatenate([tr["U"][(a, s, q)] for (a, s, _) in rows])
+            assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-13
+            if tr["cut_gap"] is None or tr["cut_gap"] > 1e-6:
+                assert np.abs(Ug @ Ug.T - Uo @ Uo.T).max() <= 1e-10
+            vrows = layout.V_rows(st["B"], QP, q)
+            Vg = np.concatenate([V[(s, b, q)] for (s, b, _) in vrows])
+            assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-13
+
+
+def _flat_problem(st):
+    from paper_1606_06790_amd.lib import Mpo
+    A, B = st["A"], st["B"]
+    return dict(left=A, right=B, w1=Mpo(st["W1"], st["dl"], st["dm"], QP), w2=Mpo(st["W2"], st["dm"], st["dr"], QP),
+                L=T(layout.envL_to_flat(st["L"], A, st["dl"])), R=T(layout.envR_to_flat(st["R"], B, st["dr"])))
+
+
+def test_lanczos_solve_batch(ctx):
+    """Same H, same start vector: energy within 1e-12, |<psi_gpu|psi_orc>| >= 1 - 1e-12."""
+    cfg, r = _oracle_states("random_chain", 32, 7, tol_res=1e-10)
+    sts = [st for st in r["states"] if st["n"] in (2, 6, 7)]
+    probs = [_flat_problem(st) for st in sts]
+    psis = [T(st["v0"]) for st in sts]
+    es, infos = lib.lanczos_solve_batch(ctx, probs, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"], "f64")
+    steps = {(s["n"], s["i"]): s for s in r["steps"]}
+    for st, e, inf, p in zip(sts, es, infos, psis):
+        ref = steps[(st["n"], st["i"])]
+        assert abs(e - ref["energy"]) <= 1e-12
+        assert abs(abs(float(H(p) @ st["psi"])) - 1.0) <= 1e-12
+        assert inf["converged"] == 1
+        assert inf["residual"] <= 1e-8
+        assert abs(inf["iters"] - ref["iters"]) <= 2
+        assert abs((1 - inf["overlap0"]) - ref["fidelity"]) <= 1e-10
+
+
+def _run_gpu(cfg, n_max, **kw):
+    from paper_1606_06790_amd.driver import IDMRG
+    d = IDMRG(cfg, **kw)
+    d.run(n_max)
+    return d
+
+
+def test_trajectory_chain():
+    """Uniform chain, l = 4, m = 32, 20 iterations: per-site energies and e_g of the
+    GPU path equal the oracle's within 1e-10; untruncated steps equal ED."""
+    cfg = workloads.workload("chain")
+    g = _run_gpu(cfg, 20)
+    o = oidmrg.run(cfg, mode="u1", n_max=20)
+    for a, b in zip(g.steps, o["steps"]):
+        assert (a["n"], a["i"]) == (b["n"], b["i"])
+        assert abs(a["e_site"] - b["e_site"]) <= 1e-10, (a, b)
+        assert a["m_kept"] == b["m_kept"]
+    for n, e in o["e_g"].items():
+        assert abs(g.e_g[n] - e) <= 1e-10
+    assert abs(g.e_g[19] - workloads.bethe_ansatz_energy()) <= 5e-4
+
+
+def test_trajectory_dimer():
+    """Dimerised limit: exact energies -3(n+1)/4, exact prediction (fidelity error 0,
+    one Lanczos step) on the GPU path too."""
+    cfg = workloads.workload("dimer", m=8, n_max=8)
+    g = _run_gpu(cfg, 8)
+    for s in g.steps:
+        assert abs(s["energy"] + 0.75 * (s["n"] + 1)) <= 1e-12
+        if s["n"] >= 3:
+            assert s["fidelity"] <= 1e-12 and s["iters"] == 1
+
+
+def test_trajectory_random_chain():
+    """Random-bond chain, l = 16 (8 superblocks per batched call), m = 48, 12 iterations."""
+    cfg = workloads.workload("random_chain", m=48)
+    g = _run_gpu(cfg, 12)
+    o = oidmrg.run(cfg, mode="u1", n_max=12)
+    for a, b in zip(g.steps, o["steps"]):
+        assert abs(a["e_site"] - b["e_site"]) <= 1e-10, (a, b)
+        assert a["m_kept"] == b["m_kept"]
+
+
+def test_errors_are_reported(ctx):
+    (W1, W2, dl, dm, dr), (M1, M2) = mpo_pair("chain", 1)
+    A, B = LEGS["small"]
+    bad = dict(left=[(1, 2), (-1, 3)], right=B, w1=M1, w2=M2, L=T(np.zeros(100)), R=T(np.zeros(100)))
+    with pytest.raises(lib.IdmrgError) as e:
+        lib.heff_apply(ctx, [bad], [T(np.zeros(10))], [T(np.zeros(10))])
+    assert e.value.code == lib.EINVAL
+    # start vector of zero norm
+    good = _heff_case("chain", "small", 50)[0]
+    n = layout.psi_size(A, B, QP)
+    with pytest.raises(lib.IdmrgError) as e:
+        lib.lanczos_solve_batch(ctx, [good], [T(np.zeros(n))])
+    assert e.value.code == lib.EINVAL
+    # k_max = 2 cannot converge: a warning, with the best Ritz pair returned
+    es, infos = lib.lanczos_solve_batch(ctx, [good], [T(workloads.gaussian(n, 50, 9))], k_max=2)
+    assert infos[0]["warn"] == lib.WARN_NOCONV and infos[0]["iters"] == 2 and np.isfinite(es[0])
