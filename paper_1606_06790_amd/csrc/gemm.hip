@@ -7,7 +7,8 @@
 //
 // FP64 uses v_mfma_f64_16x16x4_f64, FP32 uses v_mfma_f32_16x16x4_f32 (both:
 // A operand lane l holds A[l%16][l/16], B operand B[l/16][l%16], accumulator
-// register r of lane l holds C[4*(l/16)+r][l%16]).  The split-bf16 policy
+// register r of lane l holds C[4*(l/16)+r][l%16] for FP32 and the bf16 shape,
+// but C[l/16+4r][l%16] for FP64, as measured on gfx950).  The split-bf16 policy
 // (bf16x3) uses v_mfma_f32_16x16x32_bf16 with operands a = hi + lo and three
 // products hi*hi + hi*lo + lo*hi, FP32 accumulation.
 #include "internal.h"
@@ -131,7 +132,8 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gi = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        // FP64 16x16x4 keeps C[l/16 + 4r][l%16] in register r of lane l; FP32 keeps C[4(l/16) + r][l%16]
+        const int gi = m0 + wm + i * 16 + (std::is_same<T, double>::value ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
         const int gn = n0 + wn + j * 16 + (lane & 15);
         if (gi < M && gn < N) {
           T* p = C + (int64_t)gi * ldc + gn;

@@ -1,0 +1,128 @@
+"""Host-side checks of the library (CPU only, no GPU needed).
+
+* libidmrg.so loads and exports every symbol that include/idmrg.h declares;
+* the flat-layout size functions agree with the oracle's reading of the
+  storage order;
+* the work plans of heff_apply and update_env, executed by a plain host
+  interpreter (tests/hostplan/plan_exec.cpp, built here with g++), reproduce
+  the oracle's contractions.  This checks every block offset and every MPO
+  mixing coefficient of the plans without a GPU.
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import layout, mpo as omp, u1
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+QP = [1, -1]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1606_06790_amd import lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libidmrg.so not built")
+    return L
+
+
+def test_exports_match_header(lib):
+    hdr = open(os.path.join(ROOT, "include", "idmrg.h")).read()
+    names = set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(\w+)\(", hdr, re.M))
+    assert {"heff_apply", "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction"} <= names
+    L = C.CDLL(lib.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert names == set(lib.EXPORTS)
+
+
+def test_layout_sizes(lib):
+    A = [(-5, 3), (-3, 11), (-1, 20), (1, 17), (3, 9)]
+    B = [(-3, 7), (-1, 19), (1, 21), (3, 4), (5, 2)]
+    Cl = [(-2, 12), (0, 30), (2, 9)]
+    cfg = workloads.workload("yc8")
+    _, dq = omp.build_mpo(cfg["ell"], cfg["bonds"])
+    for d in dq:
+        assert lib.envL_size(A, list(d)) == layout.envL_size(A, d)
+        assert lib.envR_size(B, list(d)) == layout.envR_size(B, d)
+    assert lib.psi_size(A, B, QP) == layout.psi_size(A, B, QP)
+    assert lib.U_size(A, QP, Cl) == sum(sum(r[2] for r in layout.U_rows(A, QP, q)) * k for q, k in Cl)
+    assert lib.V_size(B, QP, Cl) == sum(sum(r[2] for r in layout.V_rows(B, QP, q)) * k for q, k in Cl)
+
+
+@pytest.fixture(scope="module")
+def hostplan(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("hostplan") / "libhostplan.so")
+    src = os.path.join(ROOT, "tests", "hostplan", "plan_exec.cpp")
+    plan = os.path.join(ROOT, "paper_1606_06790_amd", "csrc", "plan.cpp")
+    cmd = ["g++", "-O2", "-shared", "-fPIC", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(ROOT, "paper_1606_06790_amd", "csrc"),
+           src, plan, "-o", out]
+    try:
+        subprocess.check_call(cmd)
+    except (OSError, subprocess.CalledProcessError):
+        pytest.skip("g++ or HIP headers unavailable")
+    return C.CDLL(out)
+
+
+def _mpo_pair(name, c1):
+    from paper_1606_06790_amd.lib import Mpo
+    cfg = workloads.workload(name)
+    Ws, dq = omp.build_mpo(cfg["ell"], cfg["bonds"])
+    ell = cfg["ell"]
+    f = lambda k: (k - 1) % ell + 1
+    W1, W2 = Ws[f(c1) - 1], Ws[f(c1 + 1) - 1]
+    dl, dm, dr = dq[f(c1) - 1], dq[f(c1)], dq[f(c1 + 1)]
+    return (W1, W2, dl, dm, dr), (Mpo(W1, dl, dm, QP), Mpo(W2, dm, dr, QP))
+
+
+LEGS = [([(-1, 3), (1, 2)], [(-1, 2), (1, 3)]),
+        ([(-3, 5), (-1, 9), (1, 8), (3, 2)], [(-3, 3), (-1, 7), (1, 10), (3, 4)]),
+        ([(-5, 1), (-3, 6), (-1, 7), (1, 9), (3, 4), (5, 2)], [(-5, 2), (-3, 5), (-1, 8), (1, 6), (3, 3), (5, 1)])]
+
+
+@pytest.mark.parametrize("name,c1", [("chain", 1), ("yc4", 3), ("yc8", 4), ("yc8", 9), ("dimer", 2)])
+@pytest.mark.parametrize("li", [0, 1, 2])
+def test_heff_plan_on_host(lib, hostplan, name, c1, li):
+    (W1, W2, dl, dm, dr), (M1, M2) = _mpo_pair(name, c1)
+    A, B = LEGS[li]
+    nL, nR, nx = layout.envL_size(A, dl), layout.envR_size(B, dr), layout.psi_size(A, B, QP)
+    Lf, Rf, x = workloads.gaussian(nL, 60, li, 1), workloads.gaussian(nR, 60, li, 2), workloads.gaussian(nx, 60, li, 3)
+    ref = layout.psi_to_flat(u1.heff_apply(layout.flat_to_envL(Lf, A, dl), W1, W2, layout.flat_to_envR(Rf, B, dr),
+                                           layout.flat_to_psi(x, A, B, QP), A, B, QP, dl, dr), A, B, QP)
+    k = lib._Keep()
+    h = lib.Heff_t(k.leg(A), k.leg(B), k.mpo(M1), k.mpo(M2), C.c_void_p(Lf.ctypes.data), C.c_void_p(Rf.ctypes.data))
+    y = np.full(nx, np.nan)
+    assert hostplan.hostplan_heff(C.byref(h), C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data)) == 0
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name,c1", [("chain", 2), ("yc8", 4), ("dimer", 1)])
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_env_plan_on_host(lib, hostplan, name, c1, side):
+    (W1, W2, dl, dm, dr), (M1, M2) = _mpo_pair(name, c1)
+    A, B = LEGS[2]
+    Cl = [(-4, 2), (-2, 5), (0, 7), (2, 4), (4, 1)]
+    if side == "left":
+        n_iso = sum(sum(r[2] for r in layout.U_rows(A, QP, q)) * kk for q, kk in Cl)
+        Ef, If = workloads.gaussian(layout.envL_size(A, dl), 61, 1), workloads.gaussian(n_iso, 61, 2)
+        ref = layout.envL_to_flat(u1.update_env_left(layout.flat_to_envL(Ef, A, dl), W1,
+                                                     layout.flat_to_U(If, A, QP, Cl), A, QP, Cl, dl, dm), Cl, dm)
+        old, W, sd = A, M1, 0
+    else:
+        n_iso = sum(sum(r[2] for r in layout.V_rows(B, QP, q)) * kk for q, kk in Cl)
+        Ef, If = workloads.gaussian(layout.envR_size(B, dr), 62, 1), workloads.gaussian(n_iso, 62, 2)
+        ref = layout.envR_to_flat(u1.update_env_right(layout.flat_to_envR(Ef, B, dr), W2,
+                                                      layout.flat_to_V(If, B, QP, Cl), B, QP, Cl, dm, dr), Cl, dm)
+        old, W, sd = B, M2, 1
+    k = lib._Keep()
+    out = np.full(len(ref), np.nan)
+    u = lib.EnvUpdate_t(k.leg(old), k.leg(Cl), k.mpo(W), C.c_void_p(Ef.ctypes.data), C.c_void_p(If.ctypes.data),
+                        C.c_void_p(out.ctypes.data))
+    assert hostplan.hostplan_env(sd, C.byref(u)) == 0
+    assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()
