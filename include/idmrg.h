@@ -142,6 +142,18 @@ int64_t idmrg_V_size(idmrg_leg B, int32_t d, const int32_t* qp, idmrg_leg C);
  * that the matvec must move at least once (environments, input, output). */
 int idmrg_heff_work(const idmrg_heff* H, double* flops, double* bytes);
 
+/* Profiling: when enabled, every launch of the library is bracketed by HIP
+ * events on the context stream.  idmrg_profile_get() synchronises the stream
+ * and returns, for one kernel class, the number of launches, their summed
+ * duration (ms) and their summed algorithmic flops (FP64-equivalent
+ * multiply-adds x 2).  Classes: 0 H_eff GEMM stage 1, 1 H_eff GEMM stage 2,
+ * 2 H_eff mixing, 3 precision conversions, 4 Lanczos vector kernels,
+ * 5 SVD, 6 truncation gather/select/scatter, 7 environment update,
+ * 8 prediction.  idmrg_profile(ctx, 1) also clears the counters. */
+#define IDMRG_PROF_CLASSES 9
+int idmrg_profile(idmrg_ctx* ctx, int enable);
+int idmrg_profile_get(idmrg_ctx* ctx, int cls, int64_t* launches, double* ms, double* flops);
+
 /* ------------------------------------------------------------------ calls */
 
 /* y_p = H_p x_p for p < nprob (Sec. 2, Step 3; Fig. 2(b)):

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libidmrg.so")
-SOURCES = ["api.cpp", "plan.cpp", "gemm.hip", "mix.hip", "lanczos.hip", "svd.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "gemm.hip", "mix.hip", "lanczos.hip", "svd.hip", "bjsvd.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + SRC]

@@ -24,8 +24,23 @@ struct DevBuf {
 
 }  // namespace
 
+namespace {
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  double flops;
+};
+}  // namespace
+
 struct idmrg_ctx {
   int device = 0;
+  // profiling (see idmrg_profile)
+  bool prof = false;
+  std::vector<ProfRec> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t prof_n[IDMRG_PROF_CLASSES] = {};
+  double prof_ms[IDMRG_PROF_CLASSES] = {};
+  double prof_flops[IDMRG_PROF_CLASSES] = {};
   hipStream_t stream = nullptr;
   std::string err;
   DevBuf plan;                 // uploaded task lists and base tables
@@ -41,6 +56,50 @@ enum {
 };
 
 void sync(idmrg_ctx* c) { IDMRG_HIP(hipStreamSynchronize(c->stream)); }
+
+hipEvent_t take_event(idmrg_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  IDMRG_HIP(hipEventCreate(&e));
+  return e;
+}
+
+// Brackets the launches issued during its lifetime with events (if profiling).
+struct Prof {
+  idmrg_ctx* c;
+  ProfRec r{};
+  Prof(idmrg_ctx* ctx, int cls, double flops) : c(ctx) {
+    if (!c->prof) return;
+    r.cls = cls;
+    r.flops = flops;
+    r.a = take_event(c);
+    r.b = take_event(c);
+    IDMRG_HIP(hipEventRecord(r.a, c->stream));
+  }
+  ~Prof() {
+    if (!c->prof) return;
+    if (hipEventRecord(r.b, c->stream) == hipSuccess) c->pending.push_back(r);
+  }
+};
+
+void prof_collect(idmrg_ctx* c) {
+  if (c->pending.empty()) return;
+  IDMRG_HIP(hipStreamSynchronize(c->stream));
+  for (auto& r : c->pending) {
+    float ms = 0.f;
+    IDMRG_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    c->prof_n[r.cls] += 1;
+    c->prof_ms[r.cls] += ms;
+    c->prof_flops[r.cls] += r.flops;
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->pending.clear();
+}
 
 void* ensure(idmrg_ctx* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
@@ -137,6 +196,7 @@ struct HeffExec {
   // per-problem buffers of the low-precision policies
   std::vector<void*> xlow, xmix, ylow;
   std::vector<int64_t> npsi;
+  double flops_g1 = 0, flops_g2 = 0, flops_mix = 0;
 };
 
 size_t elem_size_operand(Prec p) { return p == Prec::F64 ? 8 : 4; }
@@ -162,6 +222,9 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
     if (ex.plan.n_psi[p] == 0) throw InvalidArg("two-site state has no allowed block");
   }
   ex.npsi = ex.plan.n_psi;
+  ex.flops_g1 = ex.plan.g1.flops();
+  ex.flops_g2 = ex.plan.g2.flops();
+  ex.flops_mix = ex.plan.mixY.flops() + ex.plan.mixT.flops();
   {
     std::vector<int64_t> sz((size_t)P * kNumBases, -1);
     for (int p = 0; p < P; ++p) {
@@ -256,6 +319,7 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
               const int32_t* active) {
   hipStream_t s = c->stream;
   if (ex.prec != Prec::F64) {
+    Prof pr(c, 3, 0.0);
     for (int p = 0; p < ex.P; ++p) {
       launch_convert(ex.prec == Prec::F32 ? 0 : 1, x[p], ex.xlow[p], ex.npsi[p], s);
       if (ex.prec == Prec::BF16X3) launch_convert(0, x[p], ex.xmix[p], ex.npsi[p], s);
@@ -264,12 +328,23 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   const int tin = ex.prec == Prec::F64 ? 0 : 1;
   const int toutT = ex.prec == Prec::F64 ? 0 : (ex.prec == Prec::F32 ? 1 : 2);
   const int toutY = ex.prec == Prec::F64 ? 0 : 1;
-  launch_gemm(ex.prec, 0, ex.g1, (int)ex.plan.g1.t.size(), ex.plan.g1.tiles, ex.bases, active, s);
-  launch_mix(tin, toutY, ex.mY, ex.sY, (int)ex.plan.mixY.t.size(), ex.plan.mixY.tiles, ex.bases, active, s);
-  launch_mix(tin, toutT, ex.mT, ex.sT, (int)ex.plan.mixT.t.size(), ex.plan.mixT.tiles, ex.bases, active, s);
-  launch_gemm(ex.prec, 1, ex.g2, (int)ex.plan.g2.t.size(), ex.plan.g2.tiles, ex.bases, active, s);
-  if (ex.prec != Prec::F64)
+  {
+    Prof pr(c, 0, ex.flops_g1);
+    launch_gemm(ex.prec, 0, ex.g1, (int)ex.plan.g1.t.size(), ex.plan.g1.tiles, ex.bases, active, s);
+  }
+  {
+    Prof pr(c, 2, ex.flops_mix);
+    launch_mix(tin, toutY, ex.mY, ex.sY, (int)ex.plan.mixY.t.size(), ex.plan.mixY.tiles, ex.bases, active, s);
+    launch_mix(tin, toutT, ex.mT, ex.sT, (int)ex.plan.mixT.t.size(), ex.plan.mixT.tiles, ex.bases, active, s);
+  }
+  {
+    Prof pr(c, 1, ex.flops_g2);
+    launch_gemm(ex.prec, 1, ex.g2, (int)ex.plan.g2.t.size(), ex.plan.g2.tiles, ex.bases, active, s);
+  }
+  if (ex.prec != Prec::F64) {
+    Prof pr(c, 3, 0.0);
     for (int p = 0; p < ex.P; ++p) launch_convert(2, ex.ylow[p], y[p], ex.npsi[p], s);
+  }
   IDMRG_HIP(hipGetLastError());
 }
 
@@ -303,6 +378,11 @@ extern "C" int idmrg_destroy(idmrg_ctx* c) {
   for (auto& b : c->ws)
     if (b.p) (void)hipFree(b.p);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto& r : c->pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
   delete c;
   return IDMRG_OK;
 }
@@ -312,6 +392,27 @@ extern "C" int idmrg_set_stream(idmrg_ctx* c, void* hip_stream) {
   (void)hipStreamSynchronize(c->stream);
   c->stream = (hipStream_t)hip_stream;
   return IDMRG_OK;
+}
+
+extern "C" int idmrg_profile(idmrg_ctx* c, int enable) {
+  return guarded(c, [&]() {
+    prof_collect(c);
+    c->prof = enable != 0;
+    if (enable)
+      for (int k = 0; k < IDMRG_PROF_CLASSES; ++k) c->prof_n[k] = 0, c->prof_ms[k] = 0, c->prof_flops[k] = 0;
+    return IDMRG_OK;
+  });
+}
+
+extern "C" int idmrg_profile_get(idmrg_ctx* c, int cls, int64_t* launches, double* ms, double* flops) {
+  return guarded(c, [&]() {
+    if (cls < 0 || cls >= IDMRG_PROF_CLASSES || !launches || !ms || !flops) throw InvalidArg("bad profile query");
+    prof_collect(c);
+    *launches = c->prof_n[cls];
+    *ms = c->prof_ms[cls];
+    *flops = c->prof_flops[cls];
+    return IDMRG_OK;
+  });
 }
 
 extern "C" const char* idmrg_last_error(const idmrg_ctx* c) { return c ? c->err.c_str() : "null context"; }
@@ -484,6 +585,7 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       for (int64_t it = 0; it < maxk;) {
         for (int k = 0; k < chunk && it < maxk; ++k, ++it) {
           heff_run(ctx, ex, vv, ww, active);
+          Prof pr(ctx, 4, 0.0);
           lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, kmax, tolE, tolR, s);
         }
         IDMRG_HIP(hipMemcpyAsync(act.data(), active, P * 4, hipMemcpyDeviceToHost, s));
@@ -644,10 +746,31 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
     const size_t a1 = pk.add(gather.t), a2 = pk.add(gather.src), a3 = pk.add(svd), a4 = pk.add(sel),
                  a5 = pk.add(ssec), a6 = pk.add(hb), a7 = pk.add(sweeps);
     char* dev = upload(ctx, pk);
-    launch_mix(0, 0, (MixTask*)(dev + a1), (MixSrc*)(dev + a2), (int)gather.t.size(), gather.tiles,
-               (void**)(dev + a6), nullptr, s);
-    launch_svd((SvdTask*)(dev + a3), (int)svd.size(), (void**)(dev + a6), (int32_t*)(dev + a7), s);
-    launch_select((SelTask*)(dev + a4), (int)sel.size(), (SelSector*)(dev + a5), dS, kept, colmap, lam_sel, scal, s);
+    {
+      Prof pr(ctx, 6, 0.0);
+      launch_mix(0, 0, (MixTask*)(dev + a1), (MixSrc*)(dev + a2), (int)gather.t.size(), gather.tiles,
+                 (void**)(dev + a6), nullptr, s);
+    }
+    {
+      Prof pr(ctx, 5, 0.0);
+      BjScratch scr;
+      int pmax = 1;
+      for (const auto& sv : svd) pmax = std::max(pmax, std::max(sv.r, sv.c));
+      scr.tol = std::max(1e-15, 4.4e-16 * std::sqrt((double)pmax));
+      auto up = [&](const std::vector<char>& h) -> char* {
+        char* d = (char*)ensure(ctx, ctx->ws[WS_READ], h.size());
+        sync(ctx);
+        IDMRG_HIP(hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice));
+        return d;
+      };
+      bj_svd(svd, (void**)(dev + a6), (SvdTask*)(dev + a3), scr, s, up, [&]() { sync(ctx); });
+      (void)a7;
+    }
+    {
+      Prof pr(ctx, 6, 0.0);
+      launch_select((SelTask*)(dev + a4), (int)sel.size(), (SelSector*)(dev + a5), dS, kept, colmap, lam_sel, scal,
+                    s);
+    }
     IDMRG_HIP(hipGetLastError());
     std::vector<int32_t> hkept(ssec.size());
     std::vector<double> hscal(4 * (size_t)P);
@@ -715,7 +838,10 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
     Packer pk2;
     const size_t b1 = pk2.add(outl.t), b2 = pk2.add(ob);
     char* dev2 = upload(ctx, pk2);
-    launch_scale((ScaleTask*)(dev2 + b1), colmap, (int)outl.t.size(), outl.tiles, 0.0, (void**)(dev2 + b2), s);
+    {
+      Prof pr(ctx, 6, 0.0);
+      launch_scale((ScaleTask*)(dev2 + b1), colmap, (int)outl.t.size(), outl.tiles, 0.0, (void**)(dev2 + b2), s);
+    }
     IDMRG_HIP(hipGetLastError());
     sync(ctx);
     for (int p = 0; p < P; ++p)
@@ -775,6 +901,7 @@ extern "C" int update_env(idmrg_ctx* ctx, int nprob, int side, const idmrg_env_u
     char* dev = upload(ctx, pk);
     void** bases = (void**)(dev + a5);
     hipStream_t s = ctx->stream;
+    Prof pr(ctx, 7, plan.ga.flops() + plan.gc.flops() + plan.mix.flops());
     launch_gemm(Prec::F64, side == IDMRG_LEFT ? 0 : 2, (GemmTask*)(dev + a1), (int)plan.ga.t.size(), plan.ga.tiles,
                 bases, nullptr, s);
     launch_mix(0, 0, (MixTask*)(dev + a2), (MixSrc*)(dev + a3), (int)plan.mix.t.size(), plan.mix.tiles, bases,
@@ -832,6 +959,7 @@ extern "C" int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const 
     const size_t a1 = pk.add(plan.scale.t), a2 = pk.add(plan.g.t), a3 = pk.add(hb);
     char* dev = upload(ctx, pk);
     void** bases = (void**)(dev + a3);
+    Prof pr(ctx, 8, plan.g.flops());
     launch_scale((ScaleTask*)(dev + a1), nullptr, (int)plan.scale.t.size(), plan.scale.tiles, lam_floor, bases,
                  ctx->stream);
     launch_gemm(Prec::F64, 2, (GemmTask*)(dev + a2), (int)plan.g.t.size(), plan.g.tiles, bases, nullptr, ctx->stream);

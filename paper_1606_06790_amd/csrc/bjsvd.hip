@@ -1,0 +1,379 @@
+// Blocked one-sided Jacobi SVD of many matrices at once (Step 4).
+//
+// Each centre-charge block M[r x c] is handled as X (n rows of length p,
+// X = M if r <= c else M^T, n = min(r, c)) whose rows are made mutually
+// orthogonal by orthogonal transformations accumulated in G (n x n), so that
+// G X = diag(sigma) Z^T.  The rows are grouped in blocks of 32.  One sweep
+// pairs every block with every other block once (round-robin, nb-1 rounds of
+// nb/2 disjoint pairs); all pairs of one round of all matrices form one
+// launch.  For a pair (I, J), one workgroup:
+//   1. forms the 64 x 64 Gram matrix S = Y Y^T of Y = [X_I; X_J] with FP64 MFMA,
+//   2. diagonalises S by cyclic two-sided Jacobi in LDS (32 disjoint rotations
+//      per step), accumulating Q with Q^T S Q diagonal,
+//   3. replaces Y by Q^T Y and [G_I; G_J] by Q^T [G_I; G_J] with FP64 MFMA.
+// A pair whose rows are already orthogonal to the relative tolerance is left
+// alone; a sweep in which no pair of a matrix moved ends that matrix.
+// k_bj_finish then takes sigma_i = |X_i|, normalises Z and replaces exactly
+// zero rows by unit vectors orthogonalised against the others.
+#include "internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <functional>
+
+namespace idmrg {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int BB = 32;          // rows per block
+constexpr int PB = 2 * BB;      // rows per pair
+constexpr int LD = PB + 1;      // LDS leading dimension
+
+struct BjMat {                  // one matrix (device)
+  int32_t n, p, prob, pad;
+  int64_t x_off, g_off;
+};
+
+struct BjTask {                 // one block pair in one round
+  int32_t mat, bi, bj, pad;
+};
+
+__device__ __forceinline__ double wsum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// C[64x64] = A[64 x K] B[K x 64] with A(i,k) = a_at(i,k), B(k,j) = b_at(k,j), FP64 MFMA, 256 threads.
+// Operands are staged through LDS tiles T[k][i] (16 x LD); AK / BK select whether
+// consecutive threads walk k (rows stored along k in memory) or the 64-wide index.
+template <bool AK, bool BK, typename FA, typename FB>
+__device__ void mfma64(FA a_at, FB b_at, int K, double (*Ta)[LD], double (*Tb)[LD], v4d acc[2][2]) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = t; e < 16 * PB; e += 256) {
+      const int k = AK ? e % 16 : e / PB, i = AK ? e / 16 : e % PB;
+      Ta[k][i] = (k0 + k < K) ? a_at(i, k0 + k) : 0.0;
+    }
+    for (int e = t; e < 16 * PB; e += 256) {
+      const int k = BK ? e % 16 : e / PB, j = BK ? e / 16 : e % PB;
+      Tb[k][j] = (k0 + k < K) ? b_at(k0 + k, j) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = Ta[kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Tb[kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+}
+
+// FP64 16x16x4 accumulator layout: register r of lane l holds C[l/16 + 4r][l%16].
+template <typename F>
+__device__ __forceinline__ void store64(const v4d acc[2][2], F put) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) put(wm + i * 16 + (lane >> 4) + 4 * r, wn + j * 16 + (lane & 15), acc[i][j][r]);
+}
+
+__global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ tasks, const BjMat* __restrict__ mats,
+                                                 void* const* __restrict__ bases, const int32_t* __restrict__ done,
+                                                 int32_t* __restrict__ changed, double tol, int inner_sweeps) {
+  __shared__ double S[PB][LD];
+  __shared__ double Q[PB][LD];
+  __shared__ double Ta[16][LD];
+  __shared__ double Tb[16][LD];
+  __shared__ double cs_[PB / 2], sn_[PB / 2];
+  __shared__ int pidx[PB / 2], qidx[PB / 2];
+  __shared__ int s_move;
+  const BjTask tk = tasks[blockIdx.x];
+  if (done[tk.mat]) return;
+  const BjMat mt = mats[tk.mat];
+  const int n = mt.n, p = mt.p;
+  double* X = reinterpret_cast<double*>(bases[mt.prob * kNumBases + 2]) + mt.x_off;
+  double* G = reinterpret_cast<double*>(bases[mt.prob * kNumBases + 3]) + mt.g_off;
+  const int t = threadIdx.x;
+  // global row of local row i (0..63), or -1 for a padding row
+  auto grow = [&](int i) -> int {
+    const int r = i < BB ? tk.bi * BB + i : tk.bj * BB + (i - BB);
+    const bool ok = i < BB ? (tk.bi >= 0 && r < n) : (tk.bj >= 0 && r < n);
+    return ok ? r : -1;
+  };
+  // 1. Gram matrix S = Y Y^T
+  v4d acc[2][2];
+  {
+    auto a_at = [&](int i, int k) -> double { const int r = grow(i); return r >= 0 ? X[(int64_t)r * p + k] : 0.0; };
+    auto b_at = [&](int k, int j) -> double { const int r = grow(j); return r >= 0 ? X[(int64_t)r * p + k] : 0.0; };
+    mfma64<true, true>(a_at, b_at, p, Ta, Tb, acc);
+    store64(acc, [&](int i, int j, double v) { S[i][j] = v; });
+  }
+  for (int e = t; e < PB * PB; e += 256) Q[e / PB][e % PB] = (e / PB == e % PB) ? 1.0 : 0.0;
+  if (t == 0) s_move = 0;
+  __syncthreads();
+  // is any pair of rows coupled beyond the tolerance?
+  {
+    bool mv = false;
+    for (int e = t; e < PB * PB; e += 256) {
+      const int i = e / PB, j = e % PB;
+      if (i < j) {
+        const double sij = S[i][j];
+        if (sij != 0.0 && fabs(sij) > tol * sqrt(S[i][i] * S[j][j])) mv = true;
+      }
+    }
+    if (mv) s_move = 1;
+  }
+  __syncthreads();
+  if (!s_move) return;
+  if (t == 0) changed[tk.mat] = 1;
+  // 2. cyclic Jacobi on S (round-robin, 32 disjoint pairs per step)
+  for (int sw = 0; sw < inner_sweeps; ++sw) {
+    for (int round = 0; round < PB - 1; ++round) {
+      if (t < PB / 2) {
+        auto L = [&](int x) { return x == 0 ? 0 : 1 + ((round + x - 1) % (PB - 1)); };
+        int a = L(t), b = L(PB - 1 - t);
+        if (a > b) { const int z = a; a = b; b = z; }
+        const double app = S[a][a], aqq = S[b][b], apq = S[a][b];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0 && fabs(apq) > 1e-300) {
+          const double zeta = (aqq - app) / (2.0 * apq);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = c * tt;
+        }
+        pidx[t] = a; qidx[t] = b; cs_[t] = c; sn_[t] = s;
+      }
+      __syncthreads();
+      // columns: S <- S J, Q <- Q J
+      for (int e = t; e < (PB / 2) * PB; e += 256) {
+        const int k = e / PB, r = e % PB;
+        const int a = pidx[k], b = qidx[k];
+        const double c = cs_[k], s = sn_[k];
+        const double x = S[r][a], y = S[r][b];
+        S[r][a] = c * x - s * y;
+        S[r][b] = s * x + c * y;
+        const double u = Q[r][a], v = Q[r][b];
+        Q[r][a] = c * u - s * v;
+        Q[r][b] = s * u + c * v;
+      }
+      __syncthreads();
+      // rows: S <- J^T S
+      for (int e = t; e < (PB / 2) * PB; e += 256) {
+        const int k = e / PB, col = e % PB;
+        const int a = pidx[k], b = qidx[k];
+        const double c = cs_[k], s = sn_[k];
+        const double x = S[a][col], y = S[b][col];
+        S[a][col] = c * x - s * y;
+        S[b][col] = s * x + c * y;
+      }
+      __syncthreads();
+    }
+  }
+  // 3. Y <- Q^T Y, G-rows <- Q^T G-rows, in column chunks of 64 (the chunk is read fully before it is written)
+  for (int pass = 0; pass < 2; ++pass) {
+    double* Mx = pass == 0 ? X : G;
+    const int len = pass == 0 ? p : n;
+    for (int c0 = 0; c0 < len; c0 += PB) {
+      auto a_at = [&](int i, int k) -> double { return Q[k][i]; };
+      auto b_at = [&](int k, int j) -> double {
+        const int r = grow(k);
+        return (r >= 0 && c0 + j < len) ? Mx[(int64_t)r * len + c0 + j] : 0.0;
+      };
+      mfma64<false, false>(a_at, b_at, PB, Ta, Tb, acc);
+      __syncthreads();
+      store64(acc, [&](int i, int j, double v) {
+        const int r = grow(i);
+        if (r >= 0 && c0 + j < len) Mx[(int64_t)r * len + c0 + j] = v;
+      });
+      __syncthreads();
+    }
+  }
+}
+
+// done[m] |= (no pair of m moved in this sweep); changed[m] = 0
+__global__ void k_bj_sweep_end(int nm, int32_t* done, int32_t* changed) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nm) return;
+  if (!changed[m]) done[m] = 1;
+  changed[m] = 0;
+}
+
+// X = M (r <= c) or M^T (r > c); G = I.  One workgroup per matrix.
+__global__ __launch_bounds__(256) void k_bj_init(const SvdTask* __restrict__ tasks, void* const* __restrict__ bases) {
+  const SvdTask tk = tasks[blockIdx.x];
+  const bool tr = tk.r > tk.c;
+  const int n = tr ? tk.c : tk.r, p = tr ? tk.r : tk.c;
+  const double* M = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 1]) + tk.m_off;
+  double* X = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 2]) + tk.x_off;
+  double* G = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 3]) + tk.g_off;
+  for (int64_t e = threadIdx.x; e < (int64_t)n * p; e += 256) {
+    const int i = (int)(e / p), k = (int)(e % p);
+    X[e] = tr ? M[(int64_t)k * tk.c + i] : M[e];
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) G[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+__device__ double block_norm2(const double* z, int p, double* red) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double a = 0.0;
+  for (int k = t; k < p; k += 1024) a += z[k] * z[k];
+  a = wsum(a);
+  if (lane == 0) red[wave] = a;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < 16; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// sigma_i = |X_i|, Z_i = X_i / sigma_i; rows of (numerically) zero norm become
+// unit vectors orthogonalised (twice) against all other rows; then the
+// singular vectors are written as U_full [r x n] and V_full [c x n].
+__global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ tasks, void* const* __restrict__ bases) {
+  __shared__ double red[16];
+  __shared__ double coef[4096];
+  const SvdTask tk = tasks[blockIdx.x];
+  const int r = tk.r, c = tk.c;
+  const bool tr = r > c;
+  const int n = tr ? c : r, p = tr ? r : c;
+  double* X = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 2]) + tk.x_off;
+  double* G = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 3]) + tk.g_off;
+  double* Uf = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 4]) + tk.u_off;
+  double* Vf = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 5]) + tk.v_off;
+  double* S = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 6]) + tk.s_off;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int i = wave; i < n; i += 16) {
+    double* xi = X + (int64_t)i * p;
+    double a = 0.0;
+    for (int k = lane; k < p; k += 64) a += xi[k] * xi[k];
+    a = wsum(a);
+    const double sg = sqrt(a);
+    const bool zero = !(sg > 1e-150);
+    if (lane == 0) S[i] = zero ? 0.0 : sg;
+    const double inv = zero ? 0.0 : 1.0 / sg;
+    for (int k = lane; k < p; k += 64) xi[k] *= inv;
+  }
+  __syncthreads();
+  int next_unit = 0;
+  for (int i = 0; i < n; ++i) {
+    if (S[i] > 0.0) continue;           // uniform: S is global and was synchronised
+    double* zi = X + (int64_t)i * p;
+    bool ok = false;
+    while (!ok && next_unit < p) {
+      for (int k = t; k < p; k += 1024) zi[k] = (k == next_unit) ? 1.0 : 0.0;
+      ++next_unit;
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int q = wave; q < n; q += 16) {
+          if (q == i) { if (lane == 0) coef[q] = 0.0; continue; }
+          const double* zq = X + (int64_t)q * p;
+          double d = 0.0;
+          for (int k = lane; k < p; k += 64) d += zq[k] * zi[k];
+          d = wsum(d);
+          if (lane == 0) coef[q] = d;
+        }
+        __syncthreads();
+        for (int k = t; k < p; k += 1024) {
+          double acc = 0.0;
+          for (int q = 0; q < n; ++q) acc += coef[q] * X[(int64_t)q * p + k];
+          zi[k] -= acc;
+        }
+        __syncthreads();
+      }
+      const double nn = sqrt(block_norm2(zi, p, red));
+      if (nn > 0.5) {
+        for (int k = t; k < p; k += 1024) zi[k] /= nn;
+        ok = true;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (!tr) {
+    for (int64_t e = t; e < (int64_t)r * n; e += 1024) Uf[e] = G[(e % n) * (int64_t)n + e / n];
+    for (int64_t e = t; e < (int64_t)c * n; e += 1024) Vf[e] = X[(e % n) * (int64_t)p + e / n];
+  } else {
+    for (int64_t e = t; e < (int64_t)r * n; e += 1024) Uf[e] = X[(e % n) * (int64_t)p + e / n];
+    for (int64_t e = t; e < (int64_t)c * n; e += 1024) Vf[e] = G[(e % n) * (int64_t)n + e / n];
+  }
+}
+
+}  // namespace
+
+void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask* dtasks, BjScratch& scr,
+            hipStream_t s, const std::function<char*(const std::vector<char>&)>& upload,
+            const std::function<void()>& sync) {
+  const int nm = (int)svd.size();
+  if (nm == 0) return;
+  std::vector<BjMat> mats(nm);
+  std::vector<std::vector<BjTask>> rounds;
+  for (int m = 0; m < nm; ++m) {
+    const SvdTask& t = svd[m];
+    const bool tr = t.r > t.c;
+    const int n = tr ? t.c : t.r, p = tr ? t.r : t.c;
+    mats[m] = BjMat{n, p, t.prob, 0, t.x_off, t.g_off};
+    const int nb = (n + BB - 1) / BB;
+    const int nbe = nb + (nb & 1);
+    for (int rd = 0; rd < nbe - 1; ++rd) {
+      if ((int)rounds.size() <= rd) rounds.emplace_back();
+      for (int slot = 0; slot < nbe / 2; ++slot) {
+        auto L = [&](int x) { return x == 0 ? 0 : 1 + ((rd + x - 1) % (nbe - 1)); };
+        int a = L(slot), b = L(nbe - 1 - slot);
+        if (a > b) std::swap(a, b);
+        rounds[rd].push_back(BjTask{m, a, b < nb ? b : -1, 0});
+      }
+    }
+  }
+  std::vector<char> host;
+  auto put = [&](const void* p, size_t bytes) {
+    const size_t off = (host.size() + 255) / 256 * 256;
+    host.resize(off + std::max<size_t>(bytes, 8));
+    if (bytes) std::memcpy(host.data() + off, p, bytes);
+    return off;
+  };
+  const size_t omats = put(mats.data(), mats.size() * sizeof(BjMat));
+  std::vector<size_t> ornd(rounds.size());
+  for (size_t r = 0; r < rounds.size(); ++r) ornd[r] = put(rounds[r].data(), rounds[r].size() * sizeof(BjTask));
+  std::vector<int32_t> zeros(2 * (size_t)nm, 0);
+  const size_t oflags = put(zeros.data(), zeros.size() * 4);
+  char* dev = upload(host);
+  const BjMat* dmats = (const BjMat*)(dev + omats);
+  int32_t* done = (int32_t*)(dev + oflags);
+  int32_t* changed = done + nm;
+  hipLaunchKernelGGL(k_bj_init, dim3(nm), dim3(256), 0, s, dtasks, dbases);
+  std::vector<int32_t> hdone(nm);
+  int sweeps = 0;
+  for (; sweeps < scr.max_sweeps; ++sweeps) {
+    for (size_t r = 0; r < rounds.size(); ++r)
+      hipLaunchKernelGGL(k_bj_pair, dim3((unsigned)rounds[r].size()), dim3(256), 0, s, (const BjTask*)(dev + ornd[r]),
+                         dmats, dbases, (const int32_t*)done, changed, scr.tol, scr.inner_sweeps);
+    hipLaunchKernelGGL(k_bj_sweep_end, dim3((nm + 255) / 256), dim3(256), 0, s, nm, done, changed);
+    if (hipMemcpyAsync(hdone.data(), done, nm * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+      throw HipFailure("hipMemcpyAsync of Jacobi flags failed");
+    sync();
+    if (std::all_of(hdone.begin(), hdone.end(), [](int32_t v) { return v != 0; })) break;
+  }
+  scr.sweeps = sweeps + 1;
+  hipLaunchKernelGGL(k_bj_finish, dim3(nm), dim3(1024), 0, s, dtasks, dbases);
+}
+
+}  // namespace idmrg

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -121,6 +122,20 @@ void launch_scale(const ScaleTask* tasks, const int32_t* colmaps, int ntask, int
 void launch_convert(int kind, const void* src, void* dst, int64_t n, hipStream_t s);
 
 void launch_svd(const SvdTask* tasks, int ntask, void* const* bases, int32_t* sweeps_out, hipStream_t s);
+
+// Blocked one-sided Jacobi (bjsvd.hip): all matrices of `svd` at once.
+// bases (device) as for launch_svd; dtasks = the same tasks on the device.
+// upload() copies a host byte array to device memory and returns its address;
+// sync() waits for the stream (the host checks the sweep flags once per sweep).
+struct BjScratch {
+  double tol = 1e-15;
+  int inner_sweeps = 3;
+  int max_sweeps = 30;
+  int sweeps = 0;   // out
+};
+void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask* dtasks, BjScratch& scr,
+            hipStream_t s, const std::function<char*(const std::vector<char>&)>& upload,
+            const std::function<void()>& sync);
 void launch_select(const SelTask* tasks, int ntask, const SelSector* secs, const double* S,
                    int32_t* kept_per_sec, int32_t* colmap, double* lam_sel, double* scal,
                    hipStream_t s);

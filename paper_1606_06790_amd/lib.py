@@ -24,7 +24,10 @@ LEFT, RIGHT = 0, 1
 
 EXPORTS = ["idmrg_create", "idmrg_destroy", "idmrg_set_stream", "idmrg_last_error", "idmrg_psi_size",
            "idmrg_envL_size", "idmrg_envR_size", "idmrg_U_size", "idmrg_V_size", "idmrg_heff_work",
-           "heff_apply", "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction"]
+           "heff_apply", "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction",
+           "idmrg_profile", "idmrg_profile_get"]
+PROF_CLASSES = ["heff_gemm1", "heff_gemm2", "heff_mix", "convert", "lanczos_vec", "svd", "trunc_other", "env",
+                "predict"]
 
 
 class IdmrgError(RuntimeError):
@@ -114,7 +117,11 @@ def load():
     lib.update_env.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(EnvUpdate_t)]
     lib.predict_wavefunction.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_int32), C.c_double,
                                          C.POINTER(Predict_t)]
-    for name in ["idmrg_create", "idmrg_destroy", "idmrg_set_stream", "idmrg_heff_work", "heff_apply",
+    lib.idmrg_profile.argtypes = [C.c_void_p, C.c_int]
+    lib.idmrg_profile_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
+    for name in ["idmrg_profile", "idmrg_profile_get", "idmrg_create", "idmrg_destroy", "idmrg_set_stream",
+                 "idmrg_heff_work", "heff_apply",
                  "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -195,6 +202,19 @@ class Context:
     def sync_stream(self):
         torch = _torch()
         self.lib.idmrg_set_stream(self.handle, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def profile(self, enable=True):
+        """Bracket every library launch with HIP events (clears the counters when enabling)."""
+        _check(self, self.lib.idmrg_profile(self.handle, 1 if enable else 0))
+
+    def profile_get(self):
+        """{class: (launches, ms, flops)} of the launches since profiling was enabled."""
+        out = {}
+        for k, name in enumerate(PROF_CLASSES):
+            n, ms, fl = C.c_int64(), C.c_double(), C.c_double()
+            _check(self, self.lib.idmrg_profile_get(self.handle, k, C.byref(n), C.byref(ms), C.byref(fl)))
+            out[name] = (int(n.value), float(ms.value), float(fl.value))
+        return out
 
     def close(self):
         if self.handle:
