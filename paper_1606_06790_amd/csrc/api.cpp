@@ -46,13 +46,14 @@ struct idmrg_ctx {
   DevBuf plan;                 // uploaded task lists and base tables
   void* pinned = nullptr;      // host staging for uploads
   size_t pinned_n = 0;
-  DevBuf ws[12];               // scratch, by purpose (see WS_*)
+  DevBuf ws[16];               // scratch, by purpose (see WS_*)
 };
 
 namespace {
 
 enum {
-  WS_T1 = 0, WS_T3, WS_LOWENV, WS_LOWVEC, WS_LZ, WS_LZSMALL, WS_SVD, WS_SEL, WS_ENV, WS_PRED, WS_READ, WS_MISC
+  WS_T1 = 0, WS_T3, WS_LOWENV, WS_LOWVEC, WS_LZ, WS_LZSMALL, WS_SVD, WS_SEL, WS_ENV, WS_PRED, WS_READ, WS_MISC,
+  WS_PLAN64, WS_PLANLOW
 };
 
 void sync(idmrg_ctx* c) { IDMRG_HIP(hipStreamSynchronize(c->stream)); }
@@ -132,9 +133,9 @@ struct Packer {
   size_t add(const std::vector<T>& v) { return add(v.data(), v.size() * sizeof(T)); }
 };
 
-char* upload(idmrg_ctx* c, const Packer& pk) {
+char* upload(idmrg_ctx* c, const Packer& pk, DevBuf* target = nullptr) {
   sync(c);   // previous work may still read the plan buffer and the staging area
-  char* dev = (char*)ensure(c, c->plan, pk.host.size());
+  char* dev = (char*)ensure(c, target ? *target : c->plan, pk.host.size());
   if (c->pinned_n < pk.host.size()) {
     if (c->pinned) IDMRG_HIP(hipHostFree(c->pinned));
     c->pinned = nullptr;
@@ -204,7 +205,7 @@ size_t elem_size_operand(Prec p) { return p == Prec::F64 ? 8 : 4; }
 // Build plans for P problems, allocate scratch, convert environments for the
 // low-precision policies, and upload.  x/y are the FP64 input/output vectors.
 void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const std::vector<double*>& x,
-                const std::vector<double*>& y, int prec) {
+                const std::vector<double*>& y, int prec, DevBuf* planbuf = nullptr) {
   if (prec < 0 || prec > 2) throw InvalidArg("unknown precision policy");
   ex.P = P;
   ex.prec = (Prec)prec;
@@ -222,6 +223,13 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
     if (ex.plan.n_psi[p] == 0) throw InvalidArg("two-site state has no allowed block");
   }
   ex.npsi = ex.plan.n_psi;
+  if (ex.prec != Prec::BF16X3) {
+    ex.plan.g1.choose_tile(true);
+    ex.plan.g2.choose_tile(true);
+  } else {   // the split-bf16 kernel has a fixed 128 x 128 tile
+    ex.plan.g1.retile(128, 128);
+    ex.plan.g2.retile(128, 128);
+  }
   ex.flops_g1 = ex.plan.g1.flops();
   ex.flops_g2 = ex.plan.g2.flops();
   ex.flops_mix = ex.plan.mixY.flops() + ex.plan.mixT.flops();
@@ -304,7 +312,7 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
   const size_t a1 = pk.add(ex.plan.g1.t), a2 = pk.add(ex.plan.g2.t), a3 = pk.add(ex.plan.mixY.t),
                a4 = pk.add(ex.plan.mixY.src), a5 = pk.add(ex.plan.mixT.t), a6 = pk.add(ex.plan.mixT.src),
                a7 = pk.add(hb);
-  char* dev = upload(c, pk);
+  char* dev = upload(c, pk, planbuf);
   ex.g1 = (GemmTask*)(dev + a1);
   ex.g2 = (GemmTask*)(dev + a2);
   ex.mY = (MixTask*)(dev + a3);
@@ -330,7 +338,8 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   const int toutY = ex.prec == Prec::F64 ? 0 : 1;
   {
     Prof pr(c, 0, ex.flops_g1);
-    launch_gemm(ex.prec, 0, ex.g1, (int)ex.plan.g1.t.size(), ex.plan.g1.tiles, ex.bases, active, s);
+    launch_gemm(ex.prec, 0, ex.g1, (int)ex.plan.g1.t.size(), ex.plan.g1.tiles, ex.bases, active, s,
+                ex.plan.g1.tiling());
   }
   {
     Prof pr(c, 2, ex.flops_mix);
@@ -339,7 +348,8 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   }
   {
     Prof pr(c, 1, ex.flops_g2);
-    launch_gemm(ex.prec, 1, ex.g2, (int)ex.plan.g2.t.size(), ex.plan.g2.tiles, ex.bases, active, s);
+    launch_gemm(ex.prec, 1, ex.g2, (int)ex.plan.g2.t.size(), ex.plan.g2.tiles, ex.bases, active, s,
+                ex.plan.g2.tiling());
   }
   if (ex.prec != Prec::F64) {
     Prof pr(c, 3, 0.0);
@@ -499,9 +509,11 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     if (!H || !psi || !o || !energy || !info) throw InvalidArg("null argument");
     if (o->k_max < 1 || o->k_max > kLzMaxK) throw InvalidArg("k_max must be 1..1024");
     if (!(o->tol_E >= 0) || !(o->tol_res >= 0)) throw InvalidArg("tolerances must be >= 0");
+    if (o->prec < 0 || o->prec > 2) throw InvalidArg("unknown precision policy");
     const int P = nprob;
     const int kmax = o->k_max;
     const int chunk = std::max(1, o->chunk > 0 ? o->chunk : 8);
+    const bool mixed = o->prec != IDMRG_PREC_F64;
     hipStream_t s = ctx->stream;
     // sizes first (plan building validates everything)
     std::vector<int64_t> N(P);
@@ -525,7 +537,6 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       tot += N[p] + 32;
     }
     double* V = (double*)ensure(ctx, ctx->ws[WS_LZ], tot * 8);
-    // small arrays
     const size_t nsm = (size_t)P * kmax;
     const size_t small_bytes = (size_t)P * kmax * kLzBlocks * 8 + 4 * nsm * 8 + P * sizeof(LzCtrl) + P * 4 + 4096;
     char* sm = (char*)ensure(ctx, ctx->ws[WS_LZSMALL], small_bytes);
@@ -538,40 +549,55 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     int32_t* active = (int32_t*)(ctrl + P);
     std::vector<double*> vv(P), ww(P);
     std::vector<LzProblem> probs(P);
-    std::vector<LzCtrl> hctrl(P);
-    std::vector<int32_t> hact(P, 1);
     for (int p = 0; p < P; ++p) {
       vv[p] = V + voff[p];
       ww[p] = V + woff[p];
       probs[p] = LzProblem{N[p], V + qoff[p], ww[p], vv[p], psi[p]};
-      LzCtrl z{};
-      z.active = 1;
-      z.kcap = (int32_t)kcap[p];
-      hctrl[p] = z;
     }
-    // low-precision stage (if any), then FP64
-    const bool mixed = o->prec != IDMRG_PREC_F64;
-    int total_fp64 = 0;
-    std::vector<LzCtrl> out(P);
-    for (int stage = mixed ? 0 : 1; stage < 2; ++stage) {
-      const int prec = stage == 0 ? o->prec : IDMRG_PREC_F64;
-      double tolE = o->tol_E, tolR = o->tol_res;
-      if (stage == 0) {   // the low-precision iteration stops at its own noise floor
-        tolE = std::max(tolE, prec == IDMRG_PREC_F32 ? 1e-9 : 1e-6);
-        tolR = std::max(tolR, prec == IDMRG_PREC_F32 ? 1e-4 : 1e-3);
+    // The FP64 plan is set up first: it needs the larger scratch, so the
+    // low-precision plan set up afterwards never reallocates under it.
+    HeffExec ex64, exlo;
+    heff_setup(ctx, ex64, P, H, vv, ww, IDMRG_PREC_F64, &ctx->ws[WS_PLAN64]);
+    if (mixed) heff_setup(ctx, exlo, P, H, vv, ww, o->prec, &ctx->ws[WS_PLANLOW]);
+    char* dprob = (char*)ensure(ctx, ctx->ws[WS_MISC], P * (sizeof(LzProblem) + sizeof(LzCtrl) + 4) + 1024);
+    LzProblem* dprobs = (LzProblem*)dprob;
+    LzCtrl* hstage = (LzCtrl*)(dprob + ((P * sizeof(LzProblem) + 255) / 256) * 256);
+    int32_t* astage = (int32_t*)((char*)hstage + ((P * sizeof(LzCtrl) + 255) / 256) * 256);
+    sync(ctx);
+    IDMRG_HIP(hipMemcpy(dprobs, probs.data(), P * sizeof(LzProblem), hipMemcpyHostToDevice));
+
+    // Mixed precision: every outer pass is a Lanczos run whose first matvec is
+    // FP64 (so alpha_0 and beta_0 are the exact Rayleigh quotient and residual
+    // norm of the current vector) and whose later matvecs use the low-precision
+    // policy; the pass's Ritz vector starts the next pass.  A pass that stops
+    // at its first step (beta_0 <= tol_res) has converged in FP64.
+    const double lowE = o->prec == IDMRG_PREC_F32 ? 1e-9 : 1e-6;
+    const double lowR = o->prec == IDMRG_PREC_F32 ? 1e-5 : 1e-4;
+    const int k_inner = 60;
+    const int max_outer = mixed ? 16 : 1;
+    std::vector<int32_t> going(P, 1);
+    std::vector<int> iters(P, 0), fp64mv(P, 0);
+    std::vector<LzCtrl> fin(P), out(P);
+    std::vector<double> ov0(P, 0.0);
+    for (int outer = 0; outer < max_outer; ++outer) {
+      std::vector<LzCtrl> hctrl(P);
+      std::vector<int32_t> hact(P);
+      int64_t maxk = 0;
+      for (int p = 0; p < P; ++p) {
+        LzCtrl z{};
+        z.active = going[p];
+        z.kcap = going[p] ? (int32_t)std::min<int64_t>(mixed && outer > 0 ? k_inner : kmax, kcap[p]) : 0;
+        hctrl[p] = z;
+        hact[p] = going[p];
+        maxk = std::max<int64_t>(maxk, z.kcap);
       }
-      HeffExec ex;
-      heff_setup(ctx, ex, P, H, vv, ww, prec);
-      Packer pk;
-      const size_t a1 = pk.add(probs), a2 = pk.add(hctrl), a3 = pk.add(hact);
-      char* dev = (char*)ensure(ctx, ctx->ws[WS_MISC], pk.host.size());
       sync(ctx);
-      IDMRG_HIP(hipMemcpy(dev, pk.host.data(), pk.host.size(), hipMemcpyHostToDevice));
-      LzProblem* dprobs = (LzProblem*)(dev + a1);
-      IDMRG_HIP(hipMemcpyAsync(ctrl, dev + a2, P * sizeof(LzCtrl), hipMemcpyDeviceToDevice, s));
-      IDMRG_HIP(hipMemcpyAsync(active, dev + a3, P * 4, hipMemcpyDeviceToDevice, s));
+      IDMRG_HIP(hipMemcpy(hstage, hctrl.data(), P * sizeof(LzCtrl), hipMemcpyHostToDevice));
+      IDMRG_HIP(hipMemcpy(astage, hact.data(), P * 4, hipMemcpyHostToDevice));
+      IDMRG_HIP(hipMemcpyAsync(ctrl, hstage, P * sizeof(LzCtrl), hipMemcpyDeviceToDevice, s));
+      IDMRG_HIP(hipMemcpyAsync(active, astage, P * 4, hipMemcpyDeviceToDevice, s));
       lz_init(P, dprobs, ctrl, partial, kmax, s);
-      {
+      if (outer == 0) {
         std::vector<LzCtrl> chk(P);
         IDMRG_HIP(hipMemcpyAsync(chk.data(), ctrl, P * sizeof(LzCtrl), hipMemcpyDeviceToHost, s));
         sync(ctx);
@@ -579,53 +605,62 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
           if (!(chk[p].norm0 > 0.0) || !std::isfinite(chk[p].norm0))
             throw InvalidArg("start vector has zero or non-finite norm (problem " + std::to_string(p) + ")");
       }
-      int64_t maxk = 0;
-      for (int p = 0; p < P; ++p) maxk = std::max(maxk, kcap[p]);
+      const double tolE = mixed ? std::max(o->tol_E, lowE) : o->tol_E;
+      const double tolR = mixed ? std::max(o->tol_res, lowR) : o->tol_res;
+      const double tolF = mixed ? o->tol_res : 0.0;
+      // refinement passes reduce the exact residual by a fixed factor each
+      const double relF = (mixed && outer > 0) ? (o->prec == IDMRG_PREC_F32 ? 1e-4 : 1e-3) : 0.0;
       std::vector<int32_t> act(P);
       for (int64_t it = 0; it < maxk;) {
         for (int k = 0; k < chunk && it < maxk; ++k, ++it) {
-          heff_run(ctx, ex, vv, ww, active);
+          heff_run(ctx, (!mixed || it == 0) ? ex64 : exlo, vv, ww, active);
           Prof pr(ctx, 4, 0.0);
-          lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, kmax, tolE, tolR, s);
+          lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, kmax, tolE, tolR, tolF, relF,
+                            s);
         }
         IDMRG_HIP(hipMemcpyAsync(act.data(), active, P * 4, hipMemcpyDeviceToHost, s));
         sync(ctx);
         if (std::all_of(act.begin(), act.end(), [](int32_t a) { return a == 0; })) break;
       }
       lz_finish(P, dprobs, ctrl, ritz, partial, kmax, s);
-      if (stage == 1) {
-        // FP64 residual of the result: w = H psi (v holds psi)
-        heff_run(ctx, ex, vv, ww, nullptr);
-        lz_residual(P, dprobs, ctrl, partial, kmax, s);
-      }
       IDMRG_HIP(hipMemcpyAsync(out.data(), ctrl, P * sizeof(LzCtrl), hipMemcpyDeviceToHost, s));
       sync(ctx);
-      if (stage == 1)
-        for (int p = 0; p < P; ++p) total_fp64 += out[p].iters + 1;
-      if (stage == 0) {
-        for (int p = 0; p < P; ++p) info[p].overlap0 = out[p].overlap0;
+      for (int p = 0; p < P; ++p) {
+        if (!going[p]) continue;
+        iters[p] += out[p].iters;
+        fp64mv[p] += 1;
+        if (outer == 0) ov0[p] = out[p].overlap0;
+        fin[p] = out[p];
+        if (!mixed || (out[p].iters == 1 && out[p].converged)) going[p] = 0;
       }
+      if (std::all_of(going.begin(), going.end(), [](int32_t g) { return g == 0; })) break;
+    }
+    if (!mixed) {
+      // FP64 residual of the result: w = H psi (v holds psi after lz_finish)
+      heff_run(ctx, ex64, vv, ww, nullptr);
+      lz_residual(P, dprobs, ctrl, partial, kmax, s);
+      IDMRG_HIP(hipMemcpyAsync(out.data(), ctrl, P * sizeof(LzCtrl), hipMemcpyDeviceToHost, s));
+      sync(ctx);
+      for (int p = 0; p < P; ++p) fin[p].residual = out[p].residual;
     }
     int rc = IDMRG_OK;
     for (int p = 0; p < P; ++p) {
-      energy[p] = out[p].theta;
-      if (!mixed) info[p].overlap0 = out[p].overlap0;
-      info[p].iters = out[p].iters;
-      info[p].converged = out[p].converged;
-      info[p].fp64_matvecs = mixed ? out[p].iters + 1 : 0;
-      info[p].flags = out[p].flags;
-      info[p].residual = out[p].residual;
-      if (!std::isfinite(out[p].theta) || !std::isfinite(out[p].residual)) {
+      energy[p] = fin[p].theta;
+      info[p].overlap0 = ov0[p];
+      info[p].iters = iters[p];
+      info[p].converged = mixed ? (going[p] ? 0 : 1) : fin[p].converged;
+      info[p].fp64_matvecs = mixed ? fp64mv[p] : 0;
+      info[p].flags = fin[p].flags;
+      info[p].residual = fin[p].residual;
+      if (!std::isfinite(fin[p].theta) || !std::isfinite(fin[p].residual)) {
         ctx->err = "non-finite energy or residual (problem " + std::to_string(p) + ")";
         return IDMRG_ENUMERIC;
       }
-      if (!out[p].converged) rc = IDMRG_WARN_NOCONV;
+      if (!info[p].converged) rc = IDMRG_WARN_NOCONV;
     }
-    (void)total_fp64;
     return rc;
   });
 }
-
 // ------------------------------------------------------------------ truncate_twosite
 
 extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp_in, int32_t m_max,

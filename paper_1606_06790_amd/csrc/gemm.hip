@@ -1,16 +1,20 @@
 // Grouped GEMM on CDNA4 matrix cores (gfx950).
 //
 // One launch runs every task of a plan: the blocks of all l/2 superblocks and
-// all symmetry sectors.  Each workgroup (256 threads = 4 wave64) owns one
-// 64 x 64 output tile; the 4 waves form a 2 x 2 grid of 32 x 32 sub-tiles made
-// of 2 x 2 MFMA 16 x 16 tiles.  K advances in steps of 16 through LDS.
+// all symmetry sectors.  Each workgroup (256 threads = 4 wave64, 2 x 2) owns
+// one BM x BN output tile.
 //
-// FP64 uses v_mfma_f64_16x16x4_f64, FP32 uses v_mfma_f32_16x16x4_f32 (both:
-// A operand lane l holds A[l%16][l/16], B operand B[l/16][l%16], accumulator
-// register r of lane l holds C[4*(l/16)+r][l%16] for FP32 and the bf16 shape,
-// but C[l/16+4r][l%16] for FP64, as measured on gfx950).  The split-bf16 policy
-// (bf16x3) uses v_mfma_f32_16x16x32_bf16 with operands a = hi + lo and three
-// products hi*hi + hi*lo + lo*hi, FP32 accumulation.
+// FP64 uses v_mfma_f64_16x16x4_f64 and FP32 v_mfma_f32_16x16x4_f32: the A
+// operand of lane l is A[l%16][l/16], the B operand B[l/16][l%16]; register r
+// of lane l holds C[4*(l/16)+r][l%16] for FP32 but C[l/16+4r][l%16] for FP64
+// (measured on gfx950).  The split-bf16 policy (bf16x3) uses
+// v_mfma_f32_16x16x32_bf16 (A: lane l holds A[l%16][8*(l/16)+0..7], B:
+// B[8*(l/16)+0..7][l%16], C as FP32) with operands a = hi + lo and the three
+// products lo*hi + hi*lo + hi*hi accumulated in FP32.
+//
+// Workgroups are dispatched round-robin over the 8 XCDs; xcd_tile() renumbers
+// them so that each XCD receives a contiguous range of tiles, and the tiles of
+// one output row band (which share their A operand) meet in one L2.
 #include "internal.h"
 
 namespace idmrg {
@@ -19,8 +23,16 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16, LDS_LD = 65;
+constexpr int kXcd = 8;
+
+// Logical tile of this workgroup (grid = kXcd * ceil(ntiles / kXcd)), or -1.
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+  const int per = (ntiles + kXcd - 1) / kXcd;
+  const int t = (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
+  return t < ntiles ? t : -1;
+}
 
 __device__ __forceinline__ int find_task(const GemmTask* tasks, int ntask, int tile) {
   int lo = 0, hi = ntask - 1;
@@ -32,27 +44,36 @@ __device__ __forceinline__ int find_task(const GemmTask* tasks, int ntask, int t
 }
 
 template <typename T>
-__device__ __forceinline__ void mfma_16x16x4(T a, T b, typename std::conditional<std::is_same<T, double>::value, v4d, v4f>::type& c);
-
+struct AccOf;
 template <>
-__device__ __forceinline__ void mfma_16x16x4<double>(double a, double b, v4d& c) {
+struct AccOf<double> { typedef v4d type; };
+template <>
+struct AccOf<float> { typedef v4f type; };
+
+__device__ __forceinline__ void mfma_16x16x4(double a, double b, v4d& c) {
   c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-template <>
-__device__ __forceinline__ void mfma_16x16x4<float>(float a, float b, v4f& c) {
+__device__ __forceinline__ void mfma_16x16x4(float a, float b, v4f& c) {
   c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Tile BM x BN per workgroup (2 x 2 waves of (BM/2) x (BN/2)), K in steps of
+// 16.  The next K-slab is fetched from global memory into registers while the
+// current one is consumed from LDS (two LDS buffers, one barrier per slab).
 // MODE: 0 = NN, 1 = NT (B given as [N x K]), 2 = TN (A given as [K x M]).
-template <typename T, int MODE>
+template <typename T, int MODE, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restrict__ tasks, int ntask,
                                                         void* const* __restrict__ bases,
-                                                        const int32_t* __restrict__ active) {
-  using acc_t = typename std::conditional<std::is_same<T, double>::value, v4d, v4f>::type;
-  __shared__ T As[BK][LDS_LD];
-  __shared__ T Bs[BK][LDS_LD];
+                                                        const int32_t* __restrict__ active, int ntiles) {
+  using acc_t = typename AccOf<T>::type;
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2, TI = WM / 16, TJ = WN / 16;
+  constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
+  __shared__ T As[2][BK][BM + 1];
+  __shared__ T Bs[2][BK][BN + 1];
 
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(ntiles);
+  if (tile < 0) return;
   const GemmTask& tk = tasks[find_task(tasks, ntask, tile)];
   if (active && !active[tk.prob]) return;
   const int local = tile - tk.tile0;
@@ -67,72 +88,83 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
 
-  acc_t acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  // slab coordinates: A (MODE 0/1) TPRA threads per row, NA consecutive k each;
+  // A (MODE 2) 16 threads per k, NA consecutive m each; B symmetrically.
+  constexpr int TPRA = 256 / BM;
+  constexpr int TPRB = 256 / BN;
+  const int a_r = MODE == 2 ? t >> 4 : t / TPRA;
+  const int a_c = MODE == 2 ? (t & 15) * NA : (t % TPRA) * NA;
+  const int b_r = MODE == 1 ? t / TPRB : t >> 4;
+  const int b_c = MODE == 1 ? (t % TPRB) * NB : (t & 15) * NB;
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // ---- stage A tile [BM x BK] into As[k][m]
-    if (MODE == 2) {
-      const int k = t >> 4, mq = (t & 15) * 4;
+  // Loads outside the matrix are skipped and read as zero (measured faster on
+  // gfx950 than clamped unconditional loads).
+  T ra[NA], rb[NB];
+  auto load = [&](int k0) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gi = m0 + mq + e, gk = k0 + k;
-        As[k][mq + e] = (gi < M && gk < K) ? A[(int64_t)gk * lda + gi] : T(0);
-      }
-    } else {
-      const int i = t >> 2, kq = (t & 3) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gi = m0 + i, gk = k0 + kq + e;
-        As[kq + e][i] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : T(0);
-      }
+    for (int e = 0; e < NA; ++e) {
+      int gi, gk;
+      if (MODE == 2) { gk = k0 + a_r; gi = m0 + a_c + e; } else { gi = m0 + a_r; gk = k0 + a_c + e; }
+      ra[e] = (gi < M && gk < K) ? (MODE == 2 ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]) : T(0);
     }
-    // ---- stage B tile [BK x BN] into Bs[k][n]
-    if (MODE == 1) {
-      const int n = t >> 2, kq = (t & 3) * 4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gn = n0 + n, gk = k0 + kq + e;
-        Bs[kq + e][n] = (gn < N && gk < K) ? B[(int64_t)gn * ldb + gk] : T(0);
-      }
-    } else {
-      const int k = t >> 4, nq = (t & 15) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gn = n0 + nq + e, gk = k0 + k;
-        Bs[k][nq + e] = (gn < N && gk < K) ? B[(int64_t)gk * ldb + gn] : T(0);
-      }
+    for (int e = 0; e < NB; ++e) {
+      int gn, gk;
+      if (MODE == 1) { gn = n0 + b_r; gk = k0 + b_c + e; } else { gk = k0 + b_r; gn = n0 + b_c + e; }
+      rb[e] = (gn < N && gk < K) ? (MODE == 1 ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : T(0);
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      if (MODE == 2) As[buf][a_r][a_c + e] = ra[e]; else As[buf][a_c + e][a_r] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      if (MODE == 1) Bs[buf][b_c + e][b_r] = rb[e]; else Bs[buf][b_r][b_c + e] = rb[e];
+    }
+  };
+
+  acc_t acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  if (K > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = 0, it = 0; k0 < K; k0 += BK, ++it) {
+    const int cur = it & 1;
+    const bool more = k0 + BK < K;
+    if (more) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      T a[2], b[2];
+      T a[TI], b[TJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+      for (int i = 0; i < TI; ++i) a[i] = As[cur][kr][wm + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+      for (int j = 0; j < TJ; ++j) b[j] = Bs[cur][kr][wn + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) mfma_16x16x4<T>(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < TJ; ++j) mfma_16x16x4(a[i], b[j], acc[i][j]);
     }
+    if (more) store(cur ^ 1);
     __syncthreads();
   }
 
-  // ---- epilogue: C (+)= acc
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // FP64 16x16x4 keeps C[l/16 + 4r][l%16] in register r of lane l; FP32 keeps C[4(l/16) + r][l%16]
         const int gi = m0 + wm + i * 16 + (std::is_same<T, double>::value ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r);
         const int gn = n0 + wn + j * 16 + (lane & 15);
         if (gi < M && gn < N) {
@@ -143,115 +175,128 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
 }
 
 // ------------------------------------------------------------------ bf16x3
-// Operands are packed pairs: the low 16 bits hold hi (bf16), the high 16 bits
-// hold lo = bf16(x - hi).  K advances in steps of 32 (one MFMA 16x16x32).
+// Operands in memory are packed pairs: bits 0..15 hold hi = bf16(x), bits
+// 16..31 hold lo = bf16(x - hi).  In LDS they are split into hi and lo planes
+// stored [row][k] (k contiguous), so that one 16-byte read gives a lane its
+// eight consecutive k values of one plane.  Tile 128 x 128, K-slab 32, 2 x 2
+// waves of 64 x 64 (4 x 4 MFMA tiles); the next slab is prefetched into
+// registers during the MFMAs.  Used for the H_eff GEMMs (MODE 0 and 1).
 
-constexpr int BK3 = 32, LDS3 = 33;
-
-__device__ __forceinline__ uint32_t ld_pair(const uint32_t* p) { return *p; }
+constexpr int B3M = 128, B3N = 128, B3K = 32, B3LD = B3K + 8;   // LDS row stride in bf16 (80 bytes)
 
 template <int MODE>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __restrict__ tasks, int ntask,
                                                           void* const* __restrict__ bases,
-                                                          const int32_t* __restrict__ active) {
-  // LDS tiles kept as [row][k] so that each lane reads 8 consecutive k values.
-  __shared__ uint32_t As[BM][LDS3];
-  __shared__ uint32_t Bs[BN][LDS3];
-
-  const int tile = blockIdx.x;
+                                                          const int32_t* __restrict__ active, int ntiles) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[B3M * B3LD], Al[B3M * B3LD], Bh[B3N * B3LD], Bl[B3N * B3LD];
+  const int tile = xcd_tile(ntiles);
+  if (tile < 0) return;
   const GemmTask& tk = tasks[find_task(tasks, ntask, tile)];
   if (active && !active[tk.prob]) return;
   const int local = tile - tk.tile0;
-  const int m0 = (local / tk.tiles_n) * BM;
-  const int n0 = (local % tk.tiles_n) * BN;
+  const int m0 = (local / tk.tiles_n) * B3M;
+  const int n0 = (local % tk.tiles_n) * B3N;
   const int M = tk.M, N = tk.N, K = tk.K;
-  const uint32_t* __restrict__ A =
-      reinterpret_cast<const uint32_t*>(bases[tk.prob * kNumBases + tk.abase]) + tk.aoff;
-  const uint32_t* __restrict__ B =
-      reinterpret_cast<const uint32_t*>(bases[tk.prob * kNumBases + tk.bbase]) + tk.boff;
+  const uint32_t* __restrict__ A = reinterpret_cast<const uint32_t*>(bases[tk.prob * kNumBases + tk.abase]) + tk.aoff;
+  const uint32_t* __restrict__ B = reinterpret_cast<const uint32_t*>(bases[tk.prob * kNumBases + tk.bbase]) + tk.boff;
   float* __restrict__ C = reinterpret_cast<float*>(bases[tk.prob * kNumBases + tk.cbase]) + tk.coff;
   const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
 
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int wave = t >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-
-  v4f acc[2][2];
+  // A slab [128 x 32]: thread t takes row t/2, k = (t%2)*16 .. +15 (A row-major in both modes).
+  const int ar = t >> 1, ak = (t & 1) * 16;
+  // B slab: MODE 1 (B given [N x K]): row n = t/2, k = (t%2)*16..; MODE 0 ([K x N]): k = t/8, n = (t%8)*16..
+  const int br = MODE == 1 ? t >> 1 : t >> 3;
+  const int bc = MODE == 1 ? (t & 1) * 16 : (t & 7) * 16;
+  uint32_t ra[16], rb[16];
+  auto load = [&](int k0) {
+    const int gi = m0 + ar, ci = gi < M ? gi : M - 1;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0, 0, 0, 0};
-
-  for (int k0 = 0; k0 < K; k0 += BK3) {
-    // A tile [64 x 32]: 2048 pairs, 8 per thread
-    if (MODE == 2) {
-      const int k = t >> 3, mq = (t & 7) * 8;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gi = m0 + mq + e, gk = k0 + k;
-        As[mq + e][k] = (gi < M && gk < K) ? ld_pair(A + (int64_t)gk * lda + gi) : 0u;
-      }
-    } else {
-      const int i = t >> 2, kq = (t & 3) * 8;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gi = m0 + i, gk = k0 + kq + e;
-        As[i][kq + e] = (gi < M && gk < K) ? ld_pair(A + (int64_t)gi * lda + gk) : 0u;
-      }
+    for (int e = 0; e < 16; ++e) {
+      const int gk = k0 + ak + e, ck = gk < K ? gk : K - 1;
+      const uint32_t v = A[(int64_t)ci * lda + ck];
+      ra[e] = (gi < M && gk < K) ? v : 0u;
     }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      int gn, gk;
+      if (MODE == 1) { gn = n0 + br; gk = k0 + bc + e; } else { gk = k0 + br; gn = n0 + bc + e; }
+      const int cn = gn < N ? gn : N - 1, ck = gk < K ? gk : K - 1;
+      const uint32_t v = MODE == 1 ? B[(int64_t)cn * ldb + ck] : B[(int64_t)ck * ldb + cn];
+      rb[e] = (gn < N && gk < K) ? v : 0u;
+    }
+  };
+  auto store = [&]() {
+    // A: 16 consecutive k of row ar -> two 16-byte writes per plane
+    uint32_t h[8], l[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      h[e] = (ra[2 * e] & 0xffffu) | (ra[2 * e + 1] << 16);
+      l[e] = (ra[2 * e] >> 16) | (ra[2 * e + 1] & 0xffff0000u);
+    }
+    *reinterpret_cast<v4u*>(&Ah[ar * B3LD + ak]) = v4u{h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<v4u*>(&Ah[ar * B3LD + ak + 8]) = v4u{h[4], h[5], h[6], h[7]};
+    *reinterpret_cast<v4u*>(&Al[ar * B3LD + ak]) = v4u{l[0], l[1], l[2], l[3]};
+    *reinterpret_cast<v4u*>(&Al[ar * B3LD + ak + 8]) = v4u{l[4], l[5], l[6], l[7]};
     if (MODE == 1) {
-      const int n = t >> 2, kq = (t & 3) * 8;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int gn = n0 + n, gk = k0 + kq + e;
-        Bs[n][kq + e] = (gn < N && gk < K) ? ld_pair(B + (int64_t)gn * ldb + gk) : 0u;
+        h[e] = (rb[2 * e] & 0xffffu) | (rb[2 * e + 1] << 16);
+        l[e] = (rb[2 * e] >> 16) | (rb[2 * e + 1] & 0xffff0000u);
       }
+      *reinterpret_cast<v4u*>(&Bh[br * B3LD + bc]) = v4u{h[0], h[1], h[2], h[3]};
+      *reinterpret_cast<v4u*>(&Bh[br * B3LD + bc + 8]) = v4u{h[4], h[5], h[6], h[7]};
+      *reinterpret_cast<v4u*>(&Bl[br * B3LD + bc]) = v4u{l[0], l[1], l[2], l[3]};
+      *reinterpret_cast<v4u*>(&Bl[br * B3LD + bc + 8]) = v4u{l[4], l[5], l[6], l[7]};
     } else {
-      const int k = t >> 3, nq = (t & 7) * 8;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gn = n0 + nq + e, gk = k0 + k;
-        Bs[nq + e][k] = (gn < N && gk < K) ? ld_pair(B + (int64_t)gk * ldb + gn) : 0u;
+      for (int e = 0; e < 16; ++e) {
+        Bh[(bc + e) * B3LD + br] = (uint16_t)(rb[e] & 0xffffu);
+        Bl[(bc + e) * B3LD + br] = (uint16_t)(rb[e] >> 16);
       }
     }
+  };
+
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+
+  const int kb = 8 * (lane >> 4);
+  if (K > 0) load(0);
+  for (int k0 = 0; k0 < K; k0 += B3K) {
+    store();
     __syncthreads();
-    const int kb = 8 * (lane >> 4);
-    v8bf ahi[2], alo[2], bhi[2], blo[2];
+    if (k0 + B3K < K) load(k0 + B3K);
+    v8bf ah[4], al[4], bh[4], bl[4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const uint32_t* row = &As[wm + i * 16 + (lane & 15)][kb];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t pr = row[e];
-        ahi[i][e] = __builtin_bit_cast(__bf16, (uint16_t)(pr & 0xffffu));
-        alo[i][e] = __builtin_bit_cast(__bf16, (uint16_t)(pr >> 16));
-      }
+    for (int i = 0; i < 4; ++i) {
+      const int row = wm + i * 16 + (lane & 15);
+      ah[i] = *reinterpret_cast<const v8bf*>(&Ah[row * B3LD + kb]);
+      al[i] = *reinterpret_cast<const v8bf*>(&Al[row * B3LD + kb]);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const uint32_t* row = &Bs[wn + j * 16 + (lane & 15)][kb];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t pr = row[e];
-        bhi[j][e] = __builtin_bit_cast(__bf16, (uint16_t)(pr & 0xffffu));
-        blo[j][e] = __builtin_bit_cast(__bf16, (uint16_t)(pr >> 16));
-      }
+    for (int j = 0; j < 4; ++j) {
+      const int row = wn + j * 16 + (lane & 15);
+      bh[j] = *reinterpret_cast<const v8bf*>(&Bh[row * B3LD + kb]);
+      bl[j] = *reinterpret_cast<const v8bf*>(&Bl[row * B3LD + kb]);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhi[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blo[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhi[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gi = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
@@ -265,25 +310,38 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
 
 }  // namespace
 
+template <typename T, int BM, int BN>
+static void launch_tile(int mode, dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask, void* const* bases,
+                        const int32_t* active, int ntiles) {
+  if (mode == 0)
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, 0, BM, BN>), grid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
+  else if (mode == 1)
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, 1, BM, BN>), grid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
+  else
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, 2, BM, BN>), grid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
+}
+
+template <typename T>
+static void launch_t(int tiling, int mode, dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask,
+                     void* const* bases, const int32_t* active, int ntiles) {
+  switch (tiling) {
+    case 1: launch_tile<T, 128, 64>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+    case 2: launch_tile<T, 64, 128>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+    case 3: launch_tile<T, 128, 128>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+    default: launch_tile<T, 64, 64>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+  }
+}
+
 void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntiles, void* const* bases,
-                 const int32_t* active, hipStream_t s) {
+                 const int32_t* active, hipStream_t s, int tiling) {
   if (ntask == 0 || ntiles == 0) return;
-  dim3 grid(ntiles), block(256);
+  dim3 grid(kXcd * ((ntiles + kXcd - 1) / kXcd)), block(256);
   switch (prec) {
-    case Prec::F64:
-      if (mode == 0) hipLaunchKernelGGL((gemm_mfma_kernel<double, 0>), grid, block, 0, s, tasks, ntask, bases, active);
-      else if (mode == 1) hipLaunchKernelGGL((gemm_mfma_kernel<double, 1>), grid, block, 0, s, tasks, ntask, bases, active);
-      else hipLaunchKernelGGL((gemm_mfma_kernel<double, 2>), grid, block, 0, s, tasks, ntask, bases, active);
-      break;
-    case Prec::F32:
-      if (mode == 0) hipLaunchKernelGGL((gemm_mfma_kernel<float, 0>), grid, block, 0, s, tasks, ntask, bases, active);
-      else if (mode == 1) hipLaunchKernelGGL((gemm_mfma_kernel<float, 1>), grid, block, 0, s, tasks, ntask, bases, active);
-      else hipLaunchKernelGGL((gemm_mfma_kernel<float, 2>), grid, block, 0, s, tasks, ntask, bases, active);
-      break;
+    case Prec::F64: launch_t<double>(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+    case Prec::F32: launch_t<float>(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;
     case Prec::BF16X3:
-      if (mode == 0) hipLaunchKernelGGL((gemm_bf16x3_kernel<0>), grid, block, 0, s, tasks, ntask, bases, active);
-      else if (mode == 1) hipLaunchKernelGGL((gemm_bf16x3_kernel<1>), grid, block, 0, s, tasks, ntask, bases, active);
-      else hipLaunchKernelGGL((gemm_bf16x3_kernel<2>), grid, block, 0, s, tasks, ntask, bases, active);
+      if (mode == 0) hipLaunchKernelGGL((gemm_bf16x3_kernel<0>), grid, block, 0, s, tasks, ntask, bases, active, ntiles);
+      else hipLaunchKernelGGL((gemm_bf16x3_kernel<1>), grid, block, 0, s, tasks, ntask, bases, active, ntiles);
       break;
   }
 }

@@ -104,12 +104,15 @@ struct InvalidArg {
 
 enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
-// Grouped GEMM over `ntask` tasks with `ntiles` total tiles (tile 64 x 64).
+// Grouped GEMM over `ntask` tasks with `ntiles` total tiles.  tiling selects the
+// tile of the FP64/FP32 kernel: 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 128x128
+// (the split-bf16 kernel always uses 64x64); tile0/tiles_n of the tasks must
+// have been computed for that tile.
 // mode: 0 = NN, 1 = NT, 2 = TN.  Element type chosen by prec:
 //   F64: double A, B, C;  F32: float A, B, C;  BF16X3: packed (hi,lo) bf16 A, B, float C.
 // `active` (nullable) holds one flag per problem; tasks of inactive problems exit at once.
 void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntiles,
-                 void* const* bases, const int32_t* active, hipStream_t s);
+                 void* const* bases, const int32_t* active, hipStream_t s, int tiling = 0);
 
 // Mix over tasks; tin/tout element types: 0 = double, 1 = float, 2 = packed bf16 pair (output only).
 void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int ntask, int ntiles,
@@ -167,7 +170,7 @@ constexpr int kLzMaxK = 1024;    // upper bound of k_max (tridiagonal kept in LD
 void lz_init(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s);
 void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* active, double* alpha, double* beta,
                        double* ritz, double* coef, double* partial, int kmax, double tol_E, double tol_res,
-                       hipStream_t s);
+                       double tol_first, double rel_first, hipStream_t s);
 void lz_finish(int P, const LzProblem* probs, LzCtrl* ctrl, double* ritz, double* partial, int kmax, hipStream_t s);
 void lz_residual(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s);
 

@@ -91,9 +91,10 @@ __global__ __launch_bounds__(TB) void k_finalize(LzCtrl* ctrl, const int32_t* ac
   }
 }
 
-// v = Q[0] = psi / norm0
+// v = Q[0] = psi / norm0   (problems with kcap == 0 sit this run out)
 __global__ __launch_bounds__(TB) void k_start(const LzProblem* probs, const LzCtrl* ctrl) {
   const int p = blockIdx.y;
+  if (ctrl[p].kcap == 0) return;
   const LzProblem pr = probs[p];
   const double inv = 1.0 / ctrl[p].norm0;
   for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
@@ -180,7 +181,8 @@ __device__ int sturm_count(const double* a, const double* b, int k, double x, do
 // Eigenvector: inverse iteration with the shift just below the eigenvalue,
 // where T - sigma I is positive definite and its LDL^T needs no pivoting.
 __global__ __launch_bounds__(64) void k_tridiag(LzCtrl* ctrl, int32_t* active, const double* alpha, double* beta,
-                                                double* ritz, int kmax, double tol_E, double tol_res) {
+                                                double* ritz, int kmax, double tol_E, double tol_res,
+                                                double tol_first, double rel_first) {
   __shared__ double a[1024], b[1024], dd[1024], ll[1024], y[1024];
   __shared__ double s_lo, s_hi;
   const int p = blockIdx.x;
@@ -256,8 +258,15 @@ __global__ __launch_bounds__(64) void k_tridiag(LzCtrl* ctrl, int32_t* active, c
     LzCtrl& c = ctrl[p];
     const double res = bnew * fabs(y[k - 1]);
     const bool have_prev = k > 1;
-    const bool stop_dtheta = have_prev && fabs(theta - c.theta_prev) <= tol_E && res <= tol_res;
-    const bool stop_inv = bnew <= 1e-14 * fabs(theta);
+    // rel_first > 0 (a refinement pass): stop once the residual estimate is
+    // rel_first times the exact residual beta_0 of the pass's start vector.
+    const bool stop_dtheta = rel_first > 0.0
+                                 ? (have_prev && res <= rel_first * beta[(int64_t)p * kmax])
+                                 : (have_prev && fabs(theta - c.theta_prev) <= tol_E && res <= tol_res);
+    // tol_first > 0: the first step used an FP64 matvec, so alpha_0 is the exact
+    // Rayleigh quotient of the start vector and beta_0 its exact residual norm.
+    const bool stop_first = k == 1 && tol_first > 0.0 && bnew <= tol_first;
+    const bool stop_inv = bnew <= 1e-14 * fabs(theta) || stop_first;
     c.theta = theta;
     for (int i = 0; i < k; ++i) ritz[(int64_t)p * kmax + i] = y[i];
     if (stop_dtheta || stop_inv || k >= c.kcap) {
@@ -295,6 +304,7 @@ __global__ __launch_bounds__(TB) void k_next(const LzProblem* probs, const LzCtr
 // psi = sum_{i < iters} y_i Q[i]
 __global__ __launch_bounds__(TB) void k_ritz(const LzProblem* probs, const LzCtrl* ctrl, const double* ritz, int kmax) {
   const int p = blockIdx.y;
+  if (ctrl[p].kcap == 0) return;
   const LzProblem pr = probs[p];
   const int k = ctrl[p].iters;
   const double* y = ritz + (int64_t)p * kmax;
@@ -308,6 +318,7 @@ __global__ __launch_bounds__(TB) void k_ritz(const LzProblem* probs, const LzCtr
 // psi /= norm0 ; v = psi (input of the residual matvec)
 __global__ __launch_bounds__(TB) void k_normalize_psi(const LzProblem* probs, const LzCtrl* ctrl) {
   const int p = blockIdx.y;
+  if (ctrl[p].kcap == 0) return;
   const LzProblem pr = probs[p];
   const double inv = 1.0 / ctrl[p].norm0;
   for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
@@ -349,7 +360,7 @@ void lz_init(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int k
 
 void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* active, double* alpha, double* beta,
                        double* ritz, double* coef, double* partial, int kmax, double tol_E, double tol_res,
-                       hipStream_t s) {
+                       double tol_first, double rel_first, hipStream_t s) {
   // alpha_j = <v, w>
   hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)active, 0, 1,
                      partial, kmax);
@@ -368,7 +379,7 @@ void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* act
                      kmax);
   hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)active, partial, alpha, kmax, 1);
   hipLaunchKernelGGL(k_tridiag, dim3(P), dim3(64), 0, s, ctrl, active, (const double*)alpha, beta, ritz, kmax, tol_E,
-                     tol_res);
+                     tol_res, tol_first, rel_first);
   hipLaunchKernelGGL(k_next, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, (const int32_t*)active,
                      (const double*)beta, kmax);
 }

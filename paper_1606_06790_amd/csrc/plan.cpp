@@ -188,10 +188,51 @@ IsoLayout V_layout(const Leg& B, const std::vector<int>& qp, const Leg& C) {
 
 void GemmList::add(GemmTask g) {
   if (g.M <= 0 || g.N <= 0) return;
-  g.tiles_n = (g.N + 63) / 64;
+  g.tiles_n = (g.N + tn - 1) / tn;
   g.tile0 = tiles;
-  tiles += ((g.M + 63) / 64) * g.tiles_n;
+  tiles += ((g.M + tm - 1) / tm) * g.tiles_n;
   t.push_back(g);
+}
+
+void GemmList::retile(int tm_, int tn_) {
+  tm = tm_;
+  tn = tn_;
+  tiles = 0;
+  for (auto& g : t) {
+    g.tiles_n = (g.N + tn - 1) / tn;
+    g.tile0 = tiles;
+    tiles += ((g.M + tm - 1) / tm) * g.tiles_n;
+  }
+}
+
+double GemmList::efficiency(int tm_, int tn_) const {
+  double use = 0, pad = 0;
+  for (const auto& g : t) {
+    const double k = std::max(g.K, 1);
+    use += (double)g.M * g.N * k;
+    pad += (double)((g.M + tm_ - 1) / tm_) * tm_ * ((g.N + tn_ - 1) / tn_) * tn_ * k;
+  }
+  return pad > 0 ? use / pad : 1.0;
+}
+
+void GemmList::choose_tile(bool allow_large) {
+  int bm = 64, bn = 64;
+  if (allow_large) {
+    const double e0 = efficiency(64, 64);
+    double best = 64 * 64 * e0;
+    const int cand[3][2] = {{128, 64}, {64, 128}, {128, 128}};
+    for (const auto& c : cand) {
+      const double e = efficiency(c[0], c[1]);
+      // a bigger tile halves operand traffic per flop; accept it unless padding eats that gain
+      const double score = c[0] * c[1] * e;
+      if (e >= 0.8 * e0 && score > best) {
+        best = score;
+        bm = c[0];
+        bn = c[1];
+      }
+    }
+  }
+  retile(bm, bn);
 }
 
 double GemmList::flops() const {

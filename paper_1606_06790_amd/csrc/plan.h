@@ -85,8 +85,14 @@ IsoLayout V_layout(const Leg& B, const std::vector<int>& qp, const Leg& C);
 struct GemmList {
   std::vector<GemmTask> t;
   int tiles = 0;
+  int tm = 64, tn = 64;              // output tile of the kernel variant
   void add(GemmTask g);              // fills tile0 / tiles_n
   double flops() const;
+  void retile(int tm_, int tn_);     // recompute tile0 / tiles_n / tiles for another tile
+  int tiling() const { return (tm == 128 ? 1 : 0) + (tn == 128 ? 2 : 0); }
+  // fraction of MFMA work that is not padding, for tile tm_ x tn_
+  double efficiency(int tm_, int tn_) const;
+  void choose_tile(bool allow_large);  // picks the largest tile whose padding costs little
 };
 
 struct MixList {

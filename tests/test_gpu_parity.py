@@ -247,3 +247,47 @@ def test_errors_are_reported(ctx):
     # k_max = 2 cannot converge: a warning, with the best Ritz pair returned
     es, infos = lib.lanczos_solve_batch(ctx, [good], [T(workloads.gaussian(n, 50, 9))], k_max=2)
     assert infos[0]["warn"] == lib.WARN_NOCONV and infos[0]["iters"] == 2 and np.isfinite(es[0])
+
+
+# ----------------------------------------------------------------- mixed precision
+
+MIXED_TOL = {"f32": 5e-6, "bf16x3": 5e-5}   # max |y - y_64| / max |y_64| of one matvec
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_heff_apply_mixed(ctx, prec):
+    """Low-precision matvec policies against the FP64 oracle, relative to the output's magnitude."""
+    cases = [_heff_case("chain", "ragged", 71), _heff_case("yc8", "wide", 72)]
+    ys = [T(np.zeros(len(c[2]))) for c in cases]
+    lib.heff_apply(ctx, [c[0] for c in cases], [T(c[1]) for c in cases], ys, prec)
+    for (p, x, y), yg in zip(cases, ys):
+        err = rel_err(H(yg), y)
+        assert err <= MIXED_TOL[prec], err
+        assert err >= 1e-9          # the policy really computed in low precision
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_lanczos_mixed_refined(ctx, prec):
+    """Mixed-precision Lanczos with FP64-anchored refinement: the energy is an FP64
+    Rayleigh quotient with FP64 residual <= tol_res, so it matches the oracle to 1e-12."""
+    cfg, r = _oracle_states("random_chain", 32, 7, tol_res=1e-10)
+    sts = [st for st in r["states"] if st["n"] in (6, 7)]
+    probs = [_flat_problem(st) for st in sts]
+    psis = [T(st["v0"]) for st in sts]
+    es, infos = lib.lanczos_solve_batch(ctx, probs, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"], prec)
+    steps = {(s["n"], s["i"]): s for s in r["steps"]}
+    for st, e, inf, p in zip(sts, es, infos, psis):
+        assert abs(e - steps[(st["n"], st["i"])]["energy"]) <= 1e-12
+        assert abs(abs(float(H(p) @ st["psi"])) - 1.0) <= 1e-11
+        assert inf["converged"] == 1 and inf["residual"] <= cfg["tol_res"]
+        assert inf["fp64_matvecs"] >= 2
+
+
+def test_trajectory_chain_mixed():
+    """Uniform chain with the split-bf16 matvec and FP64 refinement: per-site energies
+    within 1e-9 of the FP64 oracle."""
+    cfg = workloads.workload("chain")
+    g = _run_gpu(cfg, 20, prec="bf16x3")
+    o = oidmrg.run(cfg, mode="u1", n_max=20)
+    for a, b in zip(g.steps, o["steps"]):
+        assert abs(a["e_site"] - b["e_site"]) <= 1e-9, (a, b)
