@@ -208,6 +208,8 @@ typedef struct {
     double eps;                /* discarded weight, Eq. (14) */
     double eps_prime;          /* best fidelity error, Eq. (13) */
     double cut_gap;            /* relative gap at the cut (-1 if no nonzero value was cut) */
+    int32_t svd_sweeps;        /* Jacobi sweeps run (the same for every problem of the call) */
+    int32_t svd_converged;     /* 1 if every block met the orthogonality tolerance */
 } idmrg_trunc;
 
 /* Psi = U Lambda V^dagger per centre charge (FP64 one-sided Jacobi SVD on the
@@ -216,7 +218,12 @@ typedef struct {
  * values exist, zero-weight states fill in ascending charge order; the cut is
  * moved up past values within deg_rel (relative) of the last kept one.
  * lambda is normalised over the full spectrum (sum lambda^2 = 1) and the
- * kept values are not renormalised.  Synchronises the stream. */
+ * kept values are not renormalised.  Singular vectors of values at most
+ * max(lam_floor, 1e-15) times their block's Frobenius norm are replaced by an
+ * orthonormal completion (they carry no reliable direction), so U and V are
+ * isometries to rounding in every case.  Synchronises the stream.  Returns
+ * IDMRG_WARN_NOCONV if the Jacobi sweeps did not converge (the result is
+ * still written and svd_converged is 0). */
 int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp, int32_t m_max,
                      double lam_floor, double deg_rel, idmrg_trunc* t);
 

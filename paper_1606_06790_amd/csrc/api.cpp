@@ -676,6 +676,7 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
     std::vector<Leg> A(P), B(P);
     std::vector<PsiLayout> X(P);
     int64_t nM = 0, nX = 0, nG = 0, nU = 0, nV = 0, nS = 0;
+    int svd_sweeps = 0, svd_conv = 1;
     MixList gather;
     std::vector<SvdTask> svd;
     std::vector<SelTask> sel;
@@ -792,6 +793,7 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
       int pmax = 1;
       for (const auto& sv : svd) pmax = std::max(pmax, std::max(sv.r, sv.c));
       scr.tol = std::max(1e-15, 4.4e-16 * std::sqrt((double)pmax));
+      scr.zero_rel = std::max(lam_floor, 1e-15);
       auto up = [&](const std::vector<char>& h) -> char* {
         char* d = (char*)ensure(ctx, ctx->ws[WS_READ], h.size());
         sync(ctx);
@@ -800,6 +802,8 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
       };
       bj_svd(svd, (void**)(dev + a6), (SvdTask*)(dev + a3), scr, s, up, [&]() { sync(ctx); });
       (void)a7;
+      svd_sweeps = scr.sweeps;
+      svd_conv = scr.converged;
     }
     {
       Prof pr(ctx, 6, 0.0);
@@ -858,6 +862,8 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
       t[p].eps_prime = hscal[4 * p + 1];
       t[p].cut_gap = hscal[4 * p + 2];
       t[p].m_kept = (int32_t)hscal[4 * p + 3];
+      t[p].svd_sweeps = svd_sweeps;
+      t[p].svd_converged = svd_conv;
     }
     {
       std::vector<int64_t> sz((size_t)P * kNumBases, -1);
@@ -884,6 +890,10 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
         ctx->err = "non-finite singular values";
         return IDMRG_ENUMERIC;
       }
+    if (!svd_conv) {
+      ctx->err = "Jacobi SVD did not converge in " + std::to_string(svd_sweeps) + " sweeps";
+      return IDMRG_WARN_NOCONV;
+    }
     return IDMRG_OK;
   });
 }

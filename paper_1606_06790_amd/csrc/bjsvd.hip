@@ -13,8 +13,16 @@
 //   3. replaces Y by Q^T Y and [G_I; G_J] by Q^T [G_I; G_J] with FP64 MFMA.
 // A pair whose rows are already orthogonal to the relative tolerance is left
 // alone; a sweep in which no pair of a matrix moved ends that matrix.
-// k_bj_finish then takes sigma_i = |X_i|, normalises Z and replaces exactly
-// zero rows by unit vectors orthogonalised against the others.
+//
+// Null rows: a row whose norm is at most zero_rel * |M|_F carries no
+// trustworthy direction (its singular value is below the truncation floor and
+// at the level of rounding in the other rows), and Jacobi rotations between
+// such a row and a large one can fail to converge (the rotation angle
+// underflows).  Pairs involving a null row are therefore left out of the
+// convergence test, and k_bj_finish replaces every null row of Z by a unit
+// vector orthogonalised (twice) against all other rows, keeping its norm as
+// the singular value.  This keeps every returned set of singular vectors
+// orthonormal, including the zero-weight states.
 #include "internal.h"
 
 #include <algorithm>
@@ -29,6 +37,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int BB = 32;          // rows per block
 constexpr int PB = 2 * BB;      // rows per pair
 constexpr int LD = PB + 1;      // LDS leading dimension
+constexpr int kBjMaxN = 4096;   // largest min(r, c) of one matrix (LDS arrays of k_bj_finish)
 
 struct BjMat {                  // one matrix (device)
   int32_t n, p, prob, pad;
@@ -98,7 +107,8 @@ __device__ __forceinline__ void store64(const v4d acc[2][2], F put) {
 
 __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ tasks, const BjMat* __restrict__ mats,
                                                  void* const* __restrict__ bases, const int32_t* __restrict__ done,
-                                                 int32_t* __restrict__ changed, double tol, int inner_sweeps) {
+                                                 int32_t* __restrict__ changed, const double* __restrict__ thr2,
+                                                 double tol, int inner_sweeps) {
   __shared__ double S[PB][LD];
   __shared__ double Q[PB][LD];
   __shared__ double Ta[16][LD];
@@ -130,14 +140,15 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
   for (int e = t; e < PB * PB; e += 256) Q[e / PB][e % PB] = (e / PB == e % PB) ? 1.0 : 0.0;
   if (t == 0) s_move = 0;
   __syncthreads();
-  // is any pair of rows coupled beyond the tolerance?
+  // is any pair of non-null rows coupled beyond the tolerance?
   {
+    const double z2 = thr2[tk.mat];
     bool mv = false;
     for (int e = t; e < PB * PB; e += 256) {
       const int i = e / PB, j = e % PB;
       if (i < j) {
-        const double sij = S[i][j];
-        if (sij != 0.0 && fabs(sij) > tol * sqrt(S[i][i] * S[j][j])) mv = true;
+        const double sij = S[i][j], sii = S[i][i], sjj = S[j][j];
+        if (sii > z2 && sjj > z2 && fabs(sij) > tol * sqrt(sii) * sqrt(sjj)) mv = true;
       }
     }
     if (mv) s_move = 1;
@@ -217,19 +228,28 @@ __global__ void k_bj_sweep_end(int nm, int32_t* done, int32_t* changed) {
   changed[m] = 0;
 }
 
-// X = M (r <= c) or M^T (r > c); G = I.  One workgroup per matrix.
-__global__ __launch_bounds__(256) void k_bj_init(const SvdTask* __restrict__ tasks, void* const* __restrict__ bases) {
+// X = M (r <= c) or M^T (r > c); G = I; thr2 = (zero_rel |M|_F)^2.  One workgroup per matrix.
+__global__ __launch_bounds__(256) void k_bj_init(const SvdTask* __restrict__ tasks, void* const* __restrict__ bases,
+                                                 double* __restrict__ thr2, double zero_rel) {
+  __shared__ double red[4];
   const SvdTask tk = tasks[blockIdx.x];
   const bool tr = tk.r > tk.c;
   const int n = tr ? tk.c : tk.r, p = tr ? tk.r : tk.c;
   const double* M = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 1]) + tk.m_off;
   double* X = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 2]) + tk.x_off;
   double* G = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 3]) + tk.g_off;
+  double a = 0.0;
   for (int64_t e = threadIdx.x; e < (int64_t)n * p; e += 256) {
     const int i = (int)(e / p), k = (int)(e % p);
-    X[e] = tr ? M[(int64_t)k * tk.c + i] : M[e];
+    const double v = tr ? M[(int64_t)k * tk.c + i] : M[e];
+    X[e] = v;
+    a += v * v;
   }
   for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) G[e] = (e / n == e % n) ? 1.0 : 0.0;
+  a = wsum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) thr2[blockIdx.x] = zero_rel * zero_rel * (((red[0] + red[1]) + red[2]) + red[3]);
 }
 
 __device__ double block_norm2(const double* z, int p, double* red) {
@@ -245,12 +265,14 @@ __device__ double block_norm2(const double* z, int p, double* red) {
   return s;
 }
 
-// sigma_i = |X_i|, Z_i = X_i / sigma_i; rows of (numerically) zero norm become
-// unit vectors orthogonalised (twice) against all other rows; then the
-// singular vectors are written as U_full [r x n] and V_full [c x n].
-__global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ tasks, void* const* __restrict__ bases) {
+// sigma_i = |X_i|, Z_i = X_i / sigma_i; null rows (|X_i|^2 <= thr2) are zeroed
+// and then become unit vectors orthogonalised (twice) against all other rows;
+// then the singular vectors are written as U_full [r x n] and V_full [c x n].
+__global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ tasks, void* const* __restrict__ bases,
+                                                    const double* __restrict__ thr2) {
   __shared__ double red[16];
-  __shared__ double coef[4096];
+  __shared__ double coef[kBjMaxN];
+  __shared__ unsigned char nul[kBjMaxN];
   const SvdTask tk = tasks[blockIdx.x];
   const int r = tk.r, c = tk.c;
   const bool tr = r > c;
@@ -261,21 +283,26 @@ __global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ 
   double* Vf = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 5]) + tk.v_off;
   double* S = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 6]) + tk.s_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const double z2 = thr2[blockIdx.x];
   for (int i = wave; i < n; i += 16) {
     double* xi = X + (int64_t)i * p;
     double a = 0.0;
     for (int k = lane; k < p; k += 64) a += xi[k] * xi[k];
     a = wsum(a);
     const double sg = sqrt(a);
-    const bool zero = !(sg > 1e-150);
-    if (lane == 0) S[i] = zero ? 0.0 : sg;
-    const double inv = zero ? 0.0 : 1.0 / sg;
+    const bool tiny = !(sg > 1e-150);
+    const bool null_row = tiny || !(a > z2);
+    if (lane == 0) {
+      S[i] = tiny ? 0.0 : sg;
+      nul[i] = null_row ? 1 : 0;
+    }
+    const double inv = null_row ? 0.0 : 1.0 / sg;
     for (int k = lane; k < p; k += 64) xi[k] *= inv;
   }
   __syncthreads();
   int next_unit = 0;
   for (int i = 0; i < n; ++i) {
-    if (S[i] > 0.0) continue;           // uniform: S is global and was synchronised
+    if (!nul[i]) continue;              // uniform: nul is in LDS and was synchronised
     double* zi = X + (int64_t)i * p;
     bool ok = false;
     while (!ok && next_unit < p) {
@@ -355,25 +382,33 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
   for (size_t r = 0; r < rounds.size(); ++r) ornd[r] = put(rounds[r].data(), rounds[r].size() * sizeof(BjTask));
   std::vector<int32_t> zeros(2 * (size_t)nm, 0);
   const size_t oflags = put(zeros.data(), zeros.size() * 4);
+  std::vector<double> zthr(nm, 0.0);
+  const size_t othr = put(zthr.data(), zthr.size() * 8);
   char* dev = upload(host);
   const BjMat* dmats = (const BjMat*)(dev + omats);
   int32_t* done = (int32_t*)(dev + oflags);
   int32_t* changed = done + nm;
-  hipLaunchKernelGGL(k_bj_init, dim3(nm), dim3(256), 0, s, dtasks, dbases);
+  double* thr2 = (double*)(dev + othr);
+  hipLaunchKernelGGL(k_bj_init, dim3(nm), dim3(256), 0, s, dtasks, dbases, thr2, scr.zero_rel);
   std::vector<int32_t> hdone(nm);
   int sweeps = 0;
+  scr.converged = 0;
   for (; sweeps < scr.max_sweeps; ++sweeps) {
     for (size_t r = 0; r < rounds.size(); ++r)
       hipLaunchKernelGGL(k_bj_pair, dim3((unsigned)rounds[r].size()), dim3(256), 0, s, (const BjTask*)(dev + ornd[r]),
-                         dmats, dbases, (const int32_t*)done, changed, scr.tol, scr.inner_sweeps);
+                         dmats, dbases, (const int32_t*)done, changed, (const double*)thr2, scr.tol,
+                         scr.inner_sweeps);
     hipLaunchKernelGGL(k_bj_sweep_end, dim3((nm + 255) / 256), dim3(256), 0, s, nm, done, changed);
     if (hipMemcpyAsync(hdone.data(), done, nm * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
       throw HipFailure("hipMemcpyAsync of Jacobi flags failed");
     sync();
-    if (std::all_of(hdone.begin(), hdone.end(), [](int32_t v) { return v != 0; })) break;
+    if (std::all_of(hdone.begin(), hdone.end(), [](int32_t v) { return v != 0; })) {
+      scr.converged = 1;
+      break;
+    }
   }
-  scr.sweeps = sweeps + 1;
-  hipLaunchKernelGGL(k_bj_finish, dim3(nm), dim3(1024), 0, s, dtasks, dbases);
+  scr.sweeps = std::min(sweeps + 1, scr.max_sweeps);
+  hipLaunchKernelGGL(k_bj_finish, dim3(nm), dim3(1024), 0, s, dtasks, dbases, (const double*)thr2);
 }
 
 }  // namespace idmrg

@@ -131,10 +131,12 @@ void launch_svd(const SvdTask* tasks, int ntask, void* const* bases, int32_t* sw
 // upload() copies a host byte array to device memory and returns its address;
 // sync() waits for the stream (the host checks the sweep flags once per sweep).
 struct BjScratch {
-  double tol = 1e-15;
+  double tol = 1e-15;        // relative orthogonality of converged rows
+  double zero_rel = 1e-15;   // rows with norm <= zero_rel |M|_F are null rows
   int inner_sweeps = 3;
   int max_sweeps = 30;
-  int sweeps = 0;   // out
+  int sweeps = 0;            // out: sweeps run
+  int converged = 0;         // out: every matrix met the tolerance
 };
 void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask* dtasks, BjScratch& scr,
             hipStream_t s, const std::function<char*(const std::vector<char>&)>& upload,

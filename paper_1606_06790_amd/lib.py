@@ -67,7 +67,8 @@ class Trunc_t(C.Structure):
                 ("q_out", C.POINTER(C.c_int32)), ("dim_out", C.POINTER(C.c_int32)), ("U", C.c_void_p),
                 ("V", C.c_void_p), ("lambda_", C.c_void_p), ("cap_U", C.c_int64), ("cap_V", C.c_int64),
                 ("cap_lam", C.c_int64), ("nsec_out", C.c_int32), ("m_kept", C.c_int32), ("eps", C.c_double),
-                ("eps_prime", C.c_double), ("cut_gap", C.c_double)]
+                ("eps_prime", C.c_double), ("cut_gap", C.c_double), ("svd_sweeps", C.c_int32),
+                ("svd_converged", C.c_int32)]
 
 
 class EnvUpdate_t(C.Structure):
@@ -304,7 +305,7 @@ def lanczos_solve_batch(ctx, problems, psis, tol_E=1e-12, tol_res=1e-8, k_max=30
 
 def truncate_twosite(ctx, items, qp, m_max, lam_floor=1e-14, deg_rel=1e-5):
     """items: list of dict(left, right, psi).  Returns list of dict(C, U, V, lam, eps, eps_prime,
-    m_kept, cut_gap) with U, V, lam as new float64 device tensors."""
+    m_kept, cut_gap, svd_sweeps, svd_converged, warn) with U, V, lam as new float64 device tensors."""
     torch = _torch()
     k = _Keep()
     P = len(items)
@@ -326,8 +327,8 @@ def truncate_twosite(ctx, items, qp, m_max, lam_floor=1e-14, deg_rel=1e-5):
         bufs.append((U, V, lam, qo, do))
         arr[j] = Trunc_t(k.leg(A), k.leg(B), _ptr(it["psi"]), cap_sec, qo, do, C.c_void_p(U.data_ptr()),
                          C.c_void_p(V.data_ptr()), C.c_void_p(lam.data_ptr()), U.numel(), V.numel(),
-                         lam.numel(), 0, 0, 0.0, 0.0, 0.0)
-    _check(ctx, ctx.lib.truncate_twosite(ctx.handle, P, d, k.ints(qp), m_max, lam_floor, deg_rel, arr))
+                         lam.numel(), 0, 0, 0.0, 0.0, 0.0, 0, 0)
+    rc = _check(ctx, ctx.lib.truncate_twosite(ctx.handle, P, d, k.ints(qp), m_max, lam_floor, deg_rel, arr))
     out = []
     for j, it in enumerate(items):
         U, V, lam, qo, do = bufs[j]
@@ -336,7 +337,8 @@ def truncate_twosite(ctx, items, qp, m_max, lam_floor=1e-14, deg_rel=1e-5):
         nU, nV = U_size(it["left"], qp, Cleg), V_size(it["right"], qp, Cleg)
         m = sum(x for _, x in Cleg)
         out.append(dict(C=Cleg, U=U[:nU].clone(), V=V[:nV].clone(), lam=lam[:m].clone(), eps=t.eps,
-                        eps_prime=t.eps_prime, m_kept=t.m_kept, cut_gap=(None if t.cut_gap < 0 else t.cut_gap)))
+                        eps_prime=t.eps_prime, m_kept=t.m_kept, cut_gap=(None if t.cut_gap < 0 else t.cut_gap),
+                        svd_sweeps=t.svd_sweeps, svd_converged=bool(t.svd_converged), warn=rc))
     return out
 
 

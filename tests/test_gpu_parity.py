@@ -163,6 +163,66 @@ def test_truncate_twosite(ctx):
             assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-13
 
 
+def _graded_psi(seed):
+    """Two-site state of 9+9 spins (legs C(9,k)) whose centre blocks have low
+    rank k (values in [1e-3, 1]) and only k nonzero columns (as when the right
+    leg carries zero-weight states): each block is U diag(sigma) V^T with U
+    dense and V supported on k random columns.  The one-sided Jacobi iteration then has many more rows
+    than the dimension of their span, and the surplus rows decay to rounding
+    residue instead of reaching zero."""
+    from math import comb
+    A = [(2 * k - 9, comb(9, k)) for k in range(10)]
+    B = list(A)
+    psi = {}
+    for q, (rows, cols) in u1.center_sectors(A, B, QP).items():
+        r, c = sum(x[2] for x in rows), sum(x[2] for x in cols)
+        g = np.random.default_rng([seed, q + 100])
+        k = max(1, min(r, c) // 4)
+        Ur = np.linalg.qr(g.standard_normal((r, k)))[0]
+        Vr = np.zeros((c, k))
+        Vr[np.sort(g.choice(c, k, replace=False))] = np.linalg.qr(g.standard_normal((k, k)))[0]
+        sig = 10.0 ** g.uniform(-3, 0, k)
+        M = (Ur * sig) @ Vr.T
+        r0 = 0
+        for (qa, s1, da) in rows:
+            c0 = 0
+            for (s2, qb, db) in cols:
+                psi[(qa, s1, s2)] = M[r0:r0 + da, c0:c0 + db]
+                c0 += db
+            r0 += da
+    x = layout.psi_to_flat(psi, A, B, QP)
+    return A, B, x / np.linalg.norm(x)
+
+
+def test_truncate_graded_spectrum(ctx):
+    """Rows of the Jacobi iteration whose singular values are far below the
+    floor have no reliable direction; the returned U and V must still be
+    isometries, and the kept spectrum, kept legs and eps must equal the
+    oracle's (regression: such rows once came back non-orthogonal)."""
+    items, refs = [], []
+    for seed in (11, 12):
+        A, B, x = _graded_psi(seed)
+        items.append(dict(left=A, right=B, psi=T(x)))
+        refs.append((A, B, u1.truncate_twosite(layout.flat_to_psi(x, A, B, QP), A, B, QP, 512, 1e-14, 1e-5)))
+    out = lib.truncate_twosite(ctx, items, QP, 512, 1e-14, 1e-5)
+    for (A, B, tr), o in zip(refs, out):
+        assert o["svd_converged"] and o["warn"] == 0
+        assert o["C"] == tr["C"] and o["m_kept"] == tr["m_kept"]
+        assert abs(o["eps"] - tr["eps"]) <= 1e-14
+        lam = layout.flat_to_lam(H(o["lam"]), o["C"])
+        U = layout.flat_to_U(H(o["U"]), A, QP, o["C"])
+        V = layout.flat_to_V(H(o["V"]), B, QP, o["C"])
+        for q, k in o["C"]:
+            assert np.abs(lam[q] - tr["lam"][q]).max() <= 1e-13
+            Ug = np.concatenate([U[(a, s, q)] for (a, s, _) in layout.U_rows(A, QP, q)])
+            Vg = np.concatenate([V[(s, b, q)] for (s, b, _) in layout.V_rows(B, QP, q)])
+            assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-12
+            assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-12
+            real = lam[q] > 0
+            Uo = np.concatenate([tr["U"][(a, s, q)] for (a, s, _) in layout.U_rows(A, QP, q)])[:, tr["lam"][q] > 0]
+            assert np.abs(Ug[:, real] @ Ug[:, real].T - Uo @ Uo.T).max() <= 1e-10
+
+
 def _flat_problem(st):
     from paper_1606_06790_amd.lib import Mpo
     A, B = st["A"], st["B"]
