@@ -6,14 +6,20 @@ cell (6 superblocks per iteration), U(1) S^z blocks, m kept states (default
 iDMRG): the batched prediction, Lanczos solve, truncation and both
 environment updates of all six superblocks.
 
-Protocol: the chain of iterations is first grown (untimed) to n = prefill so
-that m is saturated, then `warmup` steps run untimed, then exactly `steps`
-steps are timed between two device synchronisations.  During the timed steps
-every library launch is bracketed by HIP events on the library's stream; the
-H_eff matvec throughput is the algorithmic flop count of the matvecs (from the
-U(1) block lists) divided by their summed kernel time.
+Protocol: the chain of iterations is grown (untimed, FP64) to n = prefill so
+that m is saturated, and that state is kept.  Then, for FP64 and for the
+mixed-precision matvec in turn, starting from the kept state: `warmup`
+steps untimed, then exactly `steps` steps timed between two device
+synchronisations.  Both precisions therefore solve the same iterations from
+the same state, which gives a like-for-like speed-up and the energy
+difference per result.  During the timed steps every library launch is
+bracketed by HIP events on the library's stream; the H_eff matvec throughput
+is the algorithmic flop count of the matvecs (from the U(1) block lists)
+divided by their summed kernel time.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line (value = matvec TFLOP/s of the mixed path, ms_per_step =
+its seconds per unit-cell step; the FP64 figures sit under "fp64").
+--gpus N with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -27,11 +33,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6}   # TFLOP/s, dense MFMA, MI355X
+# Dense MFMA peaks of MI355X (TFLOP/s).  The split-bf16 policy does three bf16
+# products per FP64-equivalent product, so its ceiling for algorithmic flops is
+# the bf16 peak / 3.
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0}
+MATVEC = ["heff_gemm1", "heff_gemm2", "heff_mix", "heff_gemm1_lo", "heff_gemm2_lo", "heff_mix_lo", "convert"]
 
 
-def cpu_baseline(d, budget_s=30.0):
-    """Time the oracle's H_eff matvec on superblock 1 of the current state (host cores)."""
+def cpu_baseline(d, budget_s=12.0):
+    """The oracle's H_eff matvec on superblock 1 of the current state (host cores), repeated for ~budget_s."""
     import numpy as np
     from threadpoolctl import threadpool_info
     from oracle import layout, u1
@@ -45,13 +55,54 @@ def cpu_baseline(d, budget_s=30.0):
     x = np.random.default_rng(0).standard_normal(layout.psi_size(A, B, W1.qp))
     psi = layout.flat_to_psi(x, A, B, W1.qp)
     flops, _ = lib.heff_work(h)
-    t0 = time.perf_counter()
-    u1.heff_apply(L, W1.w, W2.w, R, psi, A, B, W1.qp, dl, dr)
-    t = time.perf_counter() - t0
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        u1.heff_apply(L, W1.w, W2.w, R, psi, A, B, W1.qp, dl, dr)
+        reps += 1
+        t = time.perf_counter() - t0
+        if t >= budget_s:
+            break
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return dict(value=flops / t / 1e12, unit="TFLOP/s", cores=threads, kind="oracle",
-                sample=f"one H_eff matvec of superblock 1 at iteration {d.n + 1} "
-                       f"(N={layout.psi_size(A, B, W1.qp)}, {flops:.3e} flops, {t:.1f} s)")
+    return dict(value=round(reps * flops / t / 1e12, 6), unit="TFLOP/s", cores=threads, kind="oracle",
+                sample=f"{reps} H_eff matvec(s) of superblock 1 at iteration {d.n + 1} "
+                       f"(N={layout.psi_size(A, B, W1.qp)}, {flops:.3e} flops each) in {t:.1f} s")
+
+
+def timed(d, prec, steps, warmup):
+    """Run warmup + timed steps at one matvec precision; returns the measurements."""
+    import torch
+    d.prec = prec
+    for _ in range(warmup):
+        d.step()
+    d.ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        d.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = d.ctx.profile_get()
+    d.ctx.profile(False)
+    mv_fl = sum(prof[k][2] for k in MATVEC)
+    mv_ms = sum(prof[k][1] for k in MATVEC)
+    recs = [s for s in d.steps if s["n"] > d.n - steps]
+    return dict(prec=prec, ms_per_step=(t1 - t0) * 1e3 / steps, matvec_tflops=mv_fl / (mv_ms * 1e-3) / 1e12,
+                prof=prof, recs=recs)
+
+
+def gemm_roofline(r):
+    """Roofline entry for the H_eff GEMM kernel with the largest summed time in run r."""
+    prof = r["prof"]
+    lo = r["prec"] != "f64"
+    names = ["heff_gemm1_lo", "heff_gemm2_lo"] if lo else ["heff_gemm1", "heff_gemm2"]
+    name = max(names, key=lambda k: prof[k][1])
+    n, ms, fl = prof[name]
+    achieved = fl / (ms * 1e-3) / 1e12
+    stage = "stage 1 (L x psi)" if name.startswith("heff_gemm1") else "stage 2 (T x R^T)"
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(PEAK[r["prec"]], 1), "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK[r["prec"]], 4), "traffic": None,
+            "kernel": f"grouped H_eff GEMM {stage}, {r['prec']}", "launches": n,
+            "avg_launch_ms": round(ms / max(n, 1), 4)}
 
 
 def main():
@@ -59,68 +110,63 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prefill", type=int, default=11)
+    ap.add_argument("--prefill", type=int, default=23)
     ap.add_argument("--m", type=int, default=2048)
-    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16x3"])
+    ap.add_argument("--mixed", default="bf16x3", choices=["f32", "bf16x3"])
     ap.add_argument("--workload", default="yc8")
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU (one process, no collectives); use --gpus 1"}))
         sys.exit(2)
-    import torch
     import workloads
     from paper_1606_06790_amd.driver import IDMRG
 
     cfg = workloads.workload(a.workload, m=a.m)
-    d = IDMRG(cfg, prec=a.prec)
+    d = IDMRG(cfg, prec="f64")
     t_pre = time.perf_counter()
     while d.n < a.prefill:
         d.step()
-    for _ in range(a.warmup):
-        d.step()
     t_pre = time.perf_counter() - t_pre
-    d.ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    recs = [d.step() for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = d.ctx.profile_get()
-    d.ctx.profile(False)
-    ms_step = (t1 - t0) * 1e3 / a.steps
-    mv_fl = prof["heff_gemm1"][2] + prof["heff_gemm2"][2] + prof["heff_mix"][2]
-    mv_ms = prof["heff_gemm1"][1] + prof["heff_gemm2"][1] + prof["heff_mix"][1] + prof["convert"][1]
-    tflops = mv_fl / (mv_ms * 1e-3) / 1e12
-    g_fl = prof["heff_gemm1"][2] + prof["heff_gemm2"][2]
-    g_ms = prof["heff_gemm1"][1] + prof["heff_gemm2"][1]
-    g_launch = prof["heff_gemm1"][0] + prof["heff_gemm2"][0]
-    mult = 3.0 if a.prec == "bf16x3" else 1.0       # bf16 MFMA products per FP64-equivalent product
-    achieved = mult * g_fl / (g_ms * 1e-3) / 1e12
-    steps = [s for s in d.steps if s["n"] > d.n - a.steps]
+    snap = d.snapshot()
+    r64 = timed(d, "f64", a.steps, a.warmup)
+    d.restore(snap)
+    rmx = timed(d, a.mixed, a.steps, a.warmup)
+    e64 = {(s["n"], s["i"]): s["e_site"] for s in r64["recs"]}
+    de = [s["e_site"] - e64[(s["n"], s["i"])] for s in rmx["recs"]]
+
+    def summary(r):
+        return {"matvec_tflops": round(r["matvec_tflops"], 4), "ms_per_step": round(r["ms_per_step"], 2),
+                "lanczos_iters": [s["iters"] for s in r["recs"]],
+                "fp64_matvecs": [s["fp64_matvecs"] for s in r["recs"]],
+                "e_site": [round(s["e_site"], 12) for s in r["recs"]],
+                "residual_max": max(s["residual"] for s in r["recs"]),
+                "svd_sweeps": max(s["svd_sweeps"] for s in r["recs"]),
+                "roofline": gemm_roofline(r),
+                "breakdown_ms_per_step": {k: round(v[1] / a.steps, 2) for k, v in r["prof"].items() if v[0]}}
+
     out = {
         "metric": "H_eff matvec TFLOP/s + s per unit-cell step, kagome YC8 m=2048; mixed vs FP64",
-        "value": round(tflops, 4),
+        "value": round(rmx["matvec_tflops"], 4),
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_step, 2),
+        "ms_per_step": round(rmx["ms_per_step"], 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32+f64", "bf16x3": "bf16x3+f64"}[a.prec],
+        "dtype": f"{a.mixed}+f64",
         "data": "synthetic",
         "config": {"workload": f"{a.workload}_heisenberg_m{a.m}_u1", "superblocks": d.half,
-                   "iterations_timed": [r["n"] for r in recs], "prefill": a.prefill, "matvec_prec": a.prec},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[a.prec], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK[a.prec], 4), "traffic": None,
-                     "kernel": "grouped H_eff GEMM (stage 1 + stage 2)",
-                     "avg_launch_ms": round(g_ms / max(g_launch, 1), 4)},
-        "breakdown_ms_per_step": {k: round(v[1] / a.steps, 2) for k, v in prof.items()},
-        "lanczos_iters": [s["iters"] for s in steps],
-        "e_site": [round(s["e_site"], 10) for s in steps],
-        "residual_max": max(s["residual"] for s in steps),
+                   "iterations_timed": sorted({s["n"] for s in rmx["recs"]}), "prefill": a.prefill,
+                   "matvec_prec": a.mixed},
+        "roofline": gemm_roofline(rmx),
+        "mixed": summary(rmx),
+        "fp64": summary(r64),
+        "mixed_vs_fp64": {"speedup_step": round(r64["ms_per_step"] / rmx["ms_per_step"], 4),
+                          "speedup_matvec": round(rmx["matvec_tflops"] / r64["matvec_tflops"], 4),
+                          "e_site_diff_max": max(abs(x) for x in de)},
         "prefill_s": round(t_pre, 1),
     }
     if not a.no_cpu:

@@ -147,10 +147,12 @@ int idmrg_heff_work(const idmrg_heff* H, double* flops, double* bytes);
  * and returns, for one kernel class, the number of launches, their summed
  * duration (ms) and their summed algorithmic flops (FP64-equivalent
  * multiply-adds x 2).  Classes: 0 H_eff GEMM stage 1, 1 H_eff GEMM stage 2,
- * 2 H_eff mixing, 3 precision conversions, 4 Lanczos vector kernels,
- * 5 SVD, 6 truncation gather/select/scatter, 7 environment update,
- * 8 prediction.  idmrg_profile(ctx, 1) also clears the counters. */
-#define IDMRG_PROF_CLASSES 9
+ * 2 H_eff mixing (0-2 with FP64 arithmetic), 3 precision conversions,
+ * 4 Lanczos vector kernels, 5 SVD, 6 truncation gather/select/scatter,
+ * 7 environment update, 8 prediction, 9 H_eff GEMM stage 1, 10 H_eff GEMM
+ * stage 2, 11 H_eff mixing (9-11 with FP32 or split-bf16 arithmetic).
+ * idmrg_profile(ctx, 1) also clears the counters. */
+#define IDMRG_PROF_CLASSES 12
 int idmrg_profile(idmrg_ctx* ctx, int enable);
 int idmrg_profile_get(idmrg_ctx* ctx, int cls, int64_t* launches, double* ms, double* flops);
 

@@ -336,18 +336,19 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   const int tin = ex.prec == Prec::F64 ? 0 : 1;
   const int toutT = ex.prec == Prec::F64 ? 0 : (ex.prec == Prec::F32 ? 1 : 2);
   const int toutY = ex.prec == Prec::F64 ? 0 : 1;
+  const int lo = ex.prec == Prec::F64 ? 0 : 9;   // profile classes of the low-precision policies
   {
-    Prof pr(c, 0, ex.flops_g1);
+    Prof pr(c, lo + 0, ex.flops_g1);
     launch_gemm(ex.prec, 0, ex.g1, (int)ex.plan.g1.t.size(), ex.plan.g1.tiles, ex.bases, active, s,
                 ex.plan.g1.tiling());
   }
   {
-    Prof pr(c, 2, ex.flops_mix);
+    Prof pr(c, lo + 2, ex.flops_mix);
     launch_mix(tin, toutY, ex.mY, ex.sY, (int)ex.plan.mixY.t.size(), ex.plan.mixY.tiles, ex.bases, active, s);
     launch_mix(tin, toutT, ex.mT, ex.sT, (int)ex.plan.mixT.t.size(), ex.plan.mixT.tiles, ex.bases, active, s);
   }
   {
-    Prof pr(c, 1, ex.flops_g2);
+    Prof pr(c, lo + 1, ex.flops_g2);
     launch_gemm(ex.prec, 1, ex.g2, (int)ex.plan.g2.t.size(), ex.plan.g2.tiles, ex.bases, active, s,
                 ex.plan.g2.tiling());
   }

@@ -130,6 +130,17 @@ class IDMRG:
         return dict(n=n, seconds=t4 - t0, t_predict=t1 - t0, t_lanczos=t2 - t1, t_truncate=t3 - t2,
                     t_env=t4 - t3, iters=[inf["iters"] for inf in infos])
 
+    def snapshot(self):
+        """State after the last iteration (device tensors are never modified in place, so references suffice)."""
+        return dict(n=self.n, L=dict(self.L), R=dict(self.R), prev=dict(self.prev), lam2=dict(self.lam2),
+                    energies=dict(self.energies), e_g=dict(self.e_g), steps=list(self.steps))
+
+    def restore(self, snap):
+        self.n = snap["n"]
+        self.L, self.R = dict(snap["L"]), dict(snap["R"])
+        self.prev, self.lam2 = dict(snap["prev"]), dict(snap["lam2"])
+        self.energies, self.e_g, self.steps = dict(snap["energies"]), dict(snap["e_g"]), list(snap["steps"])
+
     def run(self, n_max):
         out = []
         while self.n < n_max:

@@ -27,7 +27,7 @@ EXPORTS = ["idmrg_create", "idmrg_destroy", "idmrg_set_stream", "idmrg_last_erro
            "heff_apply", "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction",
            "idmrg_profile", "idmrg_profile_get"]
 PROF_CLASSES = ["heff_gemm1", "heff_gemm2", "heff_mix", "convert", "lanczos_vec", "svd", "trunc_other", "env",
-                "predict"]
+                "predict", "heff_gemm1_lo", "heff_gemm2_lo", "heff_mix_lo"]
 
 
 class IdmrgError(RuntimeError):
