@@ -526,16 +526,18 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       check_dev(psi[p], N[p], 8, "psi");
     }
     // vectors: Q [kcap x N], w, v
-    std::vector<int64_t> kcap(P), qoff(P), woff(P), voff(P);
+    // every piece is a multiple of kLzAlign elements, so all rows start 2 KiB-aligned
+    std::vector<int64_t> kcap(P), qoff(P), woff(P), voff(P), ld(P);
     int64_t tot = 0;
     for (int p = 0; p < P; ++p) {
       kcap[p] = std::min<int64_t>(kmax, N[p]);
+      ld[p] = (N[p] + kLzAlign - 1) / kLzAlign * kLzAlign;
       qoff[p] = tot;
-      tot += kcap[p] * N[p] + 32;
+      tot += kcap[p] * ld[p];
       woff[p] = tot;
-      tot += N[p] + 32;
+      tot += ld[p];
       voff[p] = tot;
-      tot += N[p] + 32;
+      tot += ld[p];
     }
     double* V = (double*)ensure(ctx, ctx->ws[WS_LZ], tot * 8);
     const size_t nsm = (size_t)P * kmax;
@@ -553,7 +555,7 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     for (int p = 0; p < P; ++p) {
       vv[p] = V + voff[p];
       ww[p] = V + woff[p];
-      probs[p] = LzProblem{N[p], V + qoff[p], ww[p], vv[p], psi[p]};
+      probs[p] = LzProblem{N[p], ld[p], V + qoff[p], ww[p], vv[p], psi[p]};
     }
     // The FP64 plan is set up first: it needs the larger scratch, so the
     // low-precision plan set up afterwards never reallocates under it.

@@ -147,10 +147,11 @@ void launch_select(const SelTask* tasks, int ntask, const SelSector* secs, const
 
 // Lanczos vector kernels (batched over problems), see lanczos.hip
 struct LzProblem {
-  int64_t N;
-  double* Q;        // [kcap x N]
-  double* w;        // [N]
-  double* v;        // [N] current vector (matvec input)
+  int64_t N;        // elements of the two-site state
+  int64_t ld;       // padded length (multiple of kLzAlign): row stride of Q, length of w and v
+  double* Q;        // [kcap x ld], zero beyond N in every row
+  double* w;        // [ld] matvec output / work vector, zero beyond N
+  double* v;        // [ld] current vector (matvec input), zero beyond N
   double* psi;      // [N] caller's vector
 };
 
@@ -165,7 +166,8 @@ struct LzCtrl {     // device, one per problem
   double theta, theta_prev, beta_j, residual, norm0, overlap0, ynorm, pad2;
 };
 
-constexpr int kLzBlocks = 128;   // partial-sum blocks per problem
+constexpr int kLzBlocks = 512;   // partial-sum blocks per problem
+constexpr int kLzAlign = 256;    // padding unit of the Lanczos vectors (elements)
 constexpr int kLzMaxK = 1024;    // upper bound of k_max (tridiagonal kept in LDS)
 
 // ctrl[] and active[] are initialised by the host before lz_init.

@@ -9,10 +9,18 @@
 // problem in fixed positions, then one workgroup adds them in a fixed tree.
 //
 // Iteration j (current vector v = q_j, w = H q_j on entry):
-//   alpha_j = <q_j, w>;  w -= alpha_j q_j + beta_{j-1} q_{j-1}
-//   two passes of classical Gram-Schmidt against q_0..q_j (CGS2)
+//   c = Q^T w over q_0..q_j, alpha_j = c_j, w -= Q c   (first classical
+//       Gram-Schmidt pass; it contains the three-term step, since the
+//       coefficients of q_j and q_{j-1} are alpha_j and beta_{j-1})
+//   c = Q^T w, w -= Q c, |w|^2                          (second pass, CGS2)
 //   beta_j = |w|; lowest Ritz pair (theta, y) of T_{j+1}; stop test;
 //   otherwise q_{j+1} = w / beta_j.
+//
+// The basis rows, v and w have the padded length ld (a multiple of
+// kLzAlign elements, zero beyond N), so every block's element range starts on
+// a 16-byte boundary and the streaming kernels use 16-byte loads.  The
+// dot-product kernel keeps its block's slice of w in LDS and streams the
+// basis rows past it, so the basis is read once per pass and w once.
 #include "internal.h"
 
 namespace idmrg {
@@ -91,74 +99,121 @@ __global__ __launch_bounds__(TB) void k_finalize(LzCtrl* ctrl, const int32_t* ac
   }
 }
 
-// v = Q[0] = psi / norm0   (problems with kcap == 0 sit this run out)
+// v = Q[0] = psi / norm0 and zero padding of v, Q[0], w beyond N
+// (problems with kcap == 0 sit this run out)
 __global__ __launch_bounds__(TB) void k_start(const LzProblem* probs, const LzCtrl* ctrl) {
   const int p = blockIdx.y;
   if (ctrl[p].kcap == 0) return;
   const LzProblem pr = probs[p];
   const double inv = 1.0 / ctrl[p].norm0;
-  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
-    const double x = pr.psi[n] * inv;
+  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.ld; n += (int64_t)gridDim.x * TB) {
+    const double x = n < pr.N ? pr.psi[n] * inv : 0.0;
     pr.v[n] = x;
     pr.Q[n] = x;
+    if (n >= pr.N) pr.w[n] = 0.0;
   }
 }
 
-// w -= alpha_j v + beta_{j-1} Q[j-1]
-__global__ __launch_bounds__(TB) void k_three_term(const LzProblem* probs, const LzCtrl* ctrl, const int32_t* active,
-                                                   const double* alpha, const double* beta, int kmax) {
-  const int p = blockIdx.y;
-  if (!active[p]) return;
-  const LzProblem pr = probs[p];
-  const int j = ctrl[p].j;
-  const double a = alpha[(int64_t)p * kmax + j];
-  const double bm = j > 0 ? beta[(int64_t)p * kmax + j - 1] : 0.0;
-  const double* qm = j > 0 ? pr.Q + (int64_t)(j - 1) * pr.N : pr.Q;
-  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB)
-    pr.w[n] -= a * pr.v[n] + bm * qm[n];
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// Element range [lo, hi) of block b over a padded vector of length ld.
+__device__ __forceinline__ void pad_range(int64_t ld, int b, int64_t& lo, int64_t& hi) {
+  int64_t per = (ld + kLzBlocks - 1) / kLzBlocks;
+  per = (per + kLzAlign - 1) / kLzAlign * kLzAlign;
+  lo = per * b;
+  if (lo > ld) lo = ld;
+  hi = lo + per;
+  if (hi > ld) hi = ld;
 }
 
-// partial[p][i][b] = sum_{n in range b} Q[i][n] w[n], i = 0..j; one wave per i.
-__global__ __launch_bounds__(TB) void k_multidot_partial(const LzProblem* probs, const LzCtrl* ctrl,
-                                                         const int32_t* active, double* partial, int kmax) {
+constexpr int kSub = 4096;   // elements of w staged in LDS at a time
+
+// partial[p][i][b] = sum_{n in range b} Q[i][n] w[n], i = 0..j.
+// The block's slice of w goes through LDS kSub elements at a time; wave k
+// takes rows i = k, k + 4, ... and adds its row sums into acc[i] in a fixed
+// order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(TB) void k_mdot(const LzProblem* probs, const LzCtrl* ctrl, const int32_t* active,
+                                             double* partial, int kmax) {
+  __shared__ __attribute__((aligned(16))) double xs[kSub];
+  __shared__ double acc[kLzMaxK];
   const int p = blockIdx.y, b = blockIdx.x;
   if (!active[p]) return;
   const LzProblem pr = probs[p];
   const int j = ctrl[p].j;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   int64_t lo, hi;
-  range_of(pr.N, b, lo, hi);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = wave; i <= j; i += TB / 64) {
-    const double* q = pr.Q + (int64_t)i * pr.N;
-    double acc = 0.0;
-    for (int64_t n = lo + lane; n < hi; n += 64) acc += q[n] * pr.w[n];
-    acc = wave_sum(acc);
-    if (lane == 0) partial[((int64_t)p * kmax + i) * kLzBlocks + b] = acc;
+  pad_range(pr.ld, b, lo, hi);
+  for (int i = t; i <= j; i += TB) acc[i] = 0.0;
+  for (int64_t s0 = lo; s0 < hi; s0 += kSub) {
+    const int len = (int)(hi - s0 < kSub ? hi - s0 : kSub);
+    __syncthreads();   // previous slice fully consumed (and acc initialised)
+    for (int e = 2 * t; e < len; e += 2 * TB) *reinterpret_cast<v2d*>(&xs[e]) = *reinterpret_cast<const v2d*>(&pr.w[s0 + e]);
+    __syncthreads();
+    for (int i = wave; i <= j; i += TB / 64) {
+      const double* q = pr.Q + (int64_t)i * pr.ld + s0;
+      double a = 0.0;
+#pragma unroll 4
+      for (int e = 2 * lane; e < len; e += 128) {
+        const v2d qv = *reinterpret_cast<const v2d*>(&q[e]);
+        const v2d xv = *reinterpret_cast<const v2d*>(&xs[e]);
+        a += qv.x * xv.x + qv.y * xv.y;
+      }
+      a = wave_sum(a);
+      if (lane == 0) acc[i] += a;
+    }
   }
+  __syncthreads();
+  for (int i = t; i <= j; i += TB) partial[((int64_t)p * kmax + i) * kLzBlocks + b] = acc[i];
 }
 
 // coef[p][i] = sum_b partial[p][i][b], i = 0..j; one block per (i, p).
-__global__ __launch_bounds__(TB) void k_multidot_finalize(const LzCtrl* ctrl, const int32_t* active,
-                                                          const double* partial, double* coef, int kmax) {
+// If alpha is given, alpha_j = coef_j (the first pass).
+__global__ __launch_bounds__(TB) void k_mdot_finalize(const LzCtrl* ctrl, const int32_t* active,
+                                                      const double* partial, double* coef, double* alpha, int kmax) {
   __shared__ double sh[TB];
   const int p = blockIdx.y, i = blockIdx.x;
   if (!active[p] || i > ctrl[p].j) return;
   const double s = sum_partials(partial, p, i, kmax, sh);
-  if (threadIdx.x == 0) coef[(int64_t)p * kmax + i] = s;
+  if (threadIdx.x == 0) {
+    coef[(int64_t)p * kmax + i] = s;
+    if (alpha && i == ctrl[p].j) alpha[(int64_t)p * kmax + i] = s;
+  }
 }
 
-// w -= sum_{i<=j} coef[i] Q[i]
-__global__ __launch_bounds__(TB) void k_gs_update(const LzProblem* probs, const LzCtrl* ctrl, const int32_t* active,
-                                                  const double* coef, int kmax) {
-  const int p = blockIdx.y;
+// w -= sum_{i<=j} coef_i Q[i] over the padded length; with_norm: also
+// partial[p][0][b] = |w|^2 over the block's range (after the update).
+__global__ __launch_bounds__(TB) void k_update(const LzProblem* probs, const LzCtrl* ctrl, const int32_t* active,
+                                               const double* coef, double* partial, int kmax, int with_norm) {
+  __shared__ double cs[kLzMaxK];
+  __shared__ double sh[TB];
+  const int p = blockIdx.y, b = blockIdx.x;
   if (!active[p]) return;
   const LzProblem pr = probs[p];
   const int j = ctrl[p].j;
-  const double* c = coef + (int64_t)p * kmax;
-  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
-    double s = 0.0;
-    for (int i = 0; i <= j; ++i) s += c[i] * pr.Q[(int64_t)i * pr.N + n];
-    pr.w[n] -= s;
+  const int t = threadIdx.x;
+  for (int i = t; i <= j; i += TB) cs[i] = coef[(int64_t)p * kmax + i];
+  __syncthreads();
+  int64_t lo, hi;
+  pad_range(pr.ld, b, lo, hi);
+  double nrm = 0.0;
+  for (int64_t n = lo + 2 * t; n < hi; n += 2 * TB) {
+    v2d s = {0.0, 0.0};
+    const double* q = pr.Q + n;
+#pragma unroll 4
+    for (int i = 0; i <= j; ++i) {
+      const v2d qv = *reinterpret_cast<const v2d*>(&q[(int64_t)i * pr.ld]);
+      s.x += cs[i] * qv.x;
+      s.y += cs[i] * qv.y;
+    }
+    v2d wv = *reinterpret_cast<const v2d*>(&pr.w[n]);
+    wv.x -= s.x;
+    wv.y -= s.y;
+    *reinterpret_cast<v2d*>(&pr.w[n]) = wv;
+    nrm += wv.x * wv.x + wv.y * wv.y;
+  }
+  if (with_norm) {
+    nrm = block_sum(nrm, sh);
+    if (t == 0) partial[((int64_t)p * kmax) * kLzBlocks + b] = nrm;
   }
 }
 
@@ -293,8 +348,8 @@ __global__ __launch_bounds__(TB) void k_next(const LzProblem* probs, const LzCtr
   const LzProblem pr = probs[p];
   const int j = ctrl[p].j;
   const double inv = 1.0 / beta[(int64_t)p * kmax + j - 1];
-  double* q = pr.Q + (int64_t)j * pr.N;
-  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
+  double* q = pr.Q + (int64_t)j * pr.ld;
+  for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.ld; n += (int64_t)gridDim.x * TB) {
     const double x = pr.w[n] * inv;
     q[n] = x;
     pr.v[n] = x;
@@ -310,7 +365,7 @@ __global__ __launch_bounds__(TB) void k_ritz(const LzProblem* probs, const LzCtr
   const double* y = ritz + (int64_t)p * kmax;
   for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
     double s = 0.0;
-    for (int i = 0; i < k; ++i) s += y[i] * pr.Q[(int64_t)i * pr.N + n];
+    for (int i = 0; i < k; ++i) s += y[i] * pr.Q[(int64_t)i * pr.ld + n];
     pr.psi[n] = s;
   }
 }
@@ -361,22 +416,15 @@ void lz_init(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int k
 void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* active, double* alpha, double* beta,
                        double* ritz, double* coef, double* partial, int kmax, double tol_E, double tol_res,
                        double tol_first, double rel_first, hipStream_t s) {
-  // alpha_j = <v, w>
-  hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)active, 0, 1,
-                     partial, kmax);
-  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)active, partial, alpha, kmax, 0);
-  hipLaunchKernelGGL(k_three_term, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, (const int32_t*)active,
-                     (const double*)alpha, (const double*)beta, kmax);
+  // two classical Gram-Schmidt passes; the first yields alpha_j, the second |w|^2
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_multidot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl,
+    hipLaunchKernelGGL(k_mdot, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl,
                        (const int32_t*)active, partial, kmax);
-    hipLaunchKernelGGL(k_multidot_finalize, dim3(kmax, P), dim3(TB), 0, s, (const LzCtrl*)ctrl,
-                       (const int32_t*)active, (const double*)partial, coef, kmax);
-    hipLaunchKernelGGL(k_gs_update, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, (const int32_t*)active,
-                       (const double*)coef, kmax);
+    hipLaunchKernelGGL(k_mdot_finalize, dim3(kmax, P), dim3(TB), 0, s, (const LzCtrl*)ctrl, (const int32_t*)active,
+                       (const double*)partial, coef, pass == 0 ? alpha : (double*)nullptr, kmax);
+    hipLaunchKernelGGL(k_update, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl,
+                       (const int32_t*)active, (const double*)coef, partial, kmax, pass);
   }
-  hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)active, 1, 1, partial,
-                     kmax);
   hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)active, partial, alpha, kmax, 1);
   hipLaunchKernelGGL(k_tridiag, dim3(P), dim3(64), 0, s, ctrl, active, (const double*)alpha, beta, ritz, kmax, tol_E,
                      tol_res, tol_first, rel_first);
