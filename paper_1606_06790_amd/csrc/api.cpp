@@ -47,6 +47,9 @@ struct idmrg_ctx {
   void* pinned = nullptr;      // host staging for uploads
   size_t pinned_n = 0;
   DevBuf ws[16];               // scratch, by purpose (see WS_*)
+  // GEMM tile autotuner: measured best tiling per (precision, stage, shape bucket)
+  std::map<std::tuple<int, int, int, int, int>, int> tune;
+  hipEvent_t tev[4][4] = {};   // [variant][stage-1 start, stage-1 end, stage-2 start, stage-2 end]
 };
 
 namespace {
@@ -186,11 +189,21 @@ void check_dev(const void* p, int64_t n, size_t esize, const std::string& what) 
 
 // ------------------------------------------------------------------ H_eff execution
 
+// Output tilings of the FP64/FP32 GEMM kernel: code c -> (c & 1 ? 128 : 64) x (c & 2 ? 128 : 64).
+constexpr int kTilings = 4;
+
 struct HeffExec {
   HeffPlan plan;
   int P = 0;
   Prec prec = Prec::F64;
-  GemmTask *g1 = nullptr, *g2 = nullptr;
+  // every tiling variant of both GEMM stages is uploaded; sel[stage] is the one in use
+  GemmTask* gv[2][kTilings] = {};
+  int tiles[2][kTilings] = {};
+  int code[kTilings] = {};
+  int nvar = 1;
+  int sel[2] = {0, 0};
+  bool need_tune[2] = {false, false};
+  std::tuple<int, int, int, int, int> key[2];
   MixTask *mY = nullptr, *mT = nullptr;
   MixSrc *sY = nullptr, *sT = nullptr;
   void** bases = nullptr;      // device [P][8]
@@ -201,6 +214,41 @@ struct HeffExec {
 };
 
 size_t elem_size_operand(Prec p) { return p == Prec::F64 ? 8 : 4; }
+
+int ilog2(double x) { return x >= 1.0 ? (int)std::floor(std::log2(x)) : 0; }
+
+// Shape bucket of one GEMM stage: precision, stage, log2 of the flops and of
+// the flop-weighted mean N and K (the tile choice depends on these, not on
+// the exact block dimensions, which change a little every iteration).
+std::tuple<int, int, int, int, int> tune_key(Prec prec, int stage, const GemmList& g) {
+  double f = 0, fn = 0, fk = 0;
+  for (const auto& t : g.t) {
+    const double w = 2.0 * t.M * (double)t.N * t.K;
+    f += w;
+    fn += w * t.N;
+    fk += w * t.K;
+  }
+  return std::make_tuple((int)prec, stage, ilog2(f), f > 0 ? ilog2(fn / f) : 0, f > 0 ? ilog2(fk / f) : 0);
+}
+
+// After the trial matvecs of every variant have completed: keep the fastest
+// tiling of each stage that still needed tuning, and remember it.
+void tune_resolve(idmrg_ctx* c, HeffExec& ex, int ntried) {
+  if (ntried < 1) return;
+  for (int st = 0; st < 2; ++st) {
+    if (!ex.need_tune[st]) continue;
+    int best = -1;
+    float bms = 0.f;
+    for (int v = 0; v < ntried; ++v) {
+      float ms = 0.f;
+      IDMRG_HIP(hipEventElapsedTime(&ms, c->tev[v][2 * st], c->tev[v][2 * st + 1]));
+      if (best < 0 || ms < bms) best = v, bms = ms;
+    }
+    ex.sel[st] = best;
+    ex.need_tune[st] = false;
+    if (ntried == ex.nvar) c->tune[ex.key[st]] = best;
+  }
+}
 
 // Build plans for P problems, allocate scratch, convert environments for the
 // low-precision policies, and upload.  x/y are the FP64 input/output vectors.
@@ -223,12 +271,35 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
     if (ex.plan.n_psi[p] == 0) throw InvalidArg("two-site state has no allowed block");
   }
   ex.npsi = ex.plan.n_psi;
+  // Tile variants.  The tile shape does not change the order in which any
+  // output element accumulates over k, so all variants give identical results.
+  std::vector<GemmList> var[2];
   if (ex.prec != Prec::BF16X3) {
-    ex.plan.g1.choose_tile(true);
-    ex.plan.g2.choose_tile(true);
+    ex.nvar = kTilings;
+    for (int v = 0; v < kTilings; ++v) ex.code[v] = v;
   } else {   // the split-bf16 kernel has a fixed 128 x 128 tile
-    ex.plan.g1.retile(128, 128);
-    ex.plan.g2.retile(128, 128);
+    ex.nvar = 1;
+    ex.code[0] = 3;
+  }
+  for (int st = 0; st < 2; ++st) {
+    const GemmList& base = st == 0 ? ex.plan.g1 : ex.plan.g2;
+    for (int v = 0; v < ex.nvar; ++v) {
+      var[st].push_back(base);
+      var[st][v].retile(ex.code[v] & 1 ? 128 : 64, ex.code[v] & 2 ? 128 : 64);
+      ex.tiles[st][v] = var[st][v].tiles;
+    }
+    ex.key[st] = tune_key(ex.prec, st, base);
+    auto it = c->tune.find(ex.key[st]);
+    ex.need_tune[st] = ex.nvar > 1 && it == c->tune.end();
+    if (ex.nvar == 1) {
+      ex.sel[st] = 0;
+    } else if (it != c->tune.end()) {
+      ex.sel[st] = it->second;
+    } else {   // untuned default: padding heuristic for FP32, 64 x 64 for FP64 (two waves per SIMD or more)
+      GemmList h = base;
+      h.choose_tile(ex.prec != Prec::F64);
+      ex.sel[st] = h.tiling();
+    }
   }
   ex.flops_g1 = ex.plan.g1.flops();
   ex.flops_g2 = ex.plan.g2.flops();
@@ -309,12 +380,14 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
     }
   }
   Packer pk;
-  const size_t a1 = pk.add(ex.plan.g1.t), a2 = pk.add(ex.plan.g2.t), a3 = pk.add(ex.plan.mixY.t),
-               a4 = pk.add(ex.plan.mixY.src), a5 = pk.add(ex.plan.mixT.t), a6 = pk.add(ex.plan.mixT.src),
-               a7 = pk.add(hb);
+  size_t av[2][kTilings];
+  for (int st = 0; st < 2; ++st)
+    for (int v = 0; v < ex.nvar; ++v) av[st][v] = pk.add(var[st][v].t);
+  const size_t a3 = pk.add(ex.plan.mixY.t), a4 = pk.add(ex.plan.mixY.src), a5 = pk.add(ex.plan.mixT.t),
+               a6 = pk.add(ex.plan.mixT.src), a7 = pk.add(hb);
   char* dev = upload(c, pk, planbuf);
-  ex.g1 = (GemmTask*)(dev + a1);
-  ex.g2 = (GemmTask*)(dev + a2);
+  for (int st = 0; st < 2; ++st)
+    for (int v = 0; v < ex.nvar; ++v) ex.gv[st][v] = (GemmTask*)(dev + av[st][v]);
   ex.mY = (MixTask*)(dev + a3);
   ex.sY = (MixSrc*)(dev + a4);
   ex.mT = (MixTask*)(dev + a5);
@@ -323,8 +396,9 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
 }
 
 // y = H x for every problem (x, y: the FP64 vectors given at setup).
+// trial >= 0: run tiling variant `trial` in both stages and bracket each stage with the tuning events.
 void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const std::vector<double*>& y,
-              const int32_t* active) {
+              const int32_t* active, int trial = -1) {
   hipStream_t s = c->stream;
   if (ex.prec != Prec::F64) {
     Prof pr(c, 3, 0.0);
@@ -337,10 +411,13 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   const int toutT = ex.prec == Prec::F64 ? 0 : (ex.prec == Prec::F32 ? 1 : 2);
   const int toutY = ex.prec == Prec::F64 ? 0 : 1;
   const int lo = ex.prec == Prec::F64 ? 0 : 9;   // profile classes of the low-precision policies
+  const int v1 = trial >= 0 ? trial : ex.sel[0], v2 = trial >= 0 ? trial : ex.sel[1];
   {
     Prof pr(c, lo + 0, ex.flops_g1);
-    launch_gemm(ex.prec, 0, ex.g1, (int)ex.plan.g1.t.size(), ex.plan.g1.tiles, ex.bases, active, s,
-                ex.plan.g1.tiling());
+    if (trial >= 0) IDMRG_HIP(hipEventRecord(c->tev[trial][0], s));
+    launch_gemm(ex.prec, 0, ex.gv[0][v1], (int)ex.plan.g1.t.size(), ex.tiles[0][v1], ex.bases, active, s,
+                ex.code[v1]);
+    if (trial >= 0) IDMRG_HIP(hipEventRecord(c->tev[trial][1], s));
   }
   {
     Prof pr(c, lo + 2, ex.flops_mix);
@@ -349,8 +426,10 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   }
   {
     Prof pr(c, lo + 1, ex.flops_g2);
-    launch_gemm(ex.prec, 1, ex.g2, (int)ex.plan.g2.t.size(), ex.plan.g2.tiles, ex.bases, active, s,
-                ex.plan.g2.tiling());
+    if (trial >= 0) IDMRG_HIP(hipEventRecord(c->tev[trial][2], s));
+    launch_gemm(ex.prec, 1, ex.gv[1][v2], (int)ex.plan.g2.t.size(), ex.tiles[1][v2], ex.bases, active, s,
+                ex.code[v2]);
+    if (trial >= 0) IDMRG_HIP(hipEventRecord(c->tev[trial][3], s));
   }
   if (ex.prec != Prec::F64) {
     Prof pr(c, 3, 0.0);
@@ -394,6 +473,9 @@ extern "C" int idmrg_destroy(idmrg_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
+  for (auto& row : c->tev)
+    for (auto e : row)
+      if (e) (void)hipEventDestroy(e);
   delete c;
   return IDMRG_OK;
 }
@@ -578,6 +660,16 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     const double lowR = o->prec == IDMRG_PREC_F32 ? 1e-5 : 1e-4;
     const int k_inner = 60;
     const int max_outer = mixed ? 16 : 1;
+    // Tile autotuning: the first matvecs of the precision that does most of the
+    // work try one tiling variant each (identical results), then the fastest
+    // variant of each stage is kept and remembered for this shape bucket.
+    HeffExec& bulk = mixed ? exlo : ex64;
+    bool tuned = !(bulk.need_tune[0] || bulk.need_tune[1]);
+    int trial_next = 0;
+    if (!tuned)
+      for (auto& row : ctx->tev)
+        for (auto& e : row)
+          if (!e) IDMRG_HIP(hipEventCreate(&e));
     std::vector<int32_t> going(P, 1);
     std::vector<int> iters(P, 0), fp64mv(P, 0);
     std::vector<LzCtrl> fin(P), out(P);
@@ -616,14 +708,24 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       std::vector<int32_t> act(P);
       for (int64_t it = 0; it < maxk;) {
         for (int k = 0; k < chunk && it < maxk; ++k, ++it) {
-          heff_run(ctx, (!mixed || it == 0) ? ex64 : exlo, vv, ww, active);
+          HeffExec& e = (!mixed || it == 0) ? ex64 : exlo;
+          const int trial = (!tuned && &e == &bulk && trial_next < bulk.nvar) ? trial_next++ : -1;
+          heff_run(ctx, e, vv, ww, active, trial);
           Prof pr(ctx, 4, 0.0);
           lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, kmax, tolE, tolR, tolF, relF,
                             s);
         }
         IDMRG_HIP(hipMemcpyAsync(act.data(), active, P * 4, hipMemcpyDeviceToHost, s));
         sync(ctx);
+        if (!tuned && trial_next == bulk.nvar) {
+          tune_resolve(ctx, bulk, trial_next);
+          tuned = true;
+        }
         if (std::all_of(act.begin(), act.end(), [](int32_t a) { return a == 0; })) break;
+      }
+      if (!tuned && trial_next > 0) {   // the pass ended before every variant was tried
+        tune_resolve(ctx, bulk, trial_next);
+        tuned = true;
       }
       lz_finish(P, dprobs, ctrl, ritz, partial, kmax, s);
       IDMRG_HIP(hipMemcpyAsync(out.data(), ctrl, P * sizeof(LzCtrl), hipMemcpyDeviceToHost, s));
@@ -715,7 +817,8 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
         S.q = kv.first;
         if (S.r == 0 || S.c == 0) continue;
         const int n = std::min(S.r, S.c), pp = std::max(S.r, S.c);
-        if (n > 4096) throw InvalidArg("centre sector larger than 4096 states is not supported");
+        if (n > 4096 || pp > 8192)
+          throw InvalidArg("centre sector larger than 4096 x 8192 states is not supported");
         S.m = nM; nM += (int64_t)S.r * S.c;
         S.x = nX; nX += (int64_t)n * pp;
         S.g = nG; nG += (int64_t)n * n;

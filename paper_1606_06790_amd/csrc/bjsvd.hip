@@ -38,6 +38,7 @@ constexpr int BB = 32;          // rows per block
 constexpr int PB = 2 * BB;      // rows per pair
 constexpr int LD = PB + 1;      // LDS leading dimension
 constexpr int kBjMaxN = 4096;   // largest min(r, c) of one matrix (LDS arrays of k_bj_finish)
+constexpr int kBjMaxP = 8192;   // largest max(r, c) of one matrix
 
 struct BjMat {                  // one matrix (device)
   int32_t n, p, prob, pad;
@@ -273,6 +274,11 @@ __global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ 
   __shared__ double red[16];
   __shared__ double coef[kBjMaxN];
   __shared__ unsigned char nul[kBjMaxN];
+  __shared__ double cw[kBjMaxP];
+  __shared__ unsigned char used[kBjMaxP];
+  __shared__ double s_bv[16];
+  __shared__ int s_bk[16];
+  __shared__ int s_k;
   const SvdTask tk = tasks[blockIdx.x];
   const int r = tk.r, c = tk.c;
   const bool tr = r > c;
@@ -300,37 +306,84 @@ __global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ 
     for (int k = lane; k < p; k += 64) xi[k] *= inv;
   }
   __syncthreads();
-  int next_unit = 0;
-  for (int i = 0; i < n; ++i) {
-    if (!nul[i]) continue;              // uniform: nul is in LDS and was synchronised
-    double* zi = X + (int64_t)i * p;
-    bool ok = false;
-    while (!ok && next_unit < p) {
-      for (int k = t; k < p; k += 1024) zi[k] = (k == next_unit) ? 1.0 : 0.0;
-      ++next_unit;
-      __syncthreads();
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int q = wave; q < n; q += 16) {
-          if (q == i) { if (lane == 0) coef[q] = 0.0; continue; }
-          const double* zq = X + (int64_t)q * p;
-          double d = 0.0;
-          for (int k = lane; k < p; k += 64) d += zq[k] * zi[k];
-          d = wsum(d);
-          if (lane == 0) coef[q] = d;
+  // Completion: null row i becomes e_k, orthogonalised (twice) against all
+  // other rows, for the unused coordinate k of least weight cw[k] = sum_q Z[q][k]^2
+  // over the rows present so far.  Since the rows are orthonormal, the
+  // residual of e_k has squared norm 1 - cw[k], which is largest for that k
+  // and is positive while fewer than p rows are present.
+  __shared__ int s_nnull;
+  if (t == 0) {
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) cnt += nul[i];
+    s_nnull = cnt;
+  }
+  __syncthreads();
+  if (s_nnull > 0) {
+    for (int k = t; k < p; k += 1024) {
+      double a = 0.0;
+      for (int q = 0; q < n; ++q) {
+        const double z = X[(int64_t)q * p + k];
+        a += z * z;
+      }
+      cw[k] = a;
+      used[k] = 0;
+    }
+    __syncthreads();
+    for (int i = 0; i < n; ++i) {
+      if (!nul[i]) continue;              // uniform: nul is in LDS and was synchronised
+      double* zi = X + (int64_t)i * p;
+      bool ok = false;
+      while (!ok) {
+        double bv = 1e300;
+        int bk = p;
+        for (int k = t; k < p; k += 1024)
+          if (!used[k] && cw[k] < bv) bv = cw[k], bk = k;   // k ascending: ties keep the lowest
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ov = __shfl_xor(bv, o, 64);
+          const int ok2 = __shfl_xor(bk, o, 64);
+          if (ov < bv || (ov == bv && ok2 < bk)) bv = ov, bk = ok2;
+        }
+        if (lane == 0) s_bv[wave] = bv, s_bk[wave] = bk;
+        __syncthreads();
+        if (t == 0) {
+          double v = s_bv[0];
+          int kb = s_bk[0];
+          for (int w = 1; w < 16; ++w)
+            if (s_bv[w] < v || (s_bv[w] == v && s_bk[w] < kb)) v = s_bv[w], kb = s_bk[w];
+          s_k = kb;
+          if (kb < p) used[kb] = 1;
         }
         __syncthreads();
-        for (int k = t; k < p; k += 1024) {
-          double acc = 0.0;
-          for (int q = 0; q < n; ++q) acc += coef[q] * X[(int64_t)q * p + k];
-          zi[k] -= acc;
+        const int kk = s_k;
+        if (kk >= p) break;                 // no coordinate left (not reached while rows < p)
+        for (int k = t; k < p; k += 1024) zi[k] = (k == kk) ? 1.0 : 0.0;
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int q = wave; q < n; q += 16) {
+            if (q == i) { if (lane == 0) coef[q] = 0.0; continue; }
+            const double* zq = X + (int64_t)q * p;
+            double d = 0.0;
+            for (int k = lane; k < p; k += 64) d += zq[k] * zi[k];
+            d = wsum(d);
+            if (lane == 0) coef[q] = d;
+          }
+          __syncthreads();
+          for (int k = t; k < p; k += 1024) {
+            double acc = 0.0;
+            for (int q = 0; q < n; ++q) acc += coef[q] * X[(int64_t)q * p + k];
+            zi[k] -= acc;
+          }
+          __syncthreads();
+        }
+        const double nn = sqrt(block_norm2(zi, p, red));
+        if (nn > 1e-8) {
+          for (int k = t; k < p; k += 1024) zi[k] /= nn;
+          ok = true;
         }
         __syncthreads();
       }
-      const double nn = sqrt(block_norm2(zi, p, red));
-      if (nn > 0.5) {
-        for (int k = t; k < p; k += 1024) zi[k] /= nn;
-        ok = true;
-      }
+      for (int k = t; k < p; k += 1024) cw[k] += zi[k] * zi[k];
       __syncthreads();
     }
   }

@@ -314,6 +314,27 @@ def test_errors_are_reported(ctx):
 MIXED_TOL = {"f32": 5e-6, "bf16x3": 5e-5}   # max |y - y_64| / max |y_64| of one matvec
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lanczos_repeatable_across_tuning(prec):
+    """A fresh context tunes the GEMM tiling during its first solve (the first
+    matvecs try every tile variant); the second solve uses the chosen variant
+    throughout.  Tile shapes do not change the summation order, so both solves
+    must agree bitwise."""
+    c2 = lib.Context(0)
+    cfg, r = _oracle_states("random_chain", 32, 7, tol_res=1e-10)
+    sts = [st for st in r["states"] if st["n"] in (6, 7)]
+    probs = [_flat_problem(st) for st in sts]
+    runs = []
+    for _ in range(2):
+        psis = [T(st["v0"]) for st in sts]
+        es, infos = lib.lanczos_solve_batch(c2, probs, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"], prec)
+        assert min(i["iters"] for i in infos) >= 5
+        runs.append((es, [H(p) for p in psis]))
+    assert runs[0][0] == runs[1][0]
+    for a, b in zip(runs[0][1], runs[1][1]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
 def test_heff_apply_mixed(ctx, prec):
     """Low-precision matvec policies against the FP64 oracle, relative to the output's magnitude."""
