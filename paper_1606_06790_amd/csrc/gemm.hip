@@ -90,40 +90,38 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
   const int wave = t >> 6;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
 
-  // slab coordinates: A (MODE 0/1) TPRA threads per row, NA consecutive k each;
-  // A (MODE 2) 16 threads per k, NA consecutive m each; B symmetrically.
-  constexpr int TPRA = 256 / BM;
-  constexpr int TPRB = 256 / BN;
-  const int a_r = MODE == 2 ? t >> 4 : t / TPRA;
-  const int a_c = MODE == 2 ? (t & 15) * NA : (t % TPRA) * NA;
-  const int b_r = MODE == 1 ? t / TPRB : t >> 4;
-  const int b_c = MODE == 1 ? (t % TPRB) * NB : (t & 15) * NB;
-
-  // Loads outside the matrix are skipped and read as zero (measured faster on
-  // gfx950 than clamped unconditional loads).
+  // Slab element idx = e * 256 + t: consecutive threads take consecutive
+  // memory addresses (16 threads per row of a K-contiguous operand, a whole
+  // row of an M- or N-contiguous one), so every load instruction of a wave
+  // covers whole cache lines.  Loads outside the matrix are skipped and read
+  // as zero.
   T ra[NA], rb[NB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
+      const int idx = e * 256 + t;
       int gi, gk;
-      if (MODE == 2) { gk = k0 + a_r; gi = m0 + a_c + e; } else { gi = m0 + a_r; gk = k0 + a_c + e; }
+      if (MODE == 2) { gk = k0 + idx / BM; gi = m0 + idx % BM; } else { gi = m0 + idx / BK; gk = k0 + idx % BK; }
       ra[e] = (gi < M && gk < K) ? (MODE == 2 ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]) : T(0);
     }
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
+      const int idx = e * 256 + t;
       int gn, gk;
-      if (MODE == 1) { gn = n0 + b_r; gk = k0 + b_c + e; } else { gk = k0 + b_r; gn = n0 + b_c + e; }
+      if (MODE == 1) { gn = n0 + idx / BK; gk = k0 + idx % BK; } else { gk = k0 + idx / BN; gn = n0 + idx % BN; }
       rb[e] = (gn < N && gk < K) ? (MODE == 1 ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : T(0);
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
-      if (MODE == 2) As[buf][a_r][a_c + e] = ra[e]; else As[buf][a_c + e][a_r] = ra[e];
+      const int idx = e * 256 + t;
+      if (MODE == 2) As[buf][idx / BM][idx % BM] = ra[e]; else As[buf][idx % BK][idx / BK] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-      if (MODE == 1) Bs[buf][b_c + e][b_r] = rb[e]; else Bs[buf][b_r][b_c + e] = rb[e];
+      const int idx = e * 256 + t;
+      if (MODE == 1) Bs[buf][idx % BK][idx / BK] = rb[e]; else Bs[buf][idx / BN][idx % BN] = rb[e];
     }
   };
 
@@ -204,56 +202,57 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
 
-  // A slab [128 x 32]: thread t takes row t/2, k = (t%2)*16 .. +15 (A row-major in both modes).
-  const int ar = t >> 1, ak = (t & 1) * 16;
-  // B slab: MODE 1 (B given [N x K]): row n = t/2, k = (t%2)*16..; MODE 0 ([K x N]): k = t/8, n = (t%8)*16..
-  const int br = MODE == 1 ? t >> 1 : t >> 3;
-  const int bc = MODE == 1 ? (t & 1) * 16 : (t & 7) * 16;
+  // Loads: consecutive threads take consecutive addresses.  A (and B in MODE 1,
+  // both K-contiguous): value e of thread t is row 8e + t/32, k = t%32 (a wave
+  // reads two whole 128-byte rows per instruction).  B in MODE 0 (N-contiguous):
+  // values 2e, 2e+1 of thread t are rows k, k+1 = 4e + 2(t/128), + 1 at
+  // column t%128.  Out-of-range elements read as zero.
+  const int lk = t & 31, lr = t >> 5;
+  const int bn = t & 127, bk = 2 * (t >> 7);
   uint32_t ra[16], rb[16];
   auto load = [&](int k0) {
-    const int gi = m0 + ar, ci = gi < M ? gi : M - 1;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const int gk = k0 + ak + e, ck = gk < K ? gk : K - 1;
-      const uint32_t v = A[(int64_t)ci * lda + ck];
-      ra[e] = (gi < M && gk < K) ? v : 0u;
+      const int gi = m0 + 8 * e + lr, gk = k0 + lk;
+      ra[e] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : 0u;
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      int gn, gk;
-      if (MODE == 1) { gn = n0 + br; gk = k0 + bc + e; } else { gk = k0 + br; gn = n0 + bc + e; }
-      const int cn = gn < N ? gn : N - 1, ck = gk < K ? gk : K - 1;
-      const uint32_t v = MODE == 1 ? B[(int64_t)cn * ldb + ck] : B[(int64_t)ck * ldb + cn];
-      rb[e] = (gn < N && gk < K) ? v : 0u;
-    }
-  };
-  auto store = [&]() {
-    // A: 16 consecutive k of row ar -> two 16-byte writes per plane
-    uint32_t h[8], l[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      h[e] = (ra[2 * e] & 0xffffu) | (ra[2 * e + 1] << 16);
-      l[e] = (ra[2 * e] >> 16) | (ra[2 * e + 1] & 0xffff0000u);
-    }
-    *reinterpret_cast<v4u*>(&Ah[ar * B3LD + ak]) = v4u{h[0], h[1], h[2], h[3]};
-    *reinterpret_cast<v4u*>(&Ah[ar * B3LD + ak + 8]) = v4u{h[4], h[5], h[6], h[7]};
-    *reinterpret_cast<v4u*>(&Al[ar * B3LD + ak]) = v4u{l[0], l[1], l[2], l[3]};
-    *reinterpret_cast<v4u*>(&Al[ar * B3LD + ak + 8]) = v4u{l[4], l[5], l[6], l[7]};
     if (MODE == 1) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        h[e] = (rb[2 * e] & 0xffffu) | (rb[2 * e + 1] << 16);
-        l[e] = (rb[2 * e] >> 16) | (rb[2 * e + 1] & 0xffff0000u);
+      for (int e = 0; e < 16; ++e) {
+        const int gn = n0 + 8 * e + lr, gk = k0 + lk;
+        rb[e] = (gn < N && gk < K) ? B[(int64_t)gn * ldb + gk] : 0u;
       }
-      *reinterpret_cast<v4u*>(&Bh[br * B3LD + bc]) = v4u{h[0], h[1], h[2], h[3]};
-      *reinterpret_cast<v4u*>(&Bh[br * B3LD + bc + 8]) = v4u{h[4], h[5], h[6], h[7]};
-      *reinterpret_cast<v4u*>(&Bl[br * B3LD + bc]) = v4u{l[0], l[1], l[2], l[3]};
-      *reinterpret_cast<v4u*>(&Bl[br * B3LD + bc + 8]) = v4u{l[4], l[5], l[6], l[7]};
     } else {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        Bh[(bc + e) * B3LD + br] = (uint16_t)(rb[e] & 0xffffu);
-        Bl[(bc + e) * B3LD + br] = (uint16_t)(rb[e] >> 16);
+      for (int e = 0; e < 8; ++e) {
+        const int gn = n0 + bn, gk = k0 + 4 * e + bk;
+        rb[2 * e] = (gn < N && gk < K) ? B[(int64_t)gk * ldb + gn] : 0u;
+        rb[2 * e + 1] = (gn < N && gk + 1 < K) ? B[(int64_t)(gk + 1) * ldb + gn] : 0u;
+      }
+    }
+  };
+  // Stores into the [row][k] planes as 32-bit words holding the values of k and
+  // k+1: for K-contiguous operands a thread swaps values with its neighbour
+  // (t ^ 1); the even one writes the hi word, the odd one the lo word.
+  auto put_pair = [&](uint16_t* hi, uint16_t* lo, int row, uint32_t v) {
+    const uint32_t o = __shfl_xor(v, 1, 64);
+    if ((lk & 1) == 0)
+      *reinterpret_cast<uint32_t*>(&hi[row * B3LD + lk]) = (v & 0xffffu) | (o << 16);
+    else
+      *reinterpret_cast<uint32_t*>(&lo[row * B3LD + lk - 1]) = (o >> 16) | (v & 0xffff0000u);
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) put_pair(Ah, Al, 8 * e + lr, ra[e]);
+    if (MODE == 1) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) put_pair(Bh, Bl, 8 * e + lr, rb[e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t a = rb[2 * e], b = rb[2 * e + 1];
+        *reinterpret_cast<uint32_t*>(&Bh[bn * B3LD + 4 * e + bk]) = (a & 0xffffu) | (b << 16);
+        *reinterpret_cast<uint32_t*>(&Bl[bn * B3LD + 4 * e + bk]) = (a >> 16) | (b & 0xffff0000u);
       }
     }
   };
