@@ -274,13 +274,8 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
   // Tile variants.  The tile shape does not change the order in which any
   // output element accumulates over k, so all variants give identical results.
   std::vector<GemmList> var[2];
-  if (ex.prec != Prec::BF16X3) {
-    ex.nvar = kTilings;
-    for (int v = 0; v < kTilings; ++v) ex.code[v] = v;
-  } else {   // the split-bf16 kernel has a fixed 128 x 128 tile
-    ex.nvar = 1;
-    ex.code[0] = 3;
-  }
+  ex.nvar = kTilings;
+  for (int v = 0; v < kTilings; ++v) ex.code[v] = v;
   for (int st = 0; st < 2; ++st) {
     const GemmList& base = st == 0 ? ex.plan.g1 : ex.plan.g2;
     for (int v = 0; v < ex.nvar; ++v) {
@@ -291,11 +286,9 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
     ex.key[st] = tune_key(ex.prec, st, base);
     auto it = c->tune.find(ex.key[st]);
     ex.need_tune[st] = ex.nvar > 1 && it == c->tune.end();
-    if (ex.nvar == 1) {
-      ex.sel[st] = 0;
-    } else if (it != c->tune.end()) {
+    if (it != c->tune.end()) {
       ex.sel[st] = it->second;
-    } else {   // untuned default: padding heuristic for FP32, 64 x 64 for FP64 (two waves per SIMD or more)
+    } else {   // untuned default: padding heuristic, except 64 x 64 for FP64 (its larger tiles run one wave per SIMD)
       GemmList h = base;
       h.choose_tile(ex.prec != Prec::F64);
       ex.sel[st] = h.tiling();

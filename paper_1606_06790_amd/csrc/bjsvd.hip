@@ -142,8 +142,8 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
   if (t == 0) s_move = 0;
   __syncthreads();
   // is any pair of non-null rows coupled beyond the tolerance?
+  const double z2 = thr2[tk.mat];
   {
-    const double z2 = thr2[tk.mat];
     bool mv = false;
     for (int e = t; e < PB * PB; e += 256) {
       const int i = e / PB, j = e % PB;
@@ -157,7 +157,8 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
   __syncthreads();
   if (!s_move) return;
   if (t == 0) changed[tk.mat] = 1;
-  // 2. cyclic Jacobi on S (round-robin, 32 disjoint pairs per step)
+  // 2. cyclic Jacobi on S (round-robin, 32 disjoint pairs per step), with the
+  // threshold of the outer test, until S is diagonal to it (at most inner_sweeps)
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     for (int round = 0; round < PB - 1; ++round) {
       if (t < PB / 2) {
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
         if (a > b) { const int z = a; a = b; b = z; }
         const double app = S[a][a], aqq = S[b][b], apq = S[a][b];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0 && fabs(apq) > 1e-300) {
+        if (app > z2 && aqq > z2 && fabs(apq) > tol * sqrt(app) * sqrt(aqq)) {
           const double zeta = (aqq - app) / (2.0 * apq);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + tt * tt);
@@ -199,6 +200,19 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
       }
       __syncthreads();
     }
+    if (t == 0) s_move = 0;
+    __syncthreads();
+    bool mv = false;
+    for (int e = t; e < PB * PB; e += 256) {
+      const int i = e / PB, j = e % PB;
+      if (i < j) {
+        const double sij = S[i][j], sii = S[i][i], sjj = S[j][j];
+        if (sii > z2 && sjj > z2 && fabs(sij) > tol * sqrt(sii) * sqrt(sjj)) mv = true;
+      }
+    }
+    if (mv) s_move = 1;
+    __syncthreads();
+    if (!s_move) break;
   }
   // 3. Y <- Q^T Y, G-rows <- Q^T G-rows, in column chunks of 64 (the chunk is read fully before it is written)
   for (int pass = 0; pass < 2; ++pass) {
@@ -446,6 +460,7 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
   std::vector<int32_t> hdone(nm);
   int sweeps = 0;
   scr.converged = 0;
+  scr.done_at.assign(nm, -1);
   for (; sweeps < scr.max_sweeps; ++sweeps) {
     for (size_t r = 0; r < rounds.size(); ++r)
       hipLaunchKernelGGL(k_bj_pair, dim3((unsigned)rounds[r].size()), dim3(256), 0, s, (const BjTask*)(dev + ornd[r]),
@@ -455,6 +470,8 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
     if (hipMemcpyAsync(hdone.data(), done, nm * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
       throw HipFailure("hipMemcpyAsync of Jacobi flags failed");
     sync();
+    for (int m = 0; m < nm; ++m)
+      if (hdone[m] && scr.done_at[m] < 0) scr.done_at[m] = sweeps + 1;
     if (std::all_of(hdone.begin(), hdone.end(), [](int32_t v) { return v != 0; })) {
       scr.converged = 1;
       break;

@@ -176,56 +176,61 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
 // Operands in memory are packed pairs: bits 0..15 hold hi = bf16(x), bits
 // 16..31 hold lo = bf16(x - hi).  In LDS they are split into hi and lo planes
 // stored [row][k] (k contiguous), so that one 16-byte read gives a lane its
-// eight consecutive k values of one plane.  Tile 128 x 128, K-slab 32, 2 x 2
-// waves of 64 x 64 (4 x 4 MFMA tiles); the next slab is prefetched into
-// registers during the MFMAs.  Used for the H_eff GEMMs (MODE 0 and 1).
+// eight consecutive k values of one plane.  Tile BM x BN (64 or 128 each),
+// K-slab 32, 2 x 2 waves of (BM/2) x (BN/2); two LDS stages: the next slab is
+// loaded into registers during the MFMAs and written to the other stage, so
+// each slab needs one barrier.  Used for the H_eff GEMMs (MODE 0 and 1).
 
-constexpr int B3M = 128, B3N = 128, B3K = 32, B3LD = B3K + 8;   // LDS row stride in bf16 (80 bytes)
+constexpr int B3K = 32, B3LD = B3K + 8;   // LDS row stride in bf16 (80 bytes: conflict-free 16-byte reads)
 
-template <int MODE>
+template <int MODE, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __restrict__ tasks, int ntask,
                                                           void* const* __restrict__ bases,
                                                           const int32_t* __restrict__ active, int ntiles) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[B3M * B3LD], Al[B3M * B3LD], Bh[B3N * B3LD], Bl[B3N * B3LD];
+  constexpr int TI = BM / 32, TJ = BN / 32;       // 16 x 16 MFMA tiles per wave
+  constexpr int NA = BM / 8, NB = BN / 8;         // packed values per thread per slab
+  constexpr int G = 256 / BN;                     // MODE 0: thread groups along k
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][BM * B3LD], Al[2][BM * B3LD], Bh[2][BN * B3LD],
+      Bl[2][BN * B3LD];
   const int tile = xcd_tile(ntiles);
   if (tile < 0) return;
   const GemmTask& tk = tasks[find_task(tasks, ntask, tile)];
   if (active && !active[tk.prob]) return;
   const int local = tile - tk.tile0;
-  const int m0 = (local / tk.tiles_n) * B3M;
-  const int n0 = (local % tk.tiles_n) * B3N;
+  const int m0 = (local / tk.tiles_n) * BM;
+  const int n0 = (local % tk.tiles_n) * BN;
   const int M = tk.M, N = tk.N, K = tk.K;
   const uint32_t* __restrict__ A = reinterpret_cast<const uint32_t*>(bases[tk.prob * kNumBases + tk.abase]) + tk.aoff;
   const uint32_t* __restrict__ B = reinterpret_cast<const uint32_t*>(bases[tk.prob * kNumBases + tk.bbase]) + tk.boff;
   float* __restrict__ C = reinterpret_cast<float*>(bases[tk.prob * kNumBases + tk.cbase]) + tk.coff;
   const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
 
   // Loads: consecutive threads take consecutive addresses.  A (and B in MODE 1,
   // both K-contiguous): value e of thread t is row 8e + t/32, k = t%32 (a wave
   // reads two whole 128-byte rows per instruction).  B in MODE 0 (N-contiguous):
-  // values 2e, 2e+1 of thread t are rows k, k+1 = 4e + 2(t/128), + 1 at
-  // column t%128.  Out-of-range elements read as zero.
+  // values 2e, 2e+1 of thread t are rows k, k+1 with k = 2Ge + 2(t/BN), at column
+  // t%BN.  Out-of-range elements read as zero.
   const int lk = t & 31, lr = t >> 5;
-  const int bn = t & 127, bk = 2 * (t >> 7);
-  uint32_t ra[16], rb[16];
+  const int bn = t % BN, bk = 2 * (t / BN);
+  uint32_t ra[NA], rb[NB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
+    for (int e = 0; e < NA; ++e) {
       const int gi = m0 + 8 * e + lr, gk = k0 + lk;
       ra[e] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : 0u;
     }
     if (MODE == 1) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
+      for (int e = 0; e < NB; ++e) {
         const int gn = n0 + 8 * e + lr, gk = k0 + lk;
         rb[e] = (gn < N && gk < K) ? B[(int64_t)gn * ldb + gk] : 0u;
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gn = n0 + bn, gk = k0 + 4 * e + bk;
+      for (int e = 0; e < NB / 2; ++e) {
+        const int gn = n0 + bn, gk = k0 + 2 * G * e + bk;
         rb[2 * e] = (gn < N && gk < K) ? B[(int64_t)gk * ldb + gn] : 0u;
         rb[2 * e + 1] = (gn < N && gk + 1 < K) ? B[(int64_t)(gk + 1) * ldb + gn] : 0u;
       }
@@ -241,61 +246,67 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
     else
       *reinterpret_cast<uint32_t*>(&lo[row * B3LD + lk - 1]) = (o >> 16) | (v & 0xffff0000u);
   };
-  auto store = [&]() {
+  auto store = [&](int st) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) put_pair(Ah, Al, 8 * e + lr, ra[e]);
+    for (int e = 0; e < NA; ++e) put_pair(Ah[st], Al[st], 8 * e + lr, ra[e]);
     if (MODE == 1) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) put_pair(Bh, Bl, 8 * e + lr, rb[e]);
+      for (int e = 0; e < NB; ++e) put_pair(Bh[st], Bl[st], 8 * e + lr, rb[e]);
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < NB / 2; ++e) {
         const uint32_t a = rb[2 * e], b = rb[2 * e + 1];
-        *reinterpret_cast<uint32_t*>(&Bh[bn * B3LD + 4 * e + bk]) = (a & 0xffffu) | (b << 16);
-        *reinterpret_cast<uint32_t*>(&Bl[bn * B3LD + 4 * e + bk]) = (a >> 16) | (b & 0xffff0000u);
+        const int k = 2 * G * e + bk;
+        *reinterpret_cast<uint32_t*>(&Bh[st][bn * B3LD + k]) = (a & 0xffffu) | (b << 16);
+        *reinterpret_cast<uint32_t*>(&Bl[st][bn * B3LD + k]) = (a >> 16) | (b & 0xffff0000u);
       }
     }
   };
 
-  v4f acc[4][4];
+  v4f acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = v4f{0, 0, 0, 0};
 
   const int kb = 8 * (lane >> 4);
-  if (K > 0) load(0);
-  for (int k0 = 0; k0 < K; k0 += B3K) {
-    store();
-    __syncthreads();
-    if (k0 + B3K < K) load(k0 + B3K);
-    v8bf ah[4], al[4], bh[4], bl[4];
+  if (K > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = 0, it = 0; k0 < K; k0 += B3K, ++it) {
+    const int cur = it & 1;
+    const bool more = k0 + B3K < K;
+    if (more) load(k0 + B3K);
+    v8bf ah[TI], al[TI], bh[TJ], bl[TJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TI; ++i) {
       const int row = wm + i * 16 + (lane & 15);
-      ah[i] = *reinterpret_cast<const v8bf*>(&Ah[row * B3LD + kb]);
-      al[i] = *reinterpret_cast<const v8bf*>(&Al[row * B3LD + kb]);
+      ah[i] = *reinterpret_cast<const v8bf*>(&Ah[cur][row * B3LD + kb]);
+      al[i] = *reinterpret_cast<const v8bf*>(&Al[cur][row * B3LD + kb]);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < TJ; ++j) {
       const int row = wn + j * 16 + (lane & 15);
-      bh[j] = *reinterpret_cast<const v8bf*>(&Bh[row * B3LD + kb]);
-      bl[j] = *reinterpret_cast<const v8bf*>(&Bl[row * B3LD + kb]);
+      bh[j] = *reinterpret_cast<const v8bf*>(&Bh[cur][row * B3LD + kb]);
+      bl[j] = *reinterpret_cast<const v8bf*>(&Bl[cur][row * B3LD + kb]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < TJ; ++j) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
+    if (more) store(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gi = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
@@ -331,6 +342,25 @@ static void launch_t(int tiling, int mode, dim3 grid, hipStream_t s, const GemmT
   }
 }
 
+template <int BM, int BN>
+static void launch_b3(int mode, dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask, void* const* bases,
+                      const int32_t* active, int ntiles) {
+  if (mode == 0)
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<0, BM, BN>), grid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
+  else
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<1, BM, BN>), grid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
+}
+
+static void launch_bf16x3(int tiling, int mode, dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask,
+                          void* const* bases, const int32_t* active, int ntiles) {
+  switch (tiling) {
+    case 0: launch_b3<64, 64>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+    case 1: launch_b3<128, 64>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+    case 2: launch_b3<64, 128>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+    default: launch_b3<128, 128>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+  }
+}
+
 void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntiles, void* const* bases,
                  const int32_t* active, hipStream_t s, int tiling) {
   if (ntask == 0 || ntiles == 0) return;
@@ -338,10 +368,7 @@ void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntil
   switch (prec) {
     case Prec::F64: launch_t<double>(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;
     case Prec::F32: launch_t<float>(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;
-    case Prec::BF16X3:
-      if (mode == 0) hipLaunchKernelGGL((gemm_bf16x3_kernel<0>), grid, block, 0, s, tasks, ntask, bases, active, ntiles);
-      else hipLaunchKernelGGL((gemm_bf16x3_kernel<1>), grid, block, 0, s, tasks, ntask, bases, active, ntiles);
-      break;
+    case Prec::BF16X3: launch_bf16x3(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;
   }
 }
 

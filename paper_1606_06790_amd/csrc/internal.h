@@ -133,10 +133,11 @@ void launch_svd(const SvdTask* tasks, int ntask, void* const* bases, int32_t* sw
 struct BjScratch {
   double tol = 1e-15;        // relative orthogonality of converged rows
   double zero_rel = 1e-15;   // rows with norm <= zero_rel |M|_F are null rows
-  int inner_sweeps = 3;
+  int inner_sweeps = 3;      // cap of the sweeps that diagonalise one 64 x 64 pair Gram matrix
   int max_sweeps = 30;
   int sweeps = 0;            // out: sweeps run
   int converged = 0;         // out: every matrix met the tolerance
+  std::vector<int> done_at;  // out: per matrix, the sweep after which it met the tolerance (-1: never)
 };
 void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask* dtasks, BjScratch& scr,
             hipStream_t s, const std::function<char*(const std::vector<char>&)>& upload,
