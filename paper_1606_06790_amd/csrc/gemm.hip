@@ -34,6 +34,32 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
   return t < ntiles ? t : -1;
 }
 
+// Operands are read through global-address-space pointers (global_load, not
+// flat_load) and out-of-range values are cleared with a bit mask instead of a
+// select: the load then stays unconditional and the slab's loads are all in
+// flight together (a select lets the compiler sink each load into its own
+// branch and wait for it there).
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+  return (gptr<T>)(p);
+}
+// All-ones or zero, hidden from the optimiser (an empty register-only asm), so
+// that `value & mask` is not rewritten into a select that the compiler turns
+// into a branch around the load.
+__device__ __forceinline__ uint32_t lane_mask(bool c) {
+  uint32_t m = c ? 0xffffffffu : 0u;
+  asm("" : "+v"(m));
+  return m;
+}
+__device__ __forceinline__ uint32_t keep(uint32_t v, uint32_t m) { return v & m; }
+__device__ __forceinline__ float keep(float v, uint32_t m) { return __uint_as_float(__float_as_uint(v) & m); }
+__device__ __forceinline__ double keep(double v, uint32_t m) {
+  return __longlong_as_double(__double_as_longlong(v) & (long long)(((uint64_t)m << 32) | m));
+}
+
 __device__ __forceinline__ int find_task(const GemmTask* tasks, int ntask, int tile) {
   int lo = 0, hi = ntask - 1;
   while (lo < hi) {
@@ -93,23 +119,67 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
   // Slab element idx = e * 256 + t: consecutive threads take consecutive
   // memory addresses (16 threads per row of a K-contiguous operand, a whole
   // row of an M- or N-contiguous one), so every load instruction of a wave
-  // covers whole cache lines.  Loads outside the matrix are skipped and read
-  // as zero.
-  T ra[NA], rb[NB];
-  auto load = [&](int k0) {
+  // covers whole cache lines.  Loads are unconditional: indices are clamped
+  // into the matrix (offsets from the task base fit in 32 bits, checked on the
+  // host).  Rows of A beyond M and columns of B beyond N only feed outputs that
+  // are not stored; past K, A is cleared so those terms vanish (B there holds
+  // clamped finite values).  For a K-contiguous operand the thread's rows are
+  // fixed and its k is one per slab; for an M/N-contiguous one its column is
+  // fixed and its rows of k vary with e.
+  constexpr int AR = 256 / BK;    // rows (A, MODE 0/1) covered per e
+  constexpr int AK = 256 / BM;    // k rows (A, MODE 2) covered per e
+  constexpr int BR = 256 / BK;    // rows (B, MODE 1) per e
+  constexpr int BKR = 256 / BN;   // k rows (B, MODE 0) per e
+  int aoffs[NA], boffs[NB];
+  int acol = 0, bcol = 0;
+  if (MODE == 2) {
+    const int gm = m0 + t % BM;
+    acol = gm < M ? gm : M - 1;
+  } else {
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
-      const int idx = e * 256 + t;
-      int gi, gk;
-      if (MODE == 2) { gk = k0 + idx / BM; gi = m0 + idx % BM; } else { gi = m0 + idx / BK; gk = k0 + idx % BK; }
-      ra[e] = (gi < M && gk < K) ? (MODE == 2 ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]) : T(0);
+      const int gi = m0 + AR * e + t / BK;
+      aoffs[e] = (gi < M ? gi : M - 1) * lda;
     }
+  }
+  if (MODE == 1) {
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-      const int idx = e * 256 + t;
-      int gn, gk;
-      if (MODE == 1) { gn = n0 + idx / BK; gk = k0 + idx % BK; } else { gk = k0 + idx / BN; gn = n0 + idx % BN; }
-      rb[e] = (gn < N && gk < K) ? (MODE == 1 ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : T(0);
+      const int gn = n0 + BR * e + t / BK;
+      boffs[e] = (gn < N ? gn : N - 1) * ldb;
+    }
+  } else {
+    const int gn = n0 + t % BN;
+    bcol = gn < N ? gn : N - 1;
+  }
+  T ra[NA], rb[NB];
+  const gptr<T> Ag = as_global(A);
+  const gptr<T> Bg = as_global(B);
+  auto load = [&](int k0) {
+    if (MODE == 2) {
+#pragma unroll
+      for (int e = 0; e < NA; ++e) {
+        const int gk = k0 + AK * e + t / BM;
+        ra[e] = keep(Ag[(gk < K ? gk : K - 1) * lda + acol], lane_mask(gk < K));
+      }
+    } else {
+      const int gk = k0 + t % BK;
+      const int ck = gk < K ? gk : K - 1;
+      const uint32_t km = lane_mask(gk < K);
+#pragma unroll
+      for (int e = 0; e < NA; ++e) ra[e] = keep(Ag[aoffs[e] + ck], km);
+    }
+    if (MODE == 1) {
+      const int gk = k0 + t % BK;
+      const int ck = gk < K ? gk : K - 1;
+#pragma unroll
+      for (int e = 0; e < NB; ++e) rb[e] = Bg[boffs[e] + ck];
+    } else {
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        const int gk = k0 + BKR * e + t / BN;
+        rb[e] = Bg[(gk < K ? gk : K - 1) * ldb + bcol];
+      }
     }
   };
   auto store = [&](int buf) {
@@ -190,8 +260,8 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
   constexpr int TI = BM / 32, TJ = BN / 32;       // 16 x 16 MFMA tiles per wave
   constexpr int NA = BM / 8, NB = BN / 8;         // packed values per thread per slab
   constexpr int G = 256 / BN;                     // MODE 0: thread groups along k
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][BM * B3LD], Al[2][BM * B3LD], Bh[2][BN * B3LD],
-      Bl[2][BN * B3LD];
+  // [stage][plane (0 = hi, 1 = lo)][row * B3LD + k]
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][2][BM * B3LD], Bs[2][2][BN * B3LD];
   const int tile = xcd_tile(ntiles);
   if (tile < 0) return;
   const GemmTask& tk = tasks[find_task(tasks, ntask, tile)];
@@ -214,51 +284,75 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
   // t%BN.  Out-of-range elements read as zero.
   const int lk = t & 31, lr = t >> 5;
   const int bn = t % BN, bk = 2 * (t / BN);
-  uint32_t ra[NA], rb[NB];
-  auto load = [&](int k0) {
+  // Unconditional loads from clamped indices (32-bit offsets from the task
+  // base, checked on the host).  Rows of A beyond M and columns of B beyond N
+  // only feed outputs that are not stored; past K, A is cleared so those terms
+  // vanish (B there holds clamped finite values).
+  int aoffs[NA], boffs[MODE == 1 ? NB : 1];
 #pragma unroll
-    for (int e = 0; e < NA; ++e) {
-      const int gi = m0 + 8 * e + lr, gk = k0 + lk;
-      ra[e] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : 0u;
+  for (int e = 0; e < NA; ++e) {
+    const int gi = m0 + 8 * e + lr;
+    aoffs[e] = (gi < M ? gi : M - 1) * lda;
+  }
+  int bcol = 0;
+  if (MODE == 1) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int gn = n0 + 8 * e + lr;
+      boffs[e] = (gn < N ? gn : N - 1) * ldb;
     }
+  } else {
+    const int gn = n0 + bn;
+    bcol = gn < N ? gn : N - 1;
+  }
+  uint32_t ra[NA], rb[NB];
+  const gptr<uint32_t> Ag = as_global(A);
+  const gptr<uint32_t> Bg = as_global(B);
+  auto load = [&](int k0) {
+    const int gk = k0 + lk;
+    const int ck = gk < K ? gk : K - 1;
+    const uint32_t km = lane_mask(gk < K);
+#pragma unroll
+    for (int e = 0; e < NA; ++e) ra[e] = keep(Ag[aoffs[e] + ck], km);
     if (MODE == 1) {
 #pragma unroll
-      for (int e = 0; e < NB; ++e) {
-        const int gn = n0 + 8 * e + lr, gk = k0 + lk;
-        rb[e] = (gn < N && gk < K) ? B[(int64_t)gn * ldb + gk] : 0u;
-      }
+      for (int e = 0; e < NB; ++e) rb[e] = Bg[boffs[e] + ck];
     } else {
 #pragma unroll
       for (int e = 0; e < NB / 2; ++e) {
-        const int gn = n0 + bn, gk = k0 + 2 * G * e + bk;
-        rb[2 * e] = (gn < N && gk < K) ? B[(int64_t)gk * ldb + gn] : 0u;
-        rb[2 * e + 1] = (gn < N && gk + 1 < K) ? B[(int64_t)(gk + 1) * ldb + gn] : 0u;
+        const int g0 = k0 + 2 * G * e + bk, g1 = g0 + 1;
+        rb[2 * e] = Bg[(g0 < K ? g0 : K - 1) * ldb + bcol];
+        rb[2 * e + 1] = Bg[(g1 < K ? g1 : K - 1) * ldb + bcol];
       }
     }
   };
   // Stores into the [row][k] planes as 32-bit words holding the values of k and
   // k+1: for K-contiguous operands a thread swaps values with its neighbour
   // (t ^ 1); the even one writes the hi word, the odd one the lo word.
-  auto put_pair = [&](uint16_t* hi, uint16_t* lo, int row, uint32_t v) {
-    const uint32_t o = __shfl_xor(v, 1, 64);
-    if ((lk & 1) == 0)
-      *reinterpret_cast<uint32_t*>(&hi[row * B3LD + lk]) = (v & 0xffffu) | (o << 16);
-    else
-      *reinterpret_cast<uint32_t*>(&lo[row * B3LD + lk - 1]) = (o >> 16) | (v & 0xffff0000u);
+  // The neighbour's value comes by a DPP quad permutation [1,0,3,2] (no LDS
+  // traffic); the lane picks its word, and its plane by an index offset, with
+  // masks rather than branches.  plane points at the hi plane; the lo plane
+  // follows it at offset PS.
+  const uint32_t om = lane_mask(lk & 1);
+  auto put_pair = [&](uint16_t* plane, int PS, int row, uint32_t v) {
+    const uint32_t o = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    const uint32_t we = (v & 0xffffu) | (o << 16), wo = (o >> 16) | (v & 0xffff0000u);
+    const int idx = row * B3LD + lk + (int)(om & (uint32_t)(PS - 1));
+    *reinterpret_cast<uint32_t*>(&plane[idx]) = (we & ~om) | (wo & om);
   };
   auto store = [&](int st) {
 #pragma unroll
-    for (int e = 0; e < NA; ++e) put_pair(Ah[st], Al[st], 8 * e + lr, ra[e]);
+    for (int e = 0; e < NA; ++e) put_pair(&As[st][0][0], BM * B3LD, 8 * e + lr, ra[e]);
     if (MODE == 1) {
 #pragma unroll
-      for (int e = 0; e < NB; ++e) put_pair(Bh[st], Bl[st], 8 * e + lr, rb[e]);
+      for (int e = 0; e < NB; ++e) put_pair(&Bs[st][0][0], BN * B3LD, 8 * e + lr, rb[e]);
     } else {
 #pragma unroll
       for (int e = 0; e < NB / 2; ++e) {
         const uint32_t a = rb[2 * e], b = rb[2 * e + 1];
         const int k = 2 * G * e + bk;
-        *reinterpret_cast<uint32_t*>(&Bh[st][bn * B3LD + k]) = (a & 0xffffu) | (b << 16);
-        *reinterpret_cast<uint32_t*>(&Bl[st][bn * B3LD + k]) = (a >> 16) | (b & 0xffff0000u);
+        *reinterpret_cast<uint32_t*>(&Bs[st][0][bn * B3LD + k]) = (a & 0xffffu) | (b << 16);
+        *reinterpret_cast<uint32_t*>(&Bs[st][1][bn * B3LD + k]) = (a >> 16) | (b & 0xffff0000u);
       }
     }
   };
@@ -283,14 +377,14 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
       const int row = wm + i * 16 + (lane & 15);
-      ah[i] = *reinterpret_cast<const v8bf*>(&Ah[cur][row * B3LD + kb]);
-      al[i] = *reinterpret_cast<const v8bf*>(&Al[cur][row * B3LD + kb]);
+      ah[i] = *reinterpret_cast<const v8bf*>(&As[cur][0][row * B3LD + kb]);
+      al[i] = *reinterpret_cast<const v8bf*>(&As[cur][1][row * B3LD + kb]);
     }
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
       const int row = wn + j * 16 + (lane & 15);
-      bh[j] = *reinterpret_cast<const v8bf*>(&Bh[cur][row * B3LD + kb]);
-      bl[j] = *reinterpret_cast<const v8bf*>(&Bl[cur][row * B3LD + kb]);
+      bh[j] = *reinterpret_cast<const v8bf*>(&Bs[cur][0][row * B3LD + kb]);
+      bl[j] = *reinterpret_cast<const v8bf*>(&Bs[cur][1][row * B3LD + kb]);
     }
 #pragma unroll
     for (int i = 0; i < TI; ++i)

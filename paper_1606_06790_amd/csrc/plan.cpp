@@ -1,6 +1,7 @@
 // Host-side layouts and work-plan builders.  See plan.h and idmrg.h for the
 // storage orders; the contractions are those of the paper's Step 3 (H_eff,
 // Fig. 2(b)), Step 6 (Eqs. (4), (5)) and Step 3' (Eq. (10)).
+#include <climits>
 #include "plan.h"
 
 #include <algorithm>
@@ -413,6 +414,9 @@ void check_gemm(const GemmList& g, int mode, const std::vector<int64_t>& sizes, 
                                    : t.boff + (int64_t)(t.K - 1) * t.ldb + t.N - 1;
     in_bounds(t.aoff, a_hi, sizes, t.prob, t.abase, what);
     in_bounds(t.boff, b_hi, sizes, t.prob, t.bbase, what);
+    // the kernels address operands by 32-bit offsets from the task's base
+    if (a_hi - t.aoff >= INT32_MAX || b_hi - t.boff >= INT32_MAX)
+      throw InvalidArg(std::string(what) + ": one GEMM operand spans 2^31 elements or more");
   }
 }
 
