@@ -110,10 +110,13 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
                                                  void* const* __restrict__ bases, const int32_t* __restrict__ done,
                                                  int32_t* __restrict__ changed, const double* __restrict__ thr2,
                                                  double tol, int inner_sweeps) {
+  // The MFMA staging tiles alias the Gram matrix S: the Gram product stages
+  // through them before S is written, and the rotation products run after S
+  // is no longer needed (two workgroups fit in one CU's LDS).
   __shared__ double S[PB][LD];
   __shared__ double Q[PB][LD];
-  __shared__ double Ta[16][LD];
-  __shared__ double Tb[16][LD];
+  double(*Ta)[LD] = reinterpret_cast<double(*)[LD]>(&S[0][0]);
+  double(*Tb)[LD] = reinterpret_cast<double(*)[LD]>(&S[16][0]);
   __shared__ double cs_[PB / 2], sn_[PB / 2];
   __shared__ int pidx[PB / 2], qidx[PB / 2];
   __shared__ int s_move;
@@ -176,27 +179,24 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
         pidx[t] = a; qidx[t] = b; cs_[t] = c; sn_[t] = s;
       }
       __syncthreads();
-      // columns: S <- S J, Q <- Q J
-      for (int e = t; e < (PB / 2) * PB; e += 256) {
-        const int k = e / PB, r = e % PB;
-        const int a = pidx[k], b = qidx[k];
-        const double c = cs_[k], s = sn_[k];
-        const double x = S[r][a], y = S[r][b];
-        S[r][a] = c * x - s * y;
-        S[r][b] = s * x + c * y;
-        const double u = Q[r][a], v = Q[r][b];
-        Q[r][a] = c * u - s * v;
-        Q[r][b] = s * u + c * v;
-      }
-      __syncthreads();
-      // rows: S <- J^T S
-      for (int e = t; e < (PB / 2) * PB; e += 256) {
-        const int k = e / PB, col = e % PB;
-        const int a = pidx[k], b = qidx[k];
-        const double c = cs_[k], s = sn_[k];
-        const double x = S[a][col], y = S[b][col];
-        S[a][col] = c * x - s * y;
-        S[b][col] = s * x + c * y;
+      // S <- J^T S J and Q <- Q J in one pass: thread-owned 2 x 2 blocks
+      // (pair u of rows, pair v of columns) are rotated in place.
+      for (int e = t; e < (PB / 2) * (PB / 2); e += 256) {
+        const int u = e / (PB / 2), v = e % (PB / 2);
+        const int au = pidx[u], bu = qidx[u], av = pidx[v], bv = qidx[v];
+        const double cu = cs_[u], su = sn_[u], cv = cs_[v], sv = sn_[v];
+        const double m00 = S[au][av], m01 = S[au][bv], m10 = S[bu][av], m11 = S[bu][bv];
+        const double x00 = cv * m00 - sv * m01, x01 = sv * m00 + cv * m01;   // columns
+        const double x10 = cv * m10 - sv * m11, x11 = sv * m10 + cv * m11;
+        S[au][av] = cu * x00 - su * x10;                                      // rows
+        S[bu][av] = su * x00 + cu * x10;
+        S[au][bv] = cu * x01 - su * x11;
+        S[bu][bv] = su * x01 + cu * x11;
+        const double q00 = Q[au][av], q01 = Q[au][bv], q10 = Q[bu][av], q11 = Q[bu][bv];
+        Q[au][av] = cv * q00 - sv * q01;
+        Q[au][bv] = sv * q00 + cv * q01;
+        Q[bu][av] = cv * q10 - sv * q11;
+        Q[bu][bv] = sv * q10 + cv * q11;
       }
       __syncthreads();
     }
