@@ -49,48 +49,29 @@ struct BjTask {                 // one block pair in one round
   int32_t mat, bi, bj, pad;
 };
 
+// Operands are read through global-address-space pointers from clamped
+// (always valid) indices; a tail that must read as zero is cleared with a mask
+// the optimiser cannot turn into a branch around the load.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+  return (gptr<T>)(p);
+}
+__device__ __forceinline__ uint32_t lane_mask(bool c) {
+  uint32_t m = c ? 0xffffffffu : 0u;
+  asm("" : "+v"(m));
+  return m;
+}
+__device__ __forceinline__ double keep(double v, uint32_t m) {
+  return __longlong_as_double(__double_as_longlong(v) & (long long)(((uint64_t)m << 32) | m));
+}
+
 __device__ __forceinline__ double wsum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
-}
-
-// C[64x64] = A[64 x K] B[K x 64] with A(i,k) = a_at(i,k), B(k,j) = b_at(k,j), FP64 MFMA, 256 threads.
-// Operands are staged through LDS tiles T[k][i] (16 x LD); AK / BK select whether
-// consecutive threads walk k (rows stored along k in memory) or the 64-wide index.
-template <bool AK, bool BK, typename FA, typename FB>
-__device__ void mfma64(FA a_at, FB b_at, int K, double (*Ta)[LD], double (*Tb)[LD], v4d acc[2][2]) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int e = t; e < 16 * PB; e += 256) {
-      const int k = AK ? e % 16 : e / PB, i = AK ? e / 16 : e % PB;
-      Ta[k][i] = (k0 + k < K) ? a_at(i, k0 + k) : 0.0;
-    }
-    for (int e = t; e < 16 * PB; e += 256) {
-      const int k = BK ? e % 16 : e / PB, j = BK ? e / 16 : e % PB;
-      Tb[k][j] = (k0 + k < K) ? b_at(k0 + k, j) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = Ta[kr][wm + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Tb[kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
 }
 
 // FP64 16x16x4 accumulator layout: register r of lane l holds C[l/16 + 4r][l%16].
@@ -133,13 +114,54 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
     const bool ok = i < BB ? (tk.bi >= 0 && r < n) : (tk.bj >= 0 && r < n);
     return ok ? r : -1;
   };
-  // 1. Gram matrix S = Y Y^T
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int r_any = tk.bi * BB;   // a row of the pair that exists (the first block is never a padding block)
+  // 1. Gram matrix S = Y Y^T.  One staged tile Ta[k][i] serves as both operands.
+  // Thread t stages rows i = t/16 + 16q (q < 4) at column k0 + t%16; padding rows
+  // read a real row (clamped) and are removed from S afterwards.
   v4d acc[2][2];
   {
-    auto a_at = [&](int i, int k) -> double { const int r = grow(i); return r >= 0 ? X[(int64_t)r * p + k] : 0.0; };
-    auto b_at = [&](int k, int j) -> double { const int r = grow(j); return r >= 0 ? X[(int64_t)r * p + k] : 0.0; };
-    mfma64<true, true>(a_at, b_at, p, Ta, Tb, acc);
-    store64(acc, [&](int i, int j, double v) { S[i][j] = v; });
+    const gptr<double> Xg = as_global((const double*)X);
+    int offs[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = grow(t / 16 + 16 * q);
+      offs[q] = (r >= 0 ? r : r_any) * p;
+    }
+    double v[4];
+    auto ld = [&](int k0) {
+      const int k = k0 + (t & 15), kc = k < p ? k : p - 1;
+      const uint32_t m = lane_mask(k < p);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = keep(Xg[offs[q] + kc], m);
+    };
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+    ld(0);
+    for (int k0 = 0; k0 < p; k0 += 16) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Ta[t & 15][t / 16 + 16 * q] = v[q];
+      __syncthreads();
+      if (k0 + 16 < p) ld(k0 + 16);
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = Ta[kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Ta[kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+    store64(acc, [&](int i, int j, double v2) { S[i][j] = (grow(i) >= 0 && grow(j) >= 0) ? v2 : 0.0; });
   }
   for (int e = t; e < PB * PB; e += 256) Q[e / PB][e % PB] = (e / PB == e % PB) ? 1.0 : 0.0;
   if (t == 0) s_move = 0;
@@ -214,23 +236,48 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
     __syncthreads();
     if (!s_move) break;
   }
-  // 3. Y <- Q^T Y, G-rows <- Q^T G-rows, in column chunks of 64 (the chunk is read fully before it is written)
+  // 3. Y <- Q^T Y, G-rows <- Q^T G-rows, in column chunks of 64.  The A operand
+  // is read from Q in LDS; the B tile (rows of the pair, clamped like above)
+  // is staged in Tb.  Padding rows need no masking: Q is the identity on them,
+  // so they only feed padding outputs, which are not stored.  A chunk is read
+  // completely before any of it is written.
   for (int pass = 0; pass < 2; ++pass) {
     double* Mx = pass == 0 ? X : G;
+    const gptr<double> Mg = as_global((const double*)Mx);
     const int len = pass == 0 ? p : n;
     for (int c0 = 0; c0 < len; c0 += PB) {
-      auto a_at = [&](int i, int k) -> double { return Q[k][i]; };
-      auto b_at = [&](int k, int j) -> double {
-        const int r = grow(k);
-        return (r >= 0 && c0 + j < len) ? Mx[(int64_t)r * len + c0 + j] : 0.0;
-      };
-      mfma64<false, false>(a_at, b_at, PB, Ta, Tb, acc);
-      __syncthreads();
+      const int col = c0 + lane < len ? c0 + lane : len - 1;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+      for (int k0 = 0; k0 < PB; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int kk = wave + 4 * q;
+          const int r = grow(k0 + kk);
+          Tb[kk][lane] = Mg[(r >= 0 ? r : r_any) * len + col];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const int kr = kk + (lane >> 4);
+          double a[2], b[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) a[i] = Q[k0 + kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) b[j] = Tb[kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+      }
       store64(acc, [&](int i, int j, double v) {
         const int r = grow(i);
         if (r >= 0 && c0 + j < len) Mx[(int64_t)r * len + c0 + j] = v;
       });
-      __syncthreads();
     }
   }
 }
