@@ -90,6 +90,29 @@ def timed(d, prec, steps, warmup):
                 prof=prof, recs=recs)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bench_yc8_m2048_traffic.md")
+TRAFFIC_SOURCES = ["paper_1606_06790_amd/csrc/gemm.hip", "paper_1606_06790_amd/csrc/plan.cpp",
+                   "paper_1606_06790_amd/csrc/api.cpp"]
+
+
+def measured_traffic():
+    """(kernel, HBM bytes per launch) from the committed FETCH_SIZE/WRITE_SIZE record, or None when the
+    GEMM sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic-record: kernel=(.+?) bytes_per_launch=(\S+) sources_sha256=(\w+)", text)
+    if not m:
+        return None
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return (m.group(1), float(m.group(2))) if h.hexdigest() == m.group(3) else None
+
+
 def gemm_roofline(r):
     """Roofline entry for the H_eff GEMM kernel with the largest summed time in run r."""
     prof = r["prof"]
@@ -99,10 +122,16 @@ def gemm_roofline(r):
     n, ms, fl = prof[name]
     achieved = fl / (ms * 1e-3) / 1e12
     stage = "stage 1 (L x psi)" if name.startswith("heff_gemm1") else "stage 2 (T x R^T)"
-    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(PEAK[r["prec"]], 1), "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK[r["prec"]], 4), "traffic": None,
-            "kernel": f"grouped H_eff GEMM {stage}, {r['prec']}", "launches": n,
-            "avg_launch_ms": round(ms / max(n, 1), 4)}
+    out = {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(PEAK[r["prec"]], 1), "unit": "TFLOP/s",
+           "frac": round(achieved / PEAK[r["prec"]], 4), "traffic": None,
+           "kernel": f"grouped H_eff GEMM {stage}, {r['prec']}", "launches": n,
+           "avg_launch_ms": round(ms / max(n, 1), 4)}
+    rec = measured_traffic()
+    if rec and r["prec"] == "bf16x3" and name == "heff_gemm2_lo":
+        out["traffic"] = rec[1]
+        out["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        out["traffic_kernel"] = rec[0]
+    return out
 
 
 def main():
