@@ -56,7 +56,7 @@ namespace {
 
 enum {
   WS_T1 = 0, WS_T3, WS_LOWENV, WS_LOWVEC, WS_LZ, WS_LZSMALL, WS_SVD, WS_SEL, WS_ENV, WS_PRED, WS_READ, WS_MISC,
-  WS_PLAN64, WS_PLANLOW
+  WS_PLAN64, WS_PLANLOW, WS_T3F
 };
 
 void sync(idmrg_ctx* c) { IDMRG_HIP(hipStreamSynchronize(c->stream)); }
@@ -207,7 +207,10 @@ struct HeffExec {
   MixTask *mY = nullptr, *mT = nullptr;
   MixSrc *sY = nullptr, *sT = nullptr;
   void** bases = nullptr;      // device [P][8]
-  // per-problem buffers of the low-precision policies
+  // split-bf16: FP64 sources of the fragment packs (device [P][8]: 0 L, 1 R, 2 x) and the per-matvec x pack
+  void** sbases = nullptr;
+  PackTask* pX = nullptr;
+  // per-problem buffers of the low-precision policies (xlow: the GEMM operand, xmix: FP32 x for the mixing)
   std::vector<void*> xlow, xmix, ylow;
   std::vector<int64_t> npsi;
   double flops_g1 = 0, flops_g2 = 0, flops_mix = 0;
@@ -271,13 +274,14 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
     if (ex.plan.n_psi[p] == 0) throw InvalidArg("two-site state has no allowed block");
   }
   ex.npsi = ex.plan.n_psi;
+  const bool frag = ex.prec == Prec::BF16X3;
   // Tile variants.  The tile shape does not change the order in which any
   // output element accumulates over k, so all variants give identical results.
   std::vector<GemmList> var[2];
   ex.nvar = kTilings;
   for (int v = 0; v < kTilings; ++v) ex.code[v] = v;
   for (int st = 0; st < 2; ++st) {
-    const GemmList& base = st == 0 ? ex.plan.g1 : ex.plan.g2;
+    const GemmList& base = st == 0 ? (frag ? ex.plan.f1 : ex.plan.g1) : (frag ? ex.plan.f2 : ex.plan.g2);
     for (int v = 0; v < ex.nvar; ++v) {
       var[st].push_back(base);
       var[st][v].retile(ex.code[v] & 1 ? 128 : 64, ex.code[v] & 2 ? 128 : 64);
@@ -308,23 +312,42 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
       check_dev(x[p], ex.plan.n_psi[p], 8, "x");
       check_dev(y[p], ex.plan.n_psi[p], 8, "y");
     }
-    check_gemm(ex.plan.g1, 0, sz, "heff gemm1");
-    check_mix(ex.plan.mixY, sz, "heff mixY");
-    check_mix(ex.plan.mixT, sz, "heff mixT");
-    check_gemm(ex.plan.g2, 1, sz, "heff gemm2");
+    if (!frag) {
+      check_gemm(ex.plan.g1, 0, sz, "heff gemm1");
+      check_mix(ex.plan.mixY, sz, "heff mixY");
+      check_mix(ex.plan.mixT, sz, "heff mixT");
+      check_gemm(ex.plan.g2, 1, sz, "heff gemm2");
+    } else {
+      std::vector<int64_t> ss = sz;   // FP64 sources of the packs: 0 L, 1 R, 2 x
+      for (int p = 0; p < P; ++p) {
+        int64_t* z = &sz[(size_t)p * kNumBases];
+        z[0] = ex.plan.n_Lf[p]; z[1] = ex.plan.n_Rf[p]; z[2] = ex.plan.n_Xf[p]; z[5] = ex.plan.n_T3f[p];
+      }
+      check_gemm_frag(ex.plan.f1, sz, "heff gemm1");
+      check_mix(ex.plan.mixY, sz, "heff mixY");
+      check_mix_frag(ex.plan.mixTf, sz, "heff mixT");
+      check_gemm_frag(ex.plan.f2, sz, "heff gemm2");
+      check_pack(ex.plan.packL, ss, sz, "heff pack L");
+      check_pack(ex.plan.packR, ss, sz, "heff pack R");
+      check_pack(ex.plan.packX, ss, sz, "heff pack x");
+    }
   }
   const size_t es = ex.prec == Prec::F64 ? 8 : 4;   // accumulator / T1 element size
+  // sub-buffers start at multiples of 64 elements (256 bytes), which the 16-byte accesses of the split-bf16 kernels need
+  auto round64 = [](int64_t n) { return (n + 63) / 64 * 64; };
   int64_t nT1 = 0, nT3 = 0;
   std::vector<int64_t> o1(P), o3(P);
   for (int p = 0; p < P; ++p) {
     o1[p] = nT1;
     o3[p] = nT3;
-    nT1 += ex.plan.n_T1[p] + 64;
-    nT3 += ex.plan.n_T3[p] + 64;
+    nT1 += round64(ex.plan.n_T1[p] + 1);
+    nT3 += round64((frag ? ex.plan.n_T3f[p] : ex.plan.n_T3[p]) + 1);
   }
   char* T1 = (char*)ensure(c, c->ws[WS_T1], nT1 * es);
-  char* T3 = (char*)ensure(c, c->ws[WS_T3], nT3 * 4 * (ex.prec == Prec::F64 ? 2 : 1));
-  std::vector<void*> hb((size_t)P * kNumBases, nullptr);
+  char* T3 = (char*)ensure(c, c->ws[frag ? WS_T3F : WS_T3], nT3 * es);
+  // the fragment form of T3 is written only inside its blocks: its padding stays zero from here on
+  if (frag) IDMRG_HIP(hipMemsetAsync(T3, 0, nT3 * es, c->stream));
+  std::vector<void*> hb((size_t)P * kNumBases, nullptr), sb;
   ex.xlow.assign(P, nullptr);
   ex.xmix.assign(P, nullptr);
   ex.ylow.assign(P, nullptr);
@@ -340,29 +363,41 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
       b[6] = x[p];
     }
   } else {
+    // 4-byte units: FP32 L, R, x (also the mixing operand), y; or, for split-bf16,
+    // fragment-layout L, R, x, plus FP32 x for the mixing and y
+    const std::vector<int64_t>& nL = frag ? ex.plan.n_Lf : ex.plan.n_L;
+    const std::vector<int64_t>& nR = frag ? ex.plan.n_Rf : ex.plan.n_R;
     int64_t nenv = 0, nvec = 0;
     for (int p = 0; p < P; ++p) {
-      nenv += ex.plan.n_L[p] + ex.plan.n_R[p] + 128;
-      nvec += 3 * (ex.npsi[p] + 64);
+      nenv += round64(nL[p]) + round64(nR[p]);
+      nvec += (frag ? round64(ex.plan.n_Xf[p]) : 0) + 2 * round64(ex.npsi[p]);
     }
     char* env = (char*)ensure(c, c->ws[WS_LOWENV], nenv * 4);
     char* vec = (char*)ensure(c, c->ws[WS_LOWVEC], nvec * 4);
     int64_t oe = 0, ov = 0;
-    const int kind = ex.prec == Prec::F32 ? 0 : 1;
+    if (frag) sb.assign((size_t)P * kNumBases, nullptr);
     for (int p = 0; p < P; ++p) {
       void** b = &hb[(size_t)p * kNumBases];
       void* Ll = env + oe * 4;
-      oe += ex.plan.n_L[p] + 64;
+      oe += round64(nL[p]);
       void* Rl = env + oe * 4;
-      oe += ex.plan.n_R[p] + 64;
-      launch_convert(kind, H[p].L, Ll, ex.plan.n_L[p], c->stream);
-      launch_convert(kind, H[p].R, Rl, ex.plan.n_R[p], c->stream);
-      ex.xlow[p] = vec + ov * 4;
-      ov += ex.npsi[p] + 64;
-      ex.xmix[p] = ex.prec == Prec::F32 ? ex.xlow[p] : (void*)(vec + ov * 4);
-      ov += ex.npsi[p] + 64;
+      oe += round64(nR[p]);
+      ex.xmix[p] = vec + ov * 4;
+      ov += round64(ex.npsi[p]);
       ex.ylow[p] = vec + ov * 4;
-      ov += ex.npsi[p] + 64;
+      ov += round64(ex.npsi[p]);
+      if (frag) {
+        ex.xlow[p] = vec + ov * 4;
+        ov += round64(ex.plan.n_Xf[p]);
+        void** q = &sb[(size_t)p * kNumBases];
+        q[0] = (void*)H[p].L;
+        q[1] = (void*)H[p].R;
+        q[2] = x[p];
+      } else {
+        ex.xlow[p] = ex.xmix[p];
+        launch_convert(0, H[p].L, Ll, ex.plan.n_L[p], c->stream);
+        launch_convert(0, H[p].R, Rl, ex.plan.n_R[p], c->stream);
+      }
       b[0] = Ll;
       b[1] = Rl;
       b[2] = ex.xlow[p];
@@ -376,8 +411,16 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
   size_t av[2][kTilings];
   for (int st = 0; st < 2; ++st)
     for (int v = 0; v < ex.nvar; ++v) av[st][v] = pk.add(var[st][v].t);
-  const size_t a3 = pk.add(ex.plan.mixY.t), a4 = pk.add(ex.plan.mixY.src), a5 = pk.add(ex.plan.mixT.t),
-               a6 = pk.add(ex.plan.mixT.src), a7 = pk.add(hb);
+  const MixList& mT = frag ? ex.plan.mixTf : ex.plan.mixT;
+  const size_t a3 = pk.add(ex.plan.mixY.t), a4 = pk.add(ex.plan.mixY.src), a5 = pk.add(mT.t), a6 = pk.add(mT.src),
+               a7 = pk.add(hb);
+  size_t a8 = 0, a9 = 0, a10 = 0, a11 = 0;
+  if (frag) {
+    a8 = pk.add(sb);
+    a9 = pk.add(ex.plan.packX.t);
+    a10 = pk.add(ex.plan.packL.t);
+    a11 = pk.add(ex.plan.packR.t);
+  }
   char* dev = upload(c, pk, planbuf);
   for (int st = 0; st < 2; ++st)
     for (int v = 0; v < ex.nvar; ++v) ex.gv[st][v] = (GemmTask*)(dev + av[st][v]);
@@ -386,6 +429,16 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
   ex.mT = (MixTask*)(dev + a5);
   ex.sT = (MixSrc*)(dev + a6);
   ex.bases = (void**)(dev + a7);
+  if (frag) {
+    // operands fixed for the whole operator: packed once here
+    ex.sbases = (void**)(dev + a8);
+    ex.pX = (PackTask*)(dev + a9);
+    launch_pack((PackTask*)(dev + a10), (int)ex.plan.packL.t.size(), ex.plan.packL.tiles, ex.sbases, ex.bases, nullptr,
+                c->stream);
+    launch_pack((PackTask*)(dev + a11), (int)ex.plan.packR.t.size(), ex.plan.packR.tiles, ex.sbases, ex.bases, nullptr,
+                c->stream);
+    IDMRG_HIP(hipGetLastError());
+  }
 }
 
 // y = H x for every problem (x, y: the FP64 vectors given at setup).
@@ -395,13 +448,12 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   hipStream_t s = c->stream;
   if (ex.prec != Prec::F64) {
     Prof pr(c, 3, 0.0);
-    for (int p = 0; p < ex.P; ++p) {
-      launch_convert(ex.prec == Prec::F32 ? 0 : 1, x[p], ex.xlow[p], ex.npsi[p], s);
-      if (ex.prec == Prec::BF16X3) launch_convert(0, x[p], ex.xmix[p], ex.npsi[p], s);
-    }
+    if (ex.prec == Prec::BF16X3)
+      launch_pack(ex.pX, (int)ex.plan.packX.t.size(), ex.plan.packX.tiles, ex.sbases, ex.bases, active, s);
+    for (int p = 0; p < ex.P; ++p) launch_convert(0, x[p], ex.xmix[p], ex.npsi[p], s);
   }
   const int tin = ex.prec == Prec::F64 ? 0 : 1;
-  const int toutT = ex.prec == Prec::F64 ? 0 : (ex.prec == Prec::F32 ? 1 : 2);
+  const int toutT = ex.prec == Prec::F64 ? 0 : (ex.prec == Prec::F32 ? 1 : 3);
   const int toutY = ex.prec == Prec::F64 ? 0 : 1;
   const int lo = ex.prec == Prec::F64 ? 0 : 9;   // profile classes of the low-precision policies
   const int v1 = trial >= 0 ? trial : ex.sel[0], v2 = trial >= 0 ? trial : ex.sel[1];
@@ -415,7 +467,8 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   {
     Prof pr(c, lo + 2, ex.flops_mix);
     launch_mix(tin, toutY, ex.mY, ex.sY, (int)ex.plan.mixY.t.size(), ex.plan.mixY.tiles, ex.bases, active, s);
-    launch_mix(tin, toutT, ex.mT, ex.sT, (int)ex.plan.mixT.t.size(), ex.plan.mixT.tiles, ex.bases, active, s);
+    const MixList& mT = ex.prec == Prec::BF16X3 ? ex.plan.mixTf : ex.plan.mixT;
+    launch_mix(tin, toutT, ex.mT, ex.sT, (int)mT.t.size(), mT.tiles, ex.bases, active, s);
   }
   {
     Prof pr(c, lo + 1, ex.flops_g2);
@@ -426,7 +479,7 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   }
   if (ex.prec != Prec::F64) {
     Prof pr(c, 3, 0.0);
-    for (int p = 0; p < ex.P; ++p) launch_convert(2, ex.ylow[p], y[p], ex.npsi[p], s);
+    for (int p = 0; p < ex.P; ++p) launch_convert(1, ex.ylow[p], y[p], ex.npsi[p], s);
   }
   IDMRG_HIP(hipGetLastError());
 }

@@ -10,7 +10,8 @@
 // (measured on gfx950).  The split-bf16 policy (bf16x3) uses
 // v_mfma_f32_16x16x32_bf16 (A: lane l holds A[l%16][8*(l/16)+0..7], B:
 // B[8*(l/16)+0..7][l%16], C as FP32) with operands a = hi + lo and the three
-// products lo*hi + hi*lo + hi*hi accumulated in FP32.
+// products lo*hi + hi*lo + hi*hi accumulated in FP32; its operands come
+// pre-packed in that lane order (the fragment layout).
 //
 // Workgroups are dispatched round-robin over the 8 XCDs; xcd_tile() renumbers
 // them so that each XCD receives a contiguous range of tiles, and the tiles of
@@ -243,25 +244,27 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
 }
 
 // ------------------------------------------------------------------ bf16x3
-// Operands in memory are packed pairs: bits 0..15 hold hi = bf16(x), bits
-// 16..31 hold lo = bf16(x - hi).  In LDS they are split into hi and lo planes
-// stored [row][k] (k contiguous), so that one 16-byte read gives a lane its
-// eight consecutive k values of one plane.  Tile BM x BN (64 or 128 each),
-// K-slab 32, 2 x 2 waves of (BM/2) x (BN/2); two LDS stages: the next slab is
-// loaded into registers during the MFMAs and written to the other stage, so
-// each slab needs one barrier.  Used for the H_eff GEMMs (MODE 0 and 1).
+// Operands A[M x K] and B^T[N x K] are in the fragment layout (internal.h): a
+// fragment is one MFMA operand of 16 rows x 32 k, its hi plane then its lo
+// plane, 64 lanes x 16 bytes each, and the fragments of a row block are
+// consecutive in k.  Tile BM x BN (64 or 128 each), K-slab 32, 2 x 2 waves of
+// (BM/2) x (BN/2).  Per slab the workgroup copies BM/16 + BN/16 fragments
+// (16-byte loads from one uniform base plus a fixed per-thread offset, all
+// coalesced; rows past the operand repeat its last row block) unchanged into
+// LDS, where each wave reads its operands with conflict-free 16-byte reads.
+// Zero padding of the layout makes the K tail exact.  Two LDS stages: the next
+// slab is loaded into registers during the MFMAs and stored to the other stage,
+// so each slab needs one barrier.
 
-constexpr int B3K = 32, B3LD = B3K + 8;   // LDS row stride in bf16 (80 bytes: conflict-free 16-byte reads)
-
-template <int MODE, int BM, int BN>
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __restrict__ tasks, int ntask,
                                                           void* const* __restrict__ bases,
                                                           const int32_t* __restrict__ active, int ntiles) {
-  constexpr int TI = BM / 32, TJ = BN / 32;       // 16 x 16 MFMA tiles per wave
-  constexpr int NA = BM / 8, NB = BN / 8;         // packed values per thread per slab
-  constexpr int G = 256 / BN;                     // MODE 0: thread groups along k
-  // [stage][plane (0 = hi, 1 = lo)][row * B3LD + k]
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][2][BM * B3LD], Bs[2][2][BN * B3LD];
+  constexpr int FA = BM / 16, FB = BN / 16;    // fragments per slab
+  constexpr int UA = FA / 2, UB = FB / 2;      // 16-byte units per thread per slab (2 fragments per 256 threads)
+  constexpr int TI = BM / 32, TJ = BN / 32;    // 16 x 16 MFMA tiles per wave
+  constexpr uint32_t kFragBytes = kFragWords * 4;
+  __shared__ v4u As[2][FA * 128], Bs[2][FB * 128];
   const int tile = xcd_tile(ntiles);
   if (tile < 0) return;
   const GemmTask& tk = tasks[find_task(tasks, ntask, tile)];
@@ -269,92 +272,44 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
   const int local = tile - tk.tile0;
   const int m0 = (local / tk.tiles_n) * BM;
   const int n0 = (local % tk.tiles_n) * BN;
-  const int M = tk.M, N = tk.N, K = tk.K;
-  const uint32_t* __restrict__ A = reinterpret_cast<const uint32_t*>(bases[tk.prob * kNumBases + tk.abase]) + tk.aoff;
-  const uint32_t* __restrict__ B = reinterpret_cast<const uint32_t*>(bases[tk.prob * kNumBases + tk.bbase]) + tk.boff;
+  const int M = tk.M, N = tk.N;
+  const int KB = (tk.K + kFragK - 1) / kFragK;
+  const int RA = (M + kFragRows - 1) / kFragRows, RB = (N + kFragRows - 1) / kFragRows;
+  const char* A = reinterpret_cast<const char*>(bases[tk.prob * kNumBases + tk.abase]) + tk.aoff * 4;
+  const char* B = reinterpret_cast<const char*>(bases[tk.prob * kNumBases + tk.bbase]) + tk.boff * 4;
   float* __restrict__ C = reinterpret_cast<float*>(bases[tk.prob * kNumBases + tk.cbase]) + tk.coff;
-  const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
+  const int ldc = tk.ldc;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int wr = wave >> 1, wc = wave & 1;
 
-  // Loads: consecutive threads take consecutive addresses.  A (and B in MODE 1,
-  // both K-contiguous): value e of thread t is row 8e + t/32, k = t%32 (a wave
-  // reads two whole 128-byte rows per instruction).  B in MODE 0 (N-contiguous):
-  // values 2e, 2e+1 of thread t are rows k, k+1 with k = 2Ge + 2(t/BN), at column
-  // t%BN.  Out-of-range elements read as zero.
-  const int lk = t & 31, lr = t >> 5;
-  const int bn = t % BN, bk = 2 * (t / BN);
-  // Unconditional loads from clamped indices (32-bit offsets from the task
-  // base, checked on the host).  Rows of A beyond M and columns of B beyond N
-  // only feed outputs that are not stored; past K, A is cleared so those terms
-  // vanish (B there holds clamped finite values).
-  int aoffs[NA], boffs[MODE == 1 ? NB : 1];
+  // Unit u of thread t is fragment 2u + t/128 of the slab, bytes 16 (t % 128)
+  // of it; byte offsets of slab 0 (32-bit: checked on the host).
+  const int half = t >> 7, within = t & 127;
+  uint32_t ao[UA], bo[UB];
 #pragma unroll
-  for (int e = 0; e < NA; ++e) {
-    const int gi = m0 + 8 * e + lr;
-    aoffs[e] = (gi < M ? gi : M - 1) * lda;
+  for (int u = 0; u < UA; ++u) {
+    const int rb = min(m0 / kFragRows + 2 * u + half, RA - 1);
+    ao[u] = (uint32_t)rb * (uint32_t)KB * kFragBytes + within * 16u;
   }
-  int bcol = 0;
-  if (MODE == 1) {
 #pragma unroll
-    for (int e = 0; e < NB; ++e) {
-      const int gn = n0 + 8 * e + lr;
-      boffs[e] = (gn < N ? gn : N - 1) * ldb;
-    }
-  } else {
-    const int gn = n0 + bn;
-    bcol = gn < N ? gn : N - 1;
+  for (int u = 0; u < UB; ++u) {
+    const int rb = min(n0 / kFragRows + 2 * u + half, RB - 1);
+    bo[u] = (uint32_t)rb * (uint32_t)KB * kFragBytes + within * 16u;
   }
-  uint32_t ra[NA], rb[NB];
-  const gptr<uint32_t> Ag = as_global(A);
-  const gptr<uint32_t> Bg = as_global(B);
-  auto load = [&](int k0) {
-    const int gk = k0 + lk;
-    const int ck = gk < K ? gk : K - 1;
-    const uint32_t km = lane_mask(gk < K);
+  v4u ra[UA], rb[UB];
+  auto load = [&](int kb) {
+    const gptr<char> Ak = as_global(A + (size_t)kb * kFragBytes);
+    const gptr<char> Bk = as_global(B + (size_t)kb * kFragBytes);
 #pragma unroll
-    for (int e = 0; e < NA; ++e) ra[e] = keep(Ag[aoffs[e] + ck], km);
-    if (MODE == 1) {
+    for (int u = 0; u < UA; ++u) ra[u] = *reinterpret_cast<gptr<v4u>>(Ak + ao[u]);
 #pragma unroll
-      for (int e = 0; e < NB; ++e) rb[e] = Bg[boffs[e] + ck];
-    } else {
-#pragma unroll
-      for (int e = 0; e < NB / 2; ++e) {
-        const int g0 = k0 + 2 * G * e + bk, g1 = g0 + 1;
-        rb[2 * e] = Bg[(g0 < K ? g0 : K - 1) * ldb + bcol];
-        rb[2 * e + 1] = Bg[(g1 < K ? g1 : K - 1) * ldb + bcol];
-      }
-    }
-  };
-  // Stores into the [row][k] planes as 32-bit words holding the values of k and
-  // k+1: for K-contiguous operands a thread swaps values with its neighbour
-  // (t ^ 1); the even one writes the hi word, the odd one the lo word.
-  // The neighbour's value comes by a DPP quad permutation [1,0,3,2] (no LDS
-  // traffic); the lane picks its word, and its plane by an index offset, with
-  // masks rather than branches.  plane points at the hi plane; the lo plane
-  // follows it at offset PS.
-  const uint32_t om = lane_mask(lk & 1);
-  auto put_pair = [&](uint16_t* plane, int PS, int row, uint32_t v) {
-    const uint32_t o = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
-    const uint32_t we = (v & 0xffffu) | (o << 16), wo = (o >> 16) | (v & 0xffff0000u);
-    const int idx = row * B3LD + lk + (int)(om & (uint32_t)(PS - 1));
-    *reinterpret_cast<uint32_t*>(&plane[idx]) = (we & ~om) | (wo & om);
+    for (int u = 0; u < UB; ++u) rb[u] = *reinterpret_cast<gptr<v4u>>(Bk + bo[u]);
   };
   auto store = [&](int st) {
 #pragma unroll
-    for (int e = 0; e < NA; ++e) put_pair(&As[st][0][0], BM * B3LD, 8 * e + lr, ra[e]);
-    if (MODE == 1) {
+    for (int u = 0; u < UA; ++u) As[st][(2 * u + half) * 128 + within] = ra[u];
 #pragma unroll
-      for (int e = 0; e < NB; ++e) put_pair(&Bs[st][0][0], BN * B3LD, 8 * e + lr, rb[e]);
-    } else {
-#pragma unroll
-      for (int e = 0; e < NB / 2; ++e) {
-        const uint32_t a = rb[2 * e], b = rb[2 * e + 1];
-        const int k = 2 * G * e + bk;
-        *reinterpret_cast<uint32_t*>(&Bs[st][0][bn * B3LD + k]) = (a & 0xffffu) | (b << 16);
-        *reinterpret_cast<uint32_t*>(&Bs[st][1][bn * B3LD + k]) = (a >> 16) | (b & 0xffff0000u);
-      }
-    }
+    for (int u = 0; u < UB; ++u) Bs[st][(2 * u + half) * 128 + within] = rb[u];
   };
 
   v4f acc[TI][TJ];
@@ -363,28 +318,27 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = v4f{0, 0, 0, 0};
 
-  const int kb = 8 * (lane >> 4);
-  if (K > 0) {
+  if (KB > 0) {
     load(0);
     store(0);
   }
   __syncthreads();
-  for (int k0 = 0, it = 0; k0 < K; k0 += B3K, ++it) {
-    const int cur = it & 1;
-    const bool more = k0 + B3K < K;
-    if (more) load(k0 + B3K);
+  for (int kb = 0; kb < KB; ++kb) {
+    const int cur = kb & 1;
+    const bool more = kb + 1 < KB;
+    if (more) load(kb + 1);
     v8bf ah[TI], al[TI], bh[TJ], bl[TJ];
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
-      const int row = wm + i * 16 + (lane & 15);
-      ah[i] = *reinterpret_cast<const v8bf*>(&As[cur][0][row * B3LD + kb]);
-      al[i] = *reinterpret_cast<const v8bf*>(&As[cur][1][row * B3LD + kb]);
+      const int f = wr * TI + i;
+      ah[i] = __builtin_bit_cast(v8bf, As[cur][f * 128 + lane]);
+      al[i] = __builtin_bit_cast(v8bf, As[cur][f * 128 + 64 + lane]);
     }
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
-      const int row = wn + j * 16 + (lane & 15);
-      bh[j] = *reinterpret_cast<const v8bf*>(&Bs[cur][0][row * B3LD + kb]);
-      bl[j] = *reinterpret_cast<const v8bf*>(&Bs[cur][1][row * B3LD + kb]);
+      const int f = wc * TJ + j;
+      bh[j] = __builtin_bit_cast(v8bf, Bs[cur][f * 128 + lane]);
+      bl[j] = __builtin_bit_cast(v8bf, Bs[cur][f * 128 + 64 + lane]);
     }
 #pragma unroll
     for (int i = 0; i < TI; ++i)
@@ -403,8 +357,8 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
     for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gi = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-        const int gn = n0 + wn + j * 16 + (lane & 15);
+        const int gi = m0 + wr * (BM / 2) + i * 16 + 4 * (lane >> 4) + r;
+        const int gn = n0 + wc * (BN / 2) + j * 16 + (lane & 15);
         if (gi < M && gn < N) {
           float* p = C + (int64_t)gi * ldc + gn;
           *p = tk.beta ? (*p + acc[i][j][r]) : acc[i][j][r];
@@ -437,21 +391,18 @@ static void launch_t(int tiling, int mode, dim3 grid, hipStream_t s, const GemmT
 }
 
 template <int BM, int BN>
-static void launch_b3(int mode, dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask, void* const* bases,
+static void launch_b3(dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask, void* const* bases,
                       const int32_t* active, int ntiles) {
-  if (mode == 0)
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<0, BM, BN>), grid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
-  else
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<1, BM, BN>), grid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
+  hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN>), grid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
 }
 
-static void launch_bf16x3(int tiling, int mode, dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask,
+static void launch_bf16x3(int tiling, dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask,
                           void* const* bases, const int32_t* active, int ntiles) {
   switch (tiling) {
-    case 0: launch_b3<64, 64>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
-    case 1: launch_b3<128, 64>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
-    case 2: launch_b3<64, 128>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
-    default: launch_b3<128, 128>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+    case 0: launch_b3<64, 64>(grid, s, tasks, ntask, bases, active, ntiles); break;
+    case 1: launch_b3<128, 64>(grid, s, tasks, ntask, bases, active, ntiles); break;
+    case 2: launch_b3<64, 128>(grid, s, tasks, ntask, bases, active, ntiles); break;
+    default: launch_b3<128, 128>(grid, s, tasks, ntask, bases, active, ntiles); break;
   }
 }
 
@@ -462,7 +413,7 @@ void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntil
   switch (prec) {
     case Prec::F64: launch_t<double>(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;
     case Prec::F32: launch_t<float>(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;
-    case Prec::BF16X3: launch_bf16x3(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;
+    case Prec::BF16X3: launch_bf16x3(tiling, grid, s, tasks, ntask, bases, active, ntiles); break;
   }
 }
 

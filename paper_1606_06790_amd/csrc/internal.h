@@ -31,10 +31,12 @@ struct GemmTask {
 };
 
 // D[rows x cols] = sum_k coef_k * S_k   (S_k[r][c] at off + r*ld + c, or off + c*ld + r if trans)
+// In fragment output mode (split-bf16 T3) output (r, c) is element (r0 + r, c0 + c)
+// of a fragment-layout matrix at doff with ldd = its k-fragments per row block.
 struct MixTask {
   int32_t rows, cols, ldd, prob;
   int32_t dbase, nsrc, src0, tile0;
-  int32_t tiles_c, pad;
+  int32_t tiles_c, r0, c0, pad;
   int64_t doff;
 };
 
@@ -53,6 +55,29 @@ struct ScaleTask {
   int32_t cbase, invert_row, colmap, tile0;   // colmap < 0: identity map
   int32_t tiles_c, pad;
   int64_t soff, doff, roff, coff;
+};
+
+// Fragment layout of the split-bf16 GEMM operands.  A matrix Z[R x K] (the
+// GEMM's A, or B transposed, so K is the contraction index) is cut into
+// fragments of 16 rows x 32 k, zero-padded at the edges; fragment (rb, kb) of
+// a matrix with KB = ceil(K/32) k-fragments per row block starts at 32-bit word
+// (rb * KB + kb) * kFragWords.  A fragment holds two planes of 256 words (hi
+// bf16 parts, then lo parts); in each plane, lane l in 0..63 owns words
+// 4l..4l+3, the bf16 values of row l % 16, k = 8 (l / 16) + e for e = 0..7,
+// value e in the low (e even) or high (e odd) half of word 4l + e / 2.  This is
+// the operand order of one v_mfma_f32_16x16x32_bf16, so a plane is loaded and
+// fed to the MFMA without any rearrangement.
+constexpr int kFragRows = 16, kFragK = 32, kFragWords = 512;
+
+// Pack of an FP64 block Z[R x K] into the fragment layout: Z(r, k) at
+// soff + r * ld + k (trans: soff + k * ld + r) in source base sbase; the
+// fragments at word doff of destination base dbase (hi = bf16(float(z)),
+// lo = bf16(float(z) - hi), both rounded to nearest even).
+struct PackTask {
+  int32_t R, K, ld, trans;
+  int32_t prob, sbase, dbase, tile0;
+  int32_t RB, KB, pad0, pad1;   // ceil(R / 16), ceil(K / 32)
+  int64_t soff, doff;
 };
 
 // One-sided Jacobi SVD of M[r x c] (row-major); n = min(r, c), p = max(r, c).
@@ -105,24 +130,30 @@ struct InvalidArg {
 enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
 // Grouped GEMM over `ntask` tasks with `ntiles` total tiles.  tiling selects the
-// tile of the FP64/FP32 kernel: 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 128x128
-// (the split-bf16 kernel always uses 64x64); tile0/tiles_n of the tasks must
-// have been computed for that tile.
+// output tile: 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 128x128; tile0/tiles_n of
+// the tasks must have been computed for that tile.
 // mode: 0 = NN, 1 = NT, 2 = TN.  Element type chosen by prec:
-//   F64: double A, B, C;  F32: float A, B, C;  BF16X3: packed (hi,lo) bf16 A, B, float C.
+//   F64: double A, B, C;  F32: float A, B, C;
+//   BF16X3: A and B^T in the fragment layout (aoff, boff in 32-bit words; mode,
+//   lda and ldb are ignored), float C.
 // `active` (nullable) holds one flag per problem; tasks of inactive problems exit at once.
 void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntiles,
                  void* const* bases, const int32_t* active, hipStream_t s, int tiling = 0);
 
-// Mix over tasks; tin/tout element types: 0 = double, 1 = float, 2 = packed bf16 pair (output only).
+// Mix over tasks; tin/tout element types: 0 = double, 1 = float, 3 = split-bf16 pairs in the fragment
+// layout (output only; tasks carry r0, c0 and ldd = k-fragments per row block).
 void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int ntask, int ntiles,
                 void* const* bases, const int32_t* active, hipStream_t s);
 
 void launch_scale(const ScaleTask* tasks, const int32_t* colmaps, int ntask, int ntiles,
                   double lam_floor, void* const* bases, hipStream_t s);
 
-// element conversions (n elements): double -> float, double -> packed bf16 pair, float -> double
+// element conversions (n elements): kind 0 double -> float, kind 1 float -> double
 void launch_convert(int kind, const void* src, void* dst, int64_t n, hipStream_t s);
+
+// Fragment packs (4 fragments per tile); sources are read through sbases, results written through dbases.
+void launch_pack(const PackTask* tasks, int ntask, int ntiles, void* const* sbases, void* const* dbases,
+                 const int32_t* active, hipStream_t s);
 
 void launch_svd(const SvdTask* tasks, int ntask, void* const* bases, int32_t* sweeps_out, hipStream_t s);
 

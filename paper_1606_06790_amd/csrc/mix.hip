@@ -1,6 +1,7 @@
 // Bandwidth-bound kernels of the plans: the MPO channel mixing between the two
 // environment GEMMs (and plain block copies), diagonal scalings with column
-// selection, and element conversions for the mixed-precision policies.
+// selection, element conversions for the mixed-precision policies, and the
+// packs of FP64 blocks into the fragment layout of the split-bf16 GEMM.
 //
 // A mix tile is 32 rows x 64 columns; 256 threads each produce 8 outputs of
 // one column, so every row segment is read and written as 512 contiguous bytes.
@@ -36,6 +37,9 @@ __device__ __forceinline__ int find_tile(const int32_t* tile0, int stride_words,
   return lo;
 }
 
+// Output tag of the mix kernel: split-bf16 pairs in the fragment layout.
+struct FragOut {};
+
 template <typename TIN, typename TOUT>
 __global__ __launch_bounds__(256) void mix_kernel(const MixTask* __restrict__ tasks, const MixSrc* __restrict__ srcs,
                                                   int ntask, void* const* __restrict__ bases,
@@ -49,7 +53,6 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixTask* __restrict__ ta
   const int c = (local % tk.tiles_c) * MC + (threadIdx.x & 63);
   const int rbase = r0 + (threadIdx.x >> 6);
   if (c >= tk.cols) return;
-  float acc32[8];
   double acc[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) acc[e] = 0.0;
@@ -66,19 +69,67 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixTask* __restrict__ ta
       }
     }
   }
-  (void)acc32;
-  TOUT* dst = reinterpret_cast<TOUT*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff;
+  if constexpr (std::is_same<TOUT, FragOut>::value) {
+    // element (r0 + r, c0 + c) of the fragment matrix: the word of its hi part is in
+    // fragment (row / 16, k / 32) at lane (row % 16) + 16 (k % 32 / 8); the lo part
+    // is half a fragment (256 words) further
+    uint16_t* dst = reinterpret_cast<uint16_t*>(bases[tk.prob * kNumBases + tk.dbase]) + 2 * tk.doff;
+    const int kk = tk.c0 + c;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int r = rbase + 4 * e;
-    if (r < tk.rows) {
-      if constexpr (std::is_same<TOUT, uint32_t>::value) {
-        dst[(int64_t)r * tk.ldd + c] = split_bf16((float)acc[e]);
-      } else {
-        dst[(int64_t)r * tk.ldd + c] = (TOUT)acc[e];
+    for (int e = 0; e < 8; ++e) {
+      const int r = rbase + 4 * e;
+      if (r < tk.rows) {
+        const int R = tk.r0 + r;
+        const int64_t w = ((int64_t)(R >> 4) * tk.ldd + (kk >> 5)) * kFragWords +
+                          ((R & 15) + 16 * ((kk & 31) >> 3)) * 4 + ((kk & 7) >> 1);
+        const uint32_t v = split_bf16((float)acc[e]);
+        dst[2 * w + (kk & 1)] = (uint16_t)(v & 0xffffu);
+        dst[2 * (w + kFragWords / 2) + (kk & 1)] = (uint16_t)(v >> 16);
       }
     }
+  } else {
+    TOUT* dst = reinterpret_cast<TOUT*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = rbase + 4 * e;
+      if (r < tk.rows) dst[(int64_t)r * tk.ldd + c] = (TOUT)acc[e];
+    }
   }
+}
+
+// One thread per (fragment, lane): the 8 values of one row in one 32-wide k
+// block, stored as 16 bytes of the hi plane and 16 bytes of the lo plane, so a
+// wave writes 2 KB contiguously.  Values outside [R x K] are zeros.
+__global__ __launch_bounds__(256) void pack_kernel(const PackTask* __restrict__ tasks, int ntask,
+                                                   void* const* __restrict__ sbases, void* const* __restrict__ dbases,
+                                                   const int32_t* __restrict__ active) {
+  const int tile = blockIdx.x;
+  const PackTask& tk = tasks[find_tile(&tasks[0].tile0, sizeof(PackTask) / 4, ntask, tile)];
+  if (active && !active[tk.prob]) return;
+  const int64_t f = (int64_t)(tile - tk.tile0) * 4 + (threadIdx.x >> 6);
+  if (f >= (int64_t)tk.RB * tk.KB) return;
+  const int lane = threadIdx.x & 63;
+  const int r = (int)(f / tk.KB) * kFragRows + (lane & 15);
+  const int k0 = (int)(f % tk.KB) * kFragK + 8 * (lane >> 4);
+  const double* S = reinterpret_cast<const double*>(sbases[tk.prob * kNumBases + tk.sbase]) + tk.soff;
+  uint32_t h[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    uint32_t pr[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int k = k0 + e + u;
+      double v = 0.0;
+      if (r < tk.R && k < tk.K) v = tk.trans ? S[(int64_t)k * tk.ld + r] : S[(int64_t)r * tk.ld + k];
+      pr[u] = split_bf16((float)v);
+    }
+    h[e / 2] = (pr[0] & 0xffffu) | (pr[1] << 16);
+    l[e / 2] = (pr[0] >> 16) | (pr[1] & 0xffff0000u);
+  }
+  uint4* D = reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(dbases[tk.prob * kNumBases + tk.dbase]) + tk.doff +
+                                      f * kFragWords);
+  D[lane] = make_uint4(h[0], h[1], h[2], h[3]);
+  D[64 + lane] = make_uint4(l[0], l[1], l[2], l[3]);
 }
 
 __global__ __launch_bounds__(256) void scale_kernel(const ScaleTask* __restrict__ tasks, const int32_t* __restrict__ colmaps,
@@ -113,8 +164,6 @@ __global__ void convert_kernel(int kind, const void* __restrict__ src, void* __r
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     if (kind == 0) {
       reinterpret_cast<float*>(dst)[i] = (float)reinterpret_cast<const double*>(src)[i];
-    } else if (kind == 1) {
-      reinterpret_cast<uint32_t*>(dst)[i] = split_bf16((float)reinterpret_cast<const double*>(src)[i]);
     } else {
       reinterpret_cast<double*>(dst)[i] = (double)reinterpret_cast<const float*>(src)[i];
     }
@@ -131,10 +180,16 @@ void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int
     hipLaunchKernelGGL((mix_kernel<double, double>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
   else if (tin == 1 && tout == 1)
     hipLaunchKernelGGL((mix_kernel<float, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
-  else if (tin == 1 && tout == 2)
-    hipLaunchKernelGGL((mix_kernel<float, uint32_t>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
+  else if (tin == 1 && tout == 3)
+    hipLaunchKernelGGL((mix_kernel<float, FragOut>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
   else if (tin == 0 && tout == 1)
     hipLaunchKernelGGL((mix_kernel<double, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
+}
+
+void launch_pack(const PackTask* tasks, int ntask, int ntiles, void* const* sbases, void* const* dbases,
+                 const int32_t* active, hipStream_t s) {
+  if (ntask == 0 || ntiles == 0) return;
+  hipLaunchKernelGGL(pack_kernel, dim3(ntiles), dim3(256), 0, s, tasks, ntask, sbases, dbases, active);
 }
 
 void launch_scale(const ScaleTask* tasks, const int32_t* colmaps, int ntask, int ntiles, double lam_floor,

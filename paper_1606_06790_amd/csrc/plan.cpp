@@ -267,6 +267,27 @@ void ScaleList::add(ScaleTask s) {
   t.push_back(s);
 }
 
+int64_t frag_words(int R, int K) {
+  return (int64_t)((R + kFragRows - 1) / kFragRows) * ((K + kFragK - 1) / kFragK) * kFragWords;
+}
+
+void PackList::add(PackTask p) {
+  if (p.R <= 0 || p.K <= 0) return;
+  p.RB = (p.R + kFragRows - 1) / kFragRows;
+  p.KB = (p.K + kFragK - 1) / kFragK;
+  p.tile0 = tiles;
+  tiles += (int)(((int64_t)p.RB * p.KB + 3) / 4);
+  t.push_back(p);
+}
+
+static PackTask packtask(int prob, int R, int K, int sbase, int64_t soff, int ld, int trans, int dbase, int64_t doff) {
+  PackTask p{};
+  p.R = R; p.K = K; p.ld = ld; p.trans = trans;
+  p.prob = prob; p.sbase = sbase; p.dbase = dbase;
+  p.soff = soff; p.doff = doff;
+  return p;
+}
+
 static GemmTask gemm(int prob, int M, int N, int K, int ab, int64_t ao, int lda, int bb, int64_t bo, int ldb, int cb,
                      int64_t co, int ldc, int beta) {
   GemmTask g{};
@@ -344,6 +365,31 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
       nT3 += (int64_t)X.b_rows[b] * ER.K[b];
     }
   }
+  // Fragment form (split-bf16): L per column sector, x per block, T3 and R per right sector
+  std::vector<int64_t> lf(A.n(), -1), xf(X.blk.size(), -1), t3f(B.n(), -1), rf(B.n(), -1);
+  int64_t nLf = 0, nXf = 0, nT3f = 0, nRf = 0;
+  for (int a = 0; a < A.n(); ++a) {
+    if (EL.rows[a] == 0) continue;
+    lf[a] = nLf;
+    p.packL.add(packtask(prob, EL.rows[a], A.dim[a], 0, EL.stack_off[a], A.dim[a], 0, 0, nLf));
+    nLf += frag_words(EL.rows[a], A.dim[a]);
+  }
+  for (size_t x = 0; x < X.blk.size(); ++x) {
+    const auto& k = X.blk[x];
+    if (t1off[x] < 0) continue;
+    xf[x] = nXf;   // B = x block [da x db], N-contiguous: fragment rows are its columns
+    p.packX.add(packtask(prob, k.db, k.da, 2, k.off, k.db, 1, 2, nXf));
+    nXf += frag_words(k.db, k.da);
+    p.f1.add(gemm(prob, EL.rows[k.a], k.db, k.da, 0, lf[k.a], 0, 2, xf[x], 0, 4, t1off[x], k.db, 0));
+  }
+  for (int b = 0; b < B.n(); ++b) {
+    if (ER.K[b] == 0 || X.b_rows[b] == 0) continue;
+    t3f[b] = nT3f;
+    nT3f += frag_words(X.b_rows[b], ER.K[b]);
+    rf[b] = nRf;
+    p.packR.add(packtask(prob, B.dim[b], ER.K[b], 1, ER.off[b], ER.K[b], 0, 1, nRf));
+    nRf += frag_words(B.dim[b], ER.K[b]);
+  }
   const auto terms = w12_terms(W1, W2);
   // Source of T1[w](a, t1, t2, b') = (L[w] x)(a, ...): psi block (a', t1, t2) with a' = a - ql[w]
   auto source = [&](int a, int w, int t1, int t2, int bp, double c, std::vector<MixSrc>& out) {
@@ -381,14 +427,23 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
         for (const auto& tm : it->second) source(ko.a, tm.w, tm.t1, tm.t2, bp, tm.c, s);
       p.mixT.add(mixtask(prob, ko.da, B.dim[bp], 5, t3off[ko.b] + (int64_t)rowin[xo] * ER.K[ko.b] + co, ER.K[ko.b]),
                  s);
+      MixTask mf = mixtask(prob, ko.da, B.dim[bp], 5, t3f[ko.b], (ER.K[ko.b] + kFragK - 1) / kFragK);
+      mf.r0 = rowin[xo];
+      mf.c0 = co;
+      p.mixTf.add(mf, s);
     }
   }
   for (int b = 0; b < B.n(); ++b) {
     if (ER.K[b] == 0 || X.b_rows[b] == 0) continue;
     p.g2.add(gemm(prob, X.b_rows[b], B.dim[b], ER.K[b], 5, t3off[b], ER.K[b], 1, ER.off[b], ER.K[b], 3,
                   X.b_first[b], B.dim[b], 1));
+    p.f2.add(gemm(prob, X.b_rows[b], B.dim[b], ER.K[b], 5, t3f[b], 0, 1, rf[b], 0, 3, X.b_first[b], B.dim[b], 1));
   }
   p.n_psi.push_back(X.size);
+  p.n_Lf.push_back(nLf);
+  p.n_Rf.push_back(nRf);
+  p.n_Xf.push_back(nXf);
+  p.n_T3f.push_back(nT3f);
   p.n_T1.push_back(nT1);
   p.n_T3.push_back(nT3);
   p.n_L.push_back(EL.size);
@@ -430,6 +485,53 @@ void check_mix(const MixList& m, const std::vector<int64_t>& sizes, const char* 
                                  : s.off + (int64_t)(t.rows - 1) * s.ld + t.cols - 1;
       in_bounds(s.off, hi, sizes, t.prob, s.base, what);
     }
+  }
+}
+
+// Last word of a fragment-layout matrix [R x K] at off, and a check that its
+// byte extent fits the kernels' 32-bit offsets.
+static int64_t frag_last(int64_t off, int R, int K, const char* what) {
+  const int64_t w = frag_words(R, K);
+  if (w * 4 >= INT32_MAX) throw InvalidArg(std::string(what) + ": one fragment-layout operand spans 2 GiB or more");
+  return off + w - 1;
+}
+
+void check_gemm_frag(const GemmList& g, const std::vector<int64_t>& sizes, const char* what) {
+  for (const auto& t : g.t) {
+    if (t.M <= 0 || t.N <= 0) continue;
+    in_bounds(t.coff, t.coff + (int64_t)(t.M - 1) * t.ldc + t.N - 1, sizes, t.prob, t.cbase, what);
+    if (t.ldc < t.N) throw InvalidArg(std::string("internal: ") + what + " ldc < N");
+    if (t.K <= 0) continue;
+    in_bounds(t.aoff, frag_last(t.aoff, t.M, t.K, what), sizes, t.prob, t.abase, what);
+    in_bounds(t.boff, frag_last(t.boff, t.N, t.K, what), sizes, t.prob, t.bbase, what);
+  }
+}
+
+void check_mix_frag(const MixList& m, const std::vector<int64_t>& sizes, const char* what) {
+  for (const auto& t : m.t) {
+    if (t.rows <= 0 || t.cols <= 0) continue;
+    // the destination is a fragment matrix with ldd k-fragments per row block; the
+    // task covers rows [r0, r0 + rows) and columns [c0, c0 + cols) of it
+    if (t.r0 < 0 || t.c0 < 0 || t.c0 + t.cols > t.ldd * kFragK)
+      throw InvalidArg(std::string("internal: ") + what + " fragment block outside its matrix");
+    const int64_t last = t.doff + ((int64_t)((t.r0 + t.rows - 1) / kFragRows) * t.ldd + t.ldd) * kFragWords - 1;
+    in_bounds(t.doff, last, sizes, t.prob, t.dbase, what);
+    for (int k = 0; k < t.nsrc; ++k) {
+      const MixSrc& s = m.src[t.src0 + k];
+      const int64_t hi = s.trans ? s.off + (int64_t)(t.cols - 1) * s.ld + t.rows - 1
+                                 : s.off + (int64_t)(t.rows - 1) * s.ld + t.cols - 1;
+      in_bounds(s.off, hi, sizes, t.prob, s.base, what);
+    }
+  }
+}
+
+void check_pack(const PackList& pl, const std::vector<int64_t>& ssizes, const std::vector<int64_t>& dsizes,
+                const char* what) {
+  for (const auto& t : pl.t) {
+    const int64_t hi = t.trans ? t.soff + (int64_t)(t.K - 1) * t.ld + t.R - 1
+                               : t.soff + (int64_t)(t.R - 1) * t.ld + t.K - 1;
+    in_bounds(t.soff, hi, ssizes, t.prob, t.sbase, what);
+    in_bounds(t.doff, frag_last(t.doff, t.R, t.K, what), dsizes, t.prob, t.dbase, what);
   }
 }
 

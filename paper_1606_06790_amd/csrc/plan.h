@@ -109,13 +109,33 @@ struct ScaleList {
   void add(ScaleTask s);
 };
 
+struct PackList {
+  std::vector<PackTask> t;
+  int tiles = 0;
+  void add(PackTask p);              // fills RB, KB, tile0 (4 fragments per tile)
+};
+
+// Words of a [R x K] matrix in the fragment layout.
+int64_t frag_words(int R, int K);
+
 struct HeffPlan {
   GemmList g1, g2;
   MixList mixY, mixT;
   std::vector<int64_t> n_psi, n_T1, n_T3;   // per problem
   std::vector<int64_t> n_L, n_R;
+  // Split-bf16 policy: the same contraction on operands in the fragment layout.
+  // f1/f2 are g1/g2 with aoff/boff in fragment words; mixTf is mixT writing T3
+  // in the fragment layout; packL/packR (once per operator) and packX (per
+  // matvec) fill the operands from the FP64 inputs.
+  GemmList f1, f2;
+  MixList mixTf;
+  PackList packL, packR, packX;
+  std::vector<int64_t> n_Lf, n_Rf, n_Xf, n_T3f;   // words, per problem
 };
-// heff bases: 0 L, 1 R, 2 x (GEMM operand), 3 y, 4 T1, 5 T3, 6 x (mix operand)
+// heff bases: 0 L, 1 R, 2 x (GEMM operand), 3 y, 4 T1, 5 T3, 6 x (mix operand).
+// Fragment form: 0 L, 1 R, 2 x, 5 T3 in the fragment layout; 3 y, 4 T1, 6 x as
+// above; the packs read the FP64 L, R, x through bases 0, 1, 2 of a separate
+// source table.
 void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1, const Mpo& W2);
 
 struct EnvPlan {
@@ -142,6 +162,11 @@ void build_predict(PredictPlan& p, int prob, const Leg& Aa, const Leg& Bt, const
 void check_gemm(const GemmList& g, int mode, const std::vector<int64_t>& sizes, const char* what);
 void check_mix(const MixList& m, const std::vector<int64_t>& sizes, const char* what);
 void check_scale(const ScaleList& s, const std::vector<int64_t>& sizes, const char* what, int64_t colmap_bound);
+// Fragment-layout forms (sizes of fragment buffers in 32-bit words).
+void check_gemm_frag(const GemmList& g, const std::vector<int64_t>& sizes, const char* what);
+void check_mix_frag(const MixList& m, const std::vector<int64_t>& sizes, const char* what);
+void check_pack(const PackList& p, const std::vector<int64_t>& ssizes, const std::vector<int64_t>& dsizes,
+                const char* what);
 
 // Work of one heff_apply (flops of GEMMs and mixing; bytes of environments, x, y).
 void heff_work(const Leg& A, const Leg& B, const Mpo& W1, const Mpo& W2, double& flops, double& bytes);

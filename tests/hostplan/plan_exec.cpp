@@ -2,6 +2,7 @@
 // plain loops, so that the plan builders (block bookkeeping, offsets, MPO
 // mixing coefficients) can be checked against the oracle without a GPU.
 // Built only by the test suite; never linked into libidmrg.so.
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -50,6 +51,64 @@ void run_mix(const MixList& m, const std::vector<double*>& b) {
   }
 }
 
+// Fragment layout on the host: one double per bf16 slot (two per 32-bit word),
+// the value in the hi slot and zero in the lo slot, so the three split-bf16
+// products reduce to the exact FP64 product.
+int64_t frag_slot(int64_t word_off, int KB, int r, int k) {
+  return 2 * (word_off + ((int64_t)(r / kFragRows) * KB + k / kFragK) * kFragWords) + ((r % kFragRows) + 16 * ((k % kFragK) / 8)) * 8 +
+         k % 8;
+}
+
+void run_pack(const PackList& pl, const std::vector<double*>& src, const std::vector<double*>& dst) {
+  for (const auto& t : pl.t) {
+    const double* S = base_ptr(src, t.prob, t.sbase) + t.soff;
+    double* D = base_ptr(dst, t.prob, t.dbase);
+    for (int r = 0; r < t.RB * kFragRows; ++r)
+      for (int k = 0; k < t.KB * kFragK; ++k) {
+        const int64_t i = frag_slot(t.doff, t.KB, r, k);
+        D[i] = r < t.R && k < t.K ? (t.trans ? S[(int64_t)k * t.ld + r] : S[(int64_t)r * t.ld + k]) : 0.0;
+        D[i + kFragWords] = 0.0;
+      }
+  }
+}
+
+void run_gemm_frag(const GemmList& g, const std::vector<double*>& b) {
+  for (const auto& t : g.t) {
+    const int KB = (t.K + kFragK - 1) / kFragK;
+    const double* A = base_ptr(b, t.prob, t.abase);
+    const double* B = base_ptr(b, t.prob, t.bbase);
+    double* C = base_ptr(b, t.prob, t.cbase) + t.coff;
+    for (int i = 0; i < t.M; ++i)
+      for (int j = 0; j < t.N; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < KB * kFragK; ++k) {   // the zero padding past K contributes nothing
+          const int64_t ia = frag_slot(t.aoff, KB, i, k), ib = frag_slot(t.boff, KB, j, k);
+          s += A[ia] * B[ib + kFragWords] + A[ia + kFragWords] * B[ib] + A[ia] * B[ib];
+        }
+        double& c = C[(int64_t)i * t.ldc + j];
+        c = t.beta ? c + s : s;
+      }
+  }
+}
+
+void run_mix_frag(const MixList& m, const std::vector<double*>& b) {
+  for (const auto& t : m.t) {
+    double* D = base_ptr(b, t.prob, t.dbase);
+    for (int r = 0; r < t.rows; ++r)
+      for (int c = 0; c < t.cols; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < t.nsrc; ++k) {
+          const MixSrc& x = m.src[t.src0 + k];
+          const double* S = base_ptr(b, t.prob, x.base) + x.off;
+          s += x.coef * (x.trans ? S[(int64_t)c * x.ld + r] : S[(int64_t)r * x.ld + c]);
+        }
+        const int64_t i = frag_slot(t.doff, t.ldd, t.r0 + r, t.c0 + c);
+        D[i] = s;
+        D[i + kFragWords] = 0.0;
+      }
+  }
+}
+
 }  // namespace
 
 extern "C" int hostplan_heff(const idmrg_heff* H, const double* x, double* y) {
@@ -71,6 +130,46 @@ extern "C" int hostplan_heff(const idmrg_heff* H, const double* x, double* y) {
     run_mix(p.mixY, b);
     run_mix(p.mixT, b);
     run_gemm(p.g2, 1, b);
+    return 0;
+  } catch (...) {
+    return -1;
+  }
+}
+
+// The split-bf16 form of the same plan: packs, fragment GEMMs and the mixing
+// into the fragment form of T3.  Fragment buffers start as NaN except T3's,
+// which starts as zero like its device buffer, so a read of any slot that no
+// pack wrote shows up in y.
+extern "C" int hostplan_heff_frag(const idmrg_heff* H, const double* x, double* y) {
+  try {
+    HeffPlan p;
+    const Leg A = make_leg(H->left, "A"), B = make_leg(H->right, "B");
+    build_heff(p, 0, A, B, make_mpo(H->w1, "w1"), make_mpo(H->w2, "w2"));
+    const double nan = std::nan("");
+    std::vector<double> Lf(2 * p.n_Lf[0] + 2, nan), Rf(2 * p.n_Rf[0] + 2, nan), Xf(2 * p.n_Xf[0] + 2, nan),
+        T1(p.n_T1[0] + 1), T3f(2 * p.n_T3f[0] + 2, 0.0);
+    std::vector<double*> src(kNumBases, nullptr), b(kNumBases, nullptr);
+    src[0] = (double*)H->L; src[1] = (double*)H->R; src[2] = (double*)x;
+    b[0] = Lf.data(); b[1] = Rf.data(); b[2] = Xf.data(); b[3] = y; b[4] = T1.data(); b[5] = T3f.data();
+    b[6] = (double*)x;
+    std::vector<int64_t> ss(kNumBases, -1), sz(kNumBases, -1);
+    ss[0] = p.n_L[0]; ss[1] = p.n_R[0]; ss[2] = p.n_psi[0];
+    sz[0] = p.n_Lf[0]; sz[1] = p.n_Rf[0]; sz[2] = p.n_Xf[0]; sz[3] = sz[6] = p.n_psi[0]; sz[4] = p.n_T1[0];
+    sz[5] = p.n_T3f[0];
+    check_pack(p.packL, ss, sz, "packL");
+    check_pack(p.packR, ss, sz, "packR");
+    check_pack(p.packX, ss, sz, "packX");
+    check_gemm_frag(p.f1, sz, "f1");
+    check_mix(p.mixY, sz, "mixY");
+    check_mix_frag(p.mixTf, sz, "mixTf");
+    check_gemm_frag(p.f2, sz, "f2");
+    run_pack(p.packL, src, b);
+    run_pack(p.packR, src, b);
+    run_pack(p.packX, src, b);
+    run_gemm_frag(p.f1, b);
+    run_mix(p.mixY, b);
+    run_mix_frag(p.mixTf, b);
+    run_gemm_frag(p.f2, b);
     return 0;
   } catch (...) {
     return -1;

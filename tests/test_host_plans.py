@@ -83,11 +83,13 @@ def _mpo_pair(name, c1):
 
 LEGS = [([(-1, 3), (1, 2)], [(-1, 2), (1, 3)]),
         ([(-3, 5), (-1, 9), (1, 8), (3, 2)], [(-3, 3), (-1, 7), (1, 10), (3, 4)]),
-        ([(-5, 1), (-3, 6), (-1, 7), (1, 9), (3, 4), (5, 2)], [(-5, 2), (-3, 5), (-1, 8), (1, 6), (3, 3), (5, 1)])]
+        ([(-5, 1), (-3, 6), (-1, 7), (1, 9), (3, 4), (5, 2)], [(-5, 2), (-3, 5), (-1, 8), (1, 6), (3, 3), (5, 1)]),
+        # several 16-row and 32-k fragments per block, with ragged edges
+        ([(-3, 23), (-1, 37), (1, 41), (3, 19)], [(-3, 17), (-1, 45), (1, 33), (3, 21)])]
 
 
 @pytest.mark.parametrize("name,c1", [("chain", 1), ("yc4", 3), ("yc8", 4), ("yc8", 9), ("dimer", 2)])
-@pytest.mark.parametrize("li", [0, 1, 2])
+@pytest.mark.parametrize("li", [0, 1, 2, 3])
 def test_heff_plan_on_host(lib, hostplan, name, c1, li):
     (W1, W2, dl, dm, dr), (M1, M2) = _mpo_pair(name, c1)
     A, B = LEGS[li]
@@ -99,6 +101,10 @@ def test_heff_plan_on_host(lib, hostplan, name, c1, li):
     h = lib.Heff_t(k.leg(A), k.leg(B), k.mpo(M1), k.mpo(M2), C.c_void_p(Lf.ctypes.data), C.c_void_p(Rf.ctypes.data))
     y = np.full(nx, np.nan)
     assert hostplan.hostplan_heff(C.byref(h), C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data)) == 0
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    # the split-bf16 form of the plan (fragment-layout operands), executed in FP64
+    y = np.full(nx, np.nan)
+    assert hostplan.hostplan_heff_frag(C.byref(h), C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data)) == 0
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
