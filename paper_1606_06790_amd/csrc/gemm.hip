@@ -249,19 +249,27 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
 // plane, 64 lanes x 16 bytes each, and the fragments of a row block are
 // consecutive in k.  Tile BM x BN (64 or 128 each), K-slab 32, 2 x 2 waves of
 // (BM/2) x (BN/2).  Per slab the workgroup copies BM/16 + BN/16 fragments
-// (16-byte loads from one uniform base plus a fixed per-thread offset, all
-// coalesced; rows past the operand repeat its last row block) unchanged into
-// LDS, where each wave reads its operands with conflict-free 16-byte reads.
-// Zero padding of the layout makes the K tail exact.  Two LDS stages: the next
-// slab is loaded into registers during the MFMAs and stored to the other stage,
-// so each slab needs one barrier.
+// straight from global memory into LDS (global_load_lds_dwordx4: 16 bytes per
+// lane, lane l to LDS base + 16 l, so each wave copies 64 consecutive chunks
+// of a fragment; the global offsets are fixed per thread and the slab moves a
+// uniform base; rows past the operand repeat its last row block).  Each wave
+// then reads its operands with conflict-free 16-byte LDS reads.  Zero padding
+// of the layout makes the K tail exact.  Two LDS stages: the copy of slab k + 1
+// is in flight while slab k is multiplied.  (A third stage does not pay: at
+// 96 KB of LDS only one workgroup fits on a CU.)
+
+// 16 bytes per lane from global memory straight to LDS: lane l writes dst + 16 l
+// (dst must be the same for the whole wave).
+__device__ __forceinline__ void lds_copy16(gptr<char> src, v4u* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
 
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __restrict__ tasks, int ntask,
                                                           void* const* __restrict__ bases,
                                                           const int32_t* __restrict__ active, int ntiles) {
   constexpr int FA = BM / 16, FB = BN / 16;    // fragments per slab
-  constexpr int UA = FA / 2, UB = FB / 2;      // 16-byte units per thread per slab (2 fragments per 256 threads)
+  constexpr int UA = FA / 2, UB = FB / 2;      // 16-byte copies per thread per slab (2 fragments per 256 threads)
   constexpr int TI = BM / 32, TJ = BN / 32;    // 16 x 16 MFMA tiles per wave
   constexpr uint32_t kFragBytes = kFragWords * 4;
   __shared__ v4u As[2][FA * 128], Bs[2][FB * 128];
@@ -282,8 +290,9 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // Unit u of thread t is fragment 2u + t/128 of the slab, bytes 16 (t % 128)
-  // of it; byte offsets of slab 0 (32-bit: checked on the host).
+  // Copy u of thread t: fragment 2u + t/128 of the slab, chunk t % 128 of it
+  // (byte offsets of slab 0: 32-bit, checked on the host).  LDS destination of
+  // the wave: chunk 64 (wave % 2) of that fragment.
   const int half = t >> 7, within = t & 127;
   uint32_t ao[UA], bo[UB];
 #pragma unroll
@@ -296,20 +305,14 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
     const int rb = min(n0 / kFragRows + 2 * u + half, RB - 1);
     bo[u] = (uint32_t)rb * (uint32_t)KB * kFragBytes + within * 16u;
   }
-  v4u ra[UA], rb[UB];
-  auto load = [&](int kb) {
+  const int wdst = half * 128 + (wave & 1) * 64;
+  auto copy = [&](int kb, int st) {
     const gptr<char> Ak = as_global(A + (size_t)kb * kFragBytes);
     const gptr<char> Bk = as_global(B + (size_t)kb * kFragBytes);
 #pragma unroll
-    for (int u = 0; u < UA; ++u) ra[u] = *reinterpret_cast<gptr<v4u>>(Ak + ao[u]);
+    for (int u = 0; u < UA; ++u) lds_copy16(Ak + ao[u], &As[st][u * 256 + wdst]);
 #pragma unroll
-    for (int u = 0; u < UB; ++u) rb[u] = *reinterpret_cast<gptr<v4u>>(Bk + bo[u]);
-  };
-  auto store = [&](int st) {
-#pragma unroll
-    for (int u = 0; u < UA; ++u) As[st][(2 * u + half) * 128 + within] = ra[u];
-#pragma unroll
-    for (int u = 0; u < UB; ++u) Bs[st][(2 * u + half) * 128 + within] = rb[u];
+    for (int u = 0; u < UB; ++u) lds_copy16(Bk + bo[u], &Bs[st][u * 256 + wdst]);
   };
 
   v4f acc[TI][TJ];
@@ -318,15 +321,12 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = v4f{0, 0, 0, 0};
 
-  if (KB > 0) {
-    load(0);
-    store(0);
-  }
-  __syncthreads();
+  if (KB > 0) copy(0, 0);
   for (int kb = 0; kb < KB; ++kb) {
     const int cur = kb & 1;
-    const bool more = kb + 1 < KB;
-    if (more) load(kb + 1);
+    // this slab's copy has landed in every wave; the other stage is free
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
     v8bf ah[TI], al[TI], bh[TJ], bl[TJ];
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
@@ -340,6 +340,10 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
       bh[j] = __builtin_bit_cast(v8bf, Bs[cur][f * 128 + lane]);
       bl[j] = __builtin_bit_cast(v8bf, Bs[cur][f * 128 + 64 + lane]);
     }
+    // The next slab's copy goes out after this slab's LDS reads: the compiler
+    // makes an LDS read that follows an LDS copy wait for it, and the reads are
+    // what the MFMAs wait on.  It lands during the MFMAs.
+    if (kb + 1 < KB) copy(kb + 1, cur ^ 1);
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -348,8 +352,6 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
-    if (more) store(cur ^ 1);
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < TI; ++i)

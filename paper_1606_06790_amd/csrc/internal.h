@@ -32,7 +32,9 @@ struct GemmTask {
 
 // D[rows x cols] = sum_k coef_k * S_k   (S_k[r][c] at off + r*ld + c, or off + c*ld + r if trans)
 // In fragment output mode (split-bf16 T3) output (r, c) is element (r0 + r, c0 + c)
-// of a fragment-layout matrix at doff with ldd = its k-fragments per row block.
+// of a fragment-layout matrix at doff with ldd = its k-fragments per row block;
+// c0 is a multiple of 8 and the columns up to the next multiple of 8 past cols
+// are written as zeros.
 struct MixTask {
   int32_t rows, cols, ldd, prob;
   int32_t dbase, nsrc, src0, tile0;
@@ -69,14 +71,17 @@ struct ScaleTask {
 // fed to the MFMA without any rearrangement.
 constexpr int kFragRows = 16, kFragK = 32, kFragWords = 512;
 
-// Pack of an FP64 block Z[R x K] into the fragment layout: Z(r, k) at
-// soff + r * ld + k (trans: soff + k * ld + r) in source base sbase; the
-// fragments at word doff of destination base dbase (hi = bf16(float(z)),
-// lo = bf16(float(z) - hi), both rounded to nearest even).
+// Pack of an FP64 block Z[R x K] into columns [kc0, kc0 + 8 nch) of a
+// fragment-layout matrix (KB k-fragments per row block, at word doff of
+// destination base dbase): Z(r, k) at soff + r * ld + k (trans: soff + k * ld
+// + r) in source base sbase goes to column kc0 + k; the 8-wide chunks are
+// written whole for rows 0 .. 16 RB - 1, with zeros outside [R x K] (K = 0
+// writes zeros only).  kc0 is a multiple of 8.  hi = bf16(float(z)),
+// lo = bf16(float(z) - hi), both rounded to nearest even.
 struct PackTask {
   int32_t R, K, ld, trans;
   int32_t prob, sbase, dbase, tile0;
-  int32_t RB, KB, pad0, pad1;   // ceil(R / 16), ceil(K / 32)
+  int32_t RB, KB, kc0, nch;     // RB = ceil(R / 16)
   int64_t soff, doff;
 };
 
@@ -151,7 +156,8 @@ void launch_scale(const ScaleTask* tasks, const int32_t* colmaps, int ntask, int
 // element conversions (n elements): kind 0 double -> float, kind 1 float -> double
 void launch_convert(int kind, const void* src, void* dst, int64_t n, hipStream_t s);
 
-// Fragment packs (4 fragments per tile); sources are read through sbases, results written through dbases.
+// Fragment packs (256 row-chunks of 8 values per tile); sources are read through sbases, results written
+// through dbases.
 void launch_pack(const PackTask* tasks, int ntask, int ntiles, void* const* sbases, void* const* dbases,
                  const int32_t* active, hipStream_t s);
 

@@ -37,9 +37,6 @@ __device__ __forceinline__ int find_tile(const int32_t* tile0, int stride_words,
   return lo;
 }
 
-// Output tag of the mix kernel: split-bf16 pairs in the fragment layout.
-struct FragOut {};
-
 template <typename TIN, typename TOUT>
 __global__ __launch_bounds__(256) void mix_kernel(const MixTask* __restrict__ tasks, const MixSrc* __restrict__ srcs,
                                                   int ntask, void* const* __restrict__ bases,
@@ -69,67 +66,105 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixTask* __restrict__ ta
       }
     }
   }
-  if constexpr (std::is_same<TOUT, FragOut>::value) {
-    // element (r0 + r, c0 + c) of the fragment matrix: the word of its hi part is in
-    // fragment (row / 16, k / 32) at lane (row % 16) + 16 (k % 32 / 8); the lo part
-    // is half a fragment (256 words) further
-    uint16_t* dst = reinterpret_cast<uint16_t*>(bases[tk.prob * kNumBases + tk.dbase]) + 2 * tk.doff;
-    const int kk = tk.c0 + c;
+  TOUT* dst = reinterpret_cast<TOUT*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int r = rbase + 4 * e;
-      if (r < tk.rows) {
-        const int R = tk.r0 + r;
-        const int64_t w = ((int64_t)(R >> 4) * tk.ldd + (kk >> 5)) * kFragWords +
-                          ((R & 15) + 16 * ((kk & 31) >> 3)) * 4 + ((kk & 7) >> 1);
-        const uint32_t v = split_bf16((float)acc[e]);
-        dst[2 * w + (kk & 1)] = (uint16_t)(v & 0xffffu);
-        dst[2 * (w + kFragWords / 2) + (kk & 1)] = (uint16_t)(v >> 16);
-      }
-    }
-  } else {
-    TOUT* dst = reinterpret_cast<TOUT*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int r = rbase + 4 * e;
-      if (r < tk.rows) dst[(int64_t)r * tk.ldd + c] = (TOUT)acc[e];
-    }
+  for (int e = 0; e < 8; ++e) {
+    const int r = rbase + 4 * e;
+    if (r < tk.rows) dst[(int64_t)r * tk.ldd + c] = (TOUT)acc[e];
   }
 }
 
-// One thread per (fragment, lane): the 8 values of one row in one 32-wide k
-// block, stored as 16 bytes of the hi plane and 16 bytes of the lo plane, so a
-// wave writes 2 KB contiguously.  Values outside [R x K] are zeros.
+// Word offset, inside its fragment matrix (kb k-fragments per row block), of
+// the 8-value chunk of the hi plane that holds row r, columns k8 .. k8 + 7
+// (k8 a multiple of 8); the lo plane's chunk is half a fragment further.
+__device__ __forceinline__ int64_t frag_chunk(int r, int k8, int kb) {
+  return ((int64_t)(r >> 4) * kb + (k8 >> 5)) * kFragWords + ((r & 15) + 16 * ((k8 & 31) >> 3)) * 4;
+}
+
+// Split-bf16 pairs of 8 consecutive values, as the hi and lo chunks of a fragment lane.
+__device__ __forceinline__ void split8(const float (&v)[8], uint4& hi, uint4& lo) {
+  uint32_t h[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    const uint32_t p0 = split_bf16(v[e]), p1 = split_bf16(v[e + 1]);
+    h[e / 2] = (p0 & 0xffffu) | (p1 << 16);
+    l[e / 2] = (p0 >> 16) | (p1 & 0xffff0000u);
+  }
+  hi = make_uint4(h[0], h[1], h[2], h[3]);
+  lo = make_uint4(l[0], l[1], l[2], l[3]);
+}
+
+// The mixing with output in the fragment layout (T3 of the split-bf16 policy).
+// Same 32 x 64 tiles as mix_kernel, but each thread produces 8 consecutive
+// columns of one row (row t / 8, chunk t % 8 of the tile) and stores them as
+// one 16-byte hi chunk and one 16-byte lo chunk; columns past the task's end,
+// up to the chunk's end, are zeros.  Accumulation in double as in mix_kernel.
+__global__ __launch_bounds__(256) void mix_frag_kernel(const MixTask* __restrict__ tasks,
+                                                       const MixSrc* __restrict__ srcs, int ntask,
+                                                       void* const* __restrict__ bases,
+                                                       const int32_t* __restrict__ active) {
+  const int tile = blockIdx.x;
+  const MixTask& tk = tasks[find_tile(&tasks[0].tile0, sizeof(MixTask) / 4, ntask, tile)];
+  if (active && !active[tk.prob]) return;
+  const int local = tile - tk.tile0;
+  const int r = (local / tk.tiles_c) * MR + (threadIdx.x >> 3);
+  const int c0 = (local % tk.tiles_c) * MC + 8 * (threadIdx.x & 7);
+  if (r >= tk.rows || c0 >= tk.cols) return;
+  const int nc = min(8, tk.cols - c0);
+  double acc[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) acc[e] = 0.0;
+  for (int k = 0; k < tk.nsrc; ++k) {
+    const MixSrc& s = srcs[tk.src0 + k];
+    const float* S = reinterpret_cast<const float*>(bases[tk.prob * kNumBases + s.base]) + s.off;
+    const double coef = s.coef;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (e < nc) acc[e] += coef * (double)(s.trans ? S[(int64_t)(c0 + e) * s.ld + r] : S[(int64_t)r * s.ld + c0 + e]);
+  }
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = (float)acc[e];
+  uint4 hi, lo;
+  split8(v, hi, lo);
+  uint4* D = reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff +
+                                      frag_chunk(tk.r0 + r, tk.c0 + c0, tk.ldd));
+  D[0] = hi;
+  D[kFragWords / 8] = lo;
+}
+
+// One thread per row chunk: 8 consecutive columns of one row, stored as the
+// 16-byte hi and lo chunks of one fragment lane.  Threads run over (row block,
+// chunk, row % 16), so 16 consecutive threads write 256 contiguous bytes.
+// Values outside [R x K] are zeros.
 __global__ __launch_bounds__(256) void pack_kernel(const PackTask* __restrict__ tasks, int ntask,
                                                    void* const* __restrict__ sbases, void* const* __restrict__ dbases,
                                                    const int32_t* __restrict__ active) {
   const int tile = blockIdx.x;
   const PackTask& tk = tasks[find_tile(&tasks[0].tile0, sizeof(PackTask) / 4, ntask, tile)];
   if (active && !active[tk.prob]) return;
-  const int64_t f = (int64_t)(tile - tk.tile0) * 4 + (threadIdx.x >> 6);
-  if (f >= (int64_t)tk.RB * tk.KB) return;
-  const int lane = threadIdx.x & 63;
-  const int r = (int)(f / tk.KB) * kFragRows + (lane & 15);
-  const int k0 = (int)(f % tk.KB) * kFragK + 8 * (lane >> 4);
+  const int64_t i = (int64_t)(tile - tk.tile0) * 256 + threadIdx.x;
+  if (i >= (int64_t)tk.RB * tk.nch * 16) return;
+  const int rr = (int)(i & 15);
+  const int64_t q = i >> 4;
+  const int ch = (int)(q % tk.nch);
+  const int r = (int)(q / tk.nch) * kFragRows + rr;
+  const int k0 = 8 * ch;
   const double* S = reinterpret_cast<const double*>(sbases[tk.prob * kNumBases + tk.sbase]) + tk.soff;
-  uint32_t h[4], l[4];
+  float v[8];
 #pragma unroll
-  for (int e = 0; e < 8; e += 2) {
-    uint32_t pr[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int k = k0 + e + u;
-      double v = 0.0;
-      if (r < tk.R && k < tk.K) v = tk.trans ? S[(int64_t)k * tk.ld + r] : S[(int64_t)r * tk.ld + k];
-      pr[u] = split_bf16((float)v);
-    }
-    h[e / 2] = (pr[0] & 0xffffu) | (pr[1] << 16);
-    l[e / 2] = (pr[0] >> 16) | (pr[1] & 0xffff0000u);
+  for (int e = 0; e < 8; ++e) {
+    const int k = k0 + e;
+    double x = 0.0;
+    if (r < tk.R && k < tk.K) x = tk.trans ? S[(int64_t)k * tk.ld + r] : S[(int64_t)r * tk.ld + k];
+    v[e] = (float)x;
   }
+  uint4 hi, lo;
+  split8(v, hi, lo);
   uint4* D = reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(dbases[tk.prob * kNumBases + tk.dbase]) + tk.doff +
-                                      f * kFragWords);
-  D[lane] = make_uint4(h[0], h[1], h[2], h[3]);
-  D[64 + lane] = make_uint4(l[0], l[1], l[2], l[3]);
+                                      frag_chunk(r, tk.kc0 + k0, tk.KB));
+  D[0] = hi;
+  D[kFragWords / 8] = lo;
 }
 
 __global__ __launch_bounds__(256) void scale_kernel(const ScaleTask* __restrict__ tasks, const int32_t* __restrict__ colmaps,
@@ -181,7 +216,7 @@ void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int
   else if (tin == 1 && tout == 1)
     hipLaunchKernelGGL((mix_kernel<float, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
   else if (tin == 1 && tout == 3)
-    hipLaunchKernelGGL((mix_kernel<float, FragOut>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
+    hipLaunchKernelGGL(mix_frag_kernel, grid, block, 0, s, tasks, srcs, ntask, bases, active);
   else if (tin == 0 && tout == 1)
     hipLaunchKernelGGL((mix_kernel<double, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
 }

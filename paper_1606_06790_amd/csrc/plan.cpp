@@ -272,21 +272,26 @@ int64_t frag_words(int R, int K) {
 }
 
 void PackList::add(PackTask p) {
-  if (p.R <= 0 || p.K <= 0) return;
+  if (p.R <= 0 || p.nch <= 0) return;
   p.RB = (p.R + kFragRows - 1) / kFragRows;
-  p.KB = (p.K + kFragK - 1) / kFragK;
   p.tile0 = tiles;
-  tiles += (int)(((int64_t)p.RB * p.KB + 3) / 4);
+  tiles += (int)(((int64_t)p.RB * p.nch + 15) / 16);
   t.push_back(p);
 }
 
-static PackTask packtask(int prob, int R, int K, int sbase, int64_t soff, int ld, int trans, int dbase, int64_t doff) {
+// Pack of Z[R x K] into columns kc0 .. kc0 + 8 nch - 1 of a fragment matrix with KB k-fragments per row block.
+static PackTask packtask(int prob, int R, int K, int sbase, int64_t soff, int ld, int trans, int dbase, int64_t doff,
+                         int KB, int kc0, int nch) {
   PackTask p{};
   p.R = R; p.K = K; p.ld = ld; p.trans = trans;
   p.prob = prob; p.sbase = sbase; p.dbase = dbase;
+  p.KB = KB; p.kc0 = kc0; p.nch = nch;
   p.soff = soff; p.doff = doff;
   return p;
 }
+
+static int kfrags(int K) { return (K + kFragK - 1) / kFragK; }
+static int round8(int n) { return (n + 7) / 8 * 8; }
 
 static GemmTask gemm(int prob, int M, int N, int K, int ab, int64_t ao, int lda, int bb, int64_t bo, int ldb, int cb,
                      int64_t co, int ldc, int beta) {
@@ -371,24 +376,44 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
   for (int a = 0; a < A.n(); ++a) {
     if (EL.rows[a] == 0) continue;
     lf[a] = nLf;
-    p.packL.add(packtask(prob, EL.rows[a], A.dim[a], 0, EL.stack_off[a], A.dim[a], 0, 0, nLf));
+    p.packL.add(packtask(prob, EL.rows[a], A.dim[a], 0, EL.stack_off[a], A.dim[a], 0, 0, nLf, kfrags(A.dim[a]), 0,
+                         4 * kfrags(A.dim[a])));
     nLf += frag_words(EL.rows[a], A.dim[a]);
   }
   for (size_t x = 0; x < X.blk.size(); ++x) {
     const auto& k = X.blk[x];
     if (t1off[x] < 0) continue;
     xf[x] = nXf;   // B = x block [da x db], N-contiguous: fragment rows are its columns
-    p.packX.add(packtask(prob, k.db, k.da, 2, k.off, k.db, 1, 2, nXf));
+    p.packX.add(packtask(prob, k.db, k.da, 2, k.off, k.db, 1, 2, nXf, kfrags(k.da), 0, 4 * kfrags(k.da)));
     nXf += frag_words(k.db, k.da);
     p.f1.add(gemm(prob, EL.rows[k.a], k.db, k.da, 0, lf[k.a], 0, 2, xf[x], 0, 4, t1off[x], k.db, 0));
   }
+  // K of T3 and R in the fragment form: channel u of right sector b starts at cpad[b][u], a multiple of 8
+  std::vector<std::vector<int>> cpad(B.n());
+  std::vector<int> Kp(B.n(), 0);
+  for (int b = 0; b < B.n(); ++b) {
+    cpad[b].assign(DR, -1);
+    for (int u = 1; u < DR; ++u) {
+      if (ER.col_off[b][u] < 0) continue;
+      cpad[b][u] = Kp[b];
+      Kp[b] += round8(B.dim[ER.b_in[b][u]]);
+    }
+  }
   for (int b = 0; b < B.n(); ++b) {
     if (ER.K[b] == 0 || X.b_rows[b] == 0) continue;
+    const int KB = kfrags(Kp[b]);
     t3f[b] = nT3f;
-    nT3f += frag_words(X.b_rows[b], ER.K[b]);
+    nT3f += frag_words(X.b_rows[b], Kp[b]);
     rf[b] = nRf;
-    p.packR.add(packtask(prob, B.dim[b], ER.K[b], 1, ER.off[b], ER.K[b], 0, 1, nRf));
-    nRf += frag_words(B.dim[b], ER.K[b]);
+    for (int u = 1; u < DR; ++u) {
+      if (cpad[b][u] < 0) continue;
+      const int du = B.dim[ER.b_in[b][u]];
+      p.packR.add(packtask(prob, B.dim[b], du, 1, ER.off[b] + ER.col_off[b][u], ER.K[b], 0, 1, nRf, KB, cpad[b][u],
+                           (du + 7) / 8));
+    }
+    // zeros past the last channel, to the end of the last k-fragment
+    p.packR.add(packtask(prob, B.dim[b], 0, 1, 0, 0, 0, 1, nRf, KB, Kp[b], (KB * kFragK - Kp[b]) / 8));
+    nRf += frag_words(B.dim[b], Kp[b]);
   }
   const auto terms = w12_terms(W1, W2);
   // Source of T1[w](a, t1, t2, b') = (L[w] x)(a, ...): psi block (a', t1, t2) with a' = a - ql[w]
@@ -427,9 +452,9 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
         for (const auto& tm : it->second) source(ko.a, tm.w, tm.t1, tm.t2, bp, tm.c, s);
       p.mixT.add(mixtask(prob, ko.da, B.dim[bp], 5, t3off[ko.b] + (int64_t)rowin[xo] * ER.K[ko.b] + co, ER.K[ko.b]),
                  s);
-      MixTask mf = mixtask(prob, ko.da, B.dim[bp], 5, t3f[ko.b], (ER.K[ko.b] + kFragK - 1) / kFragK);
+      MixTask mf = mixtask(prob, ko.da, B.dim[bp], 5, t3f[ko.b], kfrags(Kp[ko.b]));
       mf.r0 = rowin[xo];
-      mf.c0 = co;
+      mf.c0 = cpad[ko.b][u];
       p.mixTf.add(mf, s);
     }
   }
@@ -437,7 +462,7 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
     if (ER.K[b] == 0 || X.b_rows[b] == 0) continue;
     p.g2.add(gemm(prob, X.b_rows[b], B.dim[b], ER.K[b], 5, t3off[b], ER.K[b], 1, ER.off[b], ER.K[b], 3,
                   X.b_first[b], B.dim[b], 1));
-    p.f2.add(gemm(prob, X.b_rows[b], B.dim[b], ER.K[b], 5, t3f[b], 0, 1, rf[b], 0, 3, X.b_first[b], B.dim[b], 1));
+    p.f2.add(gemm(prob, X.b_rows[b], B.dim[b], Kp[b], 5, t3f[b], 0, 1, rf[b], 0, 3, X.b_first[b], B.dim[b], 1));
   }
   p.n_psi.push_back(X.size);
   p.n_Lf.push_back(nLf);
@@ -511,8 +536,8 @@ void check_mix_frag(const MixList& m, const std::vector<int64_t>& sizes, const c
   for (const auto& t : m.t) {
     if (t.rows <= 0 || t.cols <= 0) continue;
     // the destination is a fragment matrix with ldd k-fragments per row block; the
-    // task covers rows [r0, r0 + rows) and columns [c0, c0 + cols) of it
-    if (t.r0 < 0 || t.c0 < 0 || t.c0 + t.cols > t.ldd * kFragK)
+    // task writes rows [r0, r0 + rows) and columns [c0, c0 + round8(cols)) of it
+    if (t.r0 < 0 || t.c0 < 0 || t.c0 % 8 != 0 || t.c0 + round8(t.cols) > t.ldd * kFragK)
       throw InvalidArg(std::string("internal: ") + what + " fragment block outside its matrix");
     const int64_t last = t.doff + ((int64_t)((t.r0 + t.rows - 1) / kFragRows) * t.ldd + t.ldd) * kFragWords - 1;
     in_bounds(t.doff, last, sizes, t.prob, t.dbase, what);
@@ -528,10 +553,14 @@ void check_mix_frag(const MixList& m, const std::vector<int64_t>& sizes, const c
 void check_pack(const PackList& pl, const std::vector<int64_t>& ssizes, const std::vector<int64_t>& dsizes,
                 const char* what) {
   for (const auto& t : pl.t) {
-    const int64_t hi = t.trans ? t.soff + (int64_t)(t.K - 1) * t.ld + t.R - 1
-                               : t.soff + (int64_t)(t.R - 1) * t.ld + t.K - 1;
-    in_bounds(t.soff, hi, ssizes, t.prob, t.sbase, what);
-    in_bounds(t.doff, frag_last(t.doff, t.R, t.K, what), dsizes, t.prob, t.dbase, what);
+    if (t.K > 0) {
+      const int64_t hi = t.trans ? t.soff + (int64_t)(t.K - 1) * t.ld + t.R - 1
+                                 : t.soff + (int64_t)(t.R - 1) * t.ld + t.K - 1;
+      in_bounds(t.soff, hi, ssizes, t.prob, t.sbase, what);
+    }
+    if (t.kc0 < 0 || t.kc0 % 8 != 0 || t.K > 8 * t.nch || t.kc0 + 8 * t.nch > t.KB * kFragK)
+      throw InvalidArg(std::string("internal: ") + what + " pack outside its fragment matrix");
+    in_bounds(t.doff, frag_last(t.doff, t.R, t.KB * kFragK, what), dsizes, t.prob, t.dbase, what);
   }
 }
 

@@ -112,7 +112,7 @@ struct ScaleList {
 struct PackList {
   std::vector<PackTask> t;
   int tiles = 0;
-  void add(PackTask p);              // fills RB, KB, tile0 (4 fragments per tile)
+  void add(PackTask p);              // fills RB, tile0 (256 row-chunks per tile)
 };
 
 // Words of a [R x K] matrix in the fragment layout.
@@ -131,6 +131,8 @@ struct HeffPlan {
   MixList mixTf;
   PackList packL, packR, packX;
   std::vector<int64_t> n_Lf, n_Rf, n_Xf, n_T3f;   // words, per problem
+  // In the fragment form the K index of T3 and R (channel u, column b') is
+  // re-spaced so that each channel's block starts at a multiple of 8.
 };
 // heff bases: 0 L, 1 R, 2 x (GEMM operand), 3 y, 4 T1, 5 T3, 6 x (mix operand).
 // Fragment form: 0 L, 1 R, 2 x, 5 T3 in the fragment layout; 3 y, 4 T1, 6 x as

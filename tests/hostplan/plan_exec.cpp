@@ -61,11 +61,11 @@ int64_t frag_slot(int64_t word_off, int KB, int r, int k) {
 
 void run_pack(const PackList& pl, const std::vector<double*>& src, const std::vector<double*>& dst) {
   for (const auto& t : pl.t) {
-    const double* S = base_ptr(src, t.prob, t.sbase) + t.soff;
+    const double* S = t.K > 0 ? base_ptr(src, t.prob, t.sbase) + t.soff : nullptr;
     double* D = base_ptr(dst, t.prob, t.dbase);
     for (int r = 0; r < t.RB * kFragRows; ++r)
-      for (int k = 0; k < t.KB * kFragK; ++k) {
-        const int64_t i = frag_slot(t.doff, t.KB, r, k);
+      for (int k = 0; k < 8 * t.nch; ++k) {
+        const int64_t i = frag_slot(t.doff, t.KB, r, t.kc0 + k);
         D[i] = r < t.R && k < t.K ? (t.trans ? S[(int64_t)k * t.ld + r] : S[(int64_t)r * t.ld + k]) : 0.0;
         D[i + kFragWords] = 0.0;
       }
@@ -104,6 +104,13 @@ void run_mix_frag(const MixList& m, const std::vector<double*>& b) {
         }
         const int64_t i = frag_slot(t.doff, t.ldd, t.r0 + r, t.c0 + c);
         D[i] = s;
+        D[i + kFragWords] = 0.0;
+      }
+    // the chunk holding the last column is written whole: zeros past it
+    for (int r = 0; r < t.rows; ++r)
+      for (int c = t.cols; c % 8 != 0; ++c) {
+        const int64_t i = frag_slot(t.doff, t.ldd, t.r0 + r, t.c0 + c);
+        D[i] = 0.0;
         D[i + kFragWords] = 0.0;
       }
   }
