@@ -90,6 +90,18 @@ def timed(d, prec, steps, warmup):
                 prof=prof, recs=recs)
 
 
+def copy_calibration():
+    """A plain device copy of known size, the reference that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": a.numel() * 8, "copies": 3}), flush=True)
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bench_yc8_m2048_traffic.md")
 TRAFFIC_SOURCES = ["paper_1606_06790_amd/csrc/gemm.hip", "paper_1606_06790_amd/csrc/plan.cpp",
                    "paper_1606_06790_amd/csrc/api.cpp"]
@@ -144,10 +156,15 @@ def main():
     ap.add_argument("--mixed", default="bf16x3", choices=["f32", "bf16x3"])
     ap.add_argument("--workload", default="yc8")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy three times (reference for HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU (one process, no collectives); use --gpus 1"}))
         sys.exit(2)
+    if a.copy_calibration:
+        copy_calibration()
+        return
     import workloads
     from paper_1606_06790_amd.driver import IDMRG
 
@@ -168,6 +185,7 @@ def main():
         return {"matvec_tflops": round(r["matvec_tflops"], 4), "ms_per_step": round(r["ms_per_step"], 2),
                 "lanczos_iters": [s["iters"] for s in r["recs"]],
                 "fp64_matvecs": [s["fp64_matvecs"] for s in r["recs"]],
+                "reorth_passes": [s["reorth_passes"] for s in r["recs"]],
                 "e_site": [round(s["e_site"], 12) for s in r["recs"]],
                 "residual_max": max(s["residual"] for s in r["recs"]),
                 "svd_sweeps": max(s["svd_sweeps"] for s in r["recs"]),

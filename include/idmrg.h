@@ -180,13 +180,17 @@ typedef struct {
     int32_t converged;    /* 1 if a stop rule other than k = k_max fired */
     int32_t fp64_matvecs; /* FP64 matvecs of the refinement (mixed precision) */
     int32_t flags;        /* bit 0: invariant subspace (beta ~ 0) */
+    int32_t reorth_passes; /* iterations that needed the second Gram-Schmidt pass */
+    int32_t reserved;
     double residual;      /* |H psi - e psi| (FP64 matvec) after the solve */
     double overlap0;      /* |<start/|start|, psi>|, so 1 - overlap0 is the fidelity error of Eq. (12) */
 } idmrg_lanczos_info;
 
 /* Lowest eigenpair of each H_p by Lanczos with full FP64 re-orthogonalisation
- * (classical Gram-Schmidt applied twice), FP64 tridiagonal eigensolver and
- * Ritz vector, all on the device (Step 3; Step 3' for the start vector).
+ * (classical Gram-Schmidt against the whole basis every iteration, after a
+ * shift by the first Rayleigh quotient; a second pass where the first removed
+ * more than 99 % of the vector's norm squared), FP64 tridiagonal eigensolver
+ * and Ritz vector, all on the device (Step 3; Step 3' for the start vector).
  * psi[p]: device, in: start vector (any nonzero norm), out: normalised ground
  * state.  energy[p], info[p]: host outputs.  Synchronises the stream.
  * Returns IDMRG_WARN_NOCONV if any problem stopped at k = k_max. */

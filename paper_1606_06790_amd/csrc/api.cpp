@@ -669,7 +669,8 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     }
     double* V = (double*)ensure(ctx, ctx->ws[WS_LZ], tot * 8);
     const size_t nsm = (size_t)P * kmax;
-    const size_t small_bytes = (size_t)P * kmax * kLzBlocks * 8 + 4 * nsm * 8 + P * sizeof(LzCtrl) + P * 4 + 4096;
+    const size_t small_bytes =
+        (size_t)P * (kmax + 1) * kLzBlocks * 8 + 4 * nsm * 8 + P * sizeof(LzCtrl) + P * 4 + 4096;
     char* sm = (char*)ensure(ctx, ctx->ws[WS_LZSMALL], small_bytes);
     double* partial = (double*)sm;
     double* alpha = partial + (size_t)P * kmax * kLzBlocks;
@@ -677,7 +678,8 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     double* ritz = beta + nsm;
     double* coef = ritz + nsm;
     LzCtrl* ctrl = (LzCtrl*)(coef + nsm);
-    int32_t* active = (int32_t*)(ctrl + P);
+    double* pnorm = (double*)(ctrl + P);   // [P][kLzBlocks]
+    int32_t* active = (int32_t*)(pnorm + (size_t)P * kLzBlocks);
     std::vector<double*> vv(P), ww(P);
     std::vector<LzProblem> probs(P);
     for (int p = 0; p < P; ++p) {
@@ -718,7 +720,7 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
         for (auto& e : row)
           if (!e) IDMRG_HIP(hipEventCreate(&e));
     std::vector<int32_t> going(P, 1);
-    std::vector<int> iters(P, 0), fp64mv(P, 0);
+    std::vector<int> iters(P, 0), fp64mv(P, 0), reorths(P, 0);
     std::vector<LzCtrl> fin(P), out(P);
     std::vector<double> ov0(P, 0.0);
     for (int outer = 0; outer < max_outer; ++outer) {
@@ -759,8 +761,8 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
           const int trial = (!tuned && &e == &bulk && trial_next < bulk.nvar) ? trial_next++ : -1;
           heff_run(ctx, e, vv, ww, active, trial);
           Prof pr(ctx, 4, 0.0);
-          lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, kmax, tolE, tolR, tolF, relF,
-                            s);
+          lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, pnorm, kmax, tolE, tolR, tolF,
+                            relF, s);
         }
         IDMRG_HIP(hipMemcpyAsync(act.data(), active, P * 4, hipMemcpyDeviceToHost, s));
         sync(ctx);
@@ -780,6 +782,7 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       for (int p = 0; p < P; ++p) {
         if (!going[p]) continue;
         iters[p] += out[p].iters;
+        reorths[p] += out[p].reorths;
         fp64mv[p] += 1;
         if (outer == 0) ov0[p] = out[p].overlap0;
         fin[p] = out[p];
@@ -803,6 +806,8 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       info[p].converged = mixed ? (going[p] ? 0 : 1) : fin[p].converged;
       info[p].fp64_matvecs = mixed ? fp64mv[p] : 0;
       info[p].flags = fin[p].flags;
+      info[p].reorth_passes = reorths[p];
+      info[p].reserved = 0;
       info[p].residual = fin[p].residual;
       if (!std::isfinite(fin[p].theta) || !std::isfinite(fin[p].residual)) {
         ctx->err = "non-finite energy or residual (problem " + std::to_string(p) + ")";

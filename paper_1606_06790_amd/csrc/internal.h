@@ -200,8 +200,10 @@ struct LzCtrl {     // device, one per problem
   int32_t converged;
   int32_t flags;
   int32_t kcap;
-  int32_t pad0, pad1;
-  double theta, theta_prev, beta_j, residual, norm0, overlap0, ynorm, pad2;
+  int32_t reorth;   // this iteration needs the second Gram-Schmidt pass
+  int32_t reorths;  // second passes so far
+  double theta, theta_prev, beta_j, residual, norm0, overlap0, ynorm;
+  double shift;     // sigma: from iteration 1 on, H - sigma I is orthogonalised (sigma = alpha_0)
 };
 
 constexpr int kLzBlocks = 512;   // partial-sum blocks per problem
@@ -210,9 +212,10 @@ constexpr int kLzMaxK = 1024;    // upper bound of k_max (tridiagonal kept in LD
 
 // ctrl[] and active[] are initialised by the host before lz_init.
 void lz_init(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s);
+// pnorm: [P][kLzBlocks] partial sums of the norm before orthogonalisation.
 void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* active, double* alpha, double* beta,
-                       double* ritz, double* coef, double* partial, int kmax, double tol_E, double tol_res,
-                       double tol_first, double rel_first, hipStream_t s);
+                       double* ritz, double* coef, double* partial, double* pnorm, int kmax, double tol_E,
+                       double tol_res, double tol_first, double rel_first, hipStream_t s);
 void lz_finish(int P, const LzProblem* probs, LzCtrl* ctrl, double* ritz, double* partial, int kmax, hipStream_t s);
 void lz_residual(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s);
 

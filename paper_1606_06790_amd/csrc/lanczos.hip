@@ -9,12 +9,22 @@
 // problem in fixed positions, then one workgroup adds them in a fixed tree.
 //
 // Iteration j (current vector v = q_j, w = H q_j on entry):
-//   c = Q^T w over q_0..q_j, alpha_j = c_j, w -= Q c   (first classical
-//       Gram-Schmidt pass; it contains the three-term step, since the
-//       coefficients of q_j and q_{j-1} are alpha_j and beta_{j-1})
-//   c = Q^T w, w -= Q c, |w|^2                          (second pass, CGS2)
+//   w -= sigma q_j (j > 0; sigma = alpha_0), |w|^2 before projection
+//   c = Q^T w over q_0..q_j, alpha_j = c_j + sigma, w -= Q c, |w|^2 after
+//       (classical Gram-Schmidt; it contains the three-term step, since the
+//       coefficients of q_j and q_{j-1} are alpha_j - sigma and beta_{j-1})
+//   only if |w| after < eta |w| before (or j = 0):
+//       c = Q^T w, w -= Q c, |w|^2                      (second pass)
 //   beta_j = |w|; lowest Ritz pair (theta, y) of T_{j+1}; stop test;
 //   otherwise q_{j+1} = w / beta_j.
+// One pass leaves w orthogonal to Q up to about eps |w before| / |w after|
+// (relative), so the second pass is needed only when the projection removes
+// most of w (the criterion of Daniel, Gragg, Kaufman and Stewart, here with
+// eta = 0.1, i.e. at most ~10 eps per step).  The shift matters: the effective
+// Hamiltonian carries the environments' energy as a large constant, and
+// without it |H q_j| would exceed beta_j by orders of magnitude every step.  It
+// is applied to w as its own rounding step before the projection, so that the
+// rounding error of the subtraction is projected out as well.
 //
 // The basis rows, v and w have the padded length ld (a multiple of
 // kLzAlign elements, zero beyond N), so every block's element range starts on
@@ -84,18 +94,34 @@ __device__ double sum_partials(const double* partial, int p, int i, int kmax, do
   return block_sum(x, sh);
 }
 
-// mode 0: alpha_j = sum;  mode 1: beta_j = sqrt(sum);  mode 2: norm0 = sqrt(sum);  mode 3: residual = sqrt(sum)
+constexpr double kReorthEta2 = 0.01;   // eta^2 of the second-pass criterion
+
+// mode 1: beta_j = sqrt(sum) (after a second pass, where there was one);
+// mode 2: norm0 = sqrt(sum);  mode 3: residual = sqrt(sum);
+// mode 4 (after the first pass): beta_j = sqrt(sum), and ctrl.reorth =
+// j == 0 or sum < eta^2 |w before|^2 (pnorm).
 __global__ __launch_bounds__(TB) void k_finalize(LzCtrl* ctrl, const int32_t* active, const double* partial,
-                                                 double* alpha, int kmax, int mode) {
+                                                 const double* pnorm, int kmax, int mode) {
   __shared__ double sh[TB];
   const int p = blockIdx.x;
   if (active && !active[p]) return;
+  if (mode == 1 && !ctrl[p].reorth) return;
   const double s = sum_partials(partial, p, 0, kmax, sh);
+  double before = 0.0;
+  if (mode == 4) {
+    double x = 0.0;
+    for (int b = threadIdx.x; b < kLzBlocks; b += TB) x += pnorm[(int64_t)p * kLzBlocks + b];
+    before = block_sum(x, sh);
+  }
   if (threadIdx.x == 0) {
-    if (mode == 0) alpha[(int64_t)p * kmax + ctrl[p].j] = s;
-    else if (mode == 1) ctrl[p].beta_j = sqrt(s);
-    else if (mode == 2) ctrl[p].norm0 = sqrt(s);
-    else ctrl[p].residual = sqrt(s);
+    LzCtrl& c = ctrl[p];
+    if (mode == 1 || mode == 4) c.beta_j = sqrt(s);
+    if (mode == 4) {
+      c.reorth = c.j == 0 || s < kReorthEta2 * before;
+      c.reorths += c.reorth;
+    }
+    if (mode == 2) c.norm0 = sqrt(s);
+    if (mode == 3) c.residual = sqrt(s);
   }
 }
 
@@ -132,22 +158,37 @@ constexpr int kSub = 4096;   // elements of w staged in LDS at a time
 // The block's slice of w goes through LDS kSub elements at a time; wave k
 // takes rows i = k, k + 4, ... and adds its row sums into acc[i] in a fixed
 // order, so the result does not depend on scheduling.
+// Pass 0 first replaces w by w - sigma v (j > 0) while staging it, and puts
+// the block's |w|^2 into pnorm[p][b]; pass 1 runs only where ctrl.reorth is set.
 __global__ __launch_bounds__(TB) void k_mdot(const LzProblem* probs, const LzCtrl* ctrl, const int32_t* active,
-                                             double* partial, int kmax) {
+                                             double* partial, double* pnorm, int kmax, int pass) {
   __shared__ __attribute__((aligned(16))) double xs[kSub];
   __shared__ double acc[kLzMaxK];
+  __shared__ double sh[TB];
   const int p = blockIdx.y, b = blockIdx.x;
-  if (!active[p]) return;
+  if (!active[p] || (pass == 1 && !ctrl[p].reorth)) return;
   const LzProblem pr = probs[p];
   const int j = ctrl[p].j;
+  const double sigma = pass == 0 && j > 0 ? ctrl[p].shift : 0.0;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   int64_t lo, hi;
   pad_range(pr.ld, b, lo, hi);
   for (int i = t; i <= j; i += TB) acc[i] = 0.0;
+  double nb = 0.0;
   for (int64_t s0 = lo; s0 < hi; s0 += kSub) {
     const int len = (int)(hi - s0 < kSub ? hi - s0 : kSub);
     __syncthreads();   // previous slice fully consumed (and acc initialised)
-    for (int e = 2 * t; e < len; e += 2 * TB) *reinterpret_cast<v2d*>(&xs[e]) = *reinterpret_cast<const v2d*>(&pr.w[s0 + e]);
+    for (int e = 2 * t; e < len; e += 2 * TB) {
+      v2d x = *reinterpret_cast<const v2d*>(&pr.w[s0 + e]);
+      if (sigma != 0.0) {
+        const v2d vv = *reinterpret_cast<const v2d*>(&pr.v[s0 + e]);
+        x.x -= sigma * vv.x;
+        x.y -= sigma * vv.y;
+        *reinterpret_cast<v2d*>(&pr.w[s0 + e]) = x;
+      }
+      nb += x.x * x.x + x.y * x.y;
+      *reinterpret_cast<v2d*>(&xs[e]) = x;
+    }
     __syncthreads();
     for (int i = wave; i <= j; i += TB / 64) {
       const double* q = pr.Q + (int64_t)i * pr.ld + s0;
@@ -164,30 +205,40 @@ __global__ __launch_bounds__(TB) void k_mdot(const LzProblem* probs, const LzCtr
   }
   __syncthreads();
   for (int i = t; i <= j; i += TB) partial[((int64_t)p * kmax + i) * kLzBlocks + b] = acc[i];
-}
-
-// coef[p][i] = sum_b partial[p][i][b], i = 0..j; one block per (i, p).
-// If alpha is given, alpha_j = coef_j (the first pass).
-__global__ __launch_bounds__(TB) void k_mdot_finalize(const LzCtrl* ctrl, const int32_t* active,
-                                                      const double* partial, double* coef, double* alpha, int kmax) {
-  __shared__ double sh[TB];
-  const int p = blockIdx.y, i = blockIdx.x;
-  if (!active[p] || i > ctrl[p].j) return;
-  const double s = sum_partials(partial, p, i, kmax, sh);
-  if (threadIdx.x == 0) {
-    coef[(int64_t)p * kmax + i] = s;
-    if (alpha && i == ctrl[p].j) alpha[(int64_t)p * kmax + i] = s;
+  if (pass == 0) {
+    nb = block_sum(nb, sh);
+    if (t == 0) pnorm[(int64_t)p * kLzBlocks + b] = nb;
   }
 }
 
-// w -= sum_{i<=j} coef_i Q[i] over the padded length; with_norm: also
+// coef[p][i] = sum_b partial[p][i][b], i = 0..j; one block per (i, p).
+// Pass 0: alpha_j = coef_j + sigma (and sigma = alpha_0 from j = 0);
+// pass 1 runs only where ctrl.reorth is set.
+__global__ __launch_bounds__(TB) void k_mdot_finalize(LzCtrl* ctrl, const int32_t* active, const double* partial,
+                                                      double* coef, double* alpha, int kmax, int pass) {
+  __shared__ double sh[TB];
+  const int p = blockIdx.y, i = blockIdx.x;
+  if (!active[p] || i > ctrl[p].j || (pass == 1 && !ctrl[p].reorth)) return;
+  const double s = sum_partials(partial, p, i, kmax, sh);
+  if (threadIdx.x == 0) {
+    coef[(int64_t)p * kmax + i] = s;
+    if (pass == 0 && i == ctrl[p].j) {
+      const int j = ctrl[p].j;
+      alpha[(int64_t)p * kmax + i] = s + (j > 0 ? ctrl[p].shift : 0.0);
+      if (j == 0) ctrl[p].shift = s;
+    }
+  }
+}
+
+// w -= sum_{i<=j} coef_i Q[i] over the padded length, and
 // partial[p][0][b] = |w|^2 over the block's range (after the update).
+// Pass 1 runs only where ctrl.reorth is set.
 __global__ __launch_bounds__(TB) void k_update(const LzProblem* probs, const LzCtrl* ctrl, const int32_t* active,
-                                               const double* coef, double* partial, int kmax, int with_norm) {
+                                               const double* coef, double* partial, int kmax, int pass) {
   __shared__ double cs[kLzMaxK];
   __shared__ double sh[TB];
   const int p = blockIdx.y, b = blockIdx.x;
-  if (!active[p]) return;
+  if (!active[p] || (pass == 1 && !ctrl[p].reorth)) return;
   const LzProblem pr = probs[p];
   const int j = ctrl[p].j;
   const int t = threadIdx.x;
@@ -211,10 +262,8 @@ __global__ __launch_bounds__(TB) void k_update(const LzProblem* probs, const LzC
     *reinterpret_cast<v2d*>(&pr.w[n]) = wv;
     nrm += wv.x * wv.x + wv.y * wv.y;
   }
-  if (with_norm) {
-    nrm = block_sum(nrm, sh);
-    if (t == 0) partial[((int64_t)p * kmax) * kLzBlocks + b] = nrm;
-  }
+  nrm = block_sum(nrm, sh);
+  if (t == 0) partial[((int64_t)p * kmax) * kLzBlocks + b] = nrm;
 }
 
 // Number of eigenvalues of the tridiagonal (a, b) below x (Sturm sequence).
@@ -408,24 +457,26 @@ dim3 vec_grid(int P) { return dim3(512, P); }
 void lz_init(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)nullptr, 2, 2,
                      partial, kmax);
-  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, partial, (double*)nullptr,
-                     kmax, 2);
+  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, (const double*)partial,
+                     (const double*)nullptr, kmax, 2);
   hipLaunchKernelGGL(k_start, vec_grid(P), dim3(TB), 0, s, probs, ctrl);
 }
 
 void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* active, double* alpha, double* beta,
-                       double* ritz, double* coef, double* partial, int kmax, double tol_E, double tol_res,
-                       double tol_first, double rel_first, hipStream_t s) {
-  // two classical Gram-Schmidt passes; the first yields alpha_j, the second |w|^2
+                       double* ritz, double* coef, double* partial, double* pnorm, int kmax, double tol_E,
+                       double tol_res, double tol_first, double rel_first, hipStream_t s) {
+  // first Gram-Schmidt pass (shifted; alpha_j, |w| before and after), then the
+  // second pass where the first removed most of w
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(k_mdot, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl,
-                       (const int32_t*)active, partial, kmax);
-    hipLaunchKernelGGL(k_mdot_finalize, dim3(kmax, P), dim3(TB), 0, s, (const LzCtrl*)ctrl, (const int32_t*)active,
-                       (const double*)partial, coef, pass == 0 ? alpha : (double*)nullptr, kmax);
+                       (const int32_t*)active, partial, pnorm, kmax, pass);
+    hipLaunchKernelGGL(k_mdot_finalize, dim3(kmax, P), dim3(TB), 0, s, ctrl, (const int32_t*)active,
+                       (const double*)partial, coef, alpha, kmax, pass);
     hipLaunchKernelGGL(k_update, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl,
                        (const int32_t*)active, (const double*)coef, partial, kmax, pass);
+    hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)active, (const double*)partial,
+                       (const double*)pnorm, kmax, pass == 0 ? 4 : 1);
   }
-  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)active, partial, alpha, kmax, 1);
   hipLaunchKernelGGL(k_tridiag, dim3(P), dim3(64), 0, s, ctrl, active, (const double*)alpha, beta, ritz, kmax, tol_E,
                      tol_res, tol_first, rel_first);
   hipLaunchKernelGGL(k_next, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, (const int32_t*)active,
@@ -436,16 +487,16 @@ void lz_finish(int P, const LzProblem* probs, LzCtrl* ctrl, double* ritz, double
   hipLaunchKernelGGL(k_ritz, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, (const double*)ritz, kmax);
   hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)nullptr, 2, 2,
                      partial, kmax);
-  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, partial, (double*)nullptr,
-                     kmax, 2);
+  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, (const double*)partial,
+                     (const double*)nullptr, kmax, 2);
   hipLaunchKernelGGL(k_normalize_psi, vec_grid(P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl);
 }
 
 void lz_residual(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s) {
   hipLaunchKernelGGL(k_residual_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl, partial,
                      kmax);
-  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, partial, (double*)nullptr,
-                     kmax, 3);
+  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, (const double*)partial,
+                     (const double*)nullptr, kmax, 3);
 }
 
 }  // namespace idmrg

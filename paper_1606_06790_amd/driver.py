@@ -113,7 +113,7 @@ class IDMRG:
             rec = dict(n=n, i=i, energy=e, e_site=e / (2 * n + 2), iters=inf["iters"], residual=inf["residual"],
                        fidelity=1.0 - inf["overlap0"], eps=tr["eps"], eps_prime=tr["eps_prime"],
                        m_kept=tr["m_kept"], cut_gap=tr["cut_gap"], svd_sweeps=tr["svd_sweeps"],
-                       fp64_matvecs=inf["fp64_matvecs"],
+                       fp64_matvecs=inf["fp64_matvecs"], reorth_passes=inf["reorth_passes"],
                        N=int(psis[h["i"] - 1].numel()))
             self.steps.append(rec)
             if self.log:

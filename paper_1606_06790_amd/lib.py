@@ -59,7 +59,8 @@ class LanczosOpts_t(C.Structure):
 
 class LanczosInfo_t(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("fp64_matvecs", C.c_int32), ("flags", C.c_int32),
-                ("residual", C.c_double), ("overlap0", C.c_double)]
+                ("reorth_passes", C.c_int32), ("reserved", C.c_int32), ("residual", C.c_double),
+                ("overlap0", C.c_double)]
 
 
 class Trunc_t(C.Structure):
@@ -299,7 +300,7 @@ def lanczos_solve_batch(ctx, problems, psis, tol_E=1e-12, tol_res=1e-8, k_max=30
     inf = (LanczosInfo_t * P)()
     rc = _check(ctx, ctx.lib.lanczos_solve_batch(ctx.handle, P, arr, pp, C.byref(opts), e, inf))
     infos = [dict(iters=x.iters, converged=x.converged, fp64_matvecs=x.fp64_matvecs, flags=x.flags,
-                  residual=x.residual, overlap0=x.overlap0, warn=rc) for x in inf]
+                  reorth_passes=x.reorth_passes, residual=x.residual, overlap0=x.overlap0, warn=rc) for x in inf]
     return [float(x) for x in e], infos
 
 
