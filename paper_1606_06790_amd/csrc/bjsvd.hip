@@ -91,13 +91,12 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
                                                  void* const* __restrict__ bases, const int32_t* __restrict__ done,
                                                  int32_t* __restrict__ changed, const double* __restrict__ thr2,
                                                  double tol, int inner_sweeps) {
-  // The MFMA staging tiles alias the Gram matrix S: the Gram product stages
-  // through them before S is written, and the rotation products run after S
-  // is no longer needed (two workgroups fit in one CU's LDS).
+  // The MFMA staging tile T (64 x 64) aliases the Gram matrix S: the Gram
+  // product stages through it before S is written, and the rotation products
+  // run after S is no longer needed (two workgroups fit in one CU's LDS).
   __shared__ double S[PB][LD];
   __shared__ double Q[PB][LD];
-  double(*Ta)[LD] = reinterpret_cast<double(*)[LD]>(&S[0][0]);
-  double(*Tb)[LD] = reinterpret_cast<double(*)[LD]>(&S[16][0]);
+  double(*T)[LD] = S;
   __shared__ double cs_[PB / 2], sn_[PB / 2];
   __shared__ int pidx[PB / 2], qidx[PB / 2];
   __shared__ int s_move;
@@ -117,43 +116,46 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
   const int lane = t & 63, wave = t >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int r_any = tk.bi * BB;   // a row of the pair that exists (the first block is never a padding block)
-  // 1. Gram matrix S = Y Y^T.  One staged tile Ta[k][i] serves as both operands.
-  // Thread t stages rows i = t/16 + 16q (q < 4) at column k0 + t%16; padding rows
-  // read a real row (clamped) and are removed from S afterwards.
+  // Tiles of 64 rows (local rows k = wave + 4q, q < 16) x 64 columns (c0 + lane)
+  // are loaded whole, the next one into registers while the current one is
+  // multiplied; padding rows read a real row (clamped).
+  constexpr int NQ = PB / 4;
+  // 1. Gram matrix S = Y Y^T over column tiles; the staged tile T[k][i] =
+  // Y[i][c0 + k] serves as both operands.  Columns past p read as zero.
   v4d acc[2][2];
   {
     const gptr<double> Xg = as_global((const double*)X);
-    int offs[4];
+    int offs[NQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = grow(t / 16 + 16 * q);
+    for (int q = 0; q < NQ; ++q) {
+      const int r = grow(wave + 4 * q);
       offs[q] = (r >= 0 ? r : r_any) * p;
     }
-    double v[4];
-    auto ld = [&](int k0) {
-      const int k = k0 + (t & 15), kc = k < p ? k : p - 1;
+    double v[NQ];
+    auto ld = [&](int c0) {
+      const int k = c0 + lane, kc = k < p ? k : p - 1;
       const uint32_t m = lane_mask(k < p);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = keep(Xg[offs[q] + kc], m);
+      for (int q = 0; q < NQ; ++q) v[q] = keep(Xg[offs[q] + kc], m);
     };
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
     ld(0);
-    for (int k0 = 0; k0 < p; k0 += 16) {
+    for (int c0 = 0; c0 < p; c0 += PB) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Ta[t & 15][t / 16 + 16 * q] = v[q];
+      for (int q = 0; q < NQ; ++q) T[lane][wave + 4 * q] = v[q];
       __syncthreads();
-      if (k0 + 16 < p) ld(k0 + 16);
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
+      if (c0 + PB < p) ld(c0 + PB);
+#pragma unroll 4
+      for (int kk = 0; kk < PB; kk += 4) {
         const int kr = kk + (lane >> 4);
         double a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = Ta[kr][wm + i * 16 + (lane & 15)];
+        for (int i = 0; i < 2; ++i) a[i] = T[kr][wm + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = Ta[kr][wn + j * 16 + (lane & 15)];
+        for (int j = 0; j < 2; ++j) b[j] = T[kr][wn + j * 16 + (lane & 15)];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -236,47 +238,55 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
     __syncthreads();
     if (!s_move) break;
   }
-  // 3. Y <- Q^T Y, G-rows <- Q^T G-rows, in column chunks of 64.  The A operand
-  // is read from Q in LDS; the B tile (rows of the pair, clamped like above)
-  // is staged in Tb.  Padding rows need no masking: Q is the identity on them,
-  // so they only feed padding outputs, which are not stored.  A chunk is read
-  // completely before any of it is written.
+  // 3. Y <- Q^T Y, G-rows <- Q^T G-rows, in column tiles of 64.  The A operand
+  // is read from Q in LDS; the B tile T[k][c] = rows of the pair at columns
+  // c0 + c is staged whole (the next one loaded into registers meanwhile).
+  // Padding rows need no masking: Q is the identity on them, so they only feed
+  // padding outputs, which are not stored.  A tile is read completely before
+  // any of it is written, and tiles cover disjoint columns.
   for (int pass = 0; pass < 2; ++pass) {
     double* Mx = pass == 0 ? X : G;
     const gptr<double> Mg = as_global((const double*)Mx);
     const int len = pass == 0 ? p : n;
-    for (int c0 = 0; c0 < len; c0 += PB) {
+    int offs[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int r = grow(wave + 4 * q);
+      offs[q] = (r >= 0 ? r : r_any) * len;
+    }
+    double v[NQ];
+    auto ld = [&](int c0) {
       const int col = c0 + lane < len ? c0 + lane : len - 1;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) v[q] = Mg[offs[q] + col];
+    };
+    ld(0);
+    for (int c0 = 0; c0 < len; c0 += PB) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) T[wave + 4 * q][lane] = v[q];
+      __syncthreads();
+      if (c0 + PB < len) ld(c0 + PB);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
-      for (int k0 = 0; k0 < PB; k0 += 16) {
+#pragma unroll 4
+      for (int kk = 0; kk < PB; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        double a[2], b[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int kk = wave + 4 * q;
-          const int r = grow(k0 + kk);
-          Tb[kk][lane] = Mg[(r >= 0 ? r : r_any) * len + col];
-        }
-        __syncthreads();
+        for (int i = 0; i < 2; ++i) a[i] = Q[kr][wm + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const int kr = kk + (lane >> 4);
-          double a[2], b[2];
+        for (int j = 0; j < 2; ++j) b[j] = T[kr][wn + j * 16 + (lane & 15)];
 #pragma unroll
-          for (int i = 0; i < 2; ++i) a[i] = Q[k0 + kr][wm + i * 16 + (lane & 15)];
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) b[j] = Tb[kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-        __syncthreads();
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
       }
-      store64(acc, [&](int i, int j, double v) {
+      __syncthreads();
+      store64(acc, [&](int i, int j, double v2) {
         const int r = grow(i);
-        if (r >= 0 && c0 + j < len) Mx[(int64_t)r * len + c0 + j] = v;
+        if (r >= 0 && c0 + j < len) Mx[(int64_t)r * len + c0 + j] = v2;
       });
     }
   }
@@ -290,9 +300,16 @@ __global__ void k_bj_sweep_end(int nm, int32_t* done, int32_t* changed) {
   changed[m] = 0;
 }
 
-// X = M (r <= c) or M^T (r > c); G = I; thr2 = (zero_rel |M|_F)^2.  One workgroup per matrix.
+// X = P M (r <= c) or P M^T (r > c) with the permutation P that puts the
+// rows in order of decreasing norm (ties by index); G = P; thr2 = (zero_rel
+// |M|_F)^2.  One workgroup per matrix.  Starting from norm-sorted rows (de
+// Rijk's ordering) keeps rows of similar weight in the same blocks, which
+// cuts the sweeps one-sided Jacobi needs on strongly graded matrices such as
+// the blocks of a converged two-site state.
 __global__ __launch_bounds__(256) void k_bj_init(const SvdTask* __restrict__ tasks, void* const* __restrict__ bases,
                                                  double* __restrict__ thr2, double zero_rel) {
+  __shared__ double key[kBjMaxN];
+  __shared__ int idx[kBjMaxN];
   __shared__ double red[4];
   const SvdTask tk = tasks[blockIdx.x];
   const bool tr = tk.r > tk.c;
@@ -300,18 +317,66 @@ __global__ __launch_bounds__(256) void k_bj_init(const SvdTask* __restrict__ tas
   const double* M = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 1]) + tk.m_off;
   double* X = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 2]) + tk.x_off;
   double* G = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 3]) + tk.g_off;
-  double a = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * p; e += 256) {
-    const int i = (int)(e / p), k = (int)(e % p);
-    const double v = tr ? M[(int64_t)k * tk.c + i] : M[e];
-    X[e] = v;
-    a += v * v;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // squared row norms of X (row i of X is row i of M, or column i of M)
+  if (tr) {
+    for (int i = t; i < n; i += 256) {
+      double a = 0.0;
+      for (int k = 0; k < p; ++k) {
+        const double v = M[(int64_t)k * tk.c + i];
+        a += v * v;
+      }
+      key[i] = a;
+    }
+  } else {
+    for (int i = wave; i < n; i += 4) {
+      double a = 0.0;
+      for (int k = lane; k < p; k += 64) {
+        const double v = M[(int64_t)i * p + k];
+        a += v * v;
+      }
+      a = wsum(a);
+      if (lane == 0) key[i] = a;
+    }
   }
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) G[e] = (e / n == e % n) ? 1.0 : 0.0;
-  a = wsum(a);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  int P2 = 1;
+  while (P2 < n) P2 <<= 1;
+  for (int i = t; i < P2; i += 256) {
+    if (i >= n) key[i] = -1.0;   // sorts after every real row
+    idx[i] = i;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) thr2[blockIdx.x] = zero_rel * zero_rel * (((red[0] + red[1]) + red[2]) + red[3]);
+  // |M|_F^2 in a fixed order
+  double a = 0.0;
+  for (int i = t; i < n; i += 256) a += key[i];
+  a = wsum(a);
+  if (lane == 0) red[wave] = a;
+  // bitonic sort of (key descending, index ascending)
+  for (int size = 2; size <= P2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = t; i < P2; i += 256) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;   // this run ends up in the requested order
+          const double ki = key[i], kj = key[j];
+          const int ii = idx[i], ij = idx[j];
+          const bool i_first = ki > kj || (ki == kj && ii < ij);
+          if (i_first != desc) {
+            key[i] = kj; key[j] = ki;
+            idx[i] = ij; idx[j] = ii;
+          }
+        }
+      }
+    }
+  __syncthreads();
+  for (int64_t e = t; e < (int64_t)n * p; e += 256) {
+    const int i = (int)(e / p), k = (int)(e % p);
+    const int src = idx[i];
+    X[e] = tr ? M[(int64_t)k * tk.c + src] : M[(int64_t)src * p + k];
+  }
+  for (int64_t e = t; e < (int64_t)n * n; e += 256) G[e] = (e % n == idx[e / n]) ? 1.0 : 0.0;
+  if (t == 0) thr2[blockIdx.x] = zero_rel * zero_rel * (((red[0] + red[1]) + red[2]) + red[3]);
 }
 
 __device__ double block_norm2(const double* z, int p, double* red) {

@@ -170,7 +170,7 @@ void launch_svd(const SvdTask* tasks, int ntask, void* const* bases, int32_t* sw
 struct BjScratch {
   double tol = 1e-15;        // relative orthogonality of converged rows
   double zero_rel = 1e-15;   // rows with norm <= zero_rel |M|_F are null rows
-  int inner_sweeps = 2;      // cap of the sweeps that diagonalise one 64 x 64 pair Gram matrix
+  int inner_sweeps = 1;      // cap of the sweeps that diagonalise one 64 x 64 pair Gram matrix
   int max_sweeps = 30;
   int sweeps = 0;            // out: sweeps run
   int converged = 0;         // out: every matrix met the tolerance
