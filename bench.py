@@ -108,21 +108,22 @@ TRAFFIC_SOURCES = ["paper_1606_06790_amd/csrc/gemm.hip", "paper_1606_06790_amd/c
 
 
 def measured_traffic():
-    """(kernel, HBM bytes per launch) from the committed FETCH_SIZE/WRITE_SIZE record, or None when the
-    GEMM sources have changed since the counters were taken."""
+    """{profile class: (kernel, HBM bytes per launch)} from the committed FETCH_SIZE/WRITE_SIZE records, or {} when
+    the GEMM sources have changed since the counters were taken."""
     import hashlib
     import re
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
-        return None
-    m = re.search(r"traffic-record: kernel=(.+?) bytes_per_launch=(\S+) sources_sha256=(\w+)", text)
-    if not m:
-        return None
+        return {}
     h = hashlib.sha256()
     for src in TRAFFIC_SOURCES:
         h.update(open(os.path.join(ROOT, src), "rb").read())
-    return (m.group(1), float(m.group(2))) if h.hexdigest() == m.group(3) else None
+    out = {}
+    for m in re.finditer(r"traffic-record: class=(\w+) kernel=(.+?) bytes_per_launch=(\S+) sources_sha256=(\w+)", text):
+        if m.group(4) == h.hexdigest():
+            out[m.group(1)] = (m.group(2), float(m.group(3)))
+    return out
 
 
 def gemm_roofline(r):
@@ -138,8 +139,8 @@ def gemm_roofline(r):
            "frac": round(achieved / PEAK[r["prec"]], 4), "traffic": None,
            "kernel": f"grouped H_eff GEMM {stage}, {r['prec']}", "launches": n,
            "avg_launch_ms": round(ms / max(n, 1), 4)}
-    rec = measured_traffic()
-    if rec and r["prec"] == "bf16x3" and name == "heff_gemm2_lo":
+    rec = measured_traffic().get(name) if r["prec"] == "bf16x3" else None
+    if rec:
         out["traffic"] = rec[1]
         out["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         out["traffic_kernel"] = rec[0]
