@@ -173,6 +173,9 @@ typedef struct {
     int32_t prec;       /* IDMRG_PREC_* of the matvec inside the iteration */
     int32_t chunk;      /* iterations between host checks of the device stop flags */
     int32_t refine;     /* mixed precision only: FP64 residual refinement after the iteration */
+    int32_t cgs2;       /* 1: second Gram-Schmidt pass in every iteration (classical CGS2);
+                           0: only where the first pass removes more than 99 % of |w|^2 */
+    int32_t reserved;   /* set to 0 */
 } idmrg_lanczos_opts;
 
 typedef struct {

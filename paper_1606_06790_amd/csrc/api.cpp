@@ -762,7 +762,7 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
           heff_run(ctx, e, vv, ww, active, trial);
           Prof pr(ctx, 4, 0.0);
           lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, pnorm, kmax, tolE, tolR, tolF,
-                            relF, s);
+                            relF, o->cgs2 ? 1 : 0, s);
         }
         IDMRG_HIP(hipMemcpyAsync(act.data(), active, P * 4, hipMemcpyDeviceToHost, s));
         sync(ctx);

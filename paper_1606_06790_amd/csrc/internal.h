@@ -215,7 +215,7 @@ void lz_init(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int k
 // pnorm: [P][kLzBlocks] partial sums of the norm before orthogonalisation.
 void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* active, double* alpha, double* beta,
                        double* ritz, double* coef, double* partial, double* pnorm, int kmax, double tol_E,
-                       double tol_res, double tol_first, double rel_first, hipStream_t s);
+                       double tol_res, double tol_first, double rel_first, int cgs2, hipStream_t s);
 void lz_finish(int P, const LzProblem* probs, LzCtrl* ctrl, double* ritz, double* partial, int kmax, hipStream_t s);
 void lz_residual(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s);
 

@@ -99,9 +99,9 @@ constexpr double kReorthEta2 = 0.01;   // eta^2 of the second-pass criterion
 // mode 1: beta_j = sqrt(sum) (after a second pass, where there was one);
 // mode 2: norm0 = sqrt(sum);  mode 3: residual = sqrt(sum);
 // mode 4 (after the first pass): beta_j = sqrt(sum), and ctrl.reorth =
-// j == 0 or sum < eta^2 |w before|^2 (pnorm).
+// cgs2 or j == 0 or sum < eta^2 |w before|^2 (pnorm).
 __global__ __launch_bounds__(TB) void k_finalize(LzCtrl* ctrl, const int32_t* active, const double* partial,
-                                                 const double* pnorm, int kmax, int mode) {
+                                                 const double* pnorm, int kmax, int mode, int cgs2 = 0) {
   __shared__ double sh[TB];
   const int p = blockIdx.x;
   if (active && !active[p]) return;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(TB) void k_finalize(LzCtrl* ctrl, const int32_t* ac
     LzCtrl& c = ctrl[p];
     if (mode == 1 || mode == 4) c.beta_j = sqrt(s);
     if (mode == 4) {
-      c.reorth = c.j == 0 || s < kReorthEta2 * before;
+      c.reorth = cgs2 || c.j == 0 || s < kReorthEta2 * before;
       c.reorths += c.reorth;
     }
     if (mode == 2) c.norm0 = sqrt(s);
@@ -464,7 +464,7 @@ void lz_init(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int k
 
 void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* active, double* alpha, double* beta,
                        double* ritz, double* coef, double* partial, double* pnorm, int kmax, double tol_E,
-                       double tol_res, double tol_first, double rel_first, hipStream_t s) {
+                       double tol_res, double tol_first, double rel_first, int cgs2, hipStream_t s) {
   // first Gram-Schmidt pass (shifted; alpha_j, |w| before and after), then the
   // second pass where the first removed most of w
   for (int pass = 0; pass < 2; ++pass) {
@@ -475,7 +475,7 @@ void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* act
     hipLaunchKernelGGL(k_update, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const LzCtrl*)ctrl,
                        (const int32_t*)active, (const double*)coef, partial, kmax, pass);
     hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)active, (const double*)partial,
-                       (const double*)pnorm, kmax, pass == 0 ? 4 : 1);
+                       (const double*)pnorm, kmax, pass == 0 ? 4 : 1, cgs2);
   }
   hipLaunchKernelGGL(k_tridiag, dim3(P), dim3(64), 0, s, ctrl, active, (const double*)alpha, beta, ritz, kmax, tol_E,
                      tol_res, tol_first, rel_first);

@@ -1,13 +1,14 @@
-"""GPU parity at the full size of the YC8 kagome workload (m = 2048, D up to 20).
+"""GPU parity at the full sizes of the cylinder workloads: YC8 kagome at m = 2048
+(D up to 20, split-bf16 matvec) and YC4 square at m = 1024 (D = 14, FP32 matvec).
 
-The superblock is built without the GPU path: the YC8 MPO from the oracle's
+The superblock is built without the GPU path: the MPO from the oracle's
 finite-state construction, environments grown by the oracle's own Eqs. (4)
 and (5) from the boundary vectors through twelve sites on each side, with
 seeded random block isometries (QR of Gaussian draws) in place of the
 optimised ones.  H_eff is then the projection of the segment Hamiltonian onto
-an orthonormal basis, symmetric like the real one, with legs of 13 U(1) sectors
-summing to 2048 states.  The oracle computes every output at this size in
-seconds, so the comparisons are elementwise.
+an orthonormal basis, symmetric like the real one, with legs of about a dozen
+U(1) sectors summing to m states.  The oracle computes every output at these
+sizes in seconds, so the comparisons are elementwise.
 """
 import numpy as np
 import pytest
@@ -22,13 +23,14 @@ pytestmark = pytest.mark.gpu
 
 lib = pytest.importorskip("paper_1606_06790_amd.lib")
 
-M_FULL = 2048
 MIXED_TOL = {"f32": 5e-6, "bf16x3": 5e-5}
+# (workload, m, matvec policy of its benchmark configuration, smallest MPO channel count at the centre)
+CONFIGS = {"yc8": ("yc8", 2048, "bf16x3", 14), "yc4": ("yc4", 1024, "f32", 14)}
 
 
-def _grow(m, c, nright):
-    """Environments of superblock (sites c, c+1) of the YC8 cylinder with legs of about m states."""
-    cfg = workloads.workload("yc8")
+def _grow(name, m, c, nright):
+    """Environments of superblock (sites c, c+1) of a cylinder workload with legs of about m states."""
+    cfg = workloads.workload(name)
     ell = cfg["ell"]
     Ws, dq = omp.build_mpo(ell, cfg["bonds"])
     f = lambda k: (k - 1) % ell + 1
@@ -78,13 +80,15 @@ def _grow(m, c, nright):
     return dict(L=L, A=A, R=R, B=B, W1=W(c), W2=W(c + 1), dl=cut(c - 1), dm=cut(c), dr=cut(c + 1))
 
 
-@pytest.fixture(scope="module")
-def full():
+@pytest.fixture(scope="module", params=sorted(CONFIGS))
+def full(request):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1606_06790_amd.lib import Mpo
-    s = _grow(M_FULL, 13, 12)
+    name, m, prec, dmin = CONFIGS[request.param]
+    s = _grow(name, m, 13, 12)
+    s.update(name=name, m=m, prec=prec, dmin=dmin)
     A, B = s["A"], s["B"]
     s["prob"] = dict(left=A, right=B, w1=Mpo(s["W1"], s["dl"], s["dm"], QP), w2=Mpo(s["W2"], s["dm"], s["dr"], QP),
                      L=T(layout.envL_to_flat(s["L"], A, s["dl"])), R=T(layout.envR_to_flat(s["R"], B, s["dr"])))
@@ -97,13 +101,14 @@ def full():
 
 
 def test_fullsize_shape(full):
-    assert sum(d for _, d in full["A"]) == M_FULL and sum(d for _, d in full["B"]) == M_FULL
-    assert len(full["dl"]) >= 14 and len(full["dr"]) >= 14 and full["N"] > 2_000_000
+    m = full["m"]
+    assert sum(d for _, d in full["A"]) == m and sum(d for _, d in full["B"]) == m
+    assert len(full["dl"]) >= full["dmin"] and len(full["dr"]) >= full["dmin"] and full["N"] > m * m // 4
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
 def test_fullsize_heff_apply(full, prec):
-    """Every element of H_eff x at the YC8 m = 2048 size against the oracle."""
+    """Every element of H_eff x at the full size against the oracle."""
     y = T(np.zeros(full["N"]))
     lib.heff_apply(full["ctx"], [full["prob"]], [T(full["x"])], [y], prec)
     err = rel_err(H(y), full["y"])
@@ -111,15 +116,15 @@ def test_fullsize_heff_apply(full, prec):
 
 
 def test_fullsize_truncate(full):
-    """Schmidt decomposition of a Gaussian two-site state at m = 2048: kept legs, every kept
+    """Schmidt decomposition of a Gaussian two-site state at the full m: kept legs, every kept
     singular value, eps, isometries and kept subspaces against the oracle (LAPACK SVD)."""
-    A, B = full["A"], full["B"]
+    A, B, m = full["A"], full["B"], full["m"]
     x = workloads.gaussian(full["N"], 79)
     x /= np.linalg.norm(x)
-    tr = u1.truncate_twosite(layout.flat_to_psi(x, A, B, QP), A, B, QP, M_FULL, 1e-14, 1e-5)
-    o = lib.truncate_twosite(full["ctx"], [dict(left=A, right=B, psi=T(x))], QP, M_FULL, 1e-14, 1e-5)[0]
+    tr = u1.truncate_twosite(layout.flat_to_psi(x, A, B, QP), A, B, QP, m, 1e-14, 1e-5)
+    o = lib.truncate_twosite(full["ctx"], [dict(left=A, right=B, psi=T(x))], QP, m, 1e-14, 1e-5)[0]
     assert o["svd_converged"]
-    assert o["C"] == tr["C"] and o["m_kept"] == tr["m_kept"] == M_FULL
+    assert o["C"] == tr["C"] and o["m_kept"] == tr["m_kept"] == m
     assert abs(o["eps"] - tr["eps"]) <= 1e-12
     lam = layout.flat_to_lam(H(o["lam"]), o["C"])
     U = layout.flat_to_U(H(o["U"]), A, QP, o["C"])
@@ -139,12 +144,15 @@ def test_fullsize_truncate(full):
             assert np.abs(Ug @ Ug.T - Uo @ Uo.T).max() <= 1e-9
 
 
-@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f64", "policy"])
 def test_fullsize_lanczos(full, prec):
-    """Lanczos at m = 2048 from a Gaussian start.  The returned energy must be the oracle's
-    Rayleigh quotient of the returned state, and the reported residual the oracle's
-    |H psi - E psi| (so the stop decision was taken on the true residual)."""
+    """Lanczos at the full size from a Gaussian start, in FP64 and in the configuration's mixed
+    policy.  The returned energy must be the oracle's Rayleigh quotient of the returned state,
+    and the reported residual the oracle's |H psi - E psi| (so the stop decision was taken on
+    the true residual)."""
     A, B = full["A"], full["B"]
+    if prec == "policy":
+        prec = full["prec"]
     psi = T(workloads.gaussian(full["N"], 80))
     es, infos = lib.lanczos_solve_batch(full["ctx"], [full["prob"]], [psi], 1e-12, 1e-8, 300, prec)
     p = H(psi)
