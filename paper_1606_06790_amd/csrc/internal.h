@@ -77,12 +77,21 @@ constexpr int kFragRows = 16, kFragK = 32, kFragWords = 512;
 // + r) in source base sbase goes to column kc0 + k; the 8-wide chunks are
 // written whole for rows 0 .. 16 RB - 1, with zeros outside [R x K] (K = 0
 // writes zeros only).  kc0 is a multiple of 8.  hi = bf16(float(z)),
-// lo = bf16(float(z) - hi), both rounded to nearest even.
+// lo = bf16(float(z) - hi), both rounded to nearest even.  The elements
+// Z(dr0 + i, dk0 + i), i < dlen, are packed as Z - shift (a diagonal shift).
 struct PackTask {
   int32_t R, K, ld, trans;
   int32_t prob, sbase, dbase, tile0;
   int32_t RB, KB, kc0, nch;     // RB = ceil(R / 16)
+  int32_t dr0, dk0, dlen, pad;
   int64_t soff, doff;
+  double shift;
+};
+
+// The diagonal of a square block: elements off + i (ld + 1), i < len, of base `base`.
+struct DiagTask {
+  int32_t prob, base, len, ld;
+  int64_t off;
 };
 
 // One-sided Jacobi SVD of M[r x c] (row-major); n = min(r, c), p = max(r, c).
@@ -155,6 +164,14 @@ void launch_scale(const ScaleTask* tasks, const int32_t* colmaps, int ntask, int
 
 // element conversions (n elements): kind 0 double -> float, kind 1 float -> double
 void launch_convert(int kind, const void* src, void* dst, int64_t n, hipStream_t s);
+
+// out[t] = sum of the diagonal of DiagTask t (FP64 sources; one workgroup per task).
+void launch_diag_sum(const DiagTask* tasks, int ntask, void* const* bases, double* out, hipStream_t s);
+// FP32 copies (bases dst) of FP64 blocks (bases src, same offsets): diagonal of task t = float(src - shift[t]).
+void launch_diag_shift_f32(const DiagTask* tasks, int ntask, void* const* src, void* const* dst, const double* shift,
+                           hipStream_t s);
+// dst[i] = (double)src[i] + sigma x[i] (n elements; float src, double x and dst).
+void launch_convert_add(const float* src, const double* x, double sigma, double* dst, int64_t n, hipStream_t s);
 
 // Fragment packs (256 row-chunks of 8 values per tile); sources are read through sbases, results written
 // through dbases.

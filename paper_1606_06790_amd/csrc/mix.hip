@@ -157,6 +157,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackTask* __restrict__ 
     const int k = k0 + e;
     double x = 0.0;
     if (r < tk.R && k < tk.K) x = tk.trans ? S[(int64_t)k * tk.ld + r] : S[(int64_t)r * tk.ld + k];
+    if (r - tk.dr0 == k - tk.dk0 && (unsigned)(r - tk.dr0) < (unsigned)tk.dlen) x -= tk.shift;
     v[e] = (float)x;
   }
   uint4 hi, lo;
@@ -165,6 +166,51 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackTask* __restrict__ 
                                       frag_chunk(r, tk.kc0 + k0, tk.KB));
   D[0] = hi;
   D[kFragWords / 8] = lo;
+}
+
+// Deterministic block sum (256 threads, fixed tree).
+__device__ double block_sum256(double x, double* sh) {
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// out[t] = sum of the diagonal of task t; one workgroup per task.
+__global__ __launch_bounds__(256) void diag_sum_kernel(const DiagTask* __restrict__ tasks,
+                                                       void* const* __restrict__ bases, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const DiagTask tk = tasks[blockIdx.x];
+  const double* S = reinterpret_cast<const double*>(bases[tk.prob * kNumBases + tk.base]) + tk.off;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < tk.len; i += 256) a += S[(int64_t)i * (tk.ld + 1)];
+  a = block_sum256(a, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = a;
+}
+
+// The diagonal of an FP32 copy rewritten from its FP64 source minus shift[t],
+// rounded once: d32[i, i] = float(d64[i, i] - shift).
+__global__ __launch_bounds__(256) void diag_shift_kernel(const DiagTask* __restrict__ tasks,
+                                                         void* const* __restrict__ src,
+                                                         void* const* __restrict__ dst,
+                                                         const double* __restrict__ shift) {
+  const DiagTask tk = tasks[blockIdx.x];
+  const double* S = reinterpret_cast<const double*>(src[tk.prob * kNumBases + tk.base]) + tk.off;
+  float* D = reinterpret_cast<float*>(dst[tk.prob * kNumBases + tk.base]) + tk.off;
+  const double sg = shift[blockIdx.x];
+  for (int i = threadIdx.x; i < tk.len; i += 256) {
+    const int64_t e = (int64_t)i * (tk.ld + 1);
+    D[e] = (float)(S[e] - sg);
+  }
+}
+
+__global__ void convert_add_kernel(const float* __restrict__ src, const double* __restrict__ x, double sigma,
+                                   double* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i] + sigma * x[i];
 }
 
 __global__ __launch_bounds__(256) void scale_kernel(const ScaleTask* __restrict__ tasks, const int32_t* __restrict__ colmaps,
@@ -219,6 +265,24 @@ void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int
     hipLaunchKernelGGL(mix_frag_kernel, grid, block, 0, s, tasks, srcs, ntask, bases, active);
   else if (tin == 0 && tout == 1)
     hipLaunchKernelGGL((mix_kernel<double, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
+}
+
+void launch_diag_sum(const DiagTask* tasks, int ntask, void* const* bases, double* out, hipStream_t s) {
+  if (ntask == 0) return;
+  hipLaunchKernelGGL(diag_sum_kernel, dim3(ntask), dim3(256), 0, s, tasks, bases, out);
+}
+
+void launch_diag_shift_f32(const DiagTask* tasks, int ntask, void* const* src, void* const* dst, const double* shift,
+                           hipStream_t s) {
+  if (ntask == 0) return;
+  hipLaunchKernelGGL(diag_shift_kernel, dim3(ntask), dim3(256), 0, s, tasks, src, dst, shift);
+}
+
+void launch_convert_add(const float* src, const double* x, double sigma, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(convert_add_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, x, sigma, dst, n);
 }
 
 void launch_pack(const PackTask* tasks, int ntask, int ntiles, void* const* sbases, void* const* dbases,

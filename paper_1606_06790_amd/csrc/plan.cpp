@@ -370,14 +370,42 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
       nT3 += (int64_t)X.b_rows[b] * ER.K[b];
     }
   }
+  // Energy-shift structure of the low-precision copies (see plan.h): is L's
+  // channel 0 exactly H_L and R's last channel exactly H_R?
+  const int DM = W1.dr;
+  auto only_identity = [](const Mpo& W, bool row, int idx, int keep) {
+    const int n = row ? W.dr : W.dl;
+    for (int v = 0; v < n; ++v)
+      for (int s = 0; s < W.d; ++s)
+        for (int t = 0; t < W.d; ++t) {
+          const double w = row ? W.at(idx, v, s, t) : W.at(v, idx, s, t);
+          if (w != ((v == keep && s == t) ? 1.0 : 0.0)) return false;
+        }
+    return true;
+  };
+  const bool shL = DL > 1 && W1.ql[0] == 0 && only_identity(W1, true, 0, 0) && only_identity(W2, true, 0, 0);
+  const bool shR = DR > 1 && W2.qr[DR - 1] == 0 && only_identity(W2, false, DR - 1, DM - 1) &&
+                   only_identity(W1, false, DM - 1, DL - 1);
+  p.shiftL.push_back(shL ? 1 : 0);
+  p.shiftR.push_back(shR ? 1 : 0);
   // Fragment form (split-bf16): L per column sector, x per block, T3 and R per right sector
   std::vector<int64_t> lf(A.n(), -1), xf(X.blk.size(), -1), t3f(B.n(), -1), rf(B.n(), -1);
   int64_t nLf = 0, nXf = 0, nT3f = 0, nRf = 0;
   for (int a = 0; a < A.n(); ++a) {
     if (EL.rows[a] == 0) continue;
     lf[a] = nLf;
-    p.packL.add(packtask(prob, EL.rows[a], A.dim[a], 0, EL.stack_off[a], A.dim[a], 0, 0, nLf, kfrags(A.dim[a]), 0,
-                         4 * kfrags(A.dim[a])));
+    PackTask pt = packtask(prob, EL.rows[a], A.dim[a], 0, EL.stack_off[a], A.dim[a], 0, 0, nLf, kfrags(A.dim[a]), 0,
+                           4 * kfrags(A.dim[a]));
+    if (shL && EL.row_off[a][0] >= 0) {   // the H_L block of this column sector (a square diagonal block)
+      pt.dr0 = EL.row_off[a][0];
+      pt.dk0 = 0;
+      pt.dlen = A.dim[a];
+      DiagTask dg{};
+      dg.prob = prob; dg.base = 0; dg.len = A.dim[a]; dg.ld = A.dim[a];
+      dg.off = EL.stack_off[a] + (int64_t)EL.row_off[a][0] * A.dim[a];
+      p.diagL.push_back(dg);
+    }
+    p.packL.add(pt);
     nLf += frag_words(EL.rows[a], A.dim[a]);
   }
   for (size_t x = 0; x < X.blk.size(); ++x) {
@@ -408,8 +436,14 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
     for (int u = 1; u < DR; ++u) {
       if (cpad[b][u] < 0) continue;
       const int du = B.dim[ER.b_in[b][u]];
-      p.packR.add(packtask(prob, B.dim[b], du, 1, ER.off[b] + ER.col_off[b][u], ER.K[b], 0, 1, nRf, KB, cpad[b][u],
-                           (du + 7) / 8));
+      PackTask pt = packtask(prob, B.dim[b], du, 1, ER.off[b] + ER.col_off[b][u], ER.K[b], 0, 1, nRf, KB, cpad[b][u],
+                             (du + 7) / 8);
+      if (shR && u == DR - 1) {   // the H_R block of this row sector (b_in = b, square)
+        pt.dr0 = 0;
+        pt.dk0 = 0;
+        pt.dlen = du;
+      }
+      p.packR.add(pt);
     }
     // zeros past the last channel, to the end of the last k-fragment
     p.packR.add(packtask(prob, B.dim[b], 0, 1, 0, 0, 0, 1, nRf, KB, Kp[b], (KB * kFragK - Kp[b]) / 8));
@@ -458,6 +492,15 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
       p.mixTf.add(mf, s);
     }
   }
+  if (shR)
+    for (int b = 0; b < B.n(); ++b) {
+      const int co = ER.col_off[b][DR - 1];
+      if (co < 0) continue;
+      DiagTask dg{};
+      dg.prob = prob; dg.base = 1; dg.len = B.dim[b]; dg.ld = ER.K[b];
+      dg.off = ER.off[b] + co;
+      p.diagR.push_back(dg);
+    }
   for (int b = 0; b < B.n(); ++b) {
     if (ER.K[b] == 0 || X.b_rows[b] == 0) continue;
     p.g2.add(gemm(prob, X.b_rows[b], B.dim[b], ER.K[b], 5, t3off[b], ER.K[b], 1, ER.off[b], ER.K[b], 3,

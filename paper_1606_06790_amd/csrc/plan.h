@@ -133,6 +133,17 @@ struct HeffPlan {
   std::vector<int64_t> n_Lf, n_Rf, n_Xf, n_T3f;   // words, per problem
   // In the fragment form the K index of T3 and R (channel u, column b') is
   // re-spaced so that each channel's block starts at a multiple of 8.
+  //
+  // Energy shift of the low-precision copies.  Where the MPO makes L's channel
+  // 0 the complete left Hamiltonian H_L (row 0 of W1 and of W2 the identity
+  // alone, charge 0) and R's last channel the complete right Hamiltonian H_R
+  // (last column of W2 and of W1 the identity alone, charge 0), H_eff contains
+  // H_L (x) 1 and 1 (x) H_R exactly once, so the copies may hold H_L - sL and
+  // H_R - sR and the result gets (sL + sR) x back in FP64.  diagL / diagR list
+  // the diagonals of those blocks (the shifts are their means); shiftL / shiftR
+  // say per problem whether the structure is there.
+  std::vector<DiagTask> diagL, diagR;
+  std::vector<int> shiftL, shiftR;
 };
 // heff bases: 0 L, 1 R, 2 x (GEMM operand), 3 y, 4 T1, 5 T3, 6 x (mix operand).
 // Fragment form: 0 L, 1 R, 2 x, 5 T3 in the fragment layout; 3 y, 4 T1, 6 x as

@@ -66,7 +66,9 @@ void run_pack(const PackList& pl, const std::vector<double*>& src, const std::ve
     for (int r = 0; r < t.RB * kFragRows; ++r)
       for (int k = 0; k < 8 * t.nch; ++k) {
         const int64_t i = frag_slot(t.doff, t.KB, r, t.kc0 + k);
-        D[i] = r < t.R && k < t.K ? (t.trans ? S[(int64_t)k * t.ld + r] : S[(int64_t)r * t.ld + k]) : 0.0;
+        double v = r < t.R && k < t.K ? (t.trans ? S[(int64_t)k * t.ld + r] : S[(int64_t)r * t.ld + k]) : 0.0;
+        if (r - t.dr0 == k - t.dk0 && r - t.dr0 >= 0 && r - t.dr0 < t.dlen) v -= t.shift;
+        D[i] = v;
         D[i + kFragWords] = 0.0;
       }
   }
@@ -146,8 +148,11 @@ extern "C" int hostplan_heff(const idmrg_heff* H, const double* x, double* y) {
 // The split-bf16 form of the same plan: packs, fragment GEMMs and the mixing
 // into the fragment form of T3.  Fragment buffers start as NaN except T3's,
 // which starts as zero like its device buffer, so a read of any slot that no
-// pack wrote shows up in y.
-extern "C" int hostplan_heff_frag(const idmrg_heff* H, const double* x, double* y) {
+// pack wrote shows up in y.  The packs shift the H_L and H_R diagonals by sL
+// and sR where the plan found that structure (flags[0], flags[1] on return),
+// and (sL + sR) x is added back, as on the device.
+extern "C" int hostplan_heff_frag(const idmrg_heff* H, const double* x, double* y, double sL, double sR,
+                                  int* flags) {
   try {
     HeffPlan p;
     const Leg A = make_leg(H->left, "A"), B = make_leg(H->right, "B");
@@ -163,6 +168,11 @@ extern "C" int hostplan_heff_frag(const idmrg_heff* H, const double* x, double* 
     ss[0] = p.n_L[0]; ss[1] = p.n_R[0]; ss[2] = p.n_psi[0];
     sz[0] = p.n_Lf[0]; sz[1] = p.n_Rf[0]; sz[2] = p.n_Xf[0]; sz[3] = sz[6] = p.n_psi[0]; sz[4] = p.n_T1[0];
     sz[5] = p.n_T3f[0];
+    flags[0] = p.shiftL[0];
+    flags[1] = p.shiftR[0];
+    for (auto& t : p.packL.t) t.shift = t.dlen > 0 ? sL : 0.0;
+    for (auto& t : p.packR.t) t.shift = t.dlen > 0 ? sR : 0.0;
+    const double sigma = (p.shiftL[0] ? sL : 0.0) + (p.shiftR[0] ? sR : 0.0);
     check_pack(p.packL, ss, sz, "packL");
     check_pack(p.packR, ss, sz, "packR");
     check_pack(p.packX, ss, sz, "packX");
@@ -177,6 +187,7 @@ extern "C" int hostplan_heff_frag(const idmrg_heff* H, const double* x, double* 
     run_mix(p.mixY, b);
     run_mix_frag(p.mixTf, b);
     run_gemm_frag(p.f2, b);
+    for (int64_t i = 0; i < p.n_psi[0]; ++i) y[i] += sigma * x[i];
     return 0;
   } catch (...) {
     return -1;

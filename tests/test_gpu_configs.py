@@ -133,3 +133,35 @@ def test_lanczos_exhausts_space(ctx):
     p = H(psi)
     assert abs(np.linalg.norm(p) - 1.0) <= 1e-12
     assert float(np.linalg.norm(Hd @ p - es[0] * p)) <= 1e-10 * max(1.0, abs(e_exact))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_low_precision_energy_shift(ctx, prec):
+    """The environments carry the block energies H_L, H_R as large diagonal-heavy blocks.
+    Adding c I to H_L and c I to H_R adds 2c I to H_eff; the low-precision copies hold the
+    blocks shifted by their mean diagonal and the shift comes back in FP64, so the absolute
+    error of the matvec must stay at the level it has without the offset (unshifted copies
+    would round the 2c |x| term at the low precision's relative error)."""
+    from test_gpu_fullsize import _grow
+    from paper_1606_06790_amd.lib import Mpo
+    s = _grow("yc8", 256, 10, 9)
+    A, B, dl, dr = s["A"], s["B"], s["dl"], s["dr"]
+    x = workloads.gaussian(layout.psi_size(A, B, QP), 94)
+    errs = []
+    for c in (0.0, 40.0):
+        L = {k: (v + c * np.eye(v.shape[0]) if k[0] == 0 and k[1] == k[2] else v) for k, v in s["L"].items()}
+        R = {k: (v + c * np.eye(v.shape[0]) if k[0] == len(dr) - 1 and k[1] == k[2] else v) for k, v in s["R"].items()}
+        y = layout.psi_to_flat(u1.heff_apply(L, s["W1"], s["W2"], R, layout.flat_to_psi(x, A, B, QP), A, B, QP, dl, dr),
+                               A, B, QP)
+        prob = dict(left=A, right=B, w1=Mpo(s["W1"], dl, s["dm"], QP), w2=Mpo(s["W2"], s["dm"], dr, QP),
+                    L=T(layout.envL_to_flat(L, A, dl)), R=T(layout.envR_to_flat(R, B, dr)))
+        yg = T(np.full(len(y), np.nan))
+        lib.heff_apply(ctx, [prob], [T(x)], [yg], prec)
+        errs.append(float(np.abs(H(yg) - y).max()))
+        if c > 0:   # the oracle's result does include the offset
+            assert np.abs(y - layout.psi_to_flat(u1.heff_apply(s["L"], s["W1"], s["W2"], s["R"],
+                                                                layout.flat_to_psi(x, A, B, QP), A, B, QP, dl, dr),
+                                                  A, B, QP) - 2 * c * x).max() <= 1e-11 * np.abs(y).max()
+    ulp = {"f32": 2.0 ** -24, "bf16x3": 2.0 ** -16}[prec]
+    xm = float(np.abs(x).max())
+    assert errs[1] <= 3 * errs[0] + 0.1 * ulp * 80 * xm, errs

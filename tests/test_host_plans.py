@@ -102,10 +102,15 @@ def test_heff_plan_on_host(lib, hostplan, name, c1, li):
     y = np.full(nx, np.nan)
     assert hostplan.hostplan_heff(C.byref(h), C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data)) == 0
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
-    # the split-bf16 form of the plan (fragment-layout operands), executed in FP64
+    # the split-bf16 form of the plan (fragment-layout operands), executed in FP64, with the H_L / H_R
+    # diagonals of the packed environments shifted and the shift added back
     y = np.full(nx, np.nan)
-    assert hostplan.hostplan_heff_frag(C.byref(h), C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data)) == 0
+    flags = (C.c_int * 2)()
+    assert hostplan.hostplan_heff_frag(C.byref(h), C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data),
+                                       C.c_double(1.75), C.c_double(-2.5), flags) == 0
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    # every MPO here (finite-state Heisenberg form) has the structure, so the shift path is exercised
+    assert flags[0] == 1 and flags[1] == 1, list(flags)
 
 
 @pytest.mark.parametrize("name,c1", [("chain", 2), ("yc8", 4), ("dimer", 1)])
