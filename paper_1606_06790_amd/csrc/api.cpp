@@ -324,10 +324,13 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
       for (int p = 0; p < P; ++p) {
         int64_t* z = &sz[(size_t)p * kNumBases];
         z[0] = ex.plan.n_Lf[p]; z[1] = ex.plan.n_Rf[p]; z[2] = ex.plan.n_Xf[p]; z[5] = ex.plan.n_T3f[p];
+        z[4] = ex.plan.n_T1f[p]; z[6] = ex.plan.n_Xm[p];
       }
       check_gemm_frag(ex.plan.f1, sz, "heff gemm1");
-      check_mix(ex.plan.mixY, sz, "heff mixY");
+      check_mix(ex.plan.mixYf, sz, "heff mixY");
+      check_mix_v4(ex.plan.mixYf, sz, "heff mixY");
       check_mix_frag(ex.plan.mixTf, sz, "heff mixT");
+      check_mix_v4(ex.plan.mixTf, sz, "heff mixT");
       check_gemm_frag(ex.plan.f2, sz, "heff gemm2");
       check_pack(ex.plan.packL, ss, sz, "heff pack L");
       check_pack(ex.plan.packR, ss, sz, "heff pack R");
@@ -342,7 +345,7 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
   for (int p = 0; p < P; ++p) {
     o1[p] = nT1;
     o3[p] = nT3;
-    nT1 += round64(ex.plan.n_T1[p] + 1);
+    nT1 += round64((frag ? ex.plan.n_T1f[p] : ex.plan.n_T1[p]) + 1);
     nT3 += round64((frag ? ex.plan.n_T3f[p] : ex.plan.n_T3[p]) + 1);
   }
   char* T1 = (char*)ensure(c, c->ws[WS_T1], nT1 * es);
@@ -372,7 +375,7 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
     int64_t nenv = 0, nvec = 0;
     for (int p = 0; p < P; ++p) {
       nenv += round64(nL[p]) + round64(nR[p]);
-      nvec += (frag ? round64(ex.plan.n_Xf[p]) : 0) + 2 * round64(ex.npsi[p]);
+      nvec += (frag ? round64(ex.plan.n_Xf[p]) + round64(ex.plan.n_Xm[p]) : round64(ex.npsi[p])) + round64(ex.npsi[p]);
     }
     char* env = (char*)ensure(c, c->ws[WS_LOWENV], nenv * 4);
     char* vec = (char*)ensure(c, c->ws[WS_LOWVEC], nvec * 4);
@@ -384,8 +387,8 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
       oe += round64(nL[p]);
       void* Rl = env + oe * 4;
       oe += round64(nR[p]);
-      ex.xmix[p] = vec + ov * 4;
-      ov += round64(ex.npsi[p]);
+      ex.xmix[p] = vec + ov * 4;   // split-bf16: the row-padded copy the x pack writes
+      ov += round64(frag ? ex.plan.n_Xm[p] : ex.npsi[p]);
       ex.ylow[p] = vec + ov * 4;
       ov += round64(ex.npsi[p]);
       if (frag) {
@@ -458,9 +461,9 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
   size_t av[2][kTilings];
   for (int st = 0; st < 2; ++st)
     for (int v = 0; v < ex.nvar; ++v) av[st][v] = pk.add(var[st][v].t);
+  const MixList& mY = frag ? ex.plan.mixYf : ex.plan.mixY;
   const MixList& mT = frag ? ex.plan.mixTf : ex.plan.mixT;
-  const size_t a3 = pk.add(ex.plan.mixY.t), a4 = pk.add(ex.plan.mixY.src), a5 = pk.add(mT.t), a6 = pk.add(mT.src),
-               a7 = pk.add(hb);
+  const size_t a3 = pk.add(mY.t), a4 = pk.add(mY.src), a5 = pk.add(mT.t), a6 = pk.add(mT.src), a7 = pk.add(hb);
   size_t a8 = 0, a9 = 0, a10 = 0, a11 = 0;
   if (!sb.empty()) a8 = pk.add(sb);
   if (frag) {
@@ -498,11 +501,13 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   hipStream_t s = c->stream;
   if (ex.prec != Prec::F64) {
     Prof pr(c, 3, 0.0);
-    if (ex.prec == Prec::BF16X3)
+    if (ex.prec == Prec::BF16X3)   // also writes the padded FP32 copy of x for the mixing
       launch_pack(ex.pX, (int)ex.plan.packX.t.size(), ex.plan.packX.tiles, ex.sbases, ex.bases, active, s);
-    for (int p = 0; p < ex.P; ++p) launch_convert(0, x[p], ex.xmix[p], ex.npsi[p], s);
+    else
+      for (int p = 0; p < ex.P; ++p) launch_convert(0, x[p], ex.xmix[p], ex.npsi[p], s);
   }
-  const int tin = ex.prec == Prec::F64 ? 0 : 1;
+  const bool frag = ex.prec == Prec::BF16X3;
+  const int tin = ex.prec == Prec::F64 ? 0 : (frag ? 4 : 1);
   const int toutT = ex.prec == Prec::F64 ? 0 : (ex.prec == Prec::F32 ? 1 : 3);
   const int toutY = ex.prec == Prec::F64 ? 0 : 1;
   const int lo = ex.prec == Prec::F64 ? 0 : 9;   // profile classes of the low-precision policies
@@ -516,8 +521,9 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   }
   {
     Prof pr(c, lo + 2, ex.flops_mix);
-    launch_mix(tin, toutY, ex.mY, ex.sY, (int)ex.plan.mixY.t.size(), ex.plan.mixY.tiles, ex.bases, active, s);
-    const MixList& mT = ex.prec == Prec::BF16X3 ? ex.plan.mixTf : ex.plan.mixT;
+    const MixList& mY = frag ? ex.plan.mixYf : ex.plan.mixY;
+    launch_mix(tin, toutY, ex.mY, ex.sY, (int)mY.t.size(), mY.tiles, ex.bases, active, s);
+    const MixList& mT = frag ? ex.plan.mixTf : ex.plan.mixT;
     launch_mix(tin, toutT, ex.mT, ex.sT, (int)mT.t.size(), mT.tiles, ex.bases, active, s);
   }
   {

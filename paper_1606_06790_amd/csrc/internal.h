@@ -79,13 +79,18 @@ constexpr int kFragRows = 16, kFragK = 32, kFragWords = 512;
 // writes zeros only).  kc0 is a multiple of 8.  hi = bf16(float(z)),
 // lo = bf16(float(z) - hi), both rounded to nearest even.  The elements
 // Z(dr0 + i, dk0 + i), i < dlen, are packed as Z - shift (a diagonal shift).
+// If xbase >= 0 the source block is also written as FP32 in its own
+// orientation, row-padded: source element at (row i, column j) of the stored
+// matrix goes to xoff + i * xld + j of base xbase.
 struct PackTask {
   int32_t R, K, ld, trans;
   int32_t prob, sbase, dbase, tile0;
   int32_t RB, KB, kc0, nch;     // RB = ceil(R / 16)
-  int32_t dr0, dk0, dlen, pad;
+  int32_t dr0, dk0, dlen, xbase;
   int64_t soff, doff;
   double shift;
+  int64_t xoff;
+  int32_t xld, pad;
 };
 
 // The diagonal of a square block: elements off + i (ld + 1), i < len, of base `base`.
@@ -155,7 +160,9 @@ void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntil
                  void* const* bases, const int32_t* active, hipStream_t s, int tiling = 0);
 
 // Mix over tasks; tin/tout element types: 0 = double, 1 = float, 3 = split-bf16 pairs in the fragment
-// layout (output only; tasks carry r0, c0 and ldd = k-fragments per row block).
+// layout (output only; tasks carry r0, c0 and ldd = k-fragments per row block), 4 = float sources whose
+// non-transposed rows are 16-byte aligned with lengths a multiple of 4 (input only; 4 columns per load).
+// Pairs: (0, 0), (1, 1), (0, 1), (4, 1), (4, 3).
 void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int ntask, int ntiles,
                 void* const* bases, const int32_t* active, hipStream_t s);
 

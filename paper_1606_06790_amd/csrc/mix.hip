@@ -94,43 +94,80 @@ __device__ __forceinline__ void split8(const float (&v)[8], uint4& hi, uint4& lo
   lo = make_uint4(l[0], l[1], l[2], l[3]);
 }
 
-// The mixing with output in the fragment layout (T3 of the split-bf16 policy).
-// Same 32 x 64 tiles as mix_kernel, but each thread produces 8 consecutive
-// columns of one row (row t / 8, chunk t % 8 of the tile) and stores them as
-// one 16-byte hi chunk and one 16-byte lo chunk; columns past the task's end,
-// up to the chunk's end, are zeros.  Accumulation in double as in mix_kernel.
-__global__ __launch_bounds__(256) void mix_frag_kernel(const MixTask* __restrict__ tasks,
-                                                       const MixSrc* __restrict__ srcs, int ntask,
-                                                       void* const* __restrict__ bases,
-                                                       const int32_t* __restrict__ active) {
+// The mixing of the fragment form: FP32 sources whose non-transposed rows start
+// on 16-byte boundaries with lengths that are multiples of 4 (the padded T1 and
+// x copies; checked on the host), output either plain FP32 (FRAG = false) or
+// split-bf16 pairs in the fragment layout (FRAG = true, T3).  Same 32 x 64 tiles
+// as mix_kernel; thread t takes columns 4 (t % 16) .. + 3 of rows t / 16 and
+// t / 16 + 16, so 16 lanes read 256 contiguous bytes of a row per 16-byte load.
+// In the fragment output a thread stores half a lane chunk (8 bytes of the hi
+// plane, 8 of the lo plane); columns past the task's end within its 4 are
+// zeros, and the other half of a chunk past the end keeps the zeros the buffer
+// was cleared with.  Accumulation in double as in mix_kernel.
+template <bool FRAG>
+__global__ __launch_bounds__(256) void mix4_kernel(const MixTask* __restrict__ tasks, const MixSrc* __restrict__ srcs,
+                                                   int ntask, void* const* __restrict__ bases,
+                                                   const int32_t* __restrict__ active) {
   const int tile = blockIdx.x;
   const MixTask& tk = tasks[find_tile(&tasks[0].tile0, sizeof(MixTask) / 4, ntask, tile)];
   if (active && !active[tk.prob]) return;
   const int local = tile - tk.tile0;
-  const int r = (local / tk.tiles_c) * MR + (threadIdx.x >> 3);
-  const int c0 = (local % tk.tiles_c) * MC + 8 * (threadIdx.x & 7);
-  if (r >= tk.rows || c0 >= tk.cols) return;
-  const int nc = min(8, tk.cols - c0);
-  double acc[8];
+  const int r0 = (local / tk.tiles_c) * MR + (threadIdx.x >> 4);
+  const int c = (local % tk.tiles_c) * MC + 4 * (threadIdx.x & 15);
+  if (c >= tk.cols) return;
+  const int nc = min(4, tk.cols - c);
+  double acc[2][4];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) acc[e] = 0.0;
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[h][e] = 0.0;
   for (int k = 0; k < tk.nsrc; ++k) {
     const MixSrc& s = srcs[tk.src0 + k];
     const float* S = reinterpret_cast<const float*>(bases[tk.prob * kNumBases + s.base]) + s.off;
     const double coef = s.coef;
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if (e < nc) acc[e] += coef * (double)(s.trans ? S[(int64_t)(c0 + e) * s.ld + r] : S[(int64_t)r * s.ld + c0 + e]);
-  }
-  float v[8];
+    for (int h = 0; h < 2; ++h) {
+      const int r = r0 + 16 * h;
+      if (r >= tk.rows) continue;
+      if (!s.trans) {
+        // 16-byte aligned by the layout; the columns past nc are row padding or the
+        // next columns of the same row, read but not used
+        const float4 q = *reinterpret_cast<const float4*>(&S[(int64_t)r * s.ld + c]);
+        const float qv[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = (float)acc[e];
-  uint4 hi, lo;
-  split8(v, hi, lo);
-  uint4* D = reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff +
-                                      frag_chunk(tk.r0 + r, tk.c0 + c0, tk.ldd));
-  D[0] = hi;
-  D[kFragWords / 8] = lo;
+        for (int e = 0; e < 4; ++e) acc[h][e] += coef * (double)qv[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (e < nc) acc[h][e] += coef * (double)S[(int64_t)(c + e) * s.ld + r];
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + 16 * h;
+    if (r >= tk.rows) continue;
+    if constexpr (FRAG) {
+      uint32_t hw[2], lw[2];
+#pragma unroll
+      for (int e = 0; e < 4; e += 2) {
+        const uint32_t p0 = split_bf16(e < nc ? (float)acc[h][e] : 0.f);
+        const uint32_t p1 = split_bf16(e + 1 < nc ? (float)acc[h][e + 1] : 0.f);
+        hw[e / 2] = (p0 & 0xffffu) | (p1 << 16);
+        lw[e / 2] = (p0 >> 16) | (p1 & 0xffff0000u);
+      }
+      const int kk = tk.c0 + c;   // a multiple of 4: half (kk % 8) / 4 of a lane chunk
+      uint32_t* D = reinterpret_cast<uint32_t*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff +
+                    frag_chunk(tk.r0 + r, kk & ~7, tk.ldd) + ((kk & 4) >> 1);
+      *reinterpret_cast<uint2*>(D) = make_uint2(hw[0], hw[1]);
+      *reinterpret_cast<uint2*>(D + kFragWords / 2) = make_uint2(lw[0], lw[1]);
+    } else {
+      float* D = reinterpret_cast<float*>(bases[tk.prob * kNumBases + tk.dbase]) + tk.doff + (int64_t)r * tk.ldd + c;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (e < nc) D[e] = (float)acc[h][e];
+    }
+  }
 }
 
 // One thread per row chunk: 8 consecutive columns of one row, stored as the
@@ -156,7 +193,14 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackTask* __restrict__ 
   for (int e = 0; e < 8; ++e) {
     const int k = k0 + e;
     double x = 0.0;
-    if (r < tk.R && k < tk.K) x = tk.trans ? S[(int64_t)k * tk.ld + r] : S[(int64_t)r * tk.ld + k];
+    if (r < tk.R && k < tk.K) {
+      x = tk.trans ? S[(int64_t)k * tk.ld + r] : S[(int64_t)r * tk.ld + k];
+      if (tk.xbase >= 0) {   // FP32 copy in the source's orientation
+        float* X = reinterpret_cast<float*>(dbases[tk.prob * kNumBases + tk.xbase]) + tk.xoff;
+        if (tk.trans) X[(int64_t)k * tk.xld + r] = (float)x;
+        else X[(int64_t)r * tk.xld + k] = (float)x;
+      }
+    }
     if (r - tk.dr0 == k - tk.dk0 && (unsigned)(r - tk.dr0) < (unsigned)tk.dlen) x -= tk.shift;
     v[e] = (float)x;
   }
@@ -261,8 +305,10 @@ void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int
     hipLaunchKernelGGL((mix_kernel<double, double>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
   else if (tin == 1 && tout == 1)
     hipLaunchKernelGGL((mix_kernel<float, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
-  else if (tin == 1 && tout == 3)
-    hipLaunchKernelGGL(mix_frag_kernel, grid, block, 0, s, tasks, srcs, ntask, bases, active);
+  else if (tin == 4 && tout == 1)
+    hipLaunchKernelGGL(mix4_kernel<false>, grid, block, 0, s, tasks, srcs, ntask, bases, active);
+  else if (tin == 4 && tout == 3)
+    hipLaunchKernelGGL(mix4_kernel<true>, grid, block, 0, s, tasks, srcs, ntask, bases, active);
   else if (tin == 0 && tout == 1)
     hipLaunchKernelGGL((mix_kernel<double, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
 }

@@ -283,6 +283,7 @@ void PackList::add(PackTask p) {
 static PackTask packtask(int prob, int R, int K, int sbase, int64_t soff, int ld, int trans, int dbase, int64_t doff,
                          int KB, int kc0, int nch) {
   PackTask p{};
+  p.xbase = -1;
   p.R = R; p.K = K; p.ld = ld; p.trans = trans;
   p.prob = prob; p.sbase = sbase; p.dbase = dbase;
   p.KB = KB; p.kc0 = kc0; p.nch = nch;
@@ -292,6 +293,7 @@ static PackTask packtask(int prob, int R, int K, int sbase, int64_t soff, int ld
 
 static int kfrags(int K) { return (K + kFragK - 1) / kFragK; }
 static int round8(int n) { return (n + 7) / 8 * 8; }
+static int round4(int n) { return (n + 3) / 4 * 4; }
 
 static GemmTask gemm(int prob, int M, int N, int K, int ab, int64_t ao, int lda, int bb, int64_t bo, int ldb, int cb,
                      int64_t co, int ldc, int beta) {
@@ -408,13 +410,25 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
     p.packL.add(pt);
     nLf += frag_words(EL.rows[a], A.dim[a]);
   }
+  // x: every block is packed (the GEMM operand, where stage 1 uses it) and copied
+  // to FP32 with rows padded to 4 (the mixing operand); T1 rows padded to 4
+  std::vector<int64_t> t1f(X.blk.size(), -1), xm(X.blk.size(), -1);
+  int64_t nT1f = 0, nXm = 0;
   for (size_t x = 0; x < X.blk.size(); ++x) {
     const auto& k = X.blk[x];
-    if (t1off[x] < 0) continue;
     xf[x] = nXf;   // B = x block [da x db], N-contiguous: fragment rows are its columns
-    p.packX.add(packtask(prob, k.db, k.da, 2, k.off, k.db, 1, 2, nXf, kfrags(k.da), 0, 4 * kfrags(k.da)));
+    xm[x] = nXm;
+    PackTask pt = packtask(prob, k.db, k.da, 2, k.off, k.db, 1, 2, nXf, kfrags(k.da), 0, 4 * kfrags(k.da));
+    pt.xbase = 6;
+    pt.xoff = nXm;
+    pt.xld = round4(k.db);
+    p.packX.add(pt);
     nXf += frag_words(k.db, k.da);
-    p.f1.add(gemm(prob, EL.rows[k.a], k.db, k.da, 0, lf[k.a], 0, 2, xf[x], 0, 4, t1off[x], k.db, 0));
+    nXm += (int64_t)k.da * round4(k.db);
+    if (t1off[x] < 0) continue;
+    t1f[x] = nT1f;
+    nT1f += (int64_t)EL.rows[k.a] * round4(k.db);
+    p.f1.add(gemm(prob, EL.rows[k.a], k.db, k.da, 0, lf[k.a], 0, 2, xf[x], 0, 4, t1f[x], round4(k.db), 0));
   }
   // K of T3 and R in the fragment form: channel u of right sector b starts at cpad[b][u], a multiple of 8
   std::vector<std::vector<int>> cpad(B.n());
@@ -451,7 +465,9 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
   }
   const auto terms = w12_terms(W1, W2);
   // Source of T1[w](a, t1, t2, b') = (L[w] x)(a, ...): psi block (a', t1, t2) with a' = a - ql[w]
-  auto source = [&](int a, int w, int t1, int t2, int bp, double c, std::vector<MixSrc>& out) {
+  // (out: the FP64/FP32 form; outf: the fragment form with the padded T1 and x copies)
+  auto source = [&](int a, int w, int t1, int t2, int bp, double c, std::vector<MixSrc>& out,
+                    std::vector<MixSrc>& outf) {
     const int ap = A.find(A.q[a] - W1.ql[w]);
     if (ap < 0) return;
     const int xi = X.find(ap, t1, t2);
@@ -460,36 +476,39 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
     if (k.b != bp) throw InvalidArg("internal: H_eff charge bookkeeping mismatch");
     if (w == DL - 1) {
       out.push_back(src(c, 6, k.off, k.db));
+      outf.push_back(src(c, 6, xm[xi], round4(k.db)));
     } else {
       const int ro = EL.row_off[ap][w];
       if (ro < 0 || EL.a_out[ap][w] != a) return;
       out.push_back(src(c, 4, t1off[xi] + (int64_t)ro * k.db, k.db));
+      outf.push_back(src(c, 4, t1f[xi] + (int64_t)ro * round4(k.db), round4(k.db)));
     }
   };
   for (size_t xo = 0; xo < X.blk.size(); ++xo) {
     const auto& ko = X.blk[xo];
     // R identity channel (u = 0): straight into y
     {
-      std::vector<MixSrc> s;
+      std::vector<MixSrc> s, sf;
       auto it = terms.find(std::make_tuple(ko.s1, ko.s2, 0));
       if (it != terms.end())
-        for (const auto& tm : it->second) source(ko.a, tm.w, tm.t1, tm.t2, ko.b, tm.c, s);
+        for (const auto& tm : it->second) source(ko.a, tm.w, tm.t1, tm.t2, ko.b, tm.c, s, sf);
       p.mixY.add(mixtask(prob, ko.da, ko.db, 3, ko.off, ko.db), s);
+      p.mixYf.add(mixtask(prob, ko.da, ko.db, 3, ko.off, ko.db), sf);
     }
     for (int u = 1; u < DR; ++u) {
       const int co = ER.col_off[ko.b][u];
       if (co < 0) continue;
       const int bp = ER.b_in[ko.b][u];
-      std::vector<MixSrc> s;
+      std::vector<MixSrc> s, sf;
       auto it = terms.find(std::make_tuple(ko.s1, ko.s2, u));
       if (it != terms.end())
-        for (const auto& tm : it->second) source(ko.a, tm.w, tm.t1, tm.t2, bp, tm.c, s);
+        for (const auto& tm : it->second) source(ko.a, tm.w, tm.t1, tm.t2, bp, tm.c, s, sf);
       p.mixT.add(mixtask(prob, ko.da, B.dim[bp], 5, t3off[ko.b] + (int64_t)rowin[xo] * ER.K[ko.b] + co, ER.K[ko.b]),
                  s);
       MixTask mf = mixtask(prob, ko.da, B.dim[bp], 5, t3f[ko.b], kfrags(Kp[ko.b]));
       mf.r0 = rowin[xo];
       mf.c0 = cpad[ko.b][u];
-      p.mixTf.add(mf, s);
+      p.mixTf.add(mf, sf);
     }
   }
   if (shR)
@@ -512,6 +531,8 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
   p.n_Rf.push_back(nRf);
   p.n_Xf.push_back(nXf);
   p.n_T3f.push_back(nT3f);
+  p.n_T1f.push_back(nT1f);
+  p.n_Xm.push_back(nXm);
   p.n_T1.push_back(nT1);
   p.n_T3.push_back(nT3);
   p.n_L.push_back(EL.size);
@@ -593,6 +614,19 @@ void check_mix_frag(const MixList& m, const std::vector<int64_t>& sizes, const c
   }
 }
 
+void check_mix_v4(const MixList& m, const std::vector<int64_t>& sizes, const char* what) {
+  for (const auto& t : m.t) {
+    if (t.rows <= 0 || t.cols <= 0) continue;
+    for (int k = 0; k < t.nsrc; ++k) {
+      const MixSrc& s = m.src[t.src0 + k];
+      if (s.trans) continue;
+      if (s.off % 4 != 0 || s.ld % 4 != 0 || s.ld < round4(t.cols))
+        throw InvalidArg(std::string("internal: ") + what + " source rows not 16-byte aligned and padded");
+      in_bounds(s.off, s.off + (int64_t)(t.rows - 1) * s.ld + round4(t.cols) - 1, sizes, t.prob, s.base, what);
+    }
+  }
+}
+
 void check_pack(const PackList& pl, const std::vector<int64_t>& ssizes, const std::vector<int64_t>& dsizes,
                 const char* what) {
   for (const auto& t : pl.t) {
@@ -603,6 +637,11 @@ void check_pack(const PackList& pl, const std::vector<int64_t>& ssizes, const st
     }
     if (t.kc0 < 0 || t.kc0 % 8 != 0 || t.K > 8 * t.nch || t.kc0 + 8 * t.nch > t.KB * kFragK)
       throw InvalidArg(std::string("internal: ") + what + " pack outside its fragment matrix");
+    if (t.xbase >= 0 && t.K > 0) {   // FP32 copy, in the source's orientation
+      const int rows = t.trans ? t.K : t.R, cols = t.trans ? t.R : t.K;
+      if (t.xld < cols) throw InvalidArg(std::string("internal: ") + what + " copy row shorter than the block");
+      in_bounds(t.xoff, t.xoff + (int64_t)(rows - 1) * t.xld + cols - 1, dsizes, t.prob, t.xbase, what);
+    }
     in_bounds(t.doff, frag_last(t.doff, t.R, t.KB * kFragK, what), dsizes, t.prob, t.dbase, what);
   }
 }

@@ -128,9 +128,13 @@ struct HeffPlan {
   // in the fragment layout; packL/packR (once per operator) and packX (per
   // matvec) fill the operands from the FP64 inputs.
   GemmList f1, f2;
-  MixList mixTf;
+  MixList mixYf, mixTf;
   PackList packL, packR, packX;
   std::vector<int64_t> n_Lf, n_Rf, n_Xf, n_T3f;   // words, per problem
+  // The fragment form's mixing reads T1 and an FP32 copy of x (written by the x
+  // pack) whose rows are padded to multiples of 4 floats and start on 16-byte
+  // boundaries, so that it can read 4 columns per 16-byte load.
+  std::vector<int64_t> n_T1f, n_Xm;               // floats, per problem
   // In the fragment form the K index of T3 and R (channel u, column b') is
   // re-spaced so that each channel's block starts at a multiple of 8.
   //
@@ -178,6 +182,10 @@ void check_scale(const ScaleList& s, const std::vector<int64_t>& sizes, const ch
 // Fragment-layout forms (sizes of fragment buffers in 32-bit words).
 void check_gemm_frag(const GemmList& g, const std::vector<int64_t>& sizes, const char* what);
 void check_mix_frag(const MixList& m, const std::vector<int64_t>& sizes, const char* what);
+// Sources of the 4-column mixing: non-transposed rows start at multiples of 4
+// floats, have lengths that are multiples of 4, and every row's padded length
+// lies inside its buffer.
+void check_mix_v4(const MixList& m, const std::vector<int64_t>& sizes, const char* what);
 void check_pack(const PackList& p, const std::vector<int64_t>& ssizes, const std::vector<int64_t>& dsizes,
                 const char* what);
 

@@ -67,6 +67,11 @@ void run_pack(const PackList& pl, const std::vector<double*>& src, const std::ve
       for (int k = 0; k < 8 * t.nch; ++k) {
         const int64_t i = frag_slot(t.doff, t.KB, r, t.kc0 + k);
         double v = r < t.R && k < t.K ? (t.trans ? S[(int64_t)k * t.ld + r] : S[(int64_t)r * t.ld + k]) : 0.0;
+        if (t.xbase >= 0 && r < t.R && k < t.K) {   // the row-padded copy, in the source's orientation
+          double* Xc = base_ptr(dst, t.prob, t.xbase) + t.xoff;
+          if (t.trans) Xc[(int64_t)k * t.xld + r] = v;
+          else Xc[(int64_t)r * t.xld + k] = v;
+        }
         if (r - t.dr0 == k - t.dk0 && r - t.dr0 >= 0 && r - t.dr0 < t.dlen) v -= t.shift;
         D[i] = v;
         D[i + kFragWords] = 0.0;
@@ -159,15 +164,15 @@ extern "C" int hostplan_heff_frag(const idmrg_heff* H, const double* x, double* 
     build_heff(p, 0, A, B, make_mpo(H->w1, "w1"), make_mpo(H->w2, "w2"));
     const double nan = std::nan("");
     std::vector<double> Lf(2 * p.n_Lf[0] + 2, nan), Rf(2 * p.n_Rf[0] + 2, nan), Xf(2 * p.n_Xf[0] + 2, nan),
-        T1(p.n_T1[0] + 1), T3f(2 * p.n_T3f[0] + 2, 0.0);
+        T1(p.n_T1f[0] + 1, nan), Xm(p.n_Xm[0] + 1, nan), T3f(2 * p.n_T3f[0] + 2, 0.0);
     std::vector<double*> src(kNumBases, nullptr), b(kNumBases, nullptr);
     src[0] = (double*)H->L; src[1] = (double*)H->R; src[2] = (double*)x;
     b[0] = Lf.data(); b[1] = Rf.data(); b[2] = Xf.data(); b[3] = y; b[4] = T1.data(); b[5] = T3f.data();
-    b[6] = (double*)x;
+    b[6] = Xm.data();
     std::vector<int64_t> ss(kNumBases, -1), sz(kNumBases, -1);
     ss[0] = p.n_L[0]; ss[1] = p.n_R[0]; ss[2] = p.n_psi[0];
-    sz[0] = p.n_Lf[0]; sz[1] = p.n_Rf[0]; sz[2] = p.n_Xf[0]; sz[3] = sz[6] = p.n_psi[0]; sz[4] = p.n_T1[0];
-    sz[5] = p.n_T3f[0];
+    sz[0] = p.n_Lf[0]; sz[1] = p.n_Rf[0]; sz[2] = p.n_Xf[0]; sz[3] = p.n_psi[0]; sz[4] = p.n_T1f[0];
+    sz[5] = p.n_T3f[0]; sz[6] = p.n_Xm[0];
     flags[0] = p.shiftL[0];
     flags[1] = p.shiftR[0];
     for (auto& t : p.packL.t) t.shift = t.dlen > 0 ? sL : 0.0;
@@ -177,14 +182,16 @@ extern "C" int hostplan_heff_frag(const idmrg_heff* H, const double* x, double* 
     check_pack(p.packR, ss, sz, "packR");
     check_pack(p.packX, ss, sz, "packX");
     check_gemm_frag(p.f1, sz, "f1");
-    check_mix(p.mixY, sz, "mixY");
+    check_mix(p.mixYf, sz, "mixYf");
+    check_mix_v4(p.mixYf, sz, "mixYf");
     check_mix_frag(p.mixTf, sz, "mixTf");
+    check_mix_v4(p.mixTf, sz, "mixTf");
     check_gemm_frag(p.f2, sz, "f2");
     run_pack(p.packL, src, b);
     run_pack(p.packR, src, b);
     run_pack(p.packX, src, b);
     run_gemm_frag(p.f1, b);
-    run_mix(p.mixY, b);
+    run_mix(p.mixYf, b);
     run_mix_frag(p.mixTf, b);
     run_gemm_frag(p.f2, b);
     for (int64_t i = 0; i < p.n_psi[0]; ++i) y[i] += sigma * x[i];
