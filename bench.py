@@ -17,8 +17,9 @@ bracketed by HIP events on the library's stream; the H_eff matvec throughput
 is the algorithmic flop count of the matvecs (from the U(1) block lists)
 divided by their summed kernel time.
 
-Prints one JSON line (value = matvec TFLOP/s of the mixed path, ms_per_step =
-its seconds per unit-cell step; the FP64 figures sit under "fp64").
+Prints one JSON line on stdout (value = matvec TFLOP/s of the mixed path,
+ms_per_step = its seconds per unit-cell step; the FP64 figures sit under
+"fp64"), and one progress line per unit-cell step on stderr.
 --gpus N with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -37,6 +38,7 @@ if ROOT not in sys.path:
 # products per FP64-equivalent product, so its ceiling for algorithmic flops is
 # the bf16 peak / 3.
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0}
+LATTICE = {"yc8": "kagome YC8", "yc4": "square YC4", "chain": "chain"}
 MATVEC = ["heff_gemm1", "heff_gemm2", "heff_mix", "heff_gemm1_lo", "heff_gemm2_lo", "heff_mix_lo", "convert"]
 
 
@@ -68,17 +70,23 @@ def cpu_baseline(d, budget_s=12.0):
                        f"(N={layout.psi_size(A, B, W1.qp)}, {flops:.3e} flops each) in {t:.1f} s")
 
 
+def note(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def timed(d, prec, steps, warmup):
     """Run warmup + timed steps at one matvec precision; returns the measurements."""
     import torch
     d.prec = prec
-    for _ in range(warmup):
+    for k in range(warmup):
         d.step()
+        note(f"{prec}: warmup step {k + 1}/{warmup} done (n={d.n})")
     d.ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         d.step()
+        note(f"{prec}: timed step {k + 1}/{steps} issued (n={d.n})")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = d.ctx.profile_get()
@@ -174,6 +182,7 @@ def main():
     t_pre = time.perf_counter()
     while d.n < a.prefill:
         d.step()
+        note(f"prefill: n={d.n}/{a.prefill} done, {time.perf_counter() - t_pre:.1f} s")
     t_pre = time.perf_counter() - t_pre
     snap = d.snapshot()
     r64 = timed(d, "f64", a.steps, a.warmup)
@@ -194,7 +203,8 @@ def main():
                 "breakdown_ms_per_step": {k: round(v[1] / a.steps, 2) for k, v in r["prof"].items() if v[0]}}
 
     out = {
-        "metric": "H_eff matvec TFLOP/s + s per unit-cell step, kagome YC8 m=2048; mixed vs FP64",
+        "metric": f"H_eff matvec TFLOP/s + s per unit-cell step, {LATTICE.get(a.workload, a.workload)} m={a.m}; "
+                  "mixed vs FP64",
         "value": round(rmx["matvec_tflops"], 4),
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -218,6 +228,7 @@ def main():
         "prefill_s": round(t_pre, 1),
     }
     if not a.no_cpu:
+        note("cpu baseline: timing the oracle matvec")
         out["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(out), flush=True)
 

@@ -1,5 +1,6 @@
 """GPU parity at the full sizes of the cylinder workloads: YC8 kagome at m = 2048
-(D up to 20, split-bf16 matvec) and YC4 square at m = 1024 (D = 14, FP32 matvec).
+and m = 4096 (D up to 20, split-bf16 matvec) and YC4 square at m = 1024 (D = 14,
+FP32 matvec).
 
 The superblock is built without the GPU path: the MPO from the oracle's
 finite-state construction, environments grown by the oracle's own Eqs. (4)
@@ -24,8 +25,10 @@ pytestmark = pytest.mark.gpu
 lib = pytest.importorskip("paper_1606_06790_amd.lib")
 
 MIXED_TOL = {"f32": 5e-6, "bf16x3": 5e-5}
-# (workload, m, matvec policy of its benchmark configuration, smallest MPO channel count at the centre)
-CONFIGS = {"yc8": ("yc8", 2048, "bf16x3", 14), "yc4": ("yc4", 1024, "f32", 14)}
+# (workload, m, matvec policy of its benchmark configuration, smallest MPO channel count at the centre,
+#  left sites c of the superblock, sites grown on the right)
+CONFIGS = {"yc8": ("yc8", 2048, "bf16x3", 14, 13, 12), "yc8_m4096": ("yc8", 4096, "bf16x3", 14, 15, 14),
+           "yc4": ("yc4", 1024, "f32", 14, 13, 12)}
 
 
 def _grow(name, m, c, nright):
@@ -86,8 +89,8 @@ def full(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1606_06790_amd.lib import Mpo
-    name, m, prec, dmin = CONFIGS[request.param]
-    s = _grow(name, m, 13, 12)
+    name, m, prec, dmin, c, nright = CONFIGS[request.param]
+    s = _grow(name, m, c, nright)
     s.update(name=name, m=m, prec=prec, dmin=dmin)
     A, B = s["A"], s["B"]
     s["prob"] = dict(left=A, right=B, w1=Mpo(s["W1"], s["dl"], s["dm"], QP), w2=Mpo(s["W2"], s["dm"], s["dr"], QP),
