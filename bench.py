@@ -12,10 +12,12 @@ mixed-precision matvec in turn, starting from the kept state: `warmup`
 steps untimed, then exactly `steps` steps timed between two device
 synchronisations.  Both precisions therefore solve the same iterations from
 the same state, which gives a like-for-like speed-up and the energy
-difference per result.  During the timed steps every library launch is
+difference per result.  ms_per_step is that wall clock as in production (no
+per-launch events, so full Lanczos chunks replay as HIP graphs).  The same
+steps are then run again from the same state with every library launch
 bracketed by HIP events on the library's stream; the H_eff matvec throughput
 is the algorithmic flop count of the matvecs (from the U(1) block lists)
-divided by their summed kernel time.
+divided by their summed kernel time in that run.
 
 Prints one JSON line on stdout (value = matvec TFLOP/s of the mixed path,
 ms_per_step = its seconds per unit-cell step; the FP64 figures sit under
@@ -74,28 +76,71 @@ def note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def timed(d, prec, steps, warmup):
-    """Run warmup + timed steps at one matvec precision; returns the measurements."""
+def wall(d, steps, warmup, label, profile=False):
+    """warmup + timed unit-cell steps from the current state; (seconds per step, step records)."""
     import torch
-    d.prec = prec
     for k in range(warmup):
         d.step()
-        note(f"{prec}: warmup step {k + 1}/{warmup} done (n={d.n})")
-    d.ctx.profile(True)
+        note(f"{label}: warmup step {k + 1}/{warmup} done (n={d.n})")
+    if profile:
+        d.ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         d.step()
-        note(f"{prec}: timed step {k + 1}/{steps} issued (n={d.n})")
+        note(f"{label}: timed step {k + 1}/{steps} done (n={d.n})")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    return (t1 - t0) / steps, [s for s in d.steps if s["n"] > d.n - steps]
+
+
+def timed(d, prec, steps, warmup):
+    """The timed steps at one matvec precision, twice from the same state: first as in production
+    (no per-launch events, so full Lanczos chunks replay as HIP graphs) for the wall clock, then
+    with every launch bracketed by HIP events for the kernel times."""
+    d.prec = prec
+    snap = d.snapshot()
+    t_run, recs = wall(d, steps, warmup, prec)
+    d.restore(snap)
+    t_prof, recs_p = wall(d, steps, warmup, prec + " (events)", profile=True)
     prof = d.ctx.profile_get()
     d.ctx.profile(False)
     mv_fl = sum(prof[k][2] for k in MATVEC)
     mv_ms = sum(prof[k][1] for k in MATVEC)
-    recs = [s for s in d.steps if s["n"] > d.n - steps]
-    return dict(prec=prec, ms_per_step=(t1 - t0) * 1e3 / steps, matvec_tflops=mv_fl / (mv_ms * 1e-3) / 1e12,
-                prof=prof, recs=recs)
+    return dict(prec=prec, ms_per_step=t_run * 1e3, ms_per_step_events=t_prof * 1e3,
+                matvec_tflops=mv_fl / (mv_ms * 1e-3) / 1e12, prof=prof, recs=recs,
+                identical=[r["energy"] for r in recs] == [r["energy"] for r in recs_p])
+
+
+def batching(a):
+    """Seconds per unit-cell step of one workload solved three ways from the same state: batched
+    with graph-replayed Lanczos chunks (production), batched with direct launches, and one
+    library call per superblock.  Prints one JSON line."""
+    import workloads
+    from paper_1606_06790_amd.driver import IDMRG
+    cfg = workloads.workload(a.workload, m=a.m)
+    d = IDMRG(cfg)
+    while d.n < a.prefill:
+        d.step()
+        note(f"prefill: n={d.n}/{a.prefill} done")
+    snap = d.snapshot()
+    out = {}
+    for name, batched, graph in (("batched_graph", True, True), ("batched_direct", True, False),
+                                 ("one_call_per_superblock", False, True)):
+        d.restore(snap)
+        d.batched, d.graph = batched, graph
+        t, recs = wall(d, a.steps, a.warmup, name)
+        out[name] = dict(ms_per_step=round(t * 1e3, 3), e_site=[round(r["e_site"], 12) for r in recs],
+                         lanczos_iters=[r["iters"] for r in recs])
+    e0 = [r for r in out["batched_graph"]["e_site"]]
+    print(json.dumps({"workload": f"{a.workload}_heisenberg_m{a.m}_u1", "prec": d.prec, "superblocks": d.half,
+                      "steps": a.steps, "warmup": a.warmup, "prefill": a.prefill, "runs": out,
+                      "same_energies": all(v["e_site"] == e0 for v in out.values()),
+                      "batched_speedup_vs_one_call_per_superblock": round(
+                          out["one_call_per_superblock"]["ms_per_step"] / out["batched_graph"]["ms_per_step"], 3),
+                      "graph_speedup_vs_direct": round(
+                          out["batched_direct"]["ms_per_step"] / out["batched_graph"]["ms_per_step"], 3)}),
+          flush=True)
 
 
 def copy_calibration():
@@ -165,6 +210,8 @@ def main():
     ap.add_argument("--mixed", default="bf16x3", choices=["f32", "bf16x3"])
     ap.add_argument("--workload", default="yc8")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batching", action="store_true",
+                    help="only compare batched (graph / direct) against one call per superblock on --workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (reference for HBM byte counters)")
     a = ap.parse_args()
@@ -173,6 +220,9 @@ def main():
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.batching:
+        batching(a)
         return
     import workloads
     from paper_1606_06790_amd.driver import IDMRG
@@ -193,6 +243,7 @@ def main():
 
     def summary(r):
         return {"matvec_tflops": round(r["matvec_tflops"], 4), "ms_per_step": round(r["ms_per_step"], 2),
+                "ms_per_step_events": round(r["ms_per_step_events"], 2), "events_run_identical": r["identical"],
                 "lanczos_iters": [s["iters"] for s in r["recs"]],
                 "fp64_matvecs": [s["fp64_matvecs"] for s in r["recs"]],
                 "reorth_passes": [s["reorth_passes"] for s in r["recs"]],

@@ -175,7 +175,11 @@ typedef struct {
     int32_t refine;     /* mixed precision only: FP64 residual refinement after the iteration */
     int32_t cgs2;       /* 1: second Gram-Schmidt pass in every iteration (classical CGS2);
                            0: only where the first pass removes more than 99 % of |w|^2 */
-    int32_t reserved;   /* set to 0 */
+    int32_t graph;      /* 1: once the GEMM tilings are tuned, every full chunk of iterations
+                           is captured into a HIP graph (one per pass shape, on a capture
+                           stream owned by the context) and replayed on the context stream;
+                           the same kernels in the same order, so results are bitwise those
+                           of 0 (direct launches).  Ignored while profiling is enabled. */
 } idmrg_lanczos_opts;
 
 typedef struct {

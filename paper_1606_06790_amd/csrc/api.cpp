@@ -42,6 +42,7 @@ struct idmrg_ctx {
   double prof_ms[IDMRG_PROF_CLASSES] = {};
   double prof_flops[IDMRG_PROF_CLASSES] = {};
   hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;   // graph capture only (nothing executes on it); created on first use
   std::string err;
   DevBuf plan;                 // uploaded task lists and base tables
   void* pinned = nullptr;      // host staging for uploads
@@ -545,6 +546,50 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   IDMRG_HIP(hipGetLastError());
 }
 
+// Record what body(stream) launches into a HIP graph and instantiate it.  The
+// launches go to the context's capture stream (the library's launchers read
+// c->stream, which points there for the duration), so nothing runs now; the
+// instance is replayed on the context stream.  Default priority, like every
+// stream of the library.
+template <typename F>
+hipGraphExec_t capture_graph(idmrg_ctx* c, F&& body) {
+  if (!c->cap) IDMRG_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  const hipStream_t keep = c->stream;
+  IDMRG_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  c->stream = c->cap;
+  hipGraph_t g = nullptr;
+  try {
+    body(c->cap);
+  } catch (...) {
+    c->stream = keep;
+    (void)hipStreamEndCapture(c->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  c->stream = keep;
+  IDMRG_HIP(hipStreamEndCapture(c->cap, &g));
+  hipGraphExec_t e = nullptr;
+  const hipError_t r = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (r != hipSuccess) throw HipFailure(std::string("hipGraphInstantiate: ") + hipGetErrorString(r));
+  return e;
+}
+
+// Instantiated graphs of one call; released after the stream has drained.
+struct GraphSet {
+  hipStream_t s;
+  hipGraphExec_t ex[4] = {};
+  explicit GraphSet(hipStream_t st) : s(st) {}
+  ~GraphSet() {
+    bool any = false;
+    for (auto e : ex) any = any || e;
+    if (!any) return;
+    (void)hipStreamSynchronize(s);
+    for (auto e : ex)
+      if (e) (void)hipGraphExecDestroy(e);
+  }
+};
+
 void check_nprob(int nprob) {
   if (nprob < 1 || nprob > 64) throw InvalidArg("nprob must be 1..64");
 }
@@ -580,6 +625,7 @@ extern "C" int idmrg_destroy(idmrg_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   for (auto& row : c->tev)
     for (auto e : row)
       if (e) (void)hipEventDestroy(e);
@@ -785,6 +831,7 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     std::vector<int> iters(P, 0), fp64mv(P, 0), reorths(P, 0);
     std::vector<LzCtrl> fin(P), out(P);
     std::vector<double> ov0(P, 0.0);
+    GraphSet graphs(s);
     for (int outer = 0; outer < max_outer; ++outer) {
       std::vector<LzCtrl> hctrl(P);
       std::vector<int32_t> hact(P);
@@ -817,14 +864,33 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       // refinement passes reduce the exact residual by a fixed factor each
       const double relF = (mixed && outer > 0) ? (o->prec == IDMRG_PREC_F32 ? 1e-4 : 2e-4) : 0.0;
       std::vector<int32_t> act(P);
+      // one iteration: matvec (FP64 for the first of a mixed pass) and the vector work
+      auto iteration = [&](int64_t i, int trial, hipStream_t st) {
+        HeffExec& e = (!mixed || i == 0) ? ex64 : exlo;
+        heff_run(ctx, e, vv, ww, active, trial);
+        Prof pr(ctx, 4, 0.0);
+        lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, pnorm, kmax, tolE, tolR, tolF,
+                          relF, o->cgs2 ? 1 : 0, st);
+      };
       for (int64_t it = 0; it < maxk;) {
-        for (int k = 0; k < chunk && it < maxk; ++k, ++it) {
-          HeffExec& e = (!mixed || it == 0) ? ex64 : exlo;
-          const int trial = (!tuned && &e == &bulk && trial_next < bulk.nvar) ? trial_next++ : -1;
-          heff_run(ctx, e, vv, ww, active, trial);
-          Prof pr(ctx, 4, 0.0);
-          lz_iteration_tail(P, dprobs, ctrl, active, alpha, beta, ritz, coef, partial, pnorm, kmax, tolE, tolR, tolF,
-                            relF, o->cgs2 ? 1 : 0, s);
+        if (o->graph && tuned && !ctx->prof && it + chunk <= maxk) {
+          // a full chunk as one graph launch; the launches depend only on whether the chunk
+          // opens a mixed pass (FP64 first matvec) and on the pass's tolerances (outer > 0)
+          const int key = (mixed && it == 0 ? 1 : 0) + (outer > 0 ? 2 : 0);
+          if (!graphs.ex[key]) {
+            const int64_t i0 = it;
+            graphs.ex[key] = capture_graph(ctx, [&](hipStream_t cs) {
+              for (int k = 0; k < chunk; ++k) iteration(i0 + k, -1, cs);
+            });
+          }
+          IDMRG_HIP(hipGraphLaunch(graphs.ex[key], s));
+          it += chunk;
+        } else {
+          for (int k = 0; k < chunk && it < maxk; ++k, ++it) {
+            HeffExec& e = (!mixed || it == 0) ? ex64 : exlo;
+            const int trial = (!tuned && &e == &bulk && trial_next < bulk.nvar) ? trial_next++ : -1;
+            iteration(it, trial, s);
+          }
         }
         IDMRG_HIP(hipMemcpyAsync(act.data(), active, P * 4, hipMemcpyDeviceToHost, s));
         sync(ctx);

@@ -23,7 +23,8 @@ from . import lib, models
 
 
 class IDMRG:
-    def __init__(self, cfg, device=0, prec=None, dense=False, predict=True, chunk=8, log=None):
+    def __init__(self, cfg, device=0, prec=None, dense=False, predict=True, chunk=8, log=None, graph=True,
+                 batched=True):
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -33,6 +34,8 @@ class IDMRG:
         self.prec = prec or cfg.get("prec", "f64")
         self.predict = predict
         self.chunk = chunk
+        self.graph = graph
+        self.batched = batched   # False: one library call per superblock (for comparison only)
         self.log = log
         self.W = models.heisenberg_mpo(cfg["bonds"], self.ell, dense=dense)
         self.qp = self.W[0].qp
@@ -77,8 +80,13 @@ class IDMRG:
             pi, pn = self.prev[i], self.prev[ip1]
             items.append(dict(leg_a=pi["C"], leg_beta=self.lam2[ip1][0], leg_b=pn["C"], lam_i=pi["lam"],
                               V_i=pi["V"], lam_prev=self.lam2[ip1][1], U_ip1=pn["U"], lam_ip1=pn["lam"]))
-        guesses = lib.predict_wavefunction(self.ctx, items, self.qp, self.cfg["lam_floor"])
-        return guesses
+        return self._calls(lib.predict_wavefunction, items, self.qp, self.cfg["lam_floor"])
+
+    def _calls(self, fn, items, *args):
+        """fn over the superblocks: one batched call, or one call per superblock."""
+        if self.batched:
+            return fn(self.ctx, items, *args)
+        return [r for it in items for r in fn(self.ctx, [it], *args)]
 
     def step(self):
         """One unit-cell step: iteration n for all l/2 superblocks."""
@@ -95,16 +103,26 @@ class IDMRG:
                 if nr == 0.0:
                     psis[j] = self._dev(workloads.start_vector(psis[j].numel(), n, H[j]["i"]))
         t1 = time.perf_counter()
-        es, infos = lib.lanczos_solve_batch(self.ctx, H, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"],
-                                            self.prec, self.chunk)
+        if self.batched:
+            es, infos = lib.lanczos_solve_batch(self.ctx, H, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"],
+                                                self.prec, self.chunk, graph=self.graph)
+        else:
+            es, infos = [], []
+            for h, p in zip(H, psis):
+                e1, i1 = lib.lanczos_solve_batch(self.ctx, [h], [p], cfg["tol_E"], cfg["tol_res"], cfg["k_max"],
+                                                 self.prec, self.chunk, graph=self.graph)
+                es += e1
+                infos += i1
         t2 = time.perf_counter()
-        trs = lib.truncate_twosite(self.ctx, [dict(left=h["left"], right=h["right"], psi=p) for h, p in zip(H, psis)],
-                                   self.qp, cfg["m"], cfg["lam_floor"], cfg["deg_rel"])
+        trs = self._calls(lib.truncate_twosite, [dict(left=h["left"], right=h["right"], psi=p) for h, p in zip(H, psis)],
+                          self.qp, cfg["m"], cfg["lam_floor"], cfg["deg_rel"])
         t3 = time.perf_counter()
-        newL = lib.update_env(self.ctx, lib.LEFT, [dict(old_leg=h["left"], new_leg=tr["C"], w=h["w1"], env_old=h["L"],
-                                                        iso=tr["U"]) for h, tr in zip(H, trs)])
-        newR = lib.update_env(self.ctx, lib.RIGHT, [dict(old_leg=h["right"], new_leg=tr["C"], w=h["w2"],
-                                                         env_old=h["R"], iso=tr["V"]) for h, tr in zip(H, trs)])
+        newL = self._calls(lambda c, it: lib.update_env(c, lib.LEFT, it),
+                           [dict(old_leg=h["left"], new_leg=tr["C"], w=h["w1"], env_old=h["L"], iso=tr["U"])
+                            for h, tr in zip(H, trs)])
+        newR = self._calls(lambda c, it: lib.update_env(c, lib.RIGHT, it),
+                           [dict(old_leg=h["right"], new_leg=tr["C"], w=h["w2"], env_old=h["R"], iso=tr["V"])
+                            for h, tr in zip(H, trs)])
         torch.cuda.synchronize(self.dev)
         t4 = time.perf_counter()
         for h, e, inf, tr, Ln, Rn in zip(H, es, infos, trs, newL, newR):
