@@ -223,6 +223,8 @@ typedef struct {
     double cut_gap;            /* relative gap at the cut (-1 if no nonzero value was cut) */
     int32_t svd_sweeps;        /* Jacobi sweeps run (the same for every problem of the call) */
     int32_t svd_converged;     /* 1 if every block met the orthogonality tolerance */
+    int32_t null_completed;    /* 1 if the null-row completion ran for this problem's blocks */
+    int32_t reserved;
 } idmrg_trunc;
 
 /* Psi = U Lambda V^dagger per centre charge (FP64 one-sided Jacobi SVD on the
@@ -234,7 +236,10 @@ typedef struct {
  * kept values are not renormalised.  Singular vectors of values at most
  * max(lam_floor, 1e-15) times their block's Frobenius norm are replaced by an
  * orthonormal completion (they carry no reliable direction), so U and V are
- * isometries to rounding in every case.  Synchronises the stream.  Returns
+ * isometries to rounding in every case.  The completion runs only for problems
+ * where the selection can keep a zero-weight state (fewer values above the
+ * floor than states to keep); elsewhere those vectors are never kept.
+ * Synchronises the stream.  Returns
  * IDMRG_WARN_NOCONV if the Jacobi sweeps did not converge (the result is
  * still written and svd_converged is 0). */
 int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp, int32_t m_max,

@@ -962,6 +962,7 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
     std::vector<PsiLayout> X(P);
     int64_t nM = 0, nX = 0, nG = 0, nU = 0, nV = 0, nS = 0;
     int svd_sweeps = 0, svd_conv = 1;
+    std::vector<int32_t> completed(P, 1);
     MixList gather;
     std::vector<SvdTask> svd;
     std::vector<SelTask> sel;
@@ -1086,6 +1087,32 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
         IDMRG_HIP(hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice));
         return d;
       };
+      // Null rows (sigma <= zero_rel |M_q|_F) need a completed direction only if the
+      // selection can keep a zero-weight state, i.e. if fewer than min(m_max, candidates)
+      // values of the problem lie above lam_floor after the selection's normalisation.
+      // Counted conservatively here: rows with sigma / |sigma| above
+      // max(lam_floor, zero_rel) (1 + 1e-9), which no null row reaches.
+      scr.need_completion = [&](std::vector<int32_t>& complete) {
+        std::vector<double> hS(nS);
+        IDMRG_HIP(hipMemcpyAsync(hS.data(), dS, nS * 8, hipMemcpyDeviceToHost, s));
+        sync(ctx);
+        std::vector<double> tot(P, 0.0);
+        std::vector<int64_t> cand(P, 0), above(P, 0);
+        for (const auto& sv : svd) {
+          const int n = std::min(sv.r, sv.c);
+          cand[sv.prob] += n;
+          for (int i = 0; i < n; ++i) tot[sv.prob] += hS[sv.s_off + i] * hS[sv.s_off + i];
+        }
+        const double thr = std::max(lam_floor, scr.zero_rel) * (1.0 + 1e-9);
+        for (const auto& sv : svd) {
+          const int n = std::min(sv.r, sv.c);
+          const double cut = thr * std::sqrt(tot[sv.prob]);
+          for (int i = 0; i < n; ++i) above[sv.prob] += hS[sv.s_off + i] > cut;
+        }
+        for (int pr = 0; pr < P; ++pr)
+          completed[pr] = !(tot[pr] > 0.0 && above[pr] >= std::min<int64_t>(m_max, cand[pr]));
+        for (size_t m = 0; m < svd.size(); ++m) complete[m] = completed[svd[m].prob];
+      };
       bj_svd(svd, (void**)(dev + a6), (SvdTask*)(dev + a3), scr, s, up, [&]() { sync(ctx); });
       (void)a7;
       svd_sweeps = scr.sweeps;
@@ -1150,6 +1177,8 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
       t[p].m_kept = (int32_t)hscal[4 * p + 3];
       t[p].svd_sweeps = svd_sweeps;
       t[p].svd_converged = svd_conv;
+      t[p].null_completed = completed[p];
+      t[p].reserved = 0;
     }
     {
       std::vector<int64_t> sz((size_t)P * kNumBases, -1);

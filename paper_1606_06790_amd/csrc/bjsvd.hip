@@ -392,11 +392,31 @@ __device__ double block_norm2(const double* z, int p, double* red) {
   return s;
 }
 
+// sigma_i = |X_i| of every row, by the reduction k_bj_finish uses.
+__global__ __launch_bounds__(1024) void k_bj_sigma(const SvdTask* __restrict__ tasks, void* const* __restrict__ bases) {
+  const SvdTask tk = tasks[blockIdx.x];
+  const bool tr = tk.r > tk.c;
+  const int n = tr ? tk.c : tk.r, p = tr ? tk.r : tk.c;
+  const double* X = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 2]) + tk.x_off;
+  double* S = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 6]) + tk.s_off;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int i = wave; i < n; i += 16) {
+    const double* xi = X + (int64_t)i * p;
+    double a = 0.0;
+    for (int k = lane; k < p; k += 64) a += xi[k] * xi[k];
+    a = wsum(a);
+    const double sg = sqrt(a);
+    if (lane == 0) S[i] = !(sg > 1e-150) ? 0.0 : sg;
+  }
+}
+
 // sigma_i = |X_i|, Z_i = X_i / sigma_i; null rows (|X_i|^2 <= thr2) are zeroed
-// and then become unit vectors orthogonalised (twice) against all other rows;
-// then the singular vectors are written as U_full [r x n] and V_full [c x n].
+// and then, if complete[m], become unit vectors orthogonalised (twice) against
+// all other rows; then the singular vectors are written as U_full [r x n] and
+// V_full [c x n].
 __global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ tasks, void* const* __restrict__ bases,
-                                                    const double* __restrict__ thr2) {
+                                                    const double* __restrict__ thr2,
+                                                    const int32_t* __restrict__ complete) {
   __shared__ double red[16];
   __shared__ double coef[kBjMaxN];
   __shared__ unsigned char nul[kBjMaxN];
@@ -444,7 +464,7 @@ __global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ 
     s_nnull = cnt;
   }
   __syncthreads();
-  if (s_nnull > 0) {
+  if (s_nnull > 0 && complete[blockIdx.x]) {
     for (int k = t; k < p; k += 1024) {
       double a = 0.0;
       for (int q = 0; q < n; ++q) {
@@ -563,6 +583,8 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
   const size_t oflags = put(zeros.data(), zeros.size() * 4);
   std::vector<double> zthr(nm, 0.0);
   const size_t othr = put(zthr.data(), zthr.size() * 8);
+  std::vector<int32_t> complete(nm, 1);
+  const size_t ocomp = put(complete.data(), complete.size() * 4);
   char* dev = upload(host);
   const BjMat* dmats = (const BjMat*)(dev + omats);
   int32_t* done = (int32_t*)(dev + oflags);
@@ -590,7 +612,17 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
     }
   }
   scr.sweeps = std::min(sweeps + 1, scr.max_sweeps);
-  hipLaunchKernelGGL(k_bj_finish, dim3(nm), dim3(1024), 0, s, dtasks, dbases, (const double*)thr2);
+  int32_t* dcomp = (int32_t*)(dev + ocomp);
+  if (scr.need_completion) {
+    hipLaunchKernelGGL(k_bj_sigma, dim3(nm), dim3(1024), 0, s, dtasks, dbases);
+    scr.need_completion(complete);
+    if (hipMemcpyAsync(dcomp, complete.data(), nm * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+      throw HipFailure("hipMemcpyAsync of completion flags failed");
+    sync();   // the host vector must outlive the copy
+  }
+  scr.completed = (int)std::count(complete.begin(), complete.end(), 1);
+  hipLaunchKernelGGL(k_bj_finish, dim3(nm), dim3(1024), 0, s, dtasks, dbases, (const double*)thr2,
+                     (const int32_t*)dcomp);
 }
 
 }  // namespace idmrg

@@ -195,10 +195,16 @@ struct BjScratch {
   double tol = 1e-15;        // relative orthogonality of converged rows
   double zero_rel = 1e-15;   // rows with norm <= zero_rel |M|_F are null rows
   int inner_sweeps = 1;      // cap of the sweeps that diagonalise one 64 x 64 pair Gram matrix
-  int max_sweeps = 30;
+  int max_sweeps = 40;       // YC8 kagome at m = 4096 needs up to 29
   int sweeps = 0;            // out: sweeps run
   int converged = 0;         // out: every matrix met the tolerance
   std::vector<int> done_at;  // out: per matrix, the sweep after which it met the tolerance (-1: never)
+  // Null-row completion is needed only where a zero-weight state can be kept.
+  // If set, called after the sweeps once the singular values are in S (device);
+  // it clears complete[m] for every matrix m whose null rows need no
+  // completion (they are then returned as zero vectors).  Unset: all complete.
+  std::function<void(std::vector<int32_t>& complete)> need_completion;
+  int completed = 0;         // out: matrices whose null rows were completed
 };
 void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask* dtasks, BjScratch& scr,
             hipStream_t s, const std::function<char*(const std::vector<char>&)>& upload,

@@ -69,7 +69,7 @@ class Trunc_t(C.Structure):
                 ("V", C.c_void_p), ("lambda_", C.c_void_p), ("cap_U", C.c_int64), ("cap_V", C.c_int64),
                 ("cap_lam", C.c_int64), ("nsec_out", C.c_int32), ("m_kept", C.c_int32), ("eps", C.c_double),
                 ("eps_prime", C.c_double), ("cut_gap", C.c_double), ("svd_sweeps", C.c_int32),
-                ("svd_converged", C.c_int32)]
+                ("svd_converged", C.c_int32), ("null_completed", C.c_int32), ("reserved", C.c_int32)]
 
 
 class EnvUpdate_t(C.Structure):
@@ -340,7 +340,8 @@ def truncate_twosite(ctx, items, qp, m_max, lam_floor=1e-14, deg_rel=1e-5):
         m = sum(x for _, x in Cleg)
         out.append(dict(C=Cleg, U=U[:nU].clone(), V=V[:nV].clone(), lam=lam[:m].clone(), eps=t.eps,
                         eps_prime=t.eps_prime, m_kept=t.m_kept, cut_gap=(None if t.cut_gap < 0 else t.cut_gap),
-                        svd_sweeps=t.svd_sweeps, svd_converged=bool(t.svd_converged), warn=rc))
+                        svd_sweeps=t.svd_sweeps, svd_converged=bool(t.svd_converged),
+                        null_completed=bool(t.null_completed), warn=rc))
     return out
 
 

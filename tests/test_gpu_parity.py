@@ -163,15 +163,15 @@ def test_truncate_twosite(ctx):
             assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-13
 
 
-def _graded_psi(seed):
-    """Two-site state of 9+9 spins (legs C(9,k)) whose centre blocks have low
+def _graded_psi(seed, ns=9):
+    """Two-site state of ns+ns spins (legs C(ns,k)) whose centre blocks have low
     rank k (values in [1e-3, 1]) and only k nonzero columns (as when the right
     leg carries zero-weight states): each block is U diag(sigma) V^T with U
     dense and V supported on k random columns.  The one-sided Jacobi iteration then has many more rows
     than the dimension of their span, and the surplus rows decay to rounding
     residue instead of reaching zero."""
     from math import comb
-    A = [(2 * k - 9, comb(9, k)) for k in range(10)]
+    A = [(2 * k - ns, comb(ns, k)) for k in range(ns + 1)]
     B = list(A)
     psi = {}
     for q, (rows, cols) in u1.center_sectors(A, B, QP).items():
@@ -194,6 +194,41 @@ def _graded_psi(seed):
     return A, B, x / np.linalg.norm(x)
 
 
+def _check_graded(o, A, B, tr):
+    assert o["svd_converged"] and o["warn"] == 0
+    assert o["C"] == tr["C"] and o["m_kept"] == tr["m_kept"]
+    assert abs(o["eps"] - tr["eps"]) <= 1e-14
+    lam = layout.flat_to_lam(H(o["lam"]), o["C"])
+    U = layout.flat_to_U(H(o["U"]), A, QP, o["C"])
+    V = layout.flat_to_V(H(o["V"]), B, QP, o["C"])
+    for q, k in o["C"]:
+        assert np.abs(lam[q] - tr["lam"][q]).max() <= 1e-13
+        Ug = np.concatenate([U[(a, s, q)] for (a, s, _) in layout.U_rows(A, QP, q)])
+        Vg = np.concatenate([V[(s, b, q)] for (s, b, _) in layout.V_rows(B, QP, q)])
+        assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-12
+        assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-12
+        real = lam[q] > 0
+        Uo = np.concatenate([tr["U"][(a, s, q)] for (a, s, _) in layout.U_rows(A, QP, q)])[:, tr["lam"][q] > 0]
+        assert np.abs(Ug[:, real] @ Ug[:, real].T - Uo @ Uo.T).max() <= 1e-10
+
+
+def test_truncate_completion_per_problem(ctx):
+    """One call, m = 64: the 9+9-spin state has 255 values above the floor, so no zero-weight
+    state can be kept and its null rows are left uncompleted; the 5+5-spin state has fewer
+    nonzero values than states to keep, so its zero-weight states are kept and completed.
+    Both must match the oracle and return isometries."""
+    items, refs = [], []
+    for seed, ns in ((11, 9), (13, 5)):
+        A, B, x = _graded_psi(seed, ns)
+        items.append(dict(left=A, right=B, psi=T(x)))
+        refs.append((A, B, u1.truncate_twosite(layout.flat_to_psi(x, A, B, QP), A, B, QP, 64, 1e-14, 1e-5)))
+    out = lib.truncate_twosite(ctx, items, QP, 64, 1e-14, 1e-5)
+    assert [o["null_completed"] for o in out] == [False, True]
+    assert refs[1][2]["m_kept"] > sum(1 for v in refs[1][2]["lam"].values() for l in v if l > 0)
+    for (A, B, tr), o in zip(refs, out):
+        _check_graded(o, A, B, tr)
+
+
 def test_truncate_graded_spectrum(ctx):
     """Rows of the Jacobi iteration whose singular values are far below the
     floor have no reliable direction; the returned U and V must still be
@@ -206,21 +241,8 @@ def test_truncate_graded_spectrum(ctx):
         refs.append((A, B, u1.truncate_twosite(layout.flat_to_psi(x, A, B, QP), A, B, QP, 512, 1e-14, 1e-5)))
     out = lib.truncate_twosite(ctx, items, QP, 512, 1e-14, 1e-5)
     for (A, B, tr), o in zip(refs, out):
-        assert o["svd_converged"] and o["warn"] == 0
-        assert o["C"] == tr["C"] and o["m_kept"] == tr["m_kept"]
-        assert abs(o["eps"] - tr["eps"]) <= 1e-14
-        lam = layout.flat_to_lam(H(o["lam"]), o["C"])
-        U = layout.flat_to_U(H(o["U"]), A, QP, o["C"])
-        V = layout.flat_to_V(H(o["V"]), B, QP, o["C"])
-        for q, k in o["C"]:
-            assert np.abs(lam[q] - tr["lam"][q]).max() <= 1e-13
-            Ug = np.concatenate([U[(a, s, q)] for (a, s, _) in layout.U_rows(A, QP, q)])
-            Vg = np.concatenate([V[(s, b, q)] for (s, b, _) in layout.V_rows(B, QP, q)])
-            assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-12
-            assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-12
-            real = lam[q] > 0
-            Uo = np.concatenate([tr["U"][(a, s, q)] for (a, s, _) in layout.U_rows(A, QP, q)])[:, tr["lam"][q] > 0]
-            assert np.abs(Ug[:, real] @ Ug[:, real].T - Uo @ Uo.T).max() <= 1e-10
+        assert o["null_completed"]
+        _check_graded(o, A, B, tr)
 
 
 def _flat_problem(st):
