@@ -47,7 +47,7 @@ struct idmrg_ctx {
   DevBuf plan;                 // uploaded task lists and base tables
   void* pinned = nullptr;      // host staging for uploads
   size_t pinned_n = 0;
-  DevBuf ws[16];               // scratch, by purpose (see WS_*)
+  DevBuf ws[20];               // scratch, by purpose (see WS_*)
   // GEMM tile autotuner: measured best tiling per (precision, stage, shape bucket)
   std::map<std::tuple<int, int, int, int, int>, int> tune;
   hipEvent_t tev[4][4] = {};   // [variant][stage-1 start, stage-1 end, stage-2 start, stage-2 end]
@@ -57,7 +57,7 @@ namespace {
 
 enum {
   WS_T1 = 0, WS_T3, WS_LOWENV, WS_LOWVEC, WS_LZ, WS_LZSMALL, WS_SVD, WS_SEL, WS_ENV, WS_PRED, WS_READ, WS_MISC,
-  WS_PLAN64, WS_PLANLOW, WS_T3F, WS_DIAG
+  WS_PLAN64, WS_PLANLOW, WS_T3F, WS_DIAG, WS_BJ
 };
 
 void sync(idmrg_ctx* c) { IDMRG_HIP(hipStreamSynchronize(c->stream)); }
@@ -1113,7 +1113,8 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
           completed[pr] = !(tot[pr] > 0.0 && above[pr] >= std::min<int64_t>(m_max, cand[pr]));
         for (size_t m = 0; m < svd.size(); ++m) complete[m] = completed[svd[m].prob];
       };
-      bj_svd(svd, (void**)(dev + a6), (SvdTask*)(dev + a3), scr, s, up, [&]() { sync(ctx); });
+      bj_svd(svd, (void**)(dev + a6), (SvdTask*)(dev + a3), scr, s, up,
+             [&](size_t b) { return (char*)ensure(ctx, ctx->ws[WS_BJ], b); }, [&]() { sync(ctx); });
       (void)a7;
       svd_sweeps = scr.sweeps;
       svd_conv = scr.converged;

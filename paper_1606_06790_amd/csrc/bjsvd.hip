@@ -5,12 +5,15 @@
 // orthogonal by orthogonal transformations accumulated in G (n x n), so that
 // G X = diag(sigma) Z^T.  The rows are grouped in blocks of 32.  One sweep
 // pairs every block with every other block once (round-robin, nb-1 rounds of
-// nb/2 disjoint pairs); all pairs of one round of all matrices form one
-// launch.  For a pair (I, J), one workgroup:
-//   1. forms the 64 x 64 Gram matrix S = Y Y^T of Y = [X_I; X_J] with FP64 MFMA,
-//   2. diagonalises S by cyclic two-sided Jacobi in LDS (32 disjoint rotations
-//      per step), accumulating Q with Q^T S Q diagonal,
-//   3. replaces Y by Q^T Y and [G_I; G_J] by Q^T [G_I; G_J] with FP64 MFMA.
+// nb/2 disjoint pairs).  A round of all matrices takes three launches, so
+// that the pairs of the largest blocks are spread over many workgroups:
+//   1. partial 64 x 64 Gram matrices of Y = [X_I; X_J] over column chunks of
+//      256 (FP64 MFMA), one workgroup per (pair, chunk);
+//   2. per pair, their sum S = Y Y^T (in chunk order) is diagonalised by
+//      cyclic two-sided Jacobi in LDS (32 disjoint rotations per step),
+//      accumulating Q with Q^T S Q diagonal;
+//   3. Y <- Q^T Y and [G_I; G_J] <- Q^T [G_I; G_J] (FP64 MFMA), one workgroup
+//      per (pair, chunk of 256 columns of X or of G).
 // A pair whose rows are already orthogonal to the relative tolerance is left
 // alone; a sweep in which no pair of a matrix moved ends that matrix.
 //
@@ -45,9 +48,17 @@ struct BjMat {                  // one matrix (device)
   int64_t x_off, g_off;
 };
 
-struct BjTask {                 // one block pair in one round
-  int32_t mat, bi, bj, pad;
+struct BjPair {                 // one block pair in one round (bj = -1: padding block)
+  int32_t mat, bi, bj;
+  int32_t g0, ng;               // its Gram chunks: items [g0, g0 + ng) of the round's Gram list
+  int32_t pad[3];
 };
+
+struct BjItem {                 // one column chunk [c0, c1) of a pair: of X (which = 0) or G (which = 1)
+  int32_t pair, c0, c1, which;
+};
+
+constexpr int kChunk = 256;     // columns per Gram or rotation chunk (four 64-column tiles)
 
 // Operands are read through global-address-space pointers from clamped
 // (always valid) indices; a tail that must read as zero is cleared with a mask
@@ -87,89 +98,112 @@ __device__ __forceinline__ void store64(const v4d acc[2][2], F put) {
       for (int r = 0; r < 4; ++r) put(wm + i * 16 + (lane >> 4) + 4 * r, wn + j * 16 + (lane & 15), acc[i][j][r]);
 }
 
-__global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ tasks, const BjMat* __restrict__ mats,
-                                                 void* const* __restrict__ bases, const int32_t* __restrict__ done,
-                                                 int32_t* __restrict__ changed, const double* __restrict__ thr2,
-                                                 double tol, int inner_sweeps) {
-  // The MFMA staging tile T (64 x 64) aliases the Gram matrix S: the Gram
-  // product stages through it before S is written, and the rotation products
-  // run after S is no longer needed (two workgroups fit in one CU's LDS).
+// Row of the pair's local row i (0..63) in its matrix, or -1 for a padding row.
+__device__ __forceinline__ int pair_row(const BjPair& pr, int n, int i) {
+  const int r = i < BB ? pr.bi * BB + i : pr.bj * BB + (i - BB);
+  const bool ok = i < BB ? (pr.bi >= 0 && r < n) : (pr.bj >= 0 && r < n);
+  return ok ? r : -1;
+}
+
+// 1. Partial Gram matrix of one pair over one column chunk [c0, c1) of X:
+// P = Y[:, c0:c1] Y[:, c0:c1]^T (64 x 64, padding rows included; they are
+// masked when the partials are summed).  Tiles of 64 rows (local rows
+// k = wave + 4q, q < 16) x 64 columns are loaded whole, the next one into
+// registers while the current one is multiplied; the staged tile
+// T[k][i] = Y[i][c + k] serves as both MFMA operands.  Columns past c1 read
+// as zero; padding rows read a real row (clamped).
+__global__ __launch_bounds__(256) void k_bj_gram(const BjItem* __restrict__ items, const BjPair* __restrict__ pairs,
+                                                 const BjMat* __restrict__ mats, void* const* __restrict__ bases,
+                                                 const int32_t* __restrict__ done, double* __restrict__ partial) {
+  __shared__ double T[PB][LD];
+  const BjItem it = items[blockIdx.x];
+  const BjPair pr = pairs[it.pair];
+  if (done[pr.mat]) return;
+  const BjMat mt = mats[pr.mat];
+  const int n = mt.n, p = mt.p;
+  const double* X = reinterpret_cast<double*>(bases[mt.prob * kNumBases + 2]) + mt.x_off;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  constexpr int NQ = PB / 4;
+  const gptr<double> Xg = as_global(X);
+  int offs[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int r = pair_row(pr, n, wave + 4 * q);
+    offs[q] = (r >= 0 ? r : pr.bi * BB) * p;
+  }
+  const int c1 = it.c1;
+  double v[NQ];
+  auto ld = [&](int c0) {
+    const int k = c0 + lane, kc = k < c1 ? k : c1 - 1;
+    const uint32_t m = lane_mask(k < c1);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = keep(Xg[offs[q] + kc], m);
+  };
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+  ld(it.c0);
+  for (int c0 = it.c0; c0 < c1; c0 += PB) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) T[lane][wave + 4 * q] = v[q];
+    __syncthreads();
+    if (c0 + PB < c1) ld(c0 + PB);
+#pragma unroll 4
+    for (int kk = 0; kk < PB; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = T[kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = T[kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* P = partial + (size_t)blockIdx.x * (PB * PB);
+  store64(acc, [&](int i, int j, double x) { P[i * PB + j] = x; });
+}
+
+// 2. One workgroup per pair: S = sum of the pair's partial Gram matrices (in
+// chunk order), masked on padding rows; if some pair of non-null rows is
+// coupled beyond the tolerance, S is diagonalised by cyclic two-sided Jacobi
+// (round-robin, 32 disjoint rotations per step, at most inner_sweeps sweeps)
+// and the accumulated rotation Q (Q^T S Q diagonal) is written out; move[pair]
+// says whether Q is to be applied.
+__global__ __launch_bounds__(256) void k_bj_rotate(const BjPair* __restrict__ pairs, const BjMat* __restrict__ mats,
+                                                   const int32_t* __restrict__ done, int32_t* __restrict__ changed,
+                                                   const double* __restrict__ thr2, const double* __restrict__ partial,
+                                                   double* __restrict__ Qout, int32_t* __restrict__ move, double tol,
+                                                   int inner_sweeps) {
   __shared__ double S[PB][LD];
   __shared__ double Q[PB][LD];
-  double(*T)[LD] = S;
   __shared__ double cs_[PB / 2], sn_[PB / 2];
   __shared__ int pidx[PB / 2], qidx[PB / 2];
   __shared__ int s_move;
-  const BjTask tk = tasks[blockIdx.x];
-  if (done[tk.mat]) return;
-  const BjMat mt = mats[tk.mat];
-  const int n = mt.n, p = mt.p;
-  double* X = reinterpret_cast<double*>(bases[mt.prob * kNumBases + 2]) + mt.x_off;
-  double* G = reinterpret_cast<double*>(bases[mt.prob * kNumBases + 3]) + mt.g_off;
+  const BjPair pr = pairs[blockIdx.x];
   const int t = threadIdx.x;
-  // global row of local row i (0..63), or -1 for a padding row
-  auto grow = [&](int i) -> int {
-    const int r = i < BB ? tk.bi * BB + i : tk.bj * BB + (i - BB);
-    const bool ok = i < BB ? (tk.bi >= 0 && r < n) : (tk.bj >= 0 && r < n);
-    return ok ? r : -1;
-  };
-  const int lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int r_any = tk.bi * BB;   // a row of the pair that exists (the first block is never a padding block)
-  // Tiles of 64 rows (local rows k = wave + 4q, q < 16) x 64 columns (c0 + lane)
-  // are loaded whole, the next one into registers while the current one is
-  // multiplied; padding rows read a real row (clamped).
-  constexpr int NQ = PB / 4;
-  // 1. Gram matrix S = Y Y^T over column tiles; the staged tile T[k][i] =
-  // Y[i][c0 + k] serves as both operands.  Columns past p read as zero.
-  v4d acc[2][2];
-  {
-    const gptr<double> Xg = as_global((const double*)X);
-    int offs[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int r = grow(wave + 4 * q);
-      offs[q] = (r >= 0 ? r : r_any) * p;
-    }
-    double v[NQ];
-    auto ld = [&](int c0) {
-      const int k = c0 + lane, kc = k < p ? k : p - 1;
-      const uint32_t m = lane_mask(k < p);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) v[q] = keep(Xg[offs[q] + kc], m);
-    };
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
-    ld(0);
-    for (int c0 = 0; c0 < p; c0 += PB) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) T[lane][wave + 4 * q] = v[q];
-      __syncthreads();
-      if (c0 + PB < p) ld(c0 + PB);
-#pragma unroll 4
-      for (int kk = 0; kk < PB; kk += 4) {
-        const int kr = kk + (lane >> 4);
-        double a[2], b[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = T[kr][wm + i * 16 + (lane & 15)];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = T[kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-      __syncthreads();
-    }
-    store64(acc, [&](int i, int j, double v2) { S[i][j] = (grow(i) >= 0 && grow(j) >= 0) ? v2 : 0.0; });
+  if (done[pr.mat]) {
+    if (t == 0) move[blockIdx.x] = 0;
+    return;
   }
-  for (int e = t; e < PB * PB; e += 256) Q[e / PB][e % PB] = (e / PB == e % PB) ? 1.0 : 0.0;
+  const int n = mats[pr.mat].n;
+  for (int e = t; e < PB * PB; e += 256) {
+    const int i = e / PB, j = e % PB;
+    double a = 0.0;
+    for (int g = 0; g < pr.ng; ++g) a += partial[(size_t)(pr.g0 + g) * (PB * PB) + e];
+    S[i][j] = (pair_row(pr, n, i) >= 0 && pair_row(pr, n, j) >= 0) ? a : 0.0;
+    Q[i][j] = i == j ? 1.0 : 0.0;
+  }
   if (t == 0) s_move = 0;
   __syncthreads();
   // is any pair of non-null rows coupled beyond the tolerance?
-  const double z2 = thr2[tk.mat];
+  const double z2 = thr2[pr.mat];
   {
     bool mv = false;
     for (int e = t; e < PB * PB; e += 256) {
@@ -182,10 +216,11 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
     if (mv) s_move = 1;
   }
   __syncthreads();
-  if (!s_move) return;
-  if (t == 0) changed[tk.mat] = 1;
-  // 2. cyclic Jacobi on S (round-robin, 32 disjoint pairs per step), with the
-  // threshold of the outer test, until S is diagonal to it (at most inner_sweeps)
+  if (!s_move) {
+    if (t == 0) move[blockIdx.x] = 0;
+    return;
+  }
+  if (t == 0) changed[pr.mat] = 1;
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     for (int round = 0; round < PB - 1; ++round) {
       if (t < PB / 2) {
@@ -193,14 +228,14 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
         int a = L(t), b = L(PB - 1 - t);
         if (a > b) { const int z = a; a = b; b = z; }
         const double app = S[a][a], aqq = S[b][b], apq = S[a][b];
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0;
         if (app > z2 && aqq > z2 && fabs(apq) > tol * sqrt(app) * sqrt(aqq)) {
           const double zeta = (aqq - app) / (2.0 * apq);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + tt * tt);
-          s = c * tt;
+          sn = c * tt;
         }
-        pidx[t] = a; qidx[t] = b; cs_[t] = c; sn_[t] = s;
+        pidx[t] = a; qidx[t] = b; cs_[t] = c; sn_[t] = sn;
       }
       __syncthreads();
       // S <- J^T S J and Q <- Q J in one pass: thread-owned 2 x 2 blocks
@@ -238,57 +273,81 @@ __global__ __launch_bounds__(256) void k_bj_pair(const BjTask* __restrict__ task
     __syncthreads();
     if (!s_move) break;
   }
-  // 3. Y <- Q^T Y, G-rows <- Q^T G-rows, in column tiles of 64.  The A operand
-  // is read from Q in LDS; the B tile T[k][c] = rows of the pair at columns
-  // c0 + c is staged whole (the next one loaded into registers meanwhile).
-  // Padding rows need no masking: Q is the identity on them, so they only feed
-  // padding outputs, which are not stored.  A tile is read completely before
-  // any of it is written, and tiles cover disjoint columns.
-  for (int pass = 0; pass < 2; ++pass) {
-    double* Mx = pass == 0 ? X : G;
-    const gptr<double> Mg = as_global((const double*)Mx);
-    const int len = pass == 0 ? p : n;
-    int offs[NQ];
+  double* Qg = Qout + (size_t)blockIdx.x * (PB * PB);
+  for (int e = t; e < PB * PB; e += 256) Qg[e] = Q[e / PB][e % PB];
+  if (t == 0) move[blockIdx.x] = 1;
+}
+
+// 3. Y <- Q^T Y on one column chunk [c0, c1) of X (the pair's rows) or of G.
+// The A operand is Q (LDS); the B tile T[k][c] = rows of the pair at columns
+// c + k is staged whole (the next one loaded into registers meanwhile).
+// Padding rows need no masking: Q is the identity on them, so they only feed
+// padding outputs, which are not stored.  Every output column depends only on
+// the same input column, and a tile is read completely before any of it is
+// written; reads are clamped into the chunk, so chunks of other workgroups
+// are never touched.
+__global__ __launch_bounds__(256) void k_bj_apply(const BjItem* __restrict__ items, const BjPair* __restrict__ pairs,
+                                                  const BjMat* __restrict__ mats, void* const* __restrict__ bases,
+                                                  const int32_t* __restrict__ done, const double* __restrict__ Qin,
+                                                  const int32_t* __restrict__ move) {
+  __shared__ double T[PB][LD];
+  __shared__ double Q[PB][LD];
+  const BjItem it = items[blockIdx.x];
+  const BjPair pr = pairs[it.pair];
+  if (done[pr.mat] || !move[it.pair]) return;
+  const BjMat mt = mats[pr.mat];
+  const int n = mt.n;
+  const int len = it.which ? n : mt.p;
+  double* Mx = reinterpret_cast<double*>(bases[mt.prob * kNumBases + (it.which ? 3 : 2)]) +
+               (it.which ? mt.g_off : mt.x_off);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const double* Qg = Qin + (size_t)it.pair * (PB * PB);
+  for (int e = t; e < PB * PB; e += 256) Q[e / PB][e % PB] = Qg[e];
+  constexpr int NQ = PB / 4;
+  const gptr<double> Mg = as_global((const double*)Mx);
+  int offs[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int r = grow(wave + 4 * q);
-      offs[q] = (r >= 0 ? r : r_any) * len;
-    }
-    double v[NQ];
-    auto ld = [&](int c0) {
-      const int col = c0 + lane < len ? c0 + lane : len - 1;
+  for (int q = 0; q < NQ; ++q) {
+    const int r = pair_row(pr, n, wave + 4 * q);
+    offs[q] = (r >= 0 ? r : pr.bi * BB) * len;
+  }
+  const int c1 = it.c1;
+  double v[NQ];
+  auto ld = [&](int c0) {
+    const int col = c0 + lane < c1 ? c0 + lane : c1 - 1;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) v[q] = Mg[offs[q] + col];
-    };
-    ld(0);
-    for (int c0 = 0; c0 < len; c0 += PB) {
+    for (int q = 0; q < NQ; ++q) v[q] = Mg[offs[q] + col];
+  };
+  ld(it.c0);
+  v4d acc[2][2];
+  for (int c0 = it.c0; c0 < c1; c0 += PB) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) T[wave + 4 * q][lane] = v[q];
-      __syncthreads();
-      if (c0 + PB < len) ld(c0 + PB);
+    for (int q = 0; q < NQ; ++q) T[wave + 4 * q][lane] = v[q];
+    __syncthreads();
+    if (c0 + PB < c1) ld(c0 + PB);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = 0; kk < PB; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = Q[kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = T[kr][wn + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0, 0, 0, 0};
-#pragma unroll 4
-      for (int kk = 0; kk < PB; kk += 4) {
-        const int kr = kk + (lane >> 4);
-        double a[2], b[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = Q[kr][wm + i * 16 + (lane & 15)];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = T[kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-      __syncthreads();
-      store64(acc, [&](int i, int j, double v2) {
-        const int r = grow(i);
-        if (r >= 0 && c0 + j < len) Mx[(int64_t)r * len + c0 + j] = v2;
-      });
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    __syncthreads();
+    store64(acc, [&](int i, int j, double x) {
+      const int r = pair_row(pr, n, i);
+      if (r >= 0 && c0 + j < c1) Mx[(int64_t)r * len + c0 + j] = x;
+    });
   }
 }
 
@@ -547,11 +606,15 @@ __global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ 
 
 void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask* dtasks, BjScratch& scr,
             hipStream_t s, const std::function<char*(const std::vector<char>&)>& upload,
-            const std::function<void()>& sync) {
+            const std::function<char*(size_t)>& scratch, const std::function<void()>& sync) {
   const int nm = (int)svd.size();
   if (nm == 0) return;
   std::vector<BjMat> mats(nm);
-  std::vector<std::vector<BjTask>> rounds;
+  struct Round {
+    std::vector<BjPair> pairs;
+    std::vector<BjItem> gram, apply;
+  };
+  std::vector<Round> rounds;
   for (int m = 0; m < nm; ++m) {
     const SvdTask& t = svd[m];
     const bool tr = t.r > t.c;
@@ -565,7 +628,14 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
         auto L = [&](int x) { return x == 0 ? 0 : 1 + ((rd + x - 1) % (nbe - 1)); };
         int a = L(slot), b = L(nbe - 1 - slot);
         if (a > b) std::swap(a, b);
-        rounds[rd].push_back(BjTask{m, a, b < nb ? b : -1, 0});
+        Round& R = rounds[rd];
+        const int k = (int)R.pairs.size();
+        BjPair pr{m, a, b < nb ? b : -1, (int)R.gram.size(), 0, {0, 0, 0}};
+        for (int c0 = 0; c0 < p; c0 += kChunk) R.gram.push_back(BjItem{k, c0, std::min(p, c0 + kChunk), 0});
+        pr.ng = (int)R.gram.size() - pr.g0;
+        for (int c0 = 0; c0 < p; c0 += kChunk) R.apply.push_back(BjItem{k, c0, std::min(p, c0 + kChunk), 0});
+        for (int c0 = 0; c0 < n; c0 += kChunk) R.apply.push_back(BjItem{k, c0, std::min(n, c0 + kChunk), 1});
+        R.pairs.push_back(pr);
       }
     }
   }
@@ -577,14 +647,28 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
     return off;
   };
   const size_t omats = put(mats.data(), mats.size() * sizeof(BjMat));
-  std::vector<size_t> ornd(rounds.size());
-  for (size_t r = 0; r < rounds.size(); ++r) ornd[r] = put(rounds[r].data(), rounds[r].size() * sizeof(BjTask));
+  std::vector<size_t> opair(rounds.size()), ogram(rounds.size()), oapply(rounds.size());
+  size_t max_pairs = 0, max_gram = 0;
+  for (size_t r = 0; r < rounds.size(); ++r) {
+    opair[r] = put(rounds[r].pairs.data(), rounds[r].pairs.size() * sizeof(BjPair));
+    ogram[r] = put(rounds[r].gram.data(), rounds[r].gram.size() * sizeof(BjItem));
+    oapply[r] = put(rounds[r].apply.data(), rounds[r].apply.size() * sizeof(BjItem));
+    max_pairs = std::max(max_pairs, rounds[r].pairs.size());
+    max_gram = std::max(max_gram, rounds[r].gram.size());
+  }
   std::vector<int32_t> zeros(2 * (size_t)nm, 0);
   const size_t oflags = put(zeros.data(), zeros.size() * 4);
   std::vector<double> zthr(nm, 0.0);
   const size_t othr = put(zthr.data(), zthr.size() * 8);
   std::vector<int32_t> complete(nm, 1);
   const size_t ocomp = put(complete.data(), complete.size() * 4);
+  // per round: partial Gram matrices, rotations, move flags (reused by every round)
+  const size_t tile = (size_t)PB * PB * sizeof(double);
+  const size_t b_partial = max_gram * tile, b_q = max_pairs * tile;
+  char* work = scratch(b_partial + b_q + max_pairs * 4 + 256);
+  double* partial = (double*)work;
+  double* Qs = (double*)(work + b_partial);
+  int32_t* move = (int32_t*)(work + b_partial + b_q);
   char* dev = upload(host);
   const BjMat* dmats = (const BjMat*)(dev + omats);
   int32_t* done = (int32_t*)(dev + oflags);
@@ -596,10 +680,17 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
   scr.converged = 0;
   scr.done_at.assign(nm, -1);
   for (; sweeps < scr.max_sweeps; ++sweeps) {
-    for (size_t r = 0; r < rounds.size(); ++r)
-      hipLaunchKernelGGL(k_bj_pair, dim3((unsigned)rounds[r].size()), dim3(256), 0, s, (const BjTask*)(dev + ornd[r]),
-                         dmats, dbases, (const int32_t*)done, changed, (const double*)thr2, scr.tol,
-                         scr.inner_sweeps);
+    for (size_t r = 0; r < rounds.size(); ++r) {
+      const BjPair* pr = (const BjPair*)(dev + opair[r]);
+      hipLaunchKernelGGL(k_bj_gram, dim3((unsigned)rounds[r].gram.size()), dim3(256), 0, s,
+                         (const BjItem*)(dev + ogram[r]), pr, dmats, dbases, (const int32_t*)done, partial);
+      hipLaunchKernelGGL(k_bj_rotate, dim3((unsigned)rounds[r].pairs.size()), dim3(256), 0, s, pr, dmats,
+                         (const int32_t*)done, changed, (const double*)thr2, (const double*)partial, Qs, move,
+                         scr.tol, scr.inner_sweeps);
+      hipLaunchKernelGGL(k_bj_apply, dim3((unsigned)rounds[r].apply.size()), dim3(256), 0, s,
+                         (const BjItem*)(dev + oapply[r]), pr, dmats, dbases, (const int32_t*)done,
+                         (const double*)Qs, (const int32_t*)move);
+    }
     hipLaunchKernelGGL(k_bj_sweep_end, dim3((nm + 255) / 256), dim3(256), 0, s, nm, done, changed);
     if (hipMemcpyAsync(hdone.data(), done, nm * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
       throw HipFailure("hipMemcpyAsync of Jacobi flags failed");

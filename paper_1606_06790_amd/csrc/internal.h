@@ -208,7 +208,7 @@ struct BjScratch {
 };
 void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask* dtasks, BjScratch& scr,
             hipStream_t s, const std::function<char*(const std::vector<char>&)>& upload,
-            const std::function<void()>& sync);
+            const std::function<char*(size_t)>& scratch, const std::function<void()>& sync);
 void launch_select(const SelTask* tasks, int ntask, const SelSector* secs, const double* S,
                    int32_t* kept_per_sec, int32_t* colmap, double* lam_sel, double* scal,
                    hipStream_t s);
