@@ -193,12 +193,27 @@ __global__ __launch_bounds__(256) void k_bj_rotate(const BjPair* __restrict__ pa
     return;
   }
   const int n = mats[pr.mat].n;
-  for (int e = t; e < PB * PB; e += 256) {
-    const int i = e / PB, j = e % PB;
-    double a = 0.0;
-    for (int g = 0; g < pr.ng; ++g) a += partial[(size_t)(pr.g0 + g) * (PB * PB) + e];
-    S[i][j] = (pair_row(pr, n, i) >= 0 && pair_row(pr, n, j) >= 0) ? a : 0.0;
-    Q[i][j] = i == j ? 1.0 : 0.0;
+  {
+    // element e = t + 256 k of S, k < NE; the chunks are summed in order, with all
+    // loads of one chunk in flight together
+    constexpr int NE = PB * PB / 256;
+    double a[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) a[k] = 0.0;
+    for (int g = 0; g < pr.ng; ++g) {
+      const double* P = partial + (size_t)(pr.g0 + g) * (PB * PB) + t;
+      double x[NE];
+#pragma unroll
+      for (int k = 0; k < NE; ++k) x[k] = P[256 * k];
+#pragma unroll
+      for (int k = 0; k < NE; ++k) a[k] += x[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = t + 256 * k, i = e / PB, j = e % PB;
+      S[i][j] = (pair_row(pr, n, i) >= 0 && pair_row(pr, n, j) >= 0) ? a[k] : 0.0;
+      Q[i][j] = i == j ? 1.0 : 0.0;
+    }
   }
   if (t == 0) s_move = 0;
   __syncthreads();
@@ -239,23 +254,39 @@ __global__ __launch_bounds__(256) void k_bj_rotate(const BjPair* __restrict__ pa
       }
       __syncthreads();
       // S <- J^T S J and Q <- Q J in one pass: thread-owned 2 x 2 blocks
-      // (pair u of rows, pair v of columns) are rotated in place.
-      for (int e = t; e < (PB / 2) * (PB / 2); e += 256) {
-        const int u = e / (PB / 2), v = e % (PB / 2);
-        const int au = pidx[u], bu = qidx[u], av = pidx[v], bv = qidx[v];
-        const double cu = cs_[u], su = sn_[u], cv = cs_[v], sv = sn_[v];
-        const double m00 = S[au][av], m01 = S[au][bv], m10 = S[bu][av], m11 = S[bu][bv];
-        const double x00 = cv * m00 - sv * m01, x01 = sv * m00 + cv * m01;   // columns
-        const double x10 = cv * m10 - sv * m11, x11 = sv * m10 + cv * m11;
-        S[au][av] = cu * x00 - su * x10;                                      // rows
-        S[bu][av] = su * x00 + cu * x10;
-        S[au][bv] = cu * x01 - su * x11;
-        S[bu][bv] = su * x01 + cu * x11;
-        const double q00 = Q[au][av], q01 = Q[au][bv], q10 = Q[bu][av], q11 = Q[bu][bv];
-        Q[au][av] = cv * q00 - sv * q01;
-        Q[au][bv] = sv * q00 + cv * q01;
-        Q[bu][av] = cv * q10 - sv * q11;
-        Q[bu][bv] = sv * q10 + cv * q11;
+      // (pair u of rows, pair v of columns) are rotated in place.  Thread t
+      // owns blocks (t / 32 + 8k, t % 32), k < 4; all blocks of a step are
+      // disjoint, so every load is issued before the first store.
+      {
+        constexpr int NB = (PB / 2) * (PB / 2) / 256;
+        const int v = t % (PB / 2), u0 = t / (PB / 2);
+        const int av = pidx[v], bv = qidx[v];
+        const double cv = cs_[v], sv = sn_[v];
+        int au[NB], bu[NB];
+        double cu[NB], su[NB], m[NB][4], q[NB][4];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int u = u0 + (256 / (PB / 2)) * k;
+          au[k] = pidx[u]; bu[k] = qidx[u]; cu[k] = cs_[u]; su[k] = sn_[u];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          m[k][0] = S[au[k]][av]; m[k][1] = S[au[k]][bv]; m[k][2] = S[bu[k]][av]; m[k][3] = S[bu[k]][bv];
+          q[k][0] = Q[au[k]][av]; q[k][1] = Q[au[k]][bv]; q[k][2] = Q[bu[k]][av]; q[k][3] = Q[bu[k]][bv];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const double x00 = cv * m[k][0] - sv * m[k][1], x01 = sv * m[k][0] + cv * m[k][1];   // columns
+          const double x10 = cv * m[k][2] - sv * m[k][3], x11 = sv * m[k][2] + cv * m[k][3];
+          S[au[k]][av] = cu[k] * x00 - su[k] * x10;                                            // rows
+          S[bu[k]][av] = su[k] * x00 + cu[k] * x10;
+          S[au[k]][bv] = cu[k] * x01 - su[k] * x11;
+          S[bu[k]][bv] = su[k] * x01 + cu[k] * x11;
+          Q[au[k]][av] = cv * q[k][0] - sv * q[k][1];
+          Q[au[k]][bv] = sv * q[k][0] + cv * q[k][1];
+          Q[bu[k]][av] = cv * q[k][2] - sv * q[k][3];
+          Q[bu[k]][bv] = sv * q[k][2] + cv * q[k][3];
+        }
       }
       __syncthreads();
     }
@@ -302,8 +333,15 @@ __global__ __launch_bounds__(256) void k_bj_apply(const BjItem* __restrict__ ite
                (it.which ? mt.g_off : mt.x_off);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const double* Qg = Qin + (size_t)it.pair * (PB * PB);
-  for (int e = t; e < PB * PB; e += 256) Q[e / PB][e % PB] = Qg[e];
+  {
+    constexpr int NE = PB * PB / 256;
+    const double* Qg = Qin + (size_t)it.pair * (PB * PB) + t;
+    double x[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) x[k] = Qg[256 * k];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) Q[(t + 256 * k) / PB][(t + 256 * k) % PB] = x[k];
+  }
   constexpr int NQ = PB / 4;
   const gptr<double> Mg = as_global((const double*)Mx);
   int offs[NQ];
