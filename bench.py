@@ -112,6 +112,54 @@ def timed(d, prec, steps, warmup):
                 identical=[r["energy"] for r in recs] == [r["energy"] for r in recs_p])
 
 
+def microbench(a):
+    """The H_eff matvec microbenchmark: the Heisenberg chain MPO (D = 5, d = 2) on Gaussian FP64 environments and
+    state, m = 256, 512, 1024, U(1)-blocked (the Gaussian sector profile) and dense (one sector), in FP64, FP32 and
+    split-bf16.  Kernel time by HIP events over `reps` calls after one untimed call; the FP32 and split-bf16 results
+    against the FP64 one (|y - y64| / |y64|, 2-norm).  Prints one JSON line."""
+    import torch
+    import workloads
+    from paper_1606_06790_amd import lib, models
+    cfg = workloads.workload("chain")
+    W = models.heisenberg_mpo(cfg["bonds"], cfg["ell"])
+    ctx = lib.Context(0)
+    dev = lambda x: torch.from_numpy(x).to("cuda")
+    reps, rows = 20, []
+    for m in (256, 512, 1024):
+        for kind in ("u1", "dense"):
+            if kind == "u1":
+                qs, ds = workloads.sector_dims(m)
+                A = B = list(zip(qs, ds))
+                w1, w2 = W[0], W[1]
+            else:
+                A = B = [(0, m)]
+                z = [0] * W[0].w.shape[0]
+                w1, w2 = lib.Mpo(W[0].w, z, z, [0, 0]), lib.Mpo(W[1].w, z, z, [0, 0])
+            nL, nR, nx = lib.envL_size(A, w1.ql), lib.envR_size(B, w2.qr), lib.psi_size(A, B, w1.qp)
+            prob = dict(left=A, right=B, w1=w1, w2=w2, L=dev(workloads.gaussian(nL, 2, m, int(kind == "u1"), 1)),
+                        R=dev(workloads.gaussian(nR, 2, m, int(kind == "u1"), 2)))
+            x = dev(workloads.gaussian(nx, 2, m, int(kind == "u1"), 3))
+            flops = lib.heff_work(prob)[0]
+            y64 = None
+            for prec in ("f64", "f32", "bf16x3"):
+                y = torch.empty_like(x)
+                lib.heff_apply(ctx, [prob], [x], [y], prec)
+                ctx.profile(True)
+                for _ in range(reps):
+                    lib.heff_apply(ctx, [prob], [x], [y], prec)
+                prof = ctx.profile_get()
+                ctx.profile(False)
+                ms = sum(prof[k][1] for k in MATVEC) / reps
+                if prec == "f64":
+                    y64 = y.clone()
+                err = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
+                rows.append(dict(m=m, blocks=kind, prec=prec, N=nx, flops=flops, kernel_ms=round(ms, 4),
+                                 tflops=round(flops / (ms * 1e-3) / 1e12, 2), rel_err_vs_f64=err))
+                note(f"microbench m={m} {kind} {prec}: {rows[-1]['tflops']} TFLOP/s")
+    print(json.dumps({"microbench": "H_eff matvec, Heisenberg chain MPO D=5, Gaussian environments and state",
+                      "reps": reps, "rows": rows}), flush=True)
+
+
 def batching(a):
     """Seconds per unit-cell step of one workload solved three ways from the same state: batched
     with graph-replayed Lanczos chunks (production), batched with direct launches, and one
@@ -211,6 +259,8 @@ def main():
     ap.add_argument("--mixed", default="bf16x3", choices=["f32", "bf16x3"])
     ap.add_argument("--workload", default="yc8")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only run the H_eff matvec microbenchmark (m = 256/512/1024, U(1) and dense, 3 precisions)")
     ap.add_argument("--batching", action="store_true",
                     help="only compare batched (graph / direct) against one call per superblock on --workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -224,6 +274,9 @@ def main():
         return
     if a.batching:
         batching(a)
+        return
+    if a.microbench:
+        microbench(a)
         return
     import workloads
     from paper_1606_06790_amd.driver import IDMRG
