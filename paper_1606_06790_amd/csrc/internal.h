@@ -185,10 +185,9 @@ void launch_convert_add(const float* src, const double* x, double sigma, double*
 void launch_pack(const PackTask* tasks, int ntask, int ntiles, void* const* sbases, void* const* dbases,
                  const int32_t* active, hipStream_t s);
 
-void launch_svd(const SvdTask* tasks, int ntask, void* const* bases, int32_t* sweeps_out, hipStream_t s);
-
 // Blocked one-sided Jacobi (bjsvd.hip): all matrices of `svd` at once.
-// bases (device) as for launch_svd; dtasks = the same tasks on the device.
+// bases (device): per problem kNumBases pointers, 1 M, 2 X, 3 G, 4 U, 5 V, 6 S; dtasks = the same tasks on
+// the device.
 // upload() copies a host byte array to device memory and returns its address;
 // sync() waits for the stream (the host checks the sweep flags once per sweep).
 struct BjScratch {
