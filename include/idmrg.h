@@ -239,6 +239,9 @@ typedef struct {
  * isometries to rounding in every case.  The completion runs only for problems
  * where the selection can keep a zero-weight state (fewer values above the
  * floor than states to keep); elsewhere those vectors are never kept.
+ * Rows count as orthogonal at |<x_i, x_j>| <= max(1e-15, 4.4e-16 sqrt(p)) |x_i| |x_j|
+ * with p the longest row length among all blocks of the call, so a problem's
+ * result can differ at that level between a batched and a single call.
  * Synchronises the stream.  Returns
  * IDMRG_WARN_NOCONV if the Jacobi sweeps did not converge (the result is
  * still written and svd_converged is 0). */
