@@ -73,3 +73,4 @@ def test_roofline_entry(tmp_path, monkeypatch, prec):
         assert bench.gemm_roofline(r, traffic_ok=False)["traffic"] is None
     else:
         assert out["traffic"] is None
+
