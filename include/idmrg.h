@@ -229,16 +229,18 @@ typedef struct {
 
 /* Psi = U Lambda V^dagger per centre charge (FP64 one-sided Jacobi SVD on the
  * device), keep the largest min(m_max, ...) states (Steps 4, 6).  Readings:
- * values <= lam_floor count as zero; when more states are kept than nonzero
- * values exist, zero-weight states fill in ascending charge order; the cut is
- * moved up past values within deg_rel (relative) of the last kept one.
+ * values <= lam_floor count as zero; zero-weight states are kept (in
+ * ascending charge order) only when every candidate state is kept, so that the
+ * kept space never depends on which null vectors the decomposition found;
+ * otherwise at most the nonzero values are kept (m_kept may then be below
+ * m_max); the cut is moved up past values within deg_rel (relative) of the
+ * last kept one.
  * lambda is normalised over the full spectrum (sum lambda^2 = 1) and the
  * kept values are not renormalised.  Singular vectors of values at most
- * max(lam_floor, 1e-15) times their block's Frobenius norm are replaced by an
+ * min(max(lam_floor, 1e-15), 1e-14) times their block's Frobenius norm are replaced by an
  * orthonormal completion (they carry no reliable direction), so U and V are
  * isometries to rounding in every case.  The completion runs only for problems
- * where the selection can keep a zero-weight state (fewer values above the
- * floor than states to keep); elsewhere those vectors are never kept.
+ * where the selection can keep such a vector; elsewhere they are never kept.
  * Rows count as orthogonal at |<x_i, x_j>| <= max(1e-15, 4.4e-16 sqrt(p)) |x_i| |x_j|
  * with p the longest row length among all blocks of the call, so a problem's
  * result can differ at that level between a batched and a single call.

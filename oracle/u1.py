@@ -156,8 +156,12 @@ def select_kept(cands, m, lam_floor, deg_rel):
     largest).  Readings taken here:
     * candidates with lam <= lam_floor count as zero (Eq. (10)'s lam = 0 case);
     * the kept count is min(m, number of candidates); when it exceeds the
-      number of nonzero values, zero-weight states fill it in ascending
-      sector charge, then decomposition order;
+      number of nonzero values, zero-weight states fill it (in ascending
+      sector charge, then decomposition order) only if every candidate is
+      kept, since then the kept space is the whole two-site block space and
+      does not depend on which null vectors the decomposition returned;
+      otherwise only the nonzero values are kept (a subset of the null space
+      would be an arbitrary choice that changes later iterations' energies);
     * a cut never splits a near-degenerate multiplet: while the last kept and
       first discarded nonzero values differ by <= deg_rel * last kept, one
       fewer state is kept (if that would keep nothing, the plain cut is used).
@@ -174,7 +178,9 @@ def select_kept(cands, m, lam_floor, deg_rel):
             mk = target
         gap = (pos[mk - 1][0] - pos[mk][0]) / pos[mk - 1][0]
         return pos[:mk], gap
-    return pos + zer[:target - len(pos)], None
+    if target == len(cands):
+        return pos + zer, None
+    return pos, None
 
 
 def truncate_twosite(psi, A, B, qp, m, lam_floor=1e-14, deg_rel=1e-5):

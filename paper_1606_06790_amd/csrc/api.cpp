@@ -57,7 +57,7 @@ namespace {
 
 enum {
   WS_T1 = 0, WS_T3, WS_LOWENV, WS_LOWVEC, WS_LZ, WS_LZSMALL, WS_SVD, WS_SEL, WS_ENV, WS_PRED, WS_READ, WS_MISC,
-  WS_PLAN64, WS_PLANLOW, WS_T3F, WS_DIAG, WS_BJ
+  WS_PLAN64, WS_PLANLOW, WS_T3F, WS_DIAG, WS_BJ, WS_T1LO
 };
 
 void sync(idmrg_ctx* c) { IDMRG_HIP(hipStreamSynchronize(c->stream)); }
@@ -110,10 +110,10 @@ void* ensure(idmrg_ctx* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.n >= bytes) return b.p;
   sync(c);
+  size_t want = std::max(bytes, b.n + b.n / 4);
   if (b.p) IDMRG_HIP(hipFree(b.p));
   b.p = nullptr;
   b.n = 0;
-  size_t want = std::max(bytes, b.n + b.n / 4);
   want = (want + 4095) / 4096 * 4096;
   if (hipMalloc(&b.p, want) != hipSuccess) {
     b.p = nullptr;
@@ -349,8 +349,9 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
     nT1 += round64((frag ? ex.plan.n_T1f[p] : ex.plan.n_T1[p]) + 1);
     nT3 += round64((frag ? ex.plan.n_T3f[p] : ex.plan.n_T3[p]) + 1);
   }
-  char* T1 = (char*)ensure(c, c->ws[WS_T1], nT1 * es);
-  char* T3 = (char*)ensure(c, c->ws[frag ? WS_T3F : WS_T3], nT3 * es);
+  // the FP64 and the low-precision plans of one Lanczos call are live together, so each has its own T1 and T3
+  char* T1 = (char*)ensure(c, c->ws[ex.prec == Prec::F64 ? WS_T1 : WS_T1LO], nT1 * es);
+  char* T3 = (char*)ensure(c, c->ws[ex.prec == Prec::F64 ? WS_T3 : WS_T3F], nT3 * es);
   // the fragment form of T3 is written only inside its blocks: its padding stays zero from here on
   if (frag) IDMRG_HIP(hipMemsetAsync(T3, 0, nT3 * es, c->stream));
   std::vector<void*> hb((size_t)P * kNumBases, nullptr), sb;
@@ -762,7 +763,9 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     }
     // vectors: Q [kcap x N], w, v
     // every piece is a multiple of kLzAlign elements, so all rows start 2 KiB-aligned
-    std::vector<int64_t> kcap(P), qoff(P), woff(P), voff(P), ld(P);
+    // (mixed precision also keeps the normalised start vector s0: the fidelity
+    // of Eq. (12) is taken against the refined state that is returned)
+    std::vector<int64_t> kcap(P), qoff(P), woff(P), voff(P), soff(P), ld(P);
     int64_t tot = 0;
     for (int p = 0; p < P; ++p) {
       kcap[p] = std::min<int64_t>(kmax, N[p]);
@@ -773,6 +776,8 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       tot += ld[p];
       voff[p] = tot;
       tot += ld[p];
+      soff[p] = tot;
+      if (mixed) tot += ld[p];
     }
     double* V = (double*)ensure(ctx, ctx->ws[WS_LZ], tot * 8);
     const size_t nsm = (size_t)P * kmax;
@@ -792,10 +797,10 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     for (int p = 0; p < P; ++p) {
       vv[p] = V + voff[p];
       ww[p] = V + woff[p];
-      probs[p] = LzProblem{N[p], ld[p], V + qoff[p], ww[p], vv[p], psi[p]};
+      probs[p] = LzProblem{N[p], ld[p], V + qoff[p], ww[p], vv[p], psi[p], mixed ? V + soff[p] : nullptr};
     }
-    // The FP64 plan is set up first: it needs the larger scratch, so the
-    // low-precision plan set up afterwards never reallocates under it.
+    // The two plans use disjoint scratch buffers (T1, T3, plan), so setting up
+    // the second never reallocates memory that the first has uploaded.
     HeffExec ex64, exlo;
     heff_setup(ctx, ex64, P, H, vv, ww, IDMRG_PREC_F64, &ctx->ws[WS_PLAN64]);
     if (mixed) heff_setup(ctx, exlo, P, H, vv, ww, o->prec, &ctx->ws[WS_PLANLOW]);
@@ -851,6 +856,9 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       IDMRG_HIP(hipMemcpyAsync(active, astage, P * 4, hipMemcpyDeviceToDevice, s));
       lz_init(P, dprobs, ctrl, partial, kmax, s);
       if (outer == 0) {
+        if (mixed)
+          for (int p = 0; p < P; ++p)
+            IDMRG_HIP(hipMemcpyAsync(probs[p].s0, vv[p], ld[p] * 8, hipMemcpyDeviceToDevice, s));
         std::vector<LzCtrl> chk(P);
         IDMRG_HIP(hipMemcpyAsync(chk.data(), ctrl, P * sizeof(LzCtrl), hipMemcpyDeviceToHost, s));
         sync(ctx);
@@ -917,6 +925,13 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
         if (!mixed || (out[p].iters == 1 && out[p].converged)) going[p] = 0;
       }
       if (std::all_of(going.begin(), going.end(), [](int32_t g) { return g == 0; })) break;
+    }
+    if (mixed) {
+      // |<start, psi>| against the returned (refined) state
+      lz_overlap(P, dprobs, ctrl, partial, kmax, s);
+      IDMRG_HIP(hipMemcpyAsync(out.data(), ctrl, P * sizeof(LzCtrl), hipMemcpyDeviceToHost, s));
+      sync(ctx);
+      for (int p = 0; p < P; ++p) ov0[p] = out[p].overlap0;
     }
     if (!mixed) {
       // FP64 residual of the result: w = H psi (v holds psi after lz_finish)
@@ -1080,7 +1095,10 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
       int pmax = 1;
       for (const auto& sv : svd) pmax = std::max(pmax, std::max(sv.r, sv.c));
       scr.tol = std::max(1e-15, 4.4e-16 * std::sqrt((double)pmax));
-      scr.zero_rel = std::max(lam_floor, 1e-15);
+      // null rows: at most 1e-15 .. 1e-14 of their block's norm (rounding residue); never
+      // above lam_floor, so that a null row never ranks as a nonzero value unless lam_floor
+      // itself is below 1e-15
+      scr.zero_rel = std::min(std::max(lam_floor, 1e-15), 1e-14);
       auto up = [&](const std::vector<char>& h) -> char* {
         char* d = (char*)ensure(ctx, ctx->ws[WS_READ], h.size());
         sync(ctx);
@@ -1088,10 +1106,11 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
         return d;
       };
       // Null rows (sigma <= zero_rel |M_q|_F) need a completed direction only if the
-      // selection can keep a zero-weight state, i.e. if fewer than min(m_max, candidates)
-      // values of the problem lie above lam_floor after the selection's normalisation.
-      // Counted conservatively here: rows with sigma / |sigma| above
-      // max(lam_floor, zero_rel) (1 + 1e-9), which no null row reaches.
+      // selection can keep one.  Zero-weight states are kept only when every candidate is
+      // (m_max >= candidates); otherwise a null row is kept only if it ranks as a nonzero
+      // value, which needs lam_floor < zero_rel.  "above" counts conservatively the rows
+      // with sigma / |sigma| above zero_rel (1 + 1e-9), which no null row reaches: when all
+      // of the kept states are among them, no completion is needed.
       scr.need_completion = [&](std::vector<int32_t>& complete) {
         std::vector<double> hS(nS);
         IDMRG_HIP(hipMemcpyAsync(hS.data(), dS, nS * 8, hipMemcpyDeviceToHost, s));
@@ -1103,14 +1122,18 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
           cand[sv.prob] += n;
           for (int i = 0; i < n; ++i) tot[sv.prob] += hS[sv.s_off + i] * hS[sv.s_off + i];
         }
-        const double thr = std::max(lam_floor, scr.zero_rel) * (1.0 + 1e-9);
+        const double thr = scr.zero_rel * (1.0 + 1e-9);
         for (const auto& sv : svd) {
           const int n = std::min(sv.r, sv.c);
           const double cut = thr * std::sqrt(tot[sv.prob]);
           for (int i = 0; i < n; ++i) above[sv.prob] += hS[sv.s_off + i] > cut;
         }
-        for (int pr = 0; pr < P; ++pr)
-          completed[pr] = !(tot[pr] > 0.0 && above[pr] >= std::min<int64_t>(m_max, cand[pr]));
+        for (int pr = 0; pr < P; ++pr) {
+          const bool all_kept = m_max >= cand[pr];
+          const bool null_may_rank = lam_floor < scr.zero_rel;
+          completed[pr] = !(tot[pr] > 0.0 && (all_kept ? above[pr] >= cand[pr]
+                                                       : (!null_may_rank || above[pr] >= m_max)));
+        }
         for (size_t m = 0; m < svd.size(); ++m) complete[m] = completed[svd[m].prob];
       };
       bj_svd(svd, (void**)(dev + a6), (SvdTask*)(dev + a3), scr, s, up,

@@ -220,6 +220,7 @@ struct LzProblem {
   double* w;        // [ld] matvec output / work vector, zero beyond N
   double* v;        // [ld] current vector (matvec input), zero beyond N
   double* psi;      // [N] caller's vector
+  double* s0;       // [ld] normalised start vector (mixed precision only; else null)
 };
 
 struct LzCtrl {     // device, one per problem
@@ -247,5 +248,7 @@ void lz_iteration_tail(int P, const LzProblem* probs, LzCtrl* ctrl, int32_t* act
                        double tol_res, double tol_first, double rel_first, int cgs2, hipStream_t s);
 void lz_finish(int P, const LzProblem* probs, LzCtrl* ctrl, double* ritz, double* partial, int kmax, hipStream_t s);
 void lz_residual(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s);
+// ctrl.overlap0 = |<s0, psi>| (psi normalised by lz_finish, s0 the normalised start vector)
+void lz_overlap(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s);
 
 }  // namespace idmrg

@@ -65,9 +65,9 @@ __device__ __forceinline__ void range_of(int64_t N, int b, int64_t& lo, int64_t&
   if (lo > N) lo = N;
 }
 
-// which: 0 = v, 1 = w, 2 = psi
+// which: 0 = v, 1 = w, 2 = psi, 3 = s0
 __device__ __forceinline__ double* vec_of(const LzProblem& p, int which) {
-  return which == 0 ? p.v : (which == 1 ? p.w : p.psi);
+  return which == 0 ? p.v : (which == 1 ? p.w : (which == 2 ? p.psi : p.s0));
 }
 
 // partial[p][0][b] = sum_{n in range b} x[n] * y[n]
@@ -97,7 +97,7 @@ __device__ double sum_partials(const double* partial, int p, int i, int kmax, do
 constexpr double kReorthEta2 = 0.01;   // eta^2 of the second-pass criterion
 
 // mode 1: beta_j = sqrt(sum) (after a second pass, where there was one);
-// mode 2: norm0 = sqrt(sum);  mode 3: residual = sqrt(sum);
+// mode 2: norm0 = sqrt(sum);  mode 3: residual = sqrt(sum);  mode 5: overlap0 = |sum|;
 // mode 4 (after the first pass): beta_j = sqrt(sum), and ctrl.reorth =
 // cgs2 or j == 0 or sum < eta^2 |w before|^2 (pnorm).
 __global__ __launch_bounds__(TB) void k_finalize(LzCtrl* ctrl, const int32_t* active, const double* partial,
@@ -122,6 +122,7 @@ __global__ __launch_bounds__(TB) void k_finalize(LzCtrl* ctrl, const int32_t* ac
     }
     if (mode == 2) c.norm0 = sqrt(s);
     if (mode == 3) c.residual = sqrt(s);
+    if (mode == 5) c.overlap0 = fabs(s);
   }
 }
 
@@ -497,6 +498,13 @@ void lz_residual(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, i
                      kmax);
   hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, (const double*)partial,
                      (const double*)nullptr, kmax, 3);
+}
+
+void lz_overlap(int P, const LzProblem* probs, LzCtrl* ctrl, double* partial, int kmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kLzBlocks, P), dim3(TB), 0, s, probs, (const int32_t*)nullptr, 2, 3,
+                     partial, kmax);
+  hipLaunchKernelGGL(k_finalize, dim3(P), dim3(TB), 0, s, ctrl, (const int32_t*)nullptr, (const double*)partial,
+                     (const double*)nullptr, kmax, 5);
 }
 
 }  // namespace idmrg

@@ -100,7 +100,9 @@ __global__ __launch_bounds__(ST) void k_select(const SelTask* __restrict__ tasks
       if (mk == 0) mk = target;
       gap = (lam[sorted[mk - 1]] - lam[sorted[mk]]) / lam[sorted[mk - 1]];
     } else {
-      mk = target;
+      // zero-weight states only when every candidate is kept (the whole block space);
+      // a part of the null space would be an arbitrary choice
+      mk = target == nc ? target : npos;
     }
     s_mk = mk;
     s_gap = gap;

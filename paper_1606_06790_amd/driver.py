@@ -132,6 +132,7 @@ class IDMRG:
                        fidelity=1.0 - inf["overlap0"], eps=tr["eps"], eps_prime=tr["eps_prime"],
                        m_kept=tr["m_kept"], cut_gap=tr["cut_gap"], svd_sweeps=tr["svd_sweeps"],
                        fp64_matvecs=inf["fp64_matvecs"], reorth_passes=inf["reorth_passes"],
+                       converged=bool(inf["converged"]), svd_converged=bool(tr["svd_converged"]),
                        N=int(psis[h["i"] - 1].numel()))
             self.steps.append(rec)
             if self.log:

@@ -213,10 +213,10 @@ def _check_graded(o, A, B, tr):
 
 
 def test_truncate_completion_per_problem(ctx):
-    """One call, m = 64: the 9+9-spin state has 255 values above the floor, so no zero-weight
-    state can be kept and its null rows are left uncompleted; the 5+5-spin state has fewer
-    nonzero values than states to keep, so its zero-weight states are kept and completed.
-    Both must match the oracle and return isometries."""
+    """One call, m = 64: the 9+9-spin state has 255 values above the floor and 1024
+    candidates, so no zero-weight state is kept and its null rows are left uncompleted; the
+    5+5-spin state has 64 candidates, all kept, fewer of them nonzero, so its zero-weight
+    states are kept and completed.  Both must match the oracle and return isometries."""
     items, refs = [], []
     for seed, ns in ((11, 9), (13, 5)):
         A, B, x = _graded_psi(seed, ns)
@@ -229,17 +229,31 @@ def test_truncate_completion_per_problem(ctx):
         _check_graded(o, A, B, tr)
 
 
+def test_truncate_no_partial_null_space(ctx):
+    """m = 512 lies between the ~255 nonzero values and the 1024 candidates of the graded
+    9+9-spin state: only the nonzero values are kept (no arbitrary part of the null space),
+    m_kept < m, exactly as in the oracle, and no completion is needed."""
+    A, B, x = _graded_psi(11)
+    tr = u1.truncate_twosite(layout.flat_to_psi(x, A, B, QP), A, B, QP, 512, 1e-14, 1e-5)
+    o = lib.truncate_twosite(ctx, [dict(left=A, right=B, psi=T(x))], QP, 512, 1e-14, 1e-5)[0]
+    npos = sum(1 for v in tr["lam"].values() for lam in v if lam > 0)
+    assert tr["m_kept"] == npos < 512
+    assert not o["null_completed"]
+    _check_graded(o, A, B, tr)
+
+
 def test_truncate_graded_spectrum(ctx):
     """Rows of the Jacobi iteration whose singular values are far below the
     floor have no reliable direction; the returned U and V must still be
     isometries, and the kept spectrum, kept legs and eps must equal the
-    oracle's (regression: such rows once came back non-orthogonal)."""
+    oracle's (regression: such rows once came back non-orthogonal).  m = 1024
+    keeps every candidate, zero-weight states included, so the completion runs."""
     items, refs = [], []
     for seed in (11, 12):
         A, B, x = _graded_psi(seed)
         items.append(dict(left=A, right=B, psi=T(x)))
-        refs.append((A, B, u1.truncate_twosite(layout.flat_to_psi(x, A, B, QP), A, B, QP, 512, 1e-14, 1e-5)))
-    out = lib.truncate_twosite(ctx, items, QP, 512, 1e-14, 1e-5)
+        refs.append((A, B, u1.truncate_twosite(layout.flat_to_psi(x, A, B, QP), A, B, QP, 1024, 1e-14, 1e-5)))
+    out = lib.truncate_twosite(ctx, items, QP, 1024, 1e-14, 1e-5)
     for (A, B, tr), o in zip(refs, out):
         assert o["null_completed"]
         _check_graded(o, A, B, tr)

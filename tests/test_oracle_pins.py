@@ -271,10 +271,12 @@ def test_degeneracy_guard():
     assert [c[0] for c in kept] == [0.8, 0.4]
     kept, gap = u1.select_kept(cands, 4, 1e-14, 1e-5)
     assert len(kept) == 4 and gap == pytest.approx((0.3 * (1 - 1e-7) - 0.1) / (0.3 * (1 - 1e-7)))
-    # zero-weight completion in ascending charge order
+    # zero-weight states in ascending charge order, only when every candidate is kept
     cands = [(1.0, 1, 0), (0.0, 1, 1), (0.0, -1, 0), (0.0, -1, 1)]
+    kept, gap = u1.select_kept(cands, 4, 1e-14, 1e-5)
+    assert kept == [(1.0, 1, 0), (0.0, -1, 0), (0.0, -1, 1), (0.0, 1, 1)] and gap is None
     kept, gap = u1.select_kept(cands, 3, 1e-14, 1e-5)
-    assert kept == [(1.0, 1, 0), (0.0, -1, 0), (0.0, -1, 1)] and gap is None
+    assert kept == [(1.0, 1, 0)] and gap is None
 
 
 @pytest.mark.parametrize("name", ["chain", "random_chain"])
@@ -294,3 +296,17 @@ def test_prediction_is_near_optimal(name):
     it_p = sum(s["iters"] for s in r["steps"] if s["n"] >= 6)
     it_r = sum(s["iters"] for s in rr["steps"] if s["n"] >= 6)
     assert it_p < 0.7 * it_r
+
+
+def test_zero_weight_states_only_with_every_candidate():
+    """Kept-set rule (R5 with the reading that the kept space must not depend on which null
+    vectors a decomposition returns): zero-weight states are kept only when every candidate
+    is; otherwise only nonzero values are kept, even if fewer than m."""
+    cands = [(0.8, 0, 0), (0.5, 2, 0), (0.33, -2, 0)] + [(0.0, q, 1) for q in (-2, 0, 2)] + [(1e-16, 0, 2)]
+    kept, gap = u1.select_kept(cands, 5, 1e-14, 1e-5)
+    assert [c[0] for c in kept] == [0.8, 0.5, 0.33] and gap is None
+    kept, gap = u1.select_kept(cands, 7, 1e-14, 1e-5)
+    assert len(kept) == 7 and gap is None
+    assert [(c[1], c[2]) for c in kept[3:]] == [(-2, 1), (0, 1), (0, 2), (2, 1)]
+    kept, gap = u1.select_kept(cands, 2, 1e-14, 1e-5)
+    assert [c[0] for c in kept] == [0.8, 0.5] and abs(gap - 0.34) < 1e-12

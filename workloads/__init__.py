@@ -128,7 +128,11 @@ def segment_bonds(cell_bonds, ell: int, first: int, last: int):
 # (l=12, m=2048/4096).
 # --------------------------------------------------------------------------
 
-COMMON = dict(tol_E=1e-12, tol_res=1e-8, k_max=300, lam_floor=1e-14, deg_rel=1e-5, u1=True)
+# lam_floor: Schmidt values at or below it count as zero (selection and the lambda = 0 branch of
+# Eq. (10)).  It lies above the numerical noise of a computed two-site state (Lanczos residual
+# 1e-8; measured noise tails of the spectra reach 1e-9), so that whether a value is zero does not
+# depend on rounding.
+COMMON = dict(tol_E=1e-12, tol_res=1e-8, k_max=300, lam_floor=1e-8, deg_rel=1e-5, u1=True)
 
 
 def workload(name: str, **over):
