@@ -79,9 +79,9 @@ def test_microbench_dense(ctx, m, prec):
 
 
 def _grown(name, m, c, nright):
-    """A symmetric H_eff (oracle-grown environments, see test_gpu_fullsize) as a library
+    """A symmetric H_eff (oracle-grown environments, see fullsize_ops) as a library
     problem plus the oracle's matvec on it."""
-    from test_gpu_fullsize import _grow
+    from fullsize_ops import grow as _grow
     from paper_1606_06790_amd.lib import Mpo
     s = _grow(name, m, c, nright)
     A, B = s["A"], s["B"]
@@ -142,7 +142,7 @@ def test_low_precision_energy_shift(ctx, prec):
     blocks shifted by their mean diagonal and the shift comes back in FP64, so the absolute
     error of the matvec must stay at the level it has without the offset (unshifted copies
     would round the 2c |x| term at the low precision's relative error)."""
-    from test_gpu_fullsize import _grow
+    from fullsize_ops import grow as _grow
     from paper_1606_06790_amd.lib import Mpo
     s = _grow("yc8", 256, 10, 9)
     A, B, dl, dr = s["A"], s["B"], s["dl"], s["dr"]
