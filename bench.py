@@ -44,10 +44,12 @@ LATTICE = {"yc8": "kagome YC8", "yc4": "square YC4", "chain": "chain"}
 MATVEC = ["heff_gemm1", "heff_gemm2", "heff_mix", "heff_gemm1_lo", "heff_gemm2_lo", "heff_mix_lo", "convert"]
 
 
-def cpu_baseline(d, budget_s=12.0):
-    """The oracle's H_eff matvec on superblock 1 of the current state (host cores), repeated for ~budget_s."""
+def cpu_baseline(d, budget_s=10.0, budget_1t_s=6.0):
+    """The oracle's H_eff matvec on superblock 1 of the current state (host cores), repeated for ~budget_s with
+    every BLAS thread and for ~budget_1t_s with one; plus one oracle unit-cell step of the random-bond chain
+    (m = 256) beside the GPU's step of the same iteration."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import layout, u1
     from paper_1606_06790_amd import lib
     h = d.problems(d.n + 1)[0]
@@ -59,17 +61,80 @@ def cpu_baseline(d, budget_s=12.0):
     x = np.random.default_rng(0).standard_normal(layout.psi_size(A, B, W1.qp))
     psi = layout.flat_to_psi(x, A, B, W1.qp)
     flops, _ = lib.heff_work(h)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        u1.heff_apply(L, W1.w, W2.w, R, psi, A, B, W1.qp, dl, dr)
-        reps += 1
-        t = time.perf_counter() - t0
-        if t >= budget_s:
-            break
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+
+    def rate(budget):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            u1.heff_apply(L, W1.w, W2.w, R, psi, A, B, W1.qp, dl, dr)
+            reps += 1
+            t = time.perf_counter() - t0
+            if t >= budget:
+                return reps, t
+
+    reps, t = rate(budget_s)
+    info = threadpool_info()
+    threads = max([p.get("num_threads", 1) for p in info] + [1])
+    blas = [f"{p.get('internal_api')} {p.get('version')} ({p.get('threading_layer', '-')}, {p.get('num_threads')} threads)"
+            for p in info if p.get("user_api") == "blas"]
+    with threadpool_limits(1):
+        reps1, t1 = rate(budget_1t_s)
+    note("cpu baseline: timing one oracle unit-cell step of the random-bond chain")
     return dict(value=round(reps * flops / t / 1e12, 6), unit="TFLOP/s", cores=threads, kind="oracle",
                 sample=f"{reps} H_eff matvec(s) of superblock 1 at iteration {d.n + 1} "
-                       f"(N={layout.psi_size(A, B, W1.qp)}, {flops:.3e} flops each) in {t:.1f} s")
+                       f"(N={layout.psi_size(A, B, W1.qp)}, {flops:.3e} flops each) in {t:.1f} s",
+                value_1thread=round(reps1 * flops / t1 / 1e12, 6),
+                sample_1thread=f"{reps1} of the same matvecs with one BLAS thread in {t1:.1f} s",
+                blas=blas, step=oracle_step_comparison())
+
+
+def oracle_step_comparison(wl="random_chain", m=256, n=17):
+    """Seconds of one unit-cell step (iteration n, all superblocks) of the oracle and of the GPU path (FP64,
+    batched) on the same workload.  The oracle runs its own trajectory from n = 1 (untimed up to n - 1); the GPU
+    runs its own from n = 1 as well, and its step n is timed between device synchronisations."""
+    import torch
+    import workloads
+    from oracle import idmrg as oidmrg
+    from paper_1606_06790_amd.driver import IDMRG
+    cfg = workloads.workload(wl, m=m)
+    secs = []
+    oidmrg.run(cfg, mode="u1", n_max=n, log=lambda r: secs.append(r["seconds"]) if r["n"] == n else None)
+    d = IDMRG(cfg, prec="f64")
+    d.run(n - 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d.step()
+    torch.cuda.synchronize()
+    g = time.perf_counter() - t0
+    o = sum(secs)
+    return dict(workload=f"{wl}_heisenberg_m{m}_u1", iteration=n, superblocks=len(secs), oracle_s=round(o, 4),
+                gpu_f64_s=round(g, 5), gpu_speedup=round(o / g, 1))
+
+
+def prediction_effect(d, snap):
+    """Lanczos iterations per FP64 solve of iteration snap.n + 1 from the kept state, with and without the start
+    vector of Eq. (10) (random start otherwise), under the full stop rule (|dtheta| <= tol_E and residual <= tol_res)
+    and under the |dtheta| rule alone (the rule the paper's iteration counts compare with)."""
+    out = {}
+    keep = (d.prec, d.predict, dict(d.cfg))
+    for label, predict, dtheta_only in (("with_prediction", True, False), ("with_prediction_dtheta_rule", True, True),
+                                        ("random_start", False, False), ("random_start_dtheta_rule", False, True)):
+        d.restore(snap)
+        d.prec, d.predict = "f64", predict
+        d.cfg = dict(keep[2], tol_res=1e300 if dtheta_only else keep[2]["tol_res"])
+        d.step()
+        recs = [s for s in d.steps if s["n"] == d.n]
+        out[label] = dict(iters=[s["iters"] for s in recs], converged=[s["converged"] for s in recs],
+                          fidelity_error=[s["fidelity"] for s in recs])
+        note(f"prediction effect: {label} at n={d.n}: {out[label]['iters']}")
+    d.prec, d.predict, d.cfg = keep
+    d.restore(snap)
+    mean = lambda k: sum(out[k]["iters"]) / len(out[k]["iters"])
+    out["ratio_random_over_predicted"] = round(mean("random_start") / mean("with_prediction"), 3)
+    out["ratio_random_over_predicted_dtheta_rule"] = round(
+        mean("random_start_dtheta_rule") / mean("with_prediction_dtheta_rule"), 3)
+    out["iteration"] = d.n + 1
+    out["paper"] = "about 40 iterations with prediction, about 3x as many without (YC8 kagome, its Sec. 4)"
+    return out
 
 
 def note(msg):
@@ -259,6 +324,7 @@ def main():
     ap.add_argument("--mixed", default="bf16x3", choices=["f32", "bf16x3"])
     ap.add_argument("--workload", default="yc8")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-p10", action="store_true", help="skip the Lanczos iterations with / without prediction")
     ap.add_argument("--microbench", action="store_true",
                     help="only run the H_eff matvec microbenchmark (m = 256/512/1024, U(1) and dense, 3 precisions)")
     ap.add_argument("--batching", action="store_true",
@@ -304,6 +370,9 @@ def main():
                 "fp64_matvecs": [s["fp64_matvecs"] for s in r["recs"]],
                 "reorth_passes": [s["reorth_passes"] for s in r["recs"]],
                 "e_site": [round(s["e_site"], 12) for s in r["recs"]],
+                "fidelity_error": [s["fidelity"] for s in r["recs"]],
+                "unconverged_solves": sum(1 for s in r["recs"] if not s["converged"]),
+                "unconverged_svds": sum(1 for s in r["recs"] if not s["svd_converged"]),
                 "residual_max": max(s["residual"] for s in r["recs"]),
                 "svd_sweeps": max(s["svd_sweeps"] for s in r["recs"]),
                 "roofline": gemm_roofline(r, traffic_ok),
@@ -334,8 +403,11 @@ def main():
                           "e_site_diff_max": max(abs(x) for x in de)},
         "prefill_s": round(t_pre, 1),
     }
+    if not a.no_p10:
+        out["prediction_effect"] = prediction_effect(d, snap)
     if not a.no_cpu:
         note("cpu baseline: timing the oracle matvec")
+        d.restore(snap)
         out["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(out), flush=True)
 
