@@ -53,14 +53,23 @@
  *       q_b - qp[s] == q_c.
  *   singular values lambda: for c in C, k_c values (descending, then zeros).
  *
- * Ownership: the caller allocates every input and output buffer.  The library
- * owns only its internal scratch memory (allocated on first use with
- * hipMalloc, grown when needed, freed by idmrg_destroy) and keeps no pointer
- * to caller memory after a call returns.
+ * Ownership: the caller allocates every input and output buffer.  Device
+ * scratch (intermediates, low-precision operand copies, the Krylov basis, work
+ * plans) comes from a workspace: the caller sizes it with
+ * idmrg_workspace_size() and attaches it with idmrg_set_workspace(); while one
+ * is attached no call allocates device memory.  Without one the library keeps
+ * a block of its own, allocated with hipMalloc on first use, grown (after the
+ * stream has drained) when a call needs more, and freed by idmrg_destroy.
+ * Work plans reach the device through a pinned staging ring allocated by
+ * idmrg_create.  The library keeps no pointer to caller memory after a call
+ * returns, except the attached workspace.
  *
- * Streams: all device work of a context is enqueued on its stream.  Calls
- * that return host results (lanczos_solve_batch, truncate_twosite) and every
- * call that uploads a work plan synchronise that stream before returning.
+ * Streams: all device work of a context is enqueued on its stream.  Calls that
+ * return host results (lanczos_solve_batch, truncate_twosite) synchronise that
+ * stream before returning; heff_apply, update_env and predict_wavefunction are
+ * asynchronous (the host waits only if more than the staging ring's 32 MiB of
+ * plan uploads are still queued).  Back-to-back calls may share one workspace:
+ * their work runs in stream order.
  *
  * Errors: 0 = success; > 0 = warning (IDMRG_WARN_NOCONV); < 0 = error, with a
  * message from idmrg_last_error().  No C++ exception crosses this boundary.
@@ -246,7 +255,8 @@ typedef struct {
  * result can differ at that level between a batched and a single call.
  * Synchronises the stream.  Returns
  * IDMRG_WARN_NOCONV if the Jacobi sweeps did not converge (the result is
- * still written and svd_converged is 0). */
+ * still written and svd_converged is 0), and IDMRG_ENUMERIC (nothing written)
+ * if psi holds a NaN or an infinity. */
 int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp, int32_t m_max,
                      double lam_floor, double deg_rel, idmrg_trunc* t);
 
@@ -282,6 +292,53 @@ typedef struct {
  *           u~[b,s',a'] = u_{i+1}[(b,s'),a'] lam_ip1[a'] / lam_prev[b] (0 if lam_prev[b] <= lam_floor). */
 int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp, double lam_floor,
                          const idmrg_predict* p);
+
+/* ------------------------------------------------------------------ workspace */
+
+/* Operations for idmrg_workspace_size. */
+#define IDMRG_OP_HEFF 0       /* heff_apply;            desc: idmrg_heff[nprob]       */
+#define IDMRG_OP_LANCZOS 1    /* lanczos_solve_batch;   desc: idmrg_heff[nprob]       */
+#define IDMRG_OP_TRUNCATE 2   /* truncate_twosite;      desc: idmrg_trunc[nprob]      */
+#define IDMRG_OP_ENV_LEFT 3   /* update_env(LEFT);      desc: idmrg_env_update[nprob] */
+#define IDMRG_OP_ENV_RIGHT 4  /* update_env(RIGHT);     desc: idmrg_env_update[nprob] */
+#define IDMRG_OP_PREDICT 5    /* predict_wavefunction;  desc: idmrg_predict[nprob]    */
+
+/* The scalar arguments of the call being sized (unused fields are ignored). */
+typedef struct {
+    int32_t prec;                     /* IDMRG_OP_HEFF: its prec argument */
+    int32_t m_max;                    /* IDMRG_OP_TRUNCATE */
+    int32_t d;                        /* IDMRG_OP_TRUNCATE, IDMRG_OP_PREDICT: local dimension ... */
+    int32_t pad;
+    const int32_t* qp;                /* ... and local charges */
+    const idmrg_lanczos_opts* opts;   /* IDMRG_OP_LANCZOS: its options (k_max, prec) */
+} idmrg_ws_query;
+
+/* Bytes of device workspace that the call `op` with these nprob descriptors
+ * needs (host work only: the call's plan is built, validated and kept, so that
+ * the call itself, made next with the same shapes, does not build it again).
+ * Depends on the legs, MPO tensors and options, not on device pointers or
+ * values.  Errors: IDMRG_EINVAL for invalid descriptors. */
+int idmrg_workspace_size(idmrg_ctx* ctx, int op, int nprob, const void* desc, const idmrg_ws_query* q,
+                         size_t* bytes);
+
+/* Attach a caller-owned device buffer (256-byte aligned, on the context's
+ * device, at least the size idmrg_workspace_size reports for every call that
+ * will use it) as the scratch of every later call, or detach with ptr = NULL
+ * (the library then allocates its own again).  Attaching frees the library's
+ * own block.  A call that needs more than the attached bytes returns
+ * IDMRG_ENOMEM without launching anything; calls never allocate device memory
+ * while a workspace is attached.  The caller must keep the buffer alive until
+ * the work queued on the context stream that uses it has run. */
+int idmrg_set_workspace(idmrg_ctx* ctx, void* ptr, size_t bytes);
+
+/* Counters of a context since idmrg_create. */
+typedef struct {
+    int64_t device_allocs;   /* hipMalloc calls for the library's own scratch block */
+    int64_t stream_syncs;    /* synchronisations of the context stream made by the library */
+    int64_t staged_bytes;    /* bytes of work plans copied to the device */
+    int64_t plan_builds;     /* work plans built (a size query and the call that follows it build one) */
+} idmrg_stats;
+int idmrg_get_stats(idmrg_ctx* ctx, idmrg_stats* out);
 
 #ifdef __cplusplus
 }

@@ -1,11 +1,23 @@
-// C-ABI entry points (idmrg.h): validation, workspace, plan upload and the
-// launch sequences of the five calls.
+// C-ABI entry points (idmrg.h): validation, work plans, the device scratch
+// layout of each call, plan upload and the launch sequences of the five calls.
+//
+// Every call runs in two phases.  The plan phase is host work only: it
+// validates the descriptors, builds the task lists of the grouped kernels and
+// lays out the call's device scratch as one block (idmrg_workspace_size
+// returns that block's size).  The bind phase takes the block from the
+// caller's workspace (or from scratch the library owns), copies the task lists
+// to the device through a pinned staging ring allocated with the context, and
+// enqueues the kernels.  The plan of the last call of each kind is kept, keyed
+// by a hash of everything it depends on, so that a size query followed by the
+// call plans once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <memory>
+#include <tuple>
 
 #include "idmrg.h"
 #include "internal.h"
@@ -22,14 +34,30 @@ struct DevBuf {
   size_t n = 0;
 };
 
-}  // namespace
-
-namespace {
 struct ProfRec {
   int cls;
   hipEvent_t a, b;
   double flops;
 };
+
+struct RingSlot {
+  size_t begin, end;
+  hipEvent_t ev;
+};
+
+// A call needs more device scratch than the attached workspace holds, or the
+// library could not allocate its own.
+struct OutOfWorkspace {
+  std::string what;
+};
+
+constexpr size_t kRingBytes = size_t(32) << 20;   // pinned staging ring of the plan uploads
+constexpr size_t kRingChunk = size_t(8) << 20;    // largest single staged copy
+constexpr size_t kRingSlotsMax = 256;             // copies tracked before the oldest is waited for
+constexpr int kOps = 6;
+
+struct CallPlan;
+
 }  // namespace
 
 struct idmrg_ctx {
@@ -44,23 +72,30 @@ struct idmrg_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;   // graph capture only (nothing executes on it); created on first use
   std::string err;
-  DevBuf plan;                 // uploaded task lists and base tables
-  void* pinned = nullptr;      // host staging for uploads
-  size_t pinned_n = 0;
-  DevBuf ws[20];               // scratch, by purpose (see WS_*)
+  // device scratch of the calls: the caller's workspace if one is attached, else the library's own block
+  char* user_ws = nullptr;
+  size_t user_ws_n = 0;
+  DevBuf own;
+  // pinned staging ring of the plan uploads (allocated with the context)
+  char* ring = nullptr;
+  size_t ring_head = 0;
+  std::deque<RingSlot> ring_busy;
+  std::vector<hipEvent_t> ring_events;
+  idmrg_stats stats = {};
   // GEMM tile autotuner: measured best tiling per (precision, stage, shape bucket)
   std::map<std::tuple<int, int, int, int, int>, int> tune;
   hipEvent_t tev[4][4] = {};   // [variant][stage-1 start, stage-1 end, stage-2 start, stage-2 end]
+  // the plan of the last call of each kind and the hash of its inputs
+  uint64_t cache_key[kOps] = {};
+  std::shared_ptr<CallPlan> cache[kOps];
 };
 
 namespace {
 
-enum {
-  WS_T1 = 0, WS_T3, WS_LOWENV, WS_LOWVEC, WS_LZ, WS_LZSMALL, WS_SVD, WS_SEL, WS_ENV, WS_PRED, WS_READ, WS_MISC,
-  WS_PLAN64, WS_PLANLOW, WS_T3F, WS_DIAG, WS_BJ, WS_T1LO
-};
-
-void sync(idmrg_ctx* c) { IDMRG_HIP(hipStreamSynchronize(c->stream)); }
+void sync(idmrg_ctx* c) {
+  ++c->stats.stream_syncs;
+  IDMRG_HIP(hipStreamSynchronize(c->stream));
+}
 
 hipEvent_t take_event(idmrg_ctx* c) {
   if (!c->pool.empty()) {
@@ -93,7 +128,7 @@ struct Prof {
 
 void prof_collect(idmrg_ctx* c) {
   if (c->pending.empty()) return;
-  IDMRG_HIP(hipStreamSynchronize(c->stream));
+  sync(c);
   for (auto& r : c->pending) {
     float ms = 0.f;
     IDMRG_HIP(hipEventElapsedTime(&ms, r.a, r.b));
@@ -106,52 +141,115 @@ void prof_collect(idmrg_ctx* c) {
   c->pending.clear();
 }
 
-void* ensure(idmrg_ctx* c, DevBuf& b, size_t bytes) {
-  if (bytes == 0) bytes = 256;
-  if (b.n >= bytes) return b.p;
-  sync(c);
-  size_t want = std::max(bytes, b.n + b.n / 4);
-  if (b.p) IDMRG_HIP(hipFree(b.p));
-  b.p = nullptr;
-  b.n = 0;
-  want = (want + 4095) / 4096 * 4096;
-  if (hipMalloc(&b.p, want) != hipSuccess) {
-    b.p = nullptr;
-    (void)hipGetLastError();
-    throw std::bad_alloc();
+// ------------------------------------------------------------------ device scratch and uploads
+
+// Byte layout of one call's scratch block; every region starts on a 256-byte boundary.
+struct Layout {
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    const size_t o = (total + 255) / 256 * 256;
+    total = o + std::max<size_t>(bytes, 8);
+    return o;
   }
-  b.n = want;
-  return b.p;
+};
+
+// The scratch block of a call: the attached workspace, or the library's own
+// block, grown (after the stream has drained) when a call needs more.
+char* acquire(idmrg_ctx* c, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  if (c->user_ws) {
+    if (bytes > c->user_ws_n)
+      throw OutOfWorkspace{"the attached workspace holds " + std::to_string(c->user_ws_n) +
+                           " bytes; this call needs " + std::to_string(bytes) + " (idmrg_workspace_size)"};
+    return c->user_ws;
+  }
+  if (c->own.n < bytes) {
+    sync(c);   // queued work may still use the old block
+    const size_t want = (std::max(bytes, c->own.n + c->own.n / 4) + 4095) / 4096 * 4096;
+    if (c->own.p) IDMRG_HIP(hipFree(c->own.p));
+    c->own = DevBuf{};
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      throw OutOfWorkspace{"device allocation of " + std::to_string(want) + " bytes of scratch failed"};
+    }
+    c->own = DevBuf{p, want};
+    ++c->stats.device_allocs;
+  }
+  return (char*)c->own.p;
+}
+
+hipEvent_t ring_event(idmrg_ctx* c) {
+  if (!c->ring_events.empty()) {
+    hipEvent_t e = c->ring_events.back();
+    c->ring_events.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  IDMRG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return e;
+}
+
+// Waits for the copy that last read ring slot k and for every older one (a
+// stream runs its copies in order), and releases them.
+void ring_release_through(idmrg_ctx* c, size_t k) {
+  IDMRG_HIP(hipEventSynchronize(c->ring_busy[k].ev));
+  for (size_t i = 0; i <= k; ++i) {
+    c->ring_events.push_back(c->ring_busy.front().ev);
+    c->ring_busy.pop_front();
+  }
+}
+
+// Copies host bytes to device memory at dst, asynchronously on the context
+// stream, through the pinned ring: a region of the ring is rewritten only after
+// the copy that last read it has run, so the host blocks only when more than
+// the ring's worth of uploads is still queued.
+void stage(idmrg_ctx* c, void* dst, const void* src, size_t bytes) {
+  const char* s = (const char*)src;
+  char* d = (char*)dst;
+  while (bytes > 0) {
+    const size_t n = std::min(bytes, kRingChunk);
+    size_t off = (c->ring_head + 255) / 256 * 256;
+    if (off + n > kRingBytes) off = 0;
+    size_t last = SIZE_MAX;
+    for (size_t i = 0; i < c->ring_busy.size(); ++i)
+      if (c->ring_busy[i].begin < off + n && off < c->ring_busy[i].end) last = i;
+    if (last != SIZE_MAX) ring_release_through(c, last);
+    if (c->ring_busy.size() >= kRingSlotsMax) ring_release_through(c, 0);
+    std::memcpy(c->ring + off, s, n);
+    IDMRG_HIP(hipMemcpyAsync(d, c->ring + off, n, hipMemcpyHostToDevice, c->stream));
+    hipEvent_t ev = ring_event(c);
+    IDMRG_HIP(hipEventRecord(ev, c->stream));
+    c->ring_busy.push_back(RingSlot{off, off + n, ev});
+    c->ring_head = off + n;
+    c->stats.staged_bytes += (int64_t)n;
+    s += n;
+    d += n;
+    bytes -= n;
+  }
 }
 
 // Collects host arrays into one upload; offsets aligned to 256 bytes.
+// reserve() leaves room for data known only when the call binds (pointer tables).
 struct Packer {
   std::vector<char> host;
   size_t add(const void* p, size_t bytes) {
-    const size_t off = (host.size() + 255) / 256 * 256;
-    host.resize(off + std::max<size_t>(bytes, 8));
+    const size_t off = reserve(bytes);
     if (bytes) std::memcpy(host.data() + off, p, bytes);
     return off;
   }
   template <typename T>
   size_t add(const std::vector<T>& v) { return add(v.data(), v.size() * sizeof(T)); }
-};
-
-char* upload(idmrg_ctx* c, const Packer& pk, DevBuf* target = nullptr) {
-  sync(c);   // previous work may still read the plan buffer and the staging area
-  char* dev = (char*)ensure(c, target ? *target : c->plan, pk.host.size());
-  if (c->pinned_n < pk.host.size()) {
-    if (c->pinned) IDMRG_HIP(hipHostFree(c->pinned));
-    c->pinned = nullptr;
-    c->pinned_n = 0;
-    size_t want = std::max(pk.host.size(), (size_t)1 << 20);
-    IDMRG_HIP(hipHostMalloc(&c->pinned, want, hipHostMallocDefault));
-    c->pinned_n = want;
+  size_t reserve(size_t bytes) {
+    const size_t off = (host.size() + 255) / 256 * 256;
+    host.resize(off + std::max<size_t>(bytes, 8));
+    return off;
   }
-  std::memcpy(c->pinned, pk.host.data(), pk.host.size());
-  IDMRG_HIP(hipMemcpyAsync(dev, c->pinned, pk.host.size(), hipMemcpyHostToDevice, c->stream));
-  return dev;
-}
+  template <typename T>
+  void patch(size_t off, const std::vector<T>& v) {
+    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+  }
+};
 
 template <typename F>
 int guarded(idmrg_ctx* c, F&& f) {
@@ -166,8 +264,11 @@ int guarded(idmrg_ctx* c, F&& f) {
   } catch (const HipFailure& e) {
     c->err = e.what;
     return IDMRG_EHIP;
+  } catch (const OutOfWorkspace& e) {
+    c->err = e.what;
+    return IDMRG_ENOMEM;
   } catch (const std::bad_alloc&) {
-    c->err = "device or host allocation failed";
+    c->err = "host allocation failed";
     return IDMRG_ENOMEM;
   } catch (...) {
     c->err = "unexpected internal error";
@@ -188,6 +289,70 @@ void check_dev(const void* p, int64_t n, size_t esize, const std::string& what) 
   if ((const char*)p + (size_t)n * esize > (const char*)base + size) throw InvalidArg(what + ": buffer too small");
 }
 
+void check_nprob(int nprob) {
+  if (nprob < 1 || nprob > 64) throw InvalidArg("nprob must be 1..64");
+}
+
+// ------------------------------------------------------------------ plan cache
+
+// FNV-1a over everything a plan depends on (legs, MPO tensors and charges, options).
+struct Hash {
+  uint64_t h = 1469598103934665603ull;
+  void bytes(const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  }
+  template <typename T>
+  void val(const T& v) { bytes(&v, sizeof(T)); }
+  template <typename T>
+  void arr(const T* p, int64_t n) {
+    val(n);
+    if (p && n > 0 && n < (int64_t(1) << 24)) bytes(p, (size_t)n * sizeof(T));
+    else val(p);
+  }
+  void leg(const idmrg_leg& l) {
+    arr(l.q, l.nsec);
+    arr(l.dim, l.nsec);
+  }
+  void mpo(const idmrg_mpo* m) {
+    val(m == nullptr);
+    if (!m) return;
+    val(m->dl);
+    val(m->dr);
+    val(m->d);
+    const int64_t nw = (m->dl > 0 && m->dr > 0 && m->d > 0 && m->dl < 4096 && m->dr < 4096 && m->d < 64)
+                           ? (int64_t)m->dl * m->dr * m->d * m->d : 0;
+    arr(m->w, nw);
+    arr(m->ql, m->dl);
+    arr(m->qr, m->dr);
+    arr(m->qp, m->d);
+  }
+};
+
+struct CallPlan {
+  virtual ~CallPlan() = default;
+  Layout lay;
+};
+
+// The cached plan of kind `op` if its key matches, else a new one from build() (cached in its place).
+template <typename T, typename F>
+std::shared_ptr<T> plan_of(idmrg_ctx* c, int op, uint64_t key, F&& build) {
+  if (c->cache[op] && c->cache_key[op] == key) {
+    auto p = std::dynamic_pointer_cast<T>(c->cache[op]);
+    if (p) return p;
+  }
+  c->cache[op].reset();
+  auto p = std::make_shared<T>();
+  build(*p);
+  ++c->stats.plan_builds;
+  c->cache[op] = p;
+  c->cache_key[op] = key;
+  return p;
+}
+
 // ------------------------------------------------------------------ H_eff execution
 
 // Output tilings of the FP64/FP32 GEMM kernel: code c -> (c & 1 ? 128 : 64) x (c & 2 ? 128 : 64).
@@ -197,29 +362,37 @@ struct HeffExec {
   HeffPlan plan;
   int P = 0;
   Prec prec = Prec::F64;
+  bool frag = false;
   // every tiling variant of both GEMM stages is uploaded; sel[stage] is the one in use
-  GemmTask* gv[2][kTilings] = {};
+  std::vector<GemmList> var[2];
   int tiles[2][kTilings] = {};
   int code[kTilings] = {};
   int nvar = 1;
   int sel[2] = {0, 0};
   bool need_tune[2] = {false, false};
   std::tuple<int, int, int, int, int> key[2];
+  double flops_g1 = 0, flops_g2 = 0, flops_mix = 0;
+  std::vector<int64_t> npsi;
+  std::vector<char> has_shift;   // per problem: the low-precision copies carry an energy shift
+  // scratch regions (byte offsets in the call's block) and per-problem element offsets inside them
+  size_t oT1 = 0, oT3 = 0, nT3bytes = 0, oEnv = 0, oVec = 0, oSums = 0, oShift = 0, oSig = 0, oPlan = 0;
+  std::vector<int64_t> o1, o3, oL, oR, oXmix, oYlow, oXlow;
+  std::vector<DiagTask> diag;
+  size_t nDL = 0;
+  // the uploaded plan: task lists (offsets in pk) and the pointer tables patched at bind
+  Packer pk;
+  size_t av[2][kTilings] = {}, aMY = 0, aSY = 0, aMT = 0, aST = 0, aHB = 0, aSB = 0, aPX = 0, aPL = 0, aPR = 0,
+         aDiag = 0, aFlags = 0;
+  // bound pointers
+  GemmTask* gv[2][kTilings] = {};
   MixTask *mY = nullptr, *mT = nullptr;
   MixSrc *sY = nullptr, *sT = nullptr;
   void** bases = nullptr;      // device [P][8]
-  // split-bf16: FP64 sources of the fragment packs (device [P][8]: 0 L, 1 R, 2 x) and the per-matvec x pack
-  void** sbases = nullptr;
+  void** sbases = nullptr;     // low precision: FP64 sources of the packs and diagonals (0 L, 1 R, 2 x)
   PackTask* pX = nullptr;
-  // per-problem buffers of the low-precision policies (xlow: the GEMM operand, xmix: FP32 x for the mixing)
-  std::vector<void*> xlow, xmix, ylow;
-  std::vector<int64_t> npsi;
-  // energy shift of the low-precision copies: y = (H - sigma) x in low precision + sigma x in FP64
-  std::vector<double> sigma;
-  double flops_g1 = 0, flops_g2 = 0, flops_mix = 0;
+  double* sig = nullptr;       // device [P][2] energy shifts
+  std::vector<void*> xmix, ylow;
 };
-
-size_t elem_size_operand(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
 int ilog2(double x) { return x >= 1.0 ? (int)std::floor(std::log2(x)) : 0; }
 
@@ -256,39 +429,45 @@ void tune_resolve(idmrg_ctx* c, HeffExec& ex, int ntried) {
   }
 }
 
-// Build plans for P problems, allocate scratch, convert environments for the
-// low-precision policies, and upload.  x/y are the FP64 input/output vectors.
-void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const std::vector<double*>& x,
-                const std::vector<double*>& y, int prec, DevBuf* planbuf = nullptr) {
+void hash_heff(Hash& h, int P, const idmrg_heff* H) {
+  h.val(P);
+  for (int p = 0; p < P; ++p) {
+    h.leg(H[p].left);
+    h.leg(H[p].right);
+    h.mpo(H[p].w1);
+    h.mpo(H[p].w2);
+  }
+}
+
+// Plan phase: task lists for P problems, their host-side bounds checks, and the
+// scratch regions (added to lay).  No device work.
+void heff_plan(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, int prec, Layout& lay) {
   if (prec < 0 || prec > 2) throw InvalidArg("unknown precision policy");
   ex.P = P;
   ex.prec = (Prec)prec;
-  std::vector<Leg> A(P), B(P);
-  std::vector<Mpo> W1(P), W2(P);
+  ex.frag = ex.prec == Prec::BF16X3;
+  const bool frag = ex.frag;
   for (int p = 0; p < P; ++p) {
-    if (!H[p].w1 || !H[p].w2 || !H[p].L || !H[p].R) throw InvalidArg("null field in idmrg_heff");
-    A[p] = make_leg(H[p].left, "heff.left");
-    B[p] = make_leg(H[p].right, "heff.right");
-    W1[p] = make_mpo(H[p].w1, "heff.w1");
-    W2[p] = make_mpo(H[p].w2, "heff.w2");
-    if (W1[p].dr != W2[p].dl || W1[p].qr != W2[p].ql) throw InvalidArg("w1 columns and w2 rows differ");
-    if (W1[p].qp != W2[p].qp) throw InvalidArg("w1 and w2 local charges differ");
-    build_heff(ex.plan, p, A[p], B[p], W1[p], W2[p]);
+    if (!H[p].w1 || !H[p].w2) throw InvalidArg("null field in idmrg_heff");
+    const Leg A = make_leg(H[p].left, "heff.left"), B = make_leg(H[p].right, "heff.right");
+    const Mpo W1 = make_mpo(H[p].w1, "heff.w1"), W2 = make_mpo(H[p].w2, "heff.w2");
+    if (W1.dr != W2.dl || W1.qr != W2.ql) throw InvalidArg("w1 columns and w2 rows differ");
+    if (W1.qp != W2.qp) throw InvalidArg("w1 and w2 local charges differ");
+    build_heff(ex.plan, p, A, B, W1, W2);
     if (ex.plan.n_psi[p] == 0) throw InvalidArg("two-site state has no allowed block");
   }
   ex.npsi = ex.plan.n_psi;
-  const bool frag = ex.prec == Prec::BF16X3;
   // Tile variants.  The tile shape does not change the order in which any
   // output element accumulates over k, so all variants give identical results.
-  std::vector<GemmList> var[2];
   ex.nvar = kTilings;
   for (int v = 0; v < kTilings; ++v) ex.code[v] = v;
   for (int st = 0; st < 2; ++st) {
     const GemmList& base = st == 0 ? (frag ? ex.plan.f1 : ex.plan.g1) : (frag ? ex.plan.f2 : ex.plan.g2);
+    ex.var[st].clear();
     for (int v = 0; v < ex.nvar; ++v) {
-      var[st].push_back(base);
-      var[st][v].retile(ex.code[v] & 1 ? 128 : 64, ex.code[v] & 2 ? 128 : 64);
-      ex.tiles[st][v] = var[st][v].tiles;
+      ex.var[st].push_back(base);
+      ex.var[st][v].retile(ex.code[v] & 1 ? 128 : 64, ex.code[v] & 2 ? 128 : 64);
+      ex.tiles[st][v] = ex.var[st][v].tiles;
     }
     ex.key[st] = tune_key(ex.prec, st, base);
     auto it = c->tune.find(ex.key[st]);
@@ -310,10 +489,6 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
       int64_t* z = &sz[(size_t)p * kNumBases];
       z[0] = ex.plan.n_L[p]; z[1] = ex.plan.n_R[p]; z[2] = z[3] = z[6] = ex.plan.n_psi[p];
       z[4] = ex.plan.n_T1[p]; z[5] = ex.plan.n_T3[p];
-      check_dev(H[p].L, ex.plan.n_L[p], 8, "heff.L");
-      check_dev(H[p].R, ex.plan.n_R[p], 8, "heff.R");
-      check_dev(x[p], ex.plan.n_psi[p], 8, "x");
-      check_dev(y[p], ex.plan.n_psi[p], 8, "y");
     }
     if (!frag) {
       check_gemm(ex.plan.g1, 0, sz, "heff gemm1");
@@ -342,173 +517,192 @@ void heff_setup(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, const st
   // sub-buffers start at multiples of 64 elements (256 bytes), which the 16-byte accesses of the split-bf16 kernels need
   auto round64 = [](int64_t n) { return (n + 63) / 64 * 64; };
   int64_t nT1 = 0, nT3 = 0;
-  std::vector<int64_t> o1(P), o3(P);
+  ex.o1.assign(P, 0);
+  ex.o3.assign(P, 0);
   for (int p = 0; p < P; ++p) {
-    o1[p] = nT1;
-    o3[p] = nT3;
+    ex.o1[p] = nT1;
+    ex.o3[p] = nT3;
     nT1 += round64((frag ? ex.plan.n_T1f[p] : ex.plan.n_T1[p]) + 1);
     nT3 += round64((frag ? ex.plan.n_T3f[p] : ex.plan.n_T3[p]) + 1);
   }
-  // the FP64 and the low-precision plans of one Lanczos call are live together, so each has its own T1 and T3
-  char* T1 = (char*)ensure(c, c->ws[ex.prec == Prec::F64 ? WS_T1 : WS_T1LO], nT1 * es);
-  char* T3 = (char*)ensure(c, c->ws[ex.prec == Prec::F64 ? WS_T3 : WS_T3F], nT3 * es);
-  // the fragment form of T3 is written only inside its blocks: its padding stays zero from here on
-  if (frag) IDMRG_HIP(hipMemsetAsync(T3, 0, nT3 * es, c->stream));
-  std::vector<void*> hb((size_t)P * kNumBases, nullptr), sb;
-  ex.xlow.assign(P, nullptr);
-  ex.xmix.assign(P, nullptr);
-  ex.ylow.assign(P, nullptr);
-  if (ex.prec == Prec::F64) {
-    for (int p = 0; p < P; ++p) {
-      void** b = &hb[(size_t)p * kNumBases];
-      b[0] = (void*)H[p].L;
-      b[1] = (void*)H[p].R;
-      b[2] = x[p];
-      b[3] = y[p];
-      b[4] = T1 + o1[p] * 8;
-      b[5] = T3 + o3[p] * 8;
-      b[6] = x[p];
-    }
-  } else {
+  ex.oT1 = lay.add(nT1 * es);
+  ex.nT3bytes = nT3 * es;
+  ex.oT3 = lay.add(ex.nT3bytes);
+  ex.has_shift.assign(P, 0);
+  if (ex.prec != Prec::F64) {
     // 4-byte units: FP32 L, R, x (also the mixing operand), y; or, for split-bf16,
     // fragment-layout L, R, x, plus FP32 x for the mixing and y
     const std::vector<int64_t>& nL = frag ? ex.plan.n_Lf : ex.plan.n_L;
     const std::vector<int64_t>& nR = frag ? ex.plan.n_Rf : ex.plan.n_R;
     int64_t nenv = 0, nvec = 0;
+    ex.oL.assign(P, 0);
+    ex.oR.assign(P, 0);
+    ex.oXmix.assign(P, 0);
+    ex.oYlow.assign(P, 0);
+    ex.oXlow.assign(P, -1);
     for (int p = 0; p < P; ++p) {
-      nenv += round64(nL[p]) + round64(nR[p]);
-      nvec += (frag ? round64(ex.plan.n_Xf[p]) + round64(ex.plan.n_Xm[p]) : round64(ex.npsi[p])) + round64(ex.npsi[p]);
-    }
-    char* env = (char*)ensure(c, c->ws[WS_LOWENV], nenv * 4);
-    char* vec = (char*)ensure(c, c->ws[WS_LOWVEC], nvec * 4);
-    int64_t oe = 0, ov = 0;
-    if (frag) sb.assign((size_t)P * kNumBases, nullptr);
-    for (int p = 0; p < P; ++p) {
-      void** b = &hb[(size_t)p * kNumBases];
-      void* Ll = env + oe * 4;
-      oe += round64(nL[p]);
-      void* Rl = env + oe * 4;
-      oe += round64(nR[p]);
-      ex.xmix[p] = vec + ov * 4;   // split-bf16: the row-padded copy the x pack writes
-      ov += round64(frag ? ex.plan.n_Xm[p] : ex.npsi[p]);
-      ex.ylow[p] = vec + ov * 4;
-      ov += round64(ex.npsi[p]);
+      ex.oL[p] = nenv;
+      nenv += round64(nL[p]);
+      ex.oR[p] = nenv;
+      nenv += round64(nR[p]);
+      ex.oXmix[p] = nvec;   // split-bf16: the row-padded copy the x pack writes
+      nvec += round64(frag ? ex.plan.n_Xm[p] : ex.npsi[p]);
+      ex.oYlow[p] = nvec;
+      nvec += round64(ex.npsi[p]);
       if (frag) {
-        ex.xlow[p] = vec + ov * 4;
-        ov += round64(ex.plan.n_Xf[p]);
-        void** q = &sb[(size_t)p * kNumBases];
-        q[0] = (void*)H[p].L;
-        q[1] = (void*)H[p].R;
-        q[2] = x[p];
-      } else {
-        ex.xlow[p] = ex.xmix[p];
-        launch_convert(0, H[p].L, Ll, ex.plan.n_L[p], c->stream);
-        launch_convert(0, H[p].R, Rl, ex.plan.n_R[p], c->stream);
+        ex.oXlow[p] = nvec;
+        nvec += round64(ex.plan.n_Xf[p]);
       }
-      b[0] = Ll;
-      b[1] = Rl;
-      b[2] = ex.xlow[p];
+      ex.has_shift[p] = (char)(ex.plan.shiftL[p] || ex.plan.shiftR[p]);
+    }
+    ex.oEnv = lay.add(nenv * 4);
+    ex.oVec = lay.add(nvec * 4);
+    // energy shift of the low-precision copies (see plan.h): diagonal sums, per-task and per-problem shifts
+    ex.diag = ex.plan.diagL;
+    ex.diag.insert(ex.diag.end(), ex.plan.diagR.begin(), ex.plan.diagR.end());
+    ex.nDL = ex.plan.diagL.size();
+    ex.oSums = lay.add(ex.diag.size() * 8);
+    ex.oShift = lay.add(ex.diag.size() * 8);
+    ex.oSig = lay.add((size_t)P * 2 * 8);
+  }
+  // the upload: tile variants of both stages, mixing lists, pointer tables, packs, diagonals, shift flags
+  Packer& pk = ex.pk;
+  pk.host.clear();
+  for (int st = 0; st < 2; ++st)
+    for (int v = 0; v < ex.nvar; ++v) ex.av[st][v] = pk.add(ex.var[st][v].t);
+  const MixList& mY = frag ? ex.plan.mixYf : ex.plan.mixY;
+  const MixList& mT = frag ? ex.plan.mixTf : ex.plan.mixT;
+  ex.aMY = pk.add(mY.t);
+  ex.aSY = pk.add(mY.src);
+  ex.aMT = pk.add(mT.t);
+  ex.aST = pk.add(mT.src);
+  ex.aHB = pk.reserve((size_t)P * kNumBases * sizeof(void*));
+  if (ex.prec != Prec::F64) {
+    ex.aSB = pk.reserve((size_t)P * kNumBases * sizeof(void*));
+    ex.aDiag = pk.add(ex.diag);
+    std::vector<int32_t> flags(2 * (size_t)P);
+    for (int p = 0; p < P; ++p) {
+      flags[2 * p] = ex.plan.shiftL[p];
+      flags[2 * p + 1] = ex.plan.shiftR[p];
+    }
+    ex.aFlags = pk.add(flags);
+  }
+  if (frag) {
+    ex.aPX = pk.add(ex.plan.packX.t);
+    ex.aPL = pk.add(ex.plan.packL.t);
+    ex.aPR = pk.add(ex.plan.packR.t);
+  }
+  ex.oPlan = lay.add(pk.host.size());
+}
+
+// Bind phase: the scratch regions at `base`, the vectors x / y (device, FP64),
+// the plan upload and the per-operator work (low-precision copies of L and R
+// with their energy shifts).
+void heff_bind(idmrg_ctx* c, HeffExec& ex, char* base, const idmrg_heff* H, const std::vector<double*>& x,
+               const std::vector<double*>& y) {
+  const int P = ex.P;
+  const bool frag = ex.frag;
+  hipStream_t s = c->stream;
+  for (int p = 0; p < P; ++p) {
+    if (!H[p].L || !H[p].R) throw InvalidArg("null field in idmrg_heff");
+    check_dev(H[p].L, ex.plan.n_L[p], 8, "heff.L");
+    check_dev(H[p].R, ex.plan.n_R[p], 8, "heff.R");
+    check_dev(x[p], ex.plan.n_psi[p], 8, "x");
+    check_dev(y[p], ex.plan.n_psi[p], 8, "y");
+  }
+  const size_t es = ex.prec == Prec::F64 ? 8 : 4;
+  char* T1 = base + ex.oT1;
+  char* T3 = base + ex.oT3;
+  std::vector<void*> hb((size_t)P * kNumBases, nullptr), sb;
+  ex.xmix.assign(P, nullptr);
+  ex.ylow.assign(P, nullptr);
+  char* env = base + ex.oEnv;
+  char* vec = base + ex.oVec;
+  for (int p = 0; p < P; ++p) {
+    void** b = &hb[(size_t)p * kNumBases];
+    b[4] = T1 + ex.o1[p] * es;
+    b[5] = T3 + ex.o3[p] * es;
+    if (ex.prec == Prec::F64) {
+      b[0] = (void*)H[p].L;
+      b[1] = (void*)H[p].R;
+      b[2] = x[p];
+      b[3] = y[p];
+      b[6] = x[p];
+    } else {
+      ex.xmix[p] = vec + ex.oXmix[p] * 4;
+      ex.ylow[p] = vec + ex.oYlow[p] * 4;
+      b[0] = env + ex.oL[p] * 4;
+      b[1] = env + ex.oR[p] * 4;
+      b[2] = frag ? (void*)(vec + ex.oXlow[p] * 4) : ex.xmix[p];
       b[3] = ex.ylow[p];
-      b[4] = T1 + o1[p] * 4;
-      b[5] = T3 + o3[p] * 4;
       b[6] = ex.xmix[p];
     }
   }
-  // Energy shift of the low-precision copies (see plan.h): sL, sR = mean
-  // diagonal of the H_L and H_R blocks, from their FP64 sources.
-  ex.sigma.assign(P, 0.0);
-  std::vector<DiagTask> diag = ex.plan.diagL;
-  diag.insert(diag.end(), ex.plan.diagR.begin(), ex.plan.diagR.end());
-  const size_t nDL = ex.plan.diagL.size();
-  std::vector<double> dshift(diag.size(), 0.0);
-  char* dd = nullptr;
-  size_t d1 = 0, d3 = 0;
-  if (ex.prec != Prec::F64 && !diag.empty()) {
-    if (sb.empty()) {
-      sb.assign((size_t)P * kNumBases, nullptr);
-      for (int p = 0; p < P; ++p) {
-        sb[(size_t)p * kNumBases + 0] = (void*)H[p].L;
-        sb[(size_t)p * kNumBases + 1] = (void*)H[p].R;
-        sb[(size_t)p * kNumBases + 2] = x[p];
-      }
-    }
-    Packer dk;
-    d1 = dk.add(diag);
-    const size_t d2 = dk.add(sb);
-    d3 = dk.add(dshift);
-    dd = upload(c, dk, &c->ws[WS_DIAG]);
-    launch_diag_sum((const DiagTask*)(dd + d1), (int)diag.size(), (void* const*)(dd + d2), (double*)(dd + d3),
-                    c->stream);
-    std::vector<double> sums(diag.size());
-    IDMRG_HIP(hipMemcpyAsync(sums.data(), dd + d3, sums.size() * 8, hipMemcpyDeviceToHost, c->stream));
-    sync(c);
-    std::vector<double> sL(P, 0.0), sR(P, 0.0), nL(P, 0.0), nR(P, 0.0);
-    for (size_t t = 0; t < diag.size(); ++t) {
-      const int p = diag[t].prob;
-      (t < nDL ? sL : sR)[p] += sums[t];
-      (t < nDL ? nL : nR)[p] += diag[t].len;
-    }
+  ex.pk.patch(ex.aHB, hb);
+  if (ex.prec != Prec::F64) {
+    sb.assign((size_t)P * kNumBases, nullptr);
     for (int p = 0; p < P; ++p) {
-      sL[p] = (ex.plan.shiftL[p] && nL[p] > 0) ? sL[p] / nL[p] : 0.0;
-      sR[p] = (ex.plan.shiftR[p] && nR[p] > 0) ? sR[p] / nR[p] : 0.0;
-      ex.sigma[p] = sL[p] + sR[p];
+      sb[(size_t)p * kNumBases + 0] = (void*)H[p].L;
+      sb[(size_t)p * kNumBases + 1] = (void*)H[p].R;
+      sb[(size_t)p * kNumBases + 2] = x[p];
     }
-    for (auto& t : ex.plan.packL.t) t.shift = t.dlen > 0 ? sL[t.prob] : 0.0;
-    for (auto& t : ex.plan.packR.t) t.shift = t.dlen > 0 ? sR[t.prob] : 0.0;
-    for (size_t t = 0; t < diag.size(); ++t) dshift[t] = (t < nDL ? sL : sR)[diag[t].prob];
-    IDMRG_HIP(hipMemcpyAsync(dd + d3, dshift.data(), dshift.size() * 8, hipMemcpyHostToDevice, c->stream));
-    sync(c);   // dshift is a host vector
+    ex.pk.patch(ex.aSB, sb);
   }
-  Packer pk;
-  size_t av[2][kTilings];
+  char* dev = base + ex.oPlan;
+  stage(c, dev, ex.pk.host.data(), ex.pk.host.size());
   for (int st = 0; st < 2; ++st)
-    for (int v = 0; v < ex.nvar; ++v) av[st][v] = pk.add(var[st][v].t);
-  const MixList& mY = frag ? ex.plan.mixYf : ex.plan.mixY;
-  const MixList& mT = frag ? ex.plan.mixTf : ex.plan.mixT;
-  const size_t a3 = pk.add(mY.t), a4 = pk.add(mY.src), a5 = pk.add(mT.t), a6 = pk.add(mT.src), a7 = pk.add(hb);
-  size_t a8 = 0, a9 = 0, a10 = 0, a11 = 0;
-  if (!sb.empty()) a8 = pk.add(sb);
-  if (frag) {
-    a9 = pk.add(ex.plan.packX.t);
-    a10 = pk.add(ex.plan.packL.t);
-    a11 = pk.add(ex.plan.packR.t);
+    for (int v = 0; v < ex.nvar; ++v) ex.gv[st][v] = (GemmTask*)(dev + ex.av[st][v]);
+  ex.mY = (MixTask*)(dev + ex.aMY);
+  ex.sY = (MixSrc*)(dev + ex.aSY);
+  ex.mT = (MixTask*)(dev + ex.aMT);
+  ex.sT = (MixSrc*)(dev + ex.aST);
+  ex.bases = (void**)(dev + ex.aHB);
+  ex.sbases = ex.prec != Prec::F64 ? (void**)(dev + ex.aSB) : nullptr;
+  // the fragment form of T3 is written only inside its blocks: its padding stays zero from here on
+  if (frag) IDMRG_HIP(hipMemsetAsync(T3, 0, ex.nT3bytes, s));
+  if (ex.prec == Prec::F64) return;
+  if (!frag)
+    for (int p = 0; p < P; ++p) {
+      launch_convert(0, H[p].L, hb[(size_t)p * kNumBases + 0], ex.plan.n_L[p], s);
+      launch_convert(0, H[p].R, hb[(size_t)p * kNumBases + 1], ex.plan.n_R[p], s);
+    }
+  // energy shifts of the low-precision copies: sL, sR = mean diagonal of the H_L and H_R blocks
+  ex.sig = (double*)(base + ex.oSig);
+  double* shift = (double*)(base + ex.oShift);
+  const DiagTask* dt = (const DiagTask*)(dev + ex.aDiag);
+  if (!ex.diag.empty()) {
+    launch_diag_sum(dt, (int)ex.diag.size(), ex.sbases, (double*)(base + ex.oSums), s);
+    launch_sigma(dt, (int)ex.diag.size(), (int)ex.nDL, (const double*)(base + ex.oSums),
+                 (const int32_t*)(dev + ex.aFlags), P, ex.sig, shift, s);
+  } else {
+    IDMRG_HIP(hipMemsetAsync(ex.sig, 0, (size_t)P * 2 * 8, s));
   }
-  char* dev = upload(c, pk, planbuf);
-  for (int st = 0; st < 2; ++st)
-    for (int v = 0; v < ex.nvar; ++v) ex.gv[st][v] = (GemmTask*)(dev + av[st][v]);
-  ex.mY = (MixTask*)(dev + a3);
-  ex.sY = (MixSrc*)(dev + a4);
-  ex.mT = (MixTask*)(dev + a5);
-  ex.sT = (MixSrc*)(dev + a6);
-  ex.bases = (void**)(dev + a7);
-  if (!sb.empty()) ex.sbases = (void**)(dev + a8);
-  if (ex.prec == Prec::F32 && dd)   // the FP32 copies of the H_L, H_R diagonals, shifted, from the FP64 sources
-    launch_diag_shift_f32((const DiagTask*)(dd + d1), (int)diag.size(), ex.sbases, ex.bases,
-                          (const double*)(dd + d3), c->stream);
+  if (ex.prec == Prec::F32 && !ex.diag.empty())   // the FP32 copies of the H_L, H_R diagonals, shifted
+    launch_diag_shift_f32(dt, (int)ex.diag.size(), ex.sbases, ex.bases, shift, s);
   if (frag) {
     // operands fixed for the whole operator: packed once here
-    ex.pX = (PackTask*)(dev + a9);
-    launch_pack((PackTask*)(dev + a10), (int)ex.plan.packL.t.size(), ex.plan.packL.tiles, ex.sbases, ex.bases, nullptr,
-                c->stream);
-    launch_pack((PackTask*)(dev + a11), (int)ex.plan.packR.t.size(), ex.plan.packR.tiles, ex.sbases, ex.bases, nullptr,
-                c->stream);
-    IDMRG_HIP(hipGetLastError());
+    ex.pX = (PackTask*)(dev + ex.aPX);
+    launch_pack((PackTask*)(dev + ex.aPL), (int)ex.plan.packL.t.size(), ex.plan.packL.tiles, ex.sbases, ex.bases,
+                ex.sig, nullptr, s);
+    launch_pack((PackTask*)(dev + ex.aPR), (int)ex.plan.packR.t.size(), ex.plan.packR.tiles, ex.sbases, ex.bases,
+                ex.sig, nullptr, s);
   }
+  IDMRG_HIP(hipGetLastError());
 }
 
-// y = H x for every problem (x, y: the FP64 vectors given at setup).
+// y = H x for every problem (x, y: the FP64 vectors given at bind).
 // trial >= 0: run tiling variant `trial` in both stages and bracket each stage with the tuning events.
 void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const std::vector<double*>& y,
               const int32_t* active, int trial = -1) {
   hipStream_t s = c->stream;
   if (ex.prec != Prec::F64) {
     Prof pr(c, 3, 0.0);
-    if (ex.prec == Prec::BF16X3)   // also writes the padded FP32 copy of x for the mixing
-      launch_pack(ex.pX, (int)ex.plan.packX.t.size(), ex.plan.packX.tiles, ex.sbases, ex.bases, active, s);
+    if (ex.frag)   // also writes the padded FP32 copy of x for the mixing
+      launch_pack(ex.pX, (int)ex.plan.packX.t.size(), ex.plan.packX.tiles, ex.sbases, ex.bases, ex.sig, active, s);
     else
       for (int p = 0; p < ex.P; ++p) launch_convert(0, x[p], ex.xmix[p], ex.npsi[p], s);
   }
-  const bool frag = ex.prec == Prec::BF16X3;
+  const bool frag = ex.frag;
   const int tin = ex.prec == Prec::F64 ? 0 : (frag ? 4 : 1);
   const int toutT = ex.prec == Prec::F64 ? 0 : (ex.prec == Prec::F32 ? 1 : 3);
   const int toutY = ex.prec == Prec::F64 ? 0 : 1;
@@ -538,8 +732,8 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   if (ex.prec != Prec::F64) {
     Prof pr(c, 3, 0.0);
     for (int p = 0; p < ex.P; ++p) {
-      if (ex.sigma[p] != 0.0)
-        launch_convert_add((const float*)ex.ylow[p], x[p], ex.sigma[p], y[p], ex.npsi[p], s);
+      if (ex.has_shift[p])
+        launch_convert_add((const float*)ex.ylow[p], x[p], ex.sig, p, y[p], ex.npsi[p], s);
       else
         launch_convert(1, ex.ylow[p], y[p], ex.npsi[p], s);
     }
@@ -591,8 +785,307 @@ struct GraphSet {
   }
 };
 
-void check_nprob(int nprob) {
-  if (nprob < 1 || nprob > 64) throw InvalidArg("nprob must be 1..64");
+// ------------------------------------------------------------------ plans of the five calls
+
+struct HeffCall : CallPlan {
+  HeffExec ex;
+};
+
+std::shared_ptr<HeffCall> heff_call(idmrg_ctx* c, int P, const idmrg_heff* H, int prec) {
+  Hash h;
+  h.val(prec);
+  hash_heff(h, P, H);
+  return plan_of<HeffCall>(c, IDMRG_OP_HEFF, h.h, [&](HeffCall& k) { heff_plan(c, k.ex, P, H, prec, k.lay); });
+}
+
+struct LanczosCall : CallPlan {
+  bool mixed = false;
+  int kmax = 0;
+  std::vector<int64_t> N, kcap, ld, qoff, woff, voff, soff;
+  size_t oV = 0, oSmall = 0, oProbs = 0;
+  HeffExec ex64, exlo;
+};
+
+std::shared_ptr<LanczosCall> lanczos_call(idmrg_ctx* c, int P, const idmrg_heff* H, const idmrg_lanczos_opts* o) {
+  Hash h;
+  h.val(o->k_max);
+  h.val(o->prec);
+  hash_heff(h, P, H);
+  return plan_of<LanczosCall>(c, IDMRG_OP_LANCZOS, h.h, [&](LanczosCall& k) {
+    if (o->k_max < 1 || o->k_max > kLzMaxK) throw InvalidArg("k_max must be 1..1024");
+    if (o->prec < 0 || o->prec > 2) throw InvalidArg("unknown precision policy");
+    k.mixed = o->prec != IDMRG_PREC_F64;
+    k.kmax = o->k_max;
+    k.N.assign(P, 0);
+    for (int p = 0; p < P; ++p) {
+      if (!H[p].w1) throw InvalidArg("null field in idmrg_heff");
+      k.N[p] = psi_layout(make_leg(H[p].left, "left"), make_leg(H[p].right, "right"),
+                          make_mpo(H[p].w1, "w1").qp).size;
+      if (k.N[p] == 0) throw InvalidArg("empty two-site space");
+    }
+    // vectors: Q [kcap x N], w, v (and, mixed precision, the normalised start
+    // vector s0: the fidelity of Eq. (12) is taken against the refined state);
+    // every piece is a multiple of kLzAlign elements, so all rows start 2 KiB-aligned
+    k.kcap.assign(P, 0);
+    k.ld.assign(P, 0);
+    k.qoff.assign(P, 0);
+    k.woff.assign(P, 0);
+    k.voff.assign(P, 0);
+    k.soff.assign(P, 0);
+    int64_t tot = 0;
+    for (int p = 0; p < P; ++p) {
+      k.kcap[p] = std::min<int64_t>(k.kmax, k.N[p]);
+      k.ld[p] = (k.N[p] + kLzAlign - 1) / kLzAlign * kLzAlign;
+      k.qoff[p] = tot;
+      tot += k.kcap[p] * k.ld[p];
+      k.woff[p] = tot;
+      tot += k.ld[p];
+      k.voff[p] = tot;
+      tot += k.ld[p];
+      k.soff[p] = tot;
+      if (k.mixed) tot += k.ld[p];
+    }
+    k.oV = k.lay.add(tot * 8);
+    const size_t nsm = (size_t)P * k.kmax;
+    k.oSmall = k.lay.add((size_t)P * (k.kmax + 1) * kLzBlocks * 8 + 4 * nsm * 8 + P * sizeof(LzCtrl) + P * 4 + 4096);
+    k.oProbs = k.lay.add((size_t)P * sizeof(LzProblem));
+    heff_plan(c, k.ex64, P, H, IDMRG_PREC_F64, k.lay);
+    if (k.mixed) heff_plan(c, k.exlo, P, H, o->prec, k.lay);
+  });
+}
+
+struct TruncSec {
+  int q = 0, r = 0, c = 0;
+  std::vector<std::tuple<int, int, int>> rows, cols;
+  int64_t m = 0, x = 0, g = 0, u = 0, v = 0, sv = 0;
+};
+
+struct TruncCall : CallPlan {
+  std::vector<int> qp;
+  std::vector<std::vector<TruncSec>> secs;
+  std::vector<Leg> A, B;
+  std::vector<PsiLayout> X;
+  int64_t nM = 0, nX = 0, nG = 0, nU = 0, nV = 0, nS = 0;
+  MixList gather;
+  std::vector<SvdTask> svd;
+  std::vector<SelTask> sel;
+  std::vector<SelSector> ssec;
+  int ncand_tot = 0;
+  int pmax = 1;
+  BjPlan bj;
+  Packer pk;
+  size_t a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0;
+  size_t oSvd = 0, oSel = 0, oFlag = 0, oPlan = 0, oBjPlan = 0, oBjWork = 0, oOut = 0, outBytes = 0;
+};
+
+std::shared_ptr<TruncCall> trunc_call(idmrg_ctx* c, int P, int d, const int32_t* qp_in, int32_t m_max,
+                                      const idmrg_trunc* t) {
+  Hash h;
+  h.val(P);
+  h.arr(qp_in, d);
+  h.val(m_max);
+  for (int p = 0; p < P; ++p) {
+    h.leg(t[p].left);
+    h.leg(t[p].right);
+  }
+  return plan_of<TruncCall>(c, IDMRG_OP_TRUNCATE, h.h, [&](TruncCall& k) {
+    if (m_max < 1) throw InvalidArg("bad truncation arguments");
+    k.qp = make_qp(d, qp_in);
+    k.secs.assign(P, {});
+    k.A.assign(P, Leg{});
+    k.B.assign(P, Leg{});
+    k.X.assign(P, PsiLayout{});
+    for (int p = 0; p < P; ++p) {
+      k.A[p] = make_leg(t[p].left, "trunc.left");
+      k.B[p] = make_leg(t[p].right, "trunc.right");
+      k.X[p] = psi_layout(k.A[p], k.B[p], k.qp);
+      std::map<int, TruncSec> byq;
+      for (int a = 0; a < k.A[p].n(); ++a)
+        for (int s1 = 0; s1 < d; ++s1) {
+          TruncSec& S = byq[k.A[p].q[a] + k.qp[s1]];
+          S.rows.emplace_back(a, s1, S.r);
+          S.r += k.A[p].dim[a];
+        }
+      for (int s2 = 0; s2 < d; ++s2)
+        for (int b = 0; b < k.B[p].n(); ++b) {
+          TruncSec& S = byq[k.B[p].q[b] - k.qp[s2]];
+          S.cols.emplace_back(s2, b, S.c);
+          S.c += k.B[p].dim[b];
+        }
+      SelTask st{};
+      st.sec0 = (int)k.ssec.size();
+      st.cand0 = k.ncand_tot;
+      st.m_max = m_max;
+      st.prob = p;
+      for (auto& kv : byq) {
+        TruncSec S = kv.second;
+        S.q = kv.first;
+        if (S.r == 0 || S.c == 0) continue;
+        const int n = std::min(S.r, S.c), pp = std::max(S.r, S.c);
+        if (n > 4096 || pp > 8192)
+          throw InvalidArg("centre sector larger than 4096 x 8192 states is not supported");
+        S.m = k.nM; k.nM += (int64_t)S.r * S.c;
+        S.x = k.nX; k.nX += (int64_t)n * pp;
+        S.g = k.nG; k.nG += (int64_t)n * n;
+        S.u = k.nU; k.nU += (int64_t)S.r * n;
+        S.v = k.nV; k.nV += (int64_t)S.c * n;
+        S.sv = k.nS; k.nS += n;
+        k.pmax = std::max(k.pmax, pp);
+        for (auto& rw : S.rows)
+          for (auto& cl : S.cols) {
+            const int a = std::get<0>(rw), s1 = std::get<1>(rw), ro = std::get<2>(rw);
+            const int s2 = std::get<0>(cl), b = std::get<1>(cl), co = std::get<2>(cl);
+            const int xi = k.X[p].find(a, s1, s2);
+            if (xi < 0 || k.X[p].blk[xi].b != b) throw InvalidArg("internal: truncation block bookkeeping");
+            MixTask m{};
+            m.rows = k.A[p].dim[a]; m.cols = k.B[p].dim[b]; m.ldd = S.c; m.prob = p; m.dbase = 1;
+            m.doff = S.m + (int64_t)ro * S.c + co;
+            MixSrc sr{};
+            sr.coef = 1.0; sr.base = 0; sr.off = k.X[p].blk[xi].off; sr.ld = k.B[p].dim[b];
+            k.gather.add(m, {sr});
+          }
+        SvdTask sv{};
+        sv.r = S.r; sv.c = S.c; sv.prob = p;
+        sv.m_off = S.m; sv.x_off = S.x; sv.g_off = S.g; sv.u_off = S.u; sv.v_off = S.v; sv.s_off = S.sv;
+        k.svd.push_back(sv);
+        SelSector se{};
+        se.charge = S.q; se.n = n; se.cand0 = k.ncand_tot; se.s_off = S.sv;
+        k.ssec.push_back(se);
+        k.ncand_tot += n;
+        st.ncand += n;
+        st.nsec += 1;
+        k.secs[p].push_back(S);
+      }
+      if (st.ncand > 8192) throw InvalidArg("more than 8192 singular values per problem is not supported");
+      if (st.ncand == 0) throw InvalidArg("two-site state has no centre sector");
+      k.sel.push_back(st);
+    }
+    {
+      std::vector<int64_t> sz((size_t)P * kNumBases, -1);
+      for (int p = 0; p < P; ++p) {
+        sz[(size_t)p * kNumBases + 0] = k.X[p].size;
+        sz[(size_t)p * kNumBases + 1] = k.nM;
+      }
+      check_mix(k.gather, sz, "truncation gather");
+    }
+    // SVD scratch: M, X, G, U, V, S (each padded by 64 elements)
+    k.oSvd = k.lay.add((k.nM + k.nX + k.nG + k.nU + k.nV + k.nS + 6 * 64) * 8);
+    k.oSel = k.lay.add((size_t)k.ncand_tot * (4 + 8) + k.ssec.size() * 4 + P * 32 + 4096);
+    k.oFlag = k.lay.add(4);
+    k.a1 = k.pk.add(k.gather.t);
+    k.a2 = k.pk.add(k.gather.src);
+    k.a3 = k.pk.add(k.svd);
+    k.a4 = k.pk.add(k.sel);
+    k.a5 = k.pk.add(k.ssec);
+    k.a6 = k.pk.reserve((size_t)P * kNumBases * sizeof(void*));
+    k.oPlan = k.lay.add(k.pk.host.size());
+    bj_prepare(k.svd, k.bj);
+    k.oBjPlan = k.lay.add(k.bj.host.size());
+    k.oBjWork = k.lay.add(k.bj.scratch);
+    // the output scatter: at most three tasks (U, V, lambda) per sector, and a pointer table
+    Packer most;
+    most.add(std::vector<ScaleTask>(3 * k.ssec.size()));
+    most.reserve((size_t)P * kNumBases * sizeof(void*));
+    k.outBytes = most.host.size();
+    k.oOut = k.lay.add(k.outBytes);
+  });
+}
+
+struct EnvCall : CallPlan {
+  EnvPlan plan;
+  std::vector<int64_t> sz, o1, o2;
+  size_t oT = 0, oPlan = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+  int64_t n1 = 0;
+  Packer pk;
+};
+
+std::shared_ptr<EnvCall> env_call(idmrg_ctx* c, int P, int side, const idmrg_env_update* u) {
+  Hash h;
+  h.val(P);
+  for (int p = 0; p < P; ++p) {
+    h.leg(u[p].old_leg);
+    h.leg(u[p].new_leg);
+    h.mpo(u[p].w);
+  }
+  const int op = side == IDMRG_LEFT ? IDMRG_OP_ENV_LEFT : IDMRG_OP_ENV_RIGHT;
+  return plan_of<EnvCall>(c, op, h.h, [&](EnvCall& k) {
+    k.sz.assign((size_t)P * kNumBases, -1);
+    for (int p = 0; p < P; ++p) {
+      const Leg O = make_leg(u[p].old_leg, "env.old_leg"), C = make_leg(u[p].new_leg, "env.new_leg");
+      const Mpo W = make_mpo(u[p].w, "env.w");
+      int64_t* z = &k.sz[(size_t)p * kNumBases];
+      if (side == IDMRG_LEFT) {
+        build_envL(k.plan, p, O, C, W);
+        z[0] = envL_layout(O, W.ql).size; z[1] = U_layout(O, W.qp, C).size; z[2] = envL_layout(C, W.qr).size;
+      } else {
+        build_envR(k.plan, p, O, C, W);
+        z[0] = envR_layout(O, W.qr).size; z[1] = V_layout(O, W.qp, C).size; z[2] = envR_layout(C, W.ql).size;
+      }
+      z[3] = k.plan.n_T1[p]; z[4] = k.plan.n_T2[p];
+    }
+    check_gemm(k.plan.ga, side == IDMRG_LEFT ? 0 : 2, k.sz, "env stage a");
+    check_mix(k.plan.mix, k.sz, "env mix");
+    check_gemm(k.plan.gc, side == IDMRG_LEFT ? 2 : 0, k.sz, "env stage c");
+    int64_t n1 = 0, n2 = 0;
+    k.o1.assign(P, 0);
+    k.o2.assign(P, 0);
+    for (int p = 0; p < P; ++p) {
+      k.o1[p] = n1; n1 += k.plan.n_T1[p] + 64;
+      k.o2[p] = n2; n2 += k.plan.n_T2[p] + 64;
+    }
+    k.n1 = n1;
+    k.oT = k.lay.add((n1 + n2) * 8);
+    k.a1 = k.pk.add(k.plan.ga.t);
+    k.a2 = k.pk.add(k.plan.mix.t);
+    k.a3 = k.pk.add(k.plan.mix.src);
+    k.a4 = k.pk.add(k.plan.gc.t);
+    k.a5 = k.pk.reserve((size_t)P * kNumBases * sizeof(void*));
+    k.oPlan = k.lay.add(k.pk.host.size());
+  });
+}
+
+struct PredictCall : CallPlan {
+  PredictPlan plan;
+  std::vector<int64_t> sz, ov, ou;
+  size_t oW = 0, oPlan = 0, a1 = 0, a2 = 0, a3 = 0;
+  Packer pk;
+};
+
+std::shared_ptr<PredictCall> predict_call(idmrg_ctx* c, int P, int d, const int32_t* qp_in, const idmrg_predict* pr) {
+  Hash h;
+  h.val(P);
+  h.arr(qp_in, d);
+  for (int p = 0; p < P; ++p) {
+    h.leg(pr[p].leg_a);
+    h.leg(pr[p].leg_beta);
+    h.leg(pr[p].leg_b);
+  }
+  return plan_of<PredictCall>(c, IDMRG_OP_PREDICT, h.h, [&](PredictCall& k) {
+    const std::vector<int> qp = make_qp(d, qp_in);
+    k.sz.assign((size_t)P * kNumBases, -1);
+    for (int p = 0; p < P; ++p) {
+      const Leg Aa = make_leg(pr[p].leg_a, "leg_a"), Bt = make_leg(pr[p].leg_beta, "leg_beta"),
+                Bb = make_leg(pr[p].leg_b, "leg_b");
+      build_predict(k.plan, p, Aa, Bt, Bb, qp);
+      int64_t* z = &k.sz[(size_t)p * kNumBases];
+      z[0] = Aa.total(); z[1] = z[6] = V_layout(Bt, qp, Aa).size; z[2] = Bt.total();
+      z[3] = z[7] = U_layout(Bt, qp, Bb).size; z[4] = Bb.total(); z[5] = psi_layout(Aa, Bb, qp).size;
+    }
+    check_scale(k.plan.scale, k.sz, "predict scale", 0);
+    check_gemm(k.plan.g, 2, k.sz, "predict gemm");
+    int64_t n = 0;
+    k.ov.assign(P, 0);
+    k.ou.assign(P, 0);
+    for (int p = 0; p < P; ++p) {
+      k.ov[p] = n; n += k.plan.n_Vs[p] + 64;
+      k.ou[p] = n; n += k.plan.n_Us[p] + 64;
+    }
+    k.oW = k.lay.add(n * 8);
+    k.a1 = k.pk.add(k.plan.scale.t);
+    k.a2 = k.pk.add(k.plan.g.t);
+    k.a3 = k.pk.reserve((size_t)P * kNumBases * sizeof(void*));
+    k.oPlan = k.lay.add(k.pk.host.size());
+  });
 }
 
 }  // namespace
@@ -609,6 +1102,11 @@ extern "C" int idmrg_create(idmrg_ctx** ctx, int device, void* hip_stream) {
   if (!c) return IDMRG_ENOMEM;
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (hipHostMalloc((void**)&c->ring, kRingBytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return IDMRG_ENOMEM;
+  }
   *ctx = c;
   return IDMRG_OK;
 }
@@ -617,10 +1115,11 @@ extern "C" int idmrg_destroy(idmrg_ctx* c) {
   if (!c) return IDMRG_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  if (c->plan.p) (void)hipFree(c->plan.p);
-  for (auto& b : c->ws)
-    if (b.p) (void)hipFree(b.p);
-  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto& p : c->cache) p.reset();
+  if (c->own.p) (void)hipFree(c->own.p);
+  if (c->ring) (void)hipHostFree(c->ring);
+  for (auto& r : c->ring_busy) (void)hipEventDestroy(r.ev);
+  for (auto e : c->ring_events) (void)hipEventDestroy(e);
   for (auto& r : c->pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -638,6 +1137,32 @@ extern "C" int idmrg_set_stream(idmrg_ctx* c, void* hip_stream) {
   if (!c) return IDMRG_EINVAL;
   (void)hipStreamSynchronize(c->stream);
   c->stream = (hipStream_t)hip_stream;
+  return IDMRG_OK;
+}
+
+extern "C" int idmrg_set_workspace(idmrg_ctx* c, void* ptr, size_t bytes) {
+  return guarded(c, [&]() {
+    if (!ptr) {
+      c->user_ws = nullptr;
+      c->user_ws_n = 0;
+      return IDMRG_OK;
+    }
+    if (((uintptr_t)ptr & 255) != 0) throw InvalidArg("workspace must be 256-byte aligned");
+    check_dev(ptr, (int64_t)bytes, 1, "workspace");
+    if (c->own.p) {   // the library's own block is no longer needed
+      sync(c);
+      IDMRG_HIP(hipFree(c->own.p));
+      c->own = DevBuf{};
+    }
+    c->user_ws = (char*)ptr;
+    c->user_ws_n = bytes;
+    return IDMRG_OK;
+  });
+}
+
+extern "C" int idmrg_get_stats(idmrg_ctx* c, idmrg_stats* out) {
+  if (!c || !out) return IDMRG_EINVAL;
+  *out = c->stats;
   return IDMRG_OK;
 }
 
@@ -717,6 +1242,39 @@ extern "C" int idmrg_heff_work(const idmrg_heff* H, double* flops, double* bytes
   }
 }
 
+extern "C" int idmrg_workspace_size(idmrg_ctx* ctx, int op, int nprob, const void* desc, const idmrg_ws_query* q,
+                                    size_t* bytes) {
+  return guarded(ctx, [&]() {
+    check_nprob(nprob);
+    if (!desc || !q || !bytes) throw InvalidArg("null argument");
+    size_t n = 0;
+    switch (op) {
+      case IDMRG_OP_HEFF:
+        n = heff_call(ctx, nprob, (const idmrg_heff*)desc, q->prec)->lay.total;
+        break;
+      case IDMRG_OP_LANCZOS:
+        if (!q->opts) throw InvalidArg("IDMRG_OP_LANCZOS needs the Lanczos options");
+        n = lanczos_call(ctx, nprob, (const idmrg_heff*)desc, q->opts)->lay.total;
+        break;
+      case IDMRG_OP_TRUNCATE:
+        n = trunc_call(ctx, nprob, q->d, q->qp, q->m_max, (const idmrg_trunc*)desc)->lay.total;
+        break;
+      case IDMRG_OP_ENV_LEFT:
+      case IDMRG_OP_ENV_RIGHT:
+        n = env_call(ctx, nprob, op == IDMRG_OP_ENV_LEFT ? IDMRG_LEFT : IDMRG_RIGHT,
+                     (const idmrg_env_update*)desc)->lay.total;
+        break;
+      case IDMRG_OP_PREDICT:
+        n = predict_call(ctx, nprob, q->d, q->qp, (const idmrg_predict*)desc)->lay.total;
+        break;
+      default:
+        throw InvalidArg("unknown operation");
+    }
+    *bytes = std::max<size_t>(n, 256);
+    return IDMRG_OK;
+  });
+}
+
 // ------------------------------------------------------------------ heff_apply
 
 extern "C" int heff_apply(idmrg_ctx* ctx, int nprob, const idmrg_heff* H, const double* const* x, double* const* y,
@@ -730,9 +1288,10 @@ extern "C" int heff_apply(idmrg_ctx* ctx, int nprob, const idmrg_heff* H, const 
       xs[p] = const_cast<double*>(x[p]);
       ys[p] = y[p];
     }
-    HeffExec ex;
-    heff_setup(ctx, ex, nprob, H, xs, ys, prec);
-    heff_run(ctx, ex, xs, ys, nullptr);
+    auto k = heff_call(ctx, nprob, H, prec);
+    char* base = acquire(ctx, k->lay.total);
+    heff_bind(ctx, k->ex, base, H, xs, ys);
+    heff_run(ctx, k->ex, xs, ys, nullptr);
     return IDMRG_OK;
   });
 }
@@ -744,47 +1303,22 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
   return guarded(ctx, [&]() {
     check_nprob(nprob);
     if (!H || !psi || !o || !energy || !info) throw InvalidArg("null argument");
-    if (o->k_max < 1 || o->k_max > kLzMaxK) throw InvalidArg("k_max must be 1..1024");
     if (!(o->tol_E >= 0) || !(o->tol_res >= 0)) throw InvalidArg("tolerances must be >= 0");
-    if (o->prec < 0 || o->prec > 2) throw InvalidArg("unknown precision policy");
     const int P = nprob;
-    const int kmax = o->k_max;
+    auto call = lanczos_call(ctx, P, H, o);
+    LanczosCall& k = *call;
+    const int kmax = k.kmax;
     const int chunk = std::max(1, o->chunk > 0 ? o->chunk : 8);
-    const bool mixed = o->prec != IDMRG_PREC_F64;
+    const bool mixed = k.mixed;
     hipStream_t s = ctx->stream;
-    // sizes first (plan building validates everything)
-    std::vector<int64_t> N(P);
     for (int p = 0; p < P; ++p) {
       if (!psi[p]) throw InvalidArg("null psi");
-      N[p] = psi_layout(make_leg(H[p].left, "left"), make_leg(H[p].right, "right"),
-                        make_mpo(H[p].w1, "w1").qp).size;
-      if (N[p] == 0) throw InvalidArg("empty two-site space");
-      check_dev(psi[p], N[p], 8, "psi");
+      check_dev(psi[p], k.N[p], 8, "psi");
     }
-    // vectors: Q [kcap x N], w, v
-    // every piece is a multiple of kLzAlign elements, so all rows start 2 KiB-aligned
-    // (mixed precision also keeps the normalised start vector s0: the fidelity
-    // of Eq. (12) is taken against the refined state that is returned)
-    std::vector<int64_t> kcap(P), qoff(P), woff(P), voff(P), soff(P), ld(P);
-    int64_t tot = 0;
-    for (int p = 0; p < P; ++p) {
-      kcap[p] = std::min<int64_t>(kmax, N[p]);
-      ld[p] = (N[p] + kLzAlign - 1) / kLzAlign * kLzAlign;
-      qoff[p] = tot;
-      tot += kcap[p] * ld[p];
-      woff[p] = tot;
-      tot += ld[p];
-      voff[p] = tot;
-      tot += ld[p];
-      soff[p] = tot;
-      if (mixed) tot += ld[p];
-    }
-    double* V = (double*)ensure(ctx, ctx->ws[WS_LZ], tot * 8);
+    char* base = acquire(ctx, k.lay.total);
+    double* V = (double*)(base + k.oV);
     const size_t nsm = (size_t)P * kmax;
-    const size_t small_bytes =
-        (size_t)P * (kmax + 1) * kLzBlocks * 8 + 4 * nsm * 8 + P * sizeof(LzCtrl) + P * 4 + 4096;
-    char* sm = (char*)ensure(ctx, ctx->ws[WS_LZSMALL], small_bytes);
-    double* partial = (double*)sm;
+    double* partial = (double*)(base + k.oSmall);
     double* alpha = partial + (size_t)P * kmax * kLzBlocks;
     double* beta = alpha + nsm;
     double* ritz = beta + nsm;
@@ -795,21 +1329,18 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     std::vector<double*> vv(P), ww(P);
     std::vector<LzProblem> probs(P);
     for (int p = 0; p < P; ++p) {
-      vv[p] = V + voff[p];
-      ww[p] = V + woff[p];
-      probs[p] = LzProblem{N[p], ld[p], V + qoff[p], ww[p], vv[p], psi[p], mixed ? V + soff[p] : nullptr};
+      vv[p] = V + k.voff[p];
+      ww[p] = V + k.woff[p];
+      probs[p] = LzProblem{k.N[p], k.ld[p], V + k.qoff[p], ww[p], vv[p], psi[p], mixed ? V + k.soff[p] : nullptr};
     }
-    // The two plans use disjoint scratch buffers (T1, T3, plan), so setting up
-    // the second never reallocates memory that the first has uploaded.
-    HeffExec ex64, exlo;
-    heff_setup(ctx, ex64, P, H, vv, ww, IDMRG_PREC_F64, &ctx->ws[WS_PLAN64]);
-    if (mixed) heff_setup(ctx, exlo, P, H, vv, ww, o->prec, &ctx->ws[WS_PLANLOW]);
-    char* dprob = (char*)ensure(ctx, ctx->ws[WS_MISC], P * (sizeof(LzProblem) + sizeof(LzCtrl) + 4) + 1024);
-    LzProblem* dprobs = (LzProblem*)dprob;
-    LzCtrl* hstage = (LzCtrl*)(dprob + ((P * sizeof(LzProblem) + 255) / 256) * 256);
-    int32_t* astage = (int32_t*)((char*)hstage + ((P * sizeof(LzCtrl) + 255) / 256) * 256);
-    sync(ctx);
-    IDMRG_HIP(hipMemcpy(dprobs, probs.data(), P * sizeof(LzProblem), hipMemcpyHostToDevice));
+    // The two plans use disjoint scratch regions, so binding the second never
+    // touches what the first has uploaded.
+    HeffExec& ex64 = k.ex64;
+    HeffExec& exlo = k.exlo;
+    heff_bind(ctx, ex64, base, H, vv, ww);
+    if (mixed) heff_bind(ctx, exlo, base, H, vv, ww);
+    LzProblem* dprobs = (LzProblem*)(base + k.oProbs);
+    stage(ctx, dprobs, probs.data(), P * sizeof(LzProblem));
 
     // Mixed precision: every outer pass is a Lanczos run whose first matvec is
     // FP64 (so alpha_0 and beta_0 are the exact Rayleigh quotient and residual
@@ -844,21 +1375,18 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
       for (int p = 0; p < P; ++p) {
         LzCtrl z{};
         z.active = going[p];
-        z.kcap = going[p] ? (int32_t)std::min<int64_t>(mixed && outer > 0 ? k_inner : kmax, kcap[p]) : 0;
+        z.kcap = going[p] ? (int32_t)std::min<int64_t>(mixed && outer > 0 ? k_inner : kmax, k.kcap[p]) : 0;
         hctrl[p] = z;
         hact[p] = going[p];
         maxk = std::max<int64_t>(maxk, z.kcap);
       }
-      sync(ctx);
-      IDMRG_HIP(hipMemcpy(hstage, hctrl.data(), P * sizeof(LzCtrl), hipMemcpyHostToDevice));
-      IDMRG_HIP(hipMemcpy(astage, hact.data(), P * 4, hipMemcpyHostToDevice));
-      IDMRG_HIP(hipMemcpyAsync(ctrl, hstage, P * sizeof(LzCtrl), hipMemcpyDeviceToDevice, s));
-      IDMRG_HIP(hipMemcpyAsync(active, astage, P * 4, hipMemcpyDeviceToDevice, s));
+      stage(ctx, ctrl, hctrl.data(), P * sizeof(LzCtrl));
+      stage(ctx, active, hact.data(), P * 4);
       lz_init(P, dprobs, ctrl, partial, kmax, s);
       if (outer == 0) {
         if (mixed)
           for (int p = 0; p < P; ++p)
-            IDMRG_HIP(hipMemcpyAsync(probs[p].s0, vv[p], ld[p] * 8, hipMemcpyDeviceToDevice, s));
+            IDMRG_HIP(hipMemcpyAsync(probs[p].s0, vv[p], k.ld[p] * 8, hipMemcpyDeviceToDevice, s));
         std::vector<LzCtrl> chk(P);
         IDMRG_HIP(hipMemcpyAsync(chk.data(), ctrl, P * sizeof(LzCtrl), hipMemcpyDeviceToHost, s));
         sync(ctx);
@@ -888,13 +1416,13 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
           if (!graphs.ex[key]) {
             const int64_t i0 = it;
             graphs.ex[key] = capture_graph(ctx, [&](hipStream_t cs) {
-              for (int k = 0; k < chunk; ++k) iteration(i0 + k, -1, cs);
+              for (int kk = 0; kk < chunk; ++kk) iteration(i0 + kk, -1, cs);
             });
           }
           IDMRG_HIP(hipGraphLaunch(graphs.ex[key], s));
           it += chunk;
         } else {
-          for (int k = 0; k < chunk && it < maxk; ++k, ++it) {
+          for (int kk = 0; kk < chunk && it < maxk; ++kk, ++it) {
             HeffExec& e = (!mixed || it == 0) ? ex64 : exlo;
             const int trial = (!tuned && &e == &bulk && trial_next < bulk.nvar) ? trial_next++ : -1;
             iteration(it, trial, s);
@@ -961,6 +1489,7 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     return rc;
   });
 }
+
 // ------------------------------------------------------------------ truncate_twosite
 
 extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp_in, int32_t m_max,
@@ -968,143 +1497,59 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
   return guarded(ctx, [&]() {
     check_nprob(nprob);
     if (!t || m_max < 1 || !(lam_floor >= 0) || !(deg_rel >= 0)) throw InvalidArg("bad truncation arguments");
-    const std::vector<int> qp = make_qp(d, qp_in);
     const int P = nprob;
-    hipStream_t s = ctx->stream;
-    struct Sec { int q, r, c; std::vector<std::tuple<int, int, int>> rows, cols; int64_t m, x, g, u, v, sv; };
-    std::vector<std::vector<Sec>> secs(P);
-    std::vector<Leg> A(P), B(P);
-    std::vector<PsiLayout> X(P);
-    int64_t nM = 0, nX = 0, nG = 0, nU = 0, nV = 0, nS = 0;
-    int svd_sweeps = 0, svd_conv = 1;
-    std::vector<int32_t> completed(P, 1);
-    MixList gather;
-    std::vector<SvdTask> svd;
-    std::vector<SelTask> sel;
-    std::vector<SelSector> ssec;
-    int ncand_tot = 0;
-    for (int p = 0; p < P; ++p) {
+    for (int p = 0; p < P; ++p)
       if (!t[p].psi) throw InvalidArg("null psi");
-      A[p] = make_leg(t[p].left, "trunc.left");
-      B[p] = make_leg(t[p].right, "trunc.right");
-      X[p] = psi_layout(A[p], B[p], qp);
-      std::map<int, Sec> byq;
-      for (int a = 0; a < A[p].n(); ++a)
-        for (int s1 = 0; s1 < d; ++s1) {
-          Sec& S = byq[A[p].q[a] + qp[s1]];
-          S.rows.emplace_back(a, s1, S.r);
-          S.r += A[p].dim[a];
-        }
-      for (int s2 = 0; s2 < d; ++s2)
-        for (int b = 0; b < B[p].n(); ++b) {
-          Sec& S = byq[B[p].q[b] - qp[s2]];
-          S.cols.emplace_back(s2, b, S.c);
-          S.c += B[p].dim[b];
-        }
-      SelTask st{};
-      st.sec0 = (int)ssec.size();
-      st.cand0 = ncand_tot;
-      st.m_max = m_max;
-      st.prob = p;
+    auto call = trunc_call(ctx, P, d, qp_in, m_max, t);
+    TruncCall& k = *call;
+    hipStream_t s = ctx->stream;
+    for (int p = 0; p < P; ++p) check_dev(t[p].psi, k.X[p].size, 8, "psi");
+    std::vector<SelTask> sel = k.sel;   // the floor and the guard are arguments of the call, not of the plan
+    for (auto& st : sel) {
       st.lam_floor = lam_floor;
       st.deg_rel = deg_rel;
-      for (auto& kv : byq) {
-        Sec S = kv.second;
-        S.q = kv.first;
-        if (S.r == 0 || S.c == 0) continue;
-        const int n = std::min(S.r, S.c), pp = std::max(S.r, S.c);
-        if (n > 4096 || pp > 8192)
-          throw InvalidArg("centre sector larger than 4096 x 8192 states is not supported");
-        S.m = nM; nM += (int64_t)S.r * S.c;
-        S.x = nX; nX += (int64_t)n * pp;
-        S.g = nG; nG += (int64_t)n * n;
-        S.u = nU; nU += (int64_t)S.r * n;
-        S.v = nV; nV += (int64_t)S.c * n;
-        S.sv = nS; nS += n;
-        for (auto& rw : S.rows)
-          for (auto& cl : S.cols) {
-            const int a = std::get<0>(rw), s1 = std::get<1>(rw), ro = std::get<2>(rw);
-            const int s2 = std::get<0>(cl), b = std::get<1>(cl), co = std::get<2>(cl);
-            const int xi = X[p].find(a, s1, s2);
-            if (xi < 0 || X[p].blk[xi].b != b) throw InvalidArg("internal: truncation block bookkeeping");
-            MixTask m{};
-            m.rows = A[p].dim[a]; m.cols = B[p].dim[b]; m.ldd = S.c; m.prob = p; m.dbase = 1;
-            m.doff = S.m + (int64_t)ro * S.c + co;
-            MixSrc sr{};
-            sr.coef = 1.0; sr.base = 0; sr.off = X[p].blk[xi].off; sr.ld = B[p].dim[b];
-            gather.add(m, {sr});
-          }
-        SvdTask sv{};
-        sv.r = S.r; sv.c = S.c; sv.prob = p;
-        sv.m_off = S.m; sv.x_off = S.x; sv.g_off = S.g; sv.u_off = S.u; sv.v_off = S.v; sv.s_off = S.sv;
-        svd.push_back(sv);
-        SelSector se{};
-        se.charge = S.q; se.n = n; se.cand0 = ncand_tot; se.s_off = S.sv;
-        ssec.push_back(se);
-        ncand_tot += n;
-        st.ncand += n;
-        st.nsec += 1;
-        secs[p].push_back(S);
-      }
-      if (st.ncand > 8192) throw InvalidArg("more than 8192 singular values per problem is not supported");
-      if (st.ncand == 0) throw InvalidArg("two-site state has no centre sector");
-      sel.push_back(st);
     }
-    // S values of all problems live in one array: make s_off global
-    // (each problem's sectors were given offsets into its own region; regions are disjoint)
-    char* ws = (char*)ensure(ctx, ctx->ws[WS_SVD], (nM + nX + nG + nU + nV + nS + 6 * 64) * 8);
-    double* dM = (double*)ws;
-    double* dX = dM + nM + 64;
-    double* dG = dX + nX + 64;
-    double* dU = dG + nG + 64;
-    double* dV = dU + nU + 64;
-    double* dS = dV + nV + 64;
-    const size_t selb = (size_t)ncand_tot * (4 + 8) + ssec.size() * 4 + P * 32 + 4096;
-    char* sw = (char*)ensure(ctx, ctx->ws[WS_SEL], selb);
+    k.pk.patch(k.a4, sel);
+    char* base = acquire(ctx, k.lay.total);
+    double* dM = (double*)(base + k.oSvd);
+    double* dX = dM + k.nM + 64;
+    double* dG = dX + k.nX + 64;
+    double* dU = dG + k.nG + 64;
+    double* dV = dU + k.nU + 64;
+    double* dS = dV + k.nV + 64;
+    const int64_t nS = k.nS;
+    char* sw = base + k.oSel;
     int32_t* colmap = (int32_t*)sw;
-    double* lam_sel = (double*)(sw + ((size_t)ncand_tot * 4 + 255) / 256 * 256);
-    int32_t* kept = (int32_t*)((char*)lam_sel + ((size_t)ncand_tot * 8 + 255) / 256 * 256);
-    double* scal = (double*)((char*)kept + (ssec.size() * 4 + 255) / 256 * 256);
-    {
-      std::vector<int64_t> sz((size_t)P * kNumBases, -1);
-      for (int p = 0; p < P; ++p) {
-        sz[(size_t)p * kNumBases + 0] = X[p].size;
-        sz[(size_t)p * kNumBases + 1] = nM;
-        check_dev(t[p].psi, X[p].size, 8, "psi");
-      }
-      check_mix(gather, sz, "truncation gather");
-    }
+    double* lam_sel = (double*)(sw + ((size_t)k.ncand_tot * 4 + 255) / 256 * 256);
+    int32_t* kept = (int32_t*)((char*)lam_sel + ((size_t)k.ncand_tot * 8 + 255) / 256 * 256);
+    double* scal = (double*)((char*)kept + (k.ssec.size() * 4 + 255) / 256 * 256);
     std::vector<void*> hb((size_t)P * kNumBases, nullptr);
     for (int p = 0; p < P; ++p) {
       void** b = &hb[(size_t)p * kNumBases];
       b[0] = (void*)t[p].psi; b[1] = dM; b[2] = dX; b[3] = dG; b[4] = dU; b[5] = dV; b[6] = dS;
     }
-    std::vector<int32_t> sweeps(svd.size(), 0);
-    Packer pk;
-    const size_t a1 = pk.add(gather.t), a2 = pk.add(gather.src), a3 = pk.add(svd), a4 = pk.add(sel),
-                 a5 = pk.add(ssec), a6 = pk.add(hb), a7 = pk.add(sweeps);
-    char* dev = upload(ctx, pk);
+    k.pk.patch(k.a6, hb);
+    char* dev = base + k.oPlan;
+    stage(ctx, dev, k.pk.host.data(), k.pk.host.size());
+    int svd_sweeps = 0, svd_conv = 1;
+    std::vector<int32_t> completed(P, 1);
+    int32_t* dflag = (int32_t*)(base + k.oFlag);
     {
       Prof pr(ctx, 6, 0.0);
-      launch_mix(0, 0, (MixTask*)(dev + a1), (MixSrc*)(dev + a2), (int)gather.t.size(), gather.tiles,
-                 (void**)(dev + a6), nullptr, s);
+      launch_mix(0, 0, (MixTask*)(dev + k.a1), (MixSrc*)(dev + k.a2), (int)k.gather.t.size(), k.gather.tiles,
+                 (void**)(dev + k.a6), nullptr, s);
+      // non-finite input is reported, not decomposed (the Jacobi norms would hide it)
+      IDMRG_HIP(hipMemsetAsync(dflag, 0, 4, s));
+      launch_check_finite(dM, k.nM, dflag, s);
     }
     {
       Prof pr(ctx, 5, 0.0);
       BjScratch scr;
-      int pmax = 1;
-      for (const auto& sv : svd) pmax = std::max(pmax, std::max(sv.r, sv.c));
-      scr.tol = std::max(1e-15, 4.4e-16 * std::sqrt((double)pmax));
+      scr.tol = std::max(1e-15, 4.4e-16 * std::sqrt((double)k.pmax));
       // null rows: at most 1e-15 .. 1e-14 of their block's norm (rounding residue); never
       // above lam_floor, so that a null row never ranks as a nonzero value unless lam_floor
       // itself is below 1e-15
       scr.zero_rel = std::min(std::max(lam_floor, 1e-15), 1e-14);
-      auto up = [&](const std::vector<char>& h) -> char* {
-        char* d = (char*)ensure(ctx, ctx->ws[WS_READ], h.size());
-        sync(ctx);
-        IDMRG_HIP(hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice));
-        return d;
-      };
       // Null rows (sigma <= zero_rel |M_q|_F) need a completed direction only if the
       // selection can keep one.  Zero-weight states are kept only when every candidate is
       // (m_max >= candidates); otherwise a null row is kept only if it ranks as a nonzero
@@ -1117,13 +1562,13 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
         sync(ctx);
         std::vector<double> tot(P, 0.0);
         std::vector<int64_t> cand(P, 0), above(P, 0);
-        for (const auto& sv : svd) {
+        for (const auto& sv : k.svd) {
           const int n = std::min(sv.r, sv.c);
           cand[sv.prob] += n;
           for (int i = 0; i < n; ++i) tot[sv.prob] += hS[sv.s_off + i] * hS[sv.s_off + i];
         }
         const double thr = scr.zero_rel * (1.0 + 1e-9);
-        for (const auto& sv : svd) {
+        for (const auto& sv : k.svd) {
           const int n = std::min(sv.r, sv.c);
           const double cut = thr * std::sqrt(tot[sv.prob]);
           for (int i = 0; i < n; ++i) above[sv.prob] += hS[sv.s_off + i] > cut;
@@ -1134,25 +1579,32 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
           completed[pr] = !(tot[pr] > 0.0 && (all_kept ? above[pr] >= cand[pr]
                                                        : (!null_may_rank || above[pr] >= m_max)));
         }
-        for (size_t m = 0; m < svd.size(); ++m) complete[m] = completed[svd[m].prob];
+        for (size_t m = 0; m < k.svd.size(); ++m) complete[m] = completed[k.svd[m].prob];
       };
-      bj_svd(svd, (void**)(dev + a6), (SvdTask*)(dev + a3), scr, s, up,
-             [&](size_t b) { return (char*)ensure(ctx, ctx->ws[WS_BJ], b); }, [&]() { sync(ctx); });
-      (void)a7;
+      char* bjdev = base + k.oBjPlan;
+      stage(ctx, bjdev, k.bj.host.data(), k.bj.host.size());
+      bj_svd(k.bj, (void**)(dev + k.a6), (SvdTask*)(dev + k.a3), scr, s, bjdev, base + k.oBjWork,
+             [&]() { sync(ctx); });
       svd_sweeps = scr.sweeps;
       svd_conv = scr.converged;
     }
     {
       Prof pr(ctx, 6, 0.0);
-      launch_select((SelTask*)(dev + a4), (int)sel.size(), (SelSector*)(dev + a5), dS, kept, colmap, lam_sel, scal,
-                    s);
+      launch_select((SelTask*)(dev + k.a4), (int)sel.size(), (SelSector*)(dev + k.a5), dS, kept, colmap, lam_sel,
+                    scal, s);
     }
     IDMRG_HIP(hipGetLastError());
-    std::vector<int32_t> hkept(ssec.size());
+    std::vector<int32_t> hkept(k.ssec.size());
     std::vector<double> hscal(4 * (size_t)P);
+    int32_t hflag = 0;
     IDMRG_HIP(hipMemcpyAsync(hkept.data(), kept, hkept.size() * 4, hipMemcpyDeviceToHost, s));
     IDMRG_HIP(hipMemcpyAsync(hscal.data(), scal, hscal.size() * 8, hipMemcpyDeviceToHost, s));
+    IDMRG_HIP(hipMemcpyAsync(&hflag, dflag, 4, hipMemcpyDeviceToHost, s));
     sync(ctx);
+    if (hflag) {
+      ctx->err = "the two-site state holds NaN or infinite values";
+      return IDMRG_ENUMERIC;
+    }
     // outputs
     ScaleList outl;
     std::vector<void*> ob((size_t)P * kNumBases, nullptr);
@@ -1160,14 +1612,14 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
       const SelTask& st = sel[p];
       Leg C;
       std::vector<int> which;
-      for (int k = 0; k < st.nsec; ++k)
-        if (hkept[st.sec0 + k] > 0) {
-          C.q.push_back(ssec[st.sec0 + k].charge);
-          C.dim.push_back(hkept[st.sec0 + k]);
-          which.push_back(k);
+      for (int q = 0; q < st.nsec; ++q)
+        if (hkept[st.sec0 + q] > 0) {
+          C.q.push_back(k.ssec[st.sec0 + q].charge);
+          C.dim.push_back(hkept[st.sec0 + q]);
+          which.push_back(q);
         }
       if (C.n() > t[p].cap_sec || !t[p].q_out || !t[p].dim_out) throw InvalidArg("new-leg capacity too small");
-      const IsoLayout U = U_layout(A[p], qp, C), Vl = V_layout(B[p], qp, C);
+      const IsoLayout U = U_layout(k.A[p], k.qp, C), Vl = V_layout(k.B[p], k.qp, C);
       if (U.size > t[p].cap_U || Vl.size > t[p].cap_V || C.total() > t[p].cap_lam)
         throw InvalidArg("output capacity too small (U, V or lambda)");
       if (!t[p].U || !t[p].V || !t[p].lambda) throw InvalidArg("null output buffer");
@@ -1175,24 +1627,24 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
       b[0] = dU; b[1] = dV; b[2] = lam_sel; b[3] = t[p].U; b[4] = t[p].V; b[5] = t[p].lambda;
       int64_t loff = 0;
       for (int ci = 0; ci < C.n(); ++ci) {
-        const Sec& S = secs[p][which[ci]];
-        const SelSector& se = ssec[st.sec0 + which[ci]];
-        const int n = se.n, k = C.dim[ci];
+        const TruncSec& S = k.secs[p][which[ci]];
+        const SelSector& se = k.ssec[st.sec0 + which[ci]];
+        const int n = se.n, kk = C.dim[ci];
         if (U.rows[ci] != S.r || Vl.rows[ci] != S.c) throw InvalidArg("internal: isometry row mismatch");
         ScaleTask a{};
-        a.rows = S.r; a.cols = k; a.lds = n; a.ldd = k; a.prob = p; a.sbase = 0; a.dbase = 3; a.rbase = -1;
+        a.rows = S.r; a.cols = kk; a.lds = n; a.ldd = kk; a.prob = p; a.sbase = 0; a.dbase = 3; a.rbase = -1;
         a.cbase = -1; a.colmap = se.cand0; a.soff = S.u; a.doff = U.off[ci];
         outl.add(a);
         ScaleTask v = a;
         v.rows = S.c; v.sbase = 1; v.dbase = 4; v.soff = S.v; v.doff = Vl.off[ci];
         outl.add(v);
         ScaleTask l{};
-        l.rows = 1; l.cols = k; l.lds = k; l.ldd = k; l.prob = p; l.sbase = 2; l.dbase = 5; l.rbase = -1;
+        l.rows = 1; l.cols = kk; l.lds = kk; l.ldd = kk; l.prob = p; l.sbase = 2; l.dbase = 5; l.rbase = -1;
         l.cbase = -1; l.colmap = -1; l.soff = se.cand0; l.doff = loff;
         outl.add(l);
-        loff += k;
+        loff += kk;
         t[p].q_out[ci] = C.q[ci];
-        t[p].dim_out[ci] = k;
+        t[p].dim_out[ci] = kk;
       }
       t[p].nsec_out = C.n();
       t[p].eps = hscal[4 * p + 0];
@@ -1208,16 +1660,18 @@ extern "C" int truncate_twosite(idmrg_ctx* ctx, int nprob, int32_t d, const int3
       std::vector<int64_t> sz((size_t)P * kNumBases, -1);
       for (int p = 0; p < P; ++p) {
         int64_t* z = &sz[(size_t)p * kNumBases];
-        z[0] = nU; z[1] = nV; z[2] = ncand_tot; z[3] = t[p].cap_U; z[4] = t[p].cap_V; z[5] = t[p].cap_lam;
+        z[0] = k.nU; z[1] = k.nV; z[2] = k.ncand_tot; z[3] = t[p].cap_U; z[4] = t[p].cap_V; z[5] = t[p].cap_lam;
         check_dev(t[p].U, t[p].cap_U, 8, "U");
         check_dev(t[p].V, t[p].cap_V, 8, "V");
         check_dev(t[p].lambda, t[p].cap_lam, 8, "lambda");
       }
-      check_scale(outl, sz, "truncation output", ncand_tot);
+      check_scale(outl, sz, "truncation output", k.ncand_tot);
     }
     Packer pk2;
     const size_t b1 = pk2.add(outl.t), b2 = pk2.add(ob);
-    char* dev2 = upload(ctx, pk2);
+    if (pk2.host.size() > k.outBytes) throw InvalidArg("internal: output plan larger than reserved");
+    char* dev2 = base + k.oOut;
+    stage(ctx, dev2, pk2.host.data(), pk2.host.size());
     {
       Prof pr(ctx, 6, 0.0);
       launch_scale((ScaleTask*)(dev2 + b1), colmap, (int)outl.t.size(), outl.tiles, 0.0, (void**)(dev2 + b2), s);
@@ -1244,54 +1698,36 @@ extern "C" int update_env(idmrg_ctx* ctx, int nprob, int side, const idmrg_env_u
     check_nprob(nprob);
     if (!u || (side != IDMRG_LEFT && side != IDMRG_RIGHT)) throw InvalidArg("bad update_env arguments");
     const int P = nprob;
-    EnvPlan plan;
-    std::vector<int64_t> sz((size_t)P * kNumBases, -1);
-    for (int p = 0; p < P; ++p) {
+    for (int p = 0; p < P; ++p)
       if (!u[p].env_old || !u[p].iso || !u[p].env_new) throw InvalidArg("null buffer in idmrg_env_update");
-      const Leg O = make_leg(u[p].old_leg, "env.old_leg"), C = make_leg(u[p].new_leg, "env.new_leg");
-      const Mpo W = make_mpo(u[p].w, "env.w");
-      int64_t* z = &sz[(size_t)p * kNumBases];
-      if (side == IDMRG_LEFT) {
-        build_envL(plan, p, O, C, W);
-        z[0] = envL_layout(O, W.ql).size; z[1] = U_layout(O, W.qp, C).size; z[2] = envL_layout(C, W.qr).size;
-      } else {
-        build_envR(plan, p, O, C, W);
-        z[0] = envR_layout(O, W.qr).size; z[1] = V_layout(O, W.qp, C).size; z[2] = envR_layout(C, W.ql).size;
-      }
-      z[3] = plan.n_T1[p]; z[4] = plan.n_T2[p];
+    auto call = env_call(ctx, P, side, u);
+    EnvCall& k = *call;
+    for (int p = 0; p < P; ++p) {
+      const int64_t* z = &k.sz[(size_t)p * kNumBases];
       check_dev(u[p].env_old, z[0], 8, "env_old");
       check_dev(u[p].iso, z[1], 8, "iso");
       check_dev(u[p].env_new, z[2], 8, "env_new");
     }
-    check_gemm(plan.ga, side == IDMRG_LEFT ? 0 : 2, sz, "env stage a");
-    check_mix(plan.mix, sz, "env mix");
-    check_gemm(plan.gc, side == IDMRG_LEFT ? 2 : 0, sz, "env stage c");
-    int64_t n1 = 0, n2 = 0;
-    std::vector<int64_t> o1(P), o2(P);
-    for (int p = 0; p < P; ++p) {
-      o1[p] = n1; n1 += plan.n_T1[p] + 64;
-      o2[p] = n2; n2 += plan.n_T2[p] + 64;
-    }
-    double* ws = (double*)ensure(ctx, ctx->ws[WS_ENV], (n1 + n2) * 8);
+    char* base = acquire(ctx, k.lay.total);
+    double* ws = (double*)(base + k.oT);
     std::vector<void*> hb((size_t)P * kNumBases, nullptr);
     for (int p = 0; p < P; ++p) {
       void** b = &hb[(size_t)p * kNumBases];
       b[0] = (void*)u[p].env_old; b[1] = (void*)u[p].iso; b[2] = u[p].env_new;
-      b[3] = ws + o1[p]; b[4] = ws + n1 + o2[p];
+      b[3] = ws + k.o1[p]; b[4] = ws + k.n1 + k.o2[p];
     }
-    Packer pk;
-    const size_t a1 = pk.add(plan.ga.t), a2 = pk.add(plan.mix.t), a3 = pk.add(plan.mix.src), a4 = pk.add(plan.gc.t),
-                 a5 = pk.add(hb);
-    char* dev = upload(ctx, pk);
-    void** bases = (void**)(dev + a5);
+    k.pk.patch(k.a5, hb);
+    char* dev = base + k.oPlan;
+    stage(ctx, dev, k.pk.host.data(), k.pk.host.size());
+    void** bases = (void**)(dev + k.a5);
     hipStream_t s = ctx->stream;
-    Prof pr(ctx, 7, plan.ga.flops() + plan.gc.flops() + plan.mix.flops());
-    launch_gemm(Prec::F64, side == IDMRG_LEFT ? 0 : 2, (GemmTask*)(dev + a1), (int)plan.ga.t.size(), plan.ga.tiles,
-                bases, nullptr, s);
-    launch_mix(0, 0, (MixTask*)(dev + a2), (MixSrc*)(dev + a3), (int)plan.mix.t.size(), plan.mix.tiles, bases,
-               nullptr, s);
-    launch_gemm(Prec::F64, side == IDMRG_LEFT ? 2 : 0, (GemmTask*)(dev + a4), (int)plan.gc.t.size(), plan.gc.tiles,
-                bases, nullptr, s);
+    Prof pr(ctx, 7, k.plan.ga.flops() + k.plan.gc.flops() + k.plan.mix.flops());
+    launch_gemm(Prec::F64, side == IDMRG_LEFT ? 0 : 2, (GemmTask*)(dev + k.a1), (int)k.plan.ga.t.size(),
+                k.plan.ga.tiles, bases, nullptr, s);
+    launch_mix(0, 0, (MixTask*)(dev + k.a2), (MixSrc*)(dev + k.a3), (int)k.plan.mix.t.size(), k.plan.mix.tiles,
+               bases, nullptr, s);
+    launch_gemm(Prec::F64, side == IDMRG_LEFT ? 2 : 0, (GemmTask*)(dev + k.a4), (int)k.plan.gc.t.size(),
+                k.plan.gc.tiles, bases, nullptr, s);
     IDMRG_HIP(hipGetLastError());
     return IDMRG_OK;
   });
@@ -1304,19 +1740,14 @@ extern "C" int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const 
   return guarded(ctx, [&]() {
     check_nprob(nprob);
     if (!pr || !(lam_floor >= 0)) throw InvalidArg("bad predict arguments");
-    const std::vector<int> qp = make_qp(d, qp_in);
     const int P = nprob;
-    PredictPlan plan;
-    std::vector<int64_t> sz((size_t)P * kNumBases, -1);
-    for (int p = 0; p < P; ++p) {
+    for (int p = 0; p < P; ++p)
       if (!pr[p].lam_i || !pr[p].V_i || !pr[p].lam_prev || !pr[p].U_ip1 || !pr[p].lam_ip1 || !pr[p].psi)
         throw InvalidArg("null buffer in idmrg_predict");
-      const Leg Aa = make_leg(pr[p].leg_a, "leg_a"), Bt = make_leg(pr[p].leg_beta, "leg_beta"),
-                Bb = make_leg(pr[p].leg_b, "leg_b");
-      build_predict(plan, p, Aa, Bt, Bb, qp);
-      int64_t* z = &sz[(size_t)p * kNumBases];
-      z[0] = Aa.total(); z[1] = z[6] = V_layout(Bt, qp, Aa).size; z[2] = Bt.total();
-      z[3] = z[7] = U_layout(Bt, qp, Bb).size; z[4] = Bb.total(); z[5] = psi_layout(Aa, Bb, qp).size;
+    auto call = predict_call(ctx, P, d, qp_in, pr);
+    PredictCall& k = *call;
+    for (int p = 0; p < P; ++p) {
+      const int64_t* z = &k.sz[(size_t)p * kNumBases];
       check_dev(pr[p].lam_i, z[0], 8, "lam_i");
       check_dev(pr[p].V_i, z[1], 8, "V_i");
       check_dev(pr[p].lam_prev, z[2], 8, "lam_prev");
@@ -1324,29 +1755,23 @@ extern "C" int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const 
       check_dev(pr[p].lam_ip1, z[4], 8, "lam_ip1");
       check_dev(pr[p].psi, z[5], 8, "psi");
     }
-    check_scale(plan.scale, sz, "predict scale", 0);
-    check_gemm(plan.g, 2, sz, "predict gemm");
-    int64_t n = 0;
-    std::vector<int64_t> ov(P), ou(P);
-    for (int p = 0; p < P; ++p) {
-      ov[p] = n; n += plan.n_Vs[p] + 64;
-      ou[p] = n; n += plan.n_Us[p] + 64;
-    }
-    double* ws = (double*)ensure(ctx, ctx->ws[WS_PRED], n * 8);
+    char* base = acquire(ctx, k.lay.total);
+    double* ws = (double*)(base + k.oW);
     std::vector<void*> hb((size_t)P * kNumBases, nullptr);
     for (int p = 0; p < P; ++p) {
       void** b = &hb[(size_t)p * kNumBases];
       b[0] = (void*)pr[p].lam_i; b[1] = (void*)pr[p].V_i; b[2] = (void*)pr[p].lam_prev; b[3] = (void*)pr[p].U_ip1;
-      b[4] = (void*)pr[p].lam_ip1; b[5] = pr[p].psi; b[6] = ws + ov[p]; b[7] = ws + ou[p];
+      b[4] = (void*)pr[p].lam_ip1; b[5] = pr[p].psi; b[6] = ws + k.ov[p]; b[7] = ws + k.ou[p];
     }
-    Packer pk;
-    const size_t a1 = pk.add(plan.scale.t), a2 = pk.add(plan.g.t), a3 = pk.add(hb);
-    char* dev = upload(ctx, pk);
-    void** bases = (void**)(dev + a3);
-    Prof pr(ctx, 8, plan.g.flops());
-    launch_scale((ScaleTask*)(dev + a1), nullptr, (int)plan.scale.t.size(), plan.scale.tiles, lam_floor, bases,
+    k.pk.patch(k.a3, hb);
+    char* dev = base + k.oPlan;
+    stage(ctx, dev, k.pk.host.data(), k.pk.host.size());
+    void** bases = (void**)(dev + k.a3);
+    Prof prf(ctx, 8, k.plan.g.flops());
+    launch_scale((ScaleTask*)(dev + k.a1), nullptr, (int)k.plan.scale.t.size(), k.plan.scale.tiles, lam_floor, bases,
                  ctx->stream);
-    launch_gemm(Prec::F64, 2, (GemmTask*)(dev + a2), (int)plan.g.t.size(), plan.g.tiles, bases, nullptr, ctx->stream);
+    launch_gemm(Prec::F64, 2, (GemmTask*)(dev + k.a2), (int)k.plan.g.t.size(), k.plan.g.tiles, bases, nullptr,
+                ctx->stream);
     IDMRG_HIP(hipGetLastError());
     return IDMRG_OK;
   });

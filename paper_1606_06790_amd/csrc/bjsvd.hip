@@ -642,10 +642,10 @@ __global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ 
 
 }  // namespace
 
-void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask* dtasks, BjScratch& scr,
-            hipStream_t s, const std::function<char*(const std::vector<char>&)>& upload,
-            const std::function<char*(size_t)>& scratch, const std::function<void()>& sync) {
+void bj_prepare(const std::vector<SvdTask>& svd, BjPlan& plan) {
   const int nm = (int)svd.size();
+  plan = BjPlan{};
+  plan.nm = nm;
   if (nm == 0) return;
   std::vector<BjMat> mats(nm);
   struct Round {
@@ -677,56 +677,72 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
       }
     }
   }
-  std::vector<char> host;
+  std::vector<char>& host = plan.host;
   auto put = [&](const void* p, size_t bytes) {
     const size_t off = (host.size() + 255) / 256 * 256;
     host.resize(off + std::max<size_t>(bytes, 8));
     if (bytes) std::memcpy(host.data() + off, p, bytes);
     return off;
   };
-  const size_t omats = put(mats.data(), mats.size() * sizeof(BjMat));
-  std::vector<size_t> opair(rounds.size()), ogram(rounds.size()), oapply(rounds.size());
+  plan.omats = put(mats.data(), mats.size() * sizeof(BjMat));
+  const size_t nr = rounds.size();
+  plan.opair.resize(nr);
+  plan.ogram.resize(nr);
+  plan.oapply.resize(nr);
+  plan.npair.resize(nr);
+  plan.ngram.resize(nr);
+  plan.napply.resize(nr);
   size_t max_pairs = 0, max_gram = 0;
-  for (size_t r = 0; r < rounds.size(); ++r) {
-    opair[r] = put(rounds[r].pairs.data(), rounds[r].pairs.size() * sizeof(BjPair));
-    ogram[r] = put(rounds[r].gram.data(), rounds[r].gram.size() * sizeof(BjItem));
-    oapply[r] = put(rounds[r].apply.data(), rounds[r].apply.size() * sizeof(BjItem));
+  for (size_t r = 0; r < nr; ++r) {
+    plan.opair[r] = put(rounds[r].pairs.data(), rounds[r].pairs.size() * sizeof(BjPair));
+    plan.ogram[r] = put(rounds[r].gram.data(), rounds[r].gram.size() * sizeof(BjItem));
+    plan.oapply[r] = put(rounds[r].apply.data(), rounds[r].apply.size() * sizeof(BjItem));
+    plan.npair[r] = (int)rounds[r].pairs.size();
+    plan.ngram[r] = (int)rounds[r].gram.size();
+    plan.napply[r] = (int)rounds[r].apply.size();
     max_pairs = std::max(max_pairs, rounds[r].pairs.size());
     max_gram = std::max(max_gram, rounds[r].gram.size());
   }
   std::vector<int32_t> zeros(2 * (size_t)nm, 0);
-  const size_t oflags = put(zeros.data(), zeros.size() * 4);
+  plan.oflags = put(zeros.data(), zeros.size() * 4);
   std::vector<double> zthr(nm, 0.0);
-  const size_t othr = put(zthr.data(), zthr.size() * 8);
+  plan.othr = put(zthr.data(), zthr.size() * 8);
   std::vector<int32_t> complete(nm, 1);
-  const size_t ocomp = put(complete.data(), complete.size() * 4);
+  plan.ocomp = put(complete.data(), complete.size() * 4);
   // per round: partial Gram matrices, rotations, move flags (reused by every round)
   const size_t tile = (size_t)PB * PB * sizeof(double);
-  const size_t b_partial = max_gram * tile, b_q = max_pairs * tile;
-  char* work = scratch(b_partial + b_q + max_pairs * 4 + 256);
+  plan.b_partial = max_gram * tile;
+  plan.b_q = max_pairs * tile;
+  plan.scratch = plan.b_partial + plan.b_q + max_pairs * 4 + 256;
+}
+
+void bj_svd(const BjPlan& plan, void* const* dbases, const SvdTask* dtasks, BjScratch& scr, hipStream_t s,
+            const char* dev, char* work, const std::function<void()>& sync) {
+  const int nm = plan.nm;
+  if (nm == 0) return;
   double* partial = (double*)work;
-  double* Qs = (double*)(work + b_partial);
-  int32_t* move = (int32_t*)(work + b_partial + b_q);
-  char* dev = upload(host);
-  const BjMat* dmats = (const BjMat*)(dev + omats);
-  int32_t* done = (int32_t*)(dev + oflags);
+  double* Qs = (double*)(work + plan.b_partial);
+  int32_t* move = (int32_t*)(work + plan.b_partial + plan.b_q);
+  const BjMat* dmats = (const BjMat*)(dev + plan.omats);
+  int32_t* done = (int32_t*)(dev + plan.oflags);
   int32_t* changed = done + nm;
-  double* thr2 = (double*)(dev + othr);
+  double* thr2 = (double*)(dev + plan.othr);
   hipLaunchKernelGGL(k_bj_init, dim3(nm), dim3(256), 0, s, dtasks, dbases, thr2, scr.zero_rel);
   std::vector<int32_t> hdone(nm);
   int sweeps = 0;
   scr.converged = 0;
   scr.done_at.assign(nm, -1);
+  const size_t nr = plan.opair.size();
   for (; sweeps < scr.max_sweeps; ++sweeps) {
-    for (size_t r = 0; r < rounds.size(); ++r) {
-      const BjPair* pr = (const BjPair*)(dev + opair[r]);
-      hipLaunchKernelGGL(k_bj_gram, dim3((unsigned)rounds[r].gram.size()), dim3(256), 0, s,
-                         (const BjItem*)(dev + ogram[r]), pr, dmats, dbases, (const int32_t*)done, partial);
-      hipLaunchKernelGGL(k_bj_rotate, dim3((unsigned)rounds[r].pairs.size()), dim3(256), 0, s, pr, dmats,
+    for (size_t r = 0; r < nr; ++r) {
+      const BjPair* pr = (const BjPair*)(dev + plan.opair[r]);
+      hipLaunchKernelGGL(k_bj_gram, dim3((unsigned)plan.ngram[r]), dim3(256), 0, s,
+                         (const BjItem*)(dev + plan.ogram[r]), pr, dmats, dbases, (const int32_t*)done, partial);
+      hipLaunchKernelGGL(k_bj_rotate, dim3((unsigned)plan.npair[r]), dim3(256), 0, s, pr, dmats,
                          (const int32_t*)done, changed, (const double*)thr2, (const double*)partial, Qs, move,
                          scr.tol, scr.inner_sweeps);
-      hipLaunchKernelGGL(k_bj_apply, dim3((unsigned)rounds[r].apply.size()), dim3(256), 0, s,
-                         (const BjItem*)(dev + oapply[r]), pr, dmats, dbases, (const int32_t*)done,
+      hipLaunchKernelGGL(k_bj_apply, dim3((unsigned)plan.napply[r]), dim3(256), 0, s,
+                         (const BjItem*)(dev + plan.oapply[r]), pr, dmats, dbases, (const int32_t*)done,
                          (const double*)Qs, (const int32_t*)move);
     }
     hipLaunchKernelGGL(k_bj_sweep_end, dim3((nm + 255) / 256), dim3(256), 0, s, nm, done, changed);
@@ -741,7 +757,8 @@ void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask*
     }
   }
   scr.sweeps = std::min(sweeps + 1, scr.max_sweeps);
-  int32_t* dcomp = (int32_t*)(dev + ocomp);
+  int32_t* dcomp = (int32_t*)(dev + plan.ocomp);
+  std::vector<int32_t> complete(nm, 1);
   if (scr.need_completion) {
     hipLaunchKernelGGL(k_bj_sigma, dim3(nm), dim3(1024), 0, s, dtasks, dbases);
     scr.need_completion(complete);

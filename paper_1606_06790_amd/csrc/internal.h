@@ -78,7 +78,8 @@ constexpr int kFragRows = 16, kFragK = 32, kFragWords = 512;
 // written whole for rows 0 .. 16 RB - 1, with zeros outside [R x K] (K = 0
 // writes zeros only).  kc0 is a multiple of 8.  hi = bf16(float(z)),
 // lo = bf16(float(z) - hi), both rounded to nearest even.  The elements
-// Z(dr0 + i, dk0 + i), i < dlen, are packed as Z - shift (a diagonal shift).
+// Z(dr0 + i, dk0 + i), i < dlen, are packed as Z - sig[shift_slot] (a diagonal
+// shift; sig is a device array [problem][2] of the left and right shifts).
 // If xbase >= 0 the source block is also written as FP32 in its own
 // orientation, row-padded: source element at (row i, column j) of the stored
 // matrix goes to xoff + i * xld + j of base xbase.
@@ -88,7 +89,7 @@ struct PackTask {
   int32_t RB, KB, kc0, nch;     // RB = ceil(R / 16)
   int32_t dr0, dk0, dlen, xbase;
   int64_t soff, doff;
-  double shift;
+  int32_t shift_slot, pad2;     // 2 prob (left shift) or 2 prob + 1 (right shift); -1: none
   int64_t xoff;
   int32_t xld, pad;
 };
@@ -174,21 +175,27 @@ void launch_convert(int kind, const void* src, void* dst, int64_t n, hipStream_t
 
 // out[t] = sum of the diagonal of DiagTask t (FP64 sources; one workgroup per task).
 void launch_diag_sum(const DiagTask* tasks, int ntask, void* const* bases, double* out, hipStream_t s);
+// Energy shifts of the low-precision copies from the diagonal sums: tasks [0, nleft) are diagonals of
+// the left environment, the rest of the right one.  sig[2p] (left) and sig[2p + 1] (right) = mean of
+// problem p's diagonal elements on that side if flags[2p] (flags[2p + 1]) is set, else 0 (summed in
+// task order, one thread); shift[t] = the shift of task t's side and problem.
+void launch_sigma(const DiagTask* tasks, int ntask, int nleft, const double* sums, const int32_t* flags, int P,
+                  double* sig, double* shift, hipStream_t s);
 // FP32 copies (bases dst) of FP64 blocks (bases src, same offsets): diagonal of task t = float(src - shift[t]).
 void launch_diag_shift_f32(const DiagTask* tasks, int ntask, void* const* src, void* const* dst, const double* shift,
                            hipStream_t s);
-// dst[i] = (double)src[i] + sigma x[i] (n elements; float src, double x and dst).
-void launch_convert_add(const float* src, const double* x, double sigma, double* dst, int64_t n, hipStream_t s);
+// dst[i] = (double)src[i] + (sig[2 prob] + sig[2 prob + 1]) x[i] (n elements; float src, double x and dst).
+void launch_convert_add(const float* src, const double* x, const double* sig, int prob, double* dst, int64_t n,
+                        hipStream_t s);
 
 // Fragment packs (256 row-chunks of 8 values per tile); sources are read through sbases, results written
-// through dbases.
+// through dbases; sig: the diagonal shifts (see PackTask; may be null if no task has a shift slot).
 void launch_pack(const PackTask* tasks, int ntask, int ntiles, void* const* sbases, void* const* dbases,
-                 const int32_t* active, hipStream_t s);
+                 const double* sig, const int32_t* active, hipStream_t s);
 
 // Blocked one-sided Jacobi (bjsvd.hip): all matrices of `svd` at once.
 // bases (device): per problem kNumBases pointers, 1 M, 2 X, 3 G, 4 U, 5 V, 6 S; dtasks = the same tasks on
 // the device.
-// upload() copies a host byte array to device memory and returns its address;
 // sync() waits for the stream (the host checks the sweep flags once per sweep).
 struct BjScratch {
   double tol = 1e-15;        // relative orthogonality of converged rows
@@ -205,9 +212,23 @@ struct BjScratch {
   std::function<void(std::vector<int32_t>& complete)> need_completion;
   int completed = 0;         // out: matrices whose null rows were completed
 };
-void bj_svd(const std::vector<SvdTask>& svd, void* const* dbases, const SvdTask* dtasks, BjScratch& scr,
-            hipStream_t s, const std::function<char*(const std::vector<char>&)>& upload,
-            const std::function<char*(size_t)>& scratch, const std::function<void()>& sync);
+// The host part of bj_svd, prepared before any device work: the round schedule and the other device
+// tables (host, to be copied to the device before bj_svd runs) and the bytes of device scratch the
+// rounds need.
+struct BjPlan {
+  int nm = 0;
+  std::vector<char> host;
+  size_t scratch = 0;
+  size_t omats = 0, oflags = 0, othr = 0, ocomp = 0, b_partial = 0, b_q = 0;
+  std::vector<size_t> opair, ogram, oapply;
+  std::vector<int> npair, ngram, napply;
+};
+void bj_prepare(const std::vector<SvdTask>& svd, BjPlan& plan);
+// dev: plan.host on the device; work: plan.scratch bytes of device memory.
+void bj_svd(const BjPlan& plan, void* const* dbases, const SvdTask* dtasks, BjScratch& scr, hipStream_t s,
+            const char* dev, char* work, const std::function<void()>& sync);
+// flag[0] = 1 if any of x[0..n) is NaN or infinite; the caller clears the flag first.
+void launch_check_finite(const double* x, int64_t n, int32_t* flag, hipStream_t s);
 void launch_select(const SelTask* tasks, int ntask, const SelSector* secs, const double* S,
                    int32_t* kept_per_sec, int32_t* colmap, double* lam_sel, double* scal,
                    hipStream_t s);

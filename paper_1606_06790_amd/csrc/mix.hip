@@ -176,6 +176,7 @@ __global__ __launch_bounds__(256) void mix4_kernel(const MixTask* __restrict__ t
 // Values outside [R x K] are zeros.
 __global__ __launch_bounds__(256) void pack_kernel(const PackTask* __restrict__ tasks, int ntask,
                                                    void* const* __restrict__ sbases, void* const* __restrict__ dbases,
+                                                   const double* __restrict__ sig,
                                                    const int32_t* __restrict__ active) {
   const int tile = blockIdx.x;
   const PackTask& tk = tasks[find_tile(&tasks[0].tile0, sizeof(PackTask) / 4, ntask, tile)];
@@ -188,6 +189,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackTask* __restrict__ 
   const int r = (int)(q / tk.nch) * kFragRows + rr;
   const int k0 = 8 * ch;
   const double* S = reinterpret_cast<const double*>(sbases[tk.prob * kNumBases + tk.sbase]) + tk.soff;
+  const double shift = tk.shift_slot >= 0 ? sig[tk.shift_slot] : 0.0;
   float v[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackTask* __restrict__ 
         else X[(int64_t)r * tk.xld + k] = (float)x;
       }
     }
-    if (r - tk.dr0 == k - tk.dk0 && (unsigned)(r - tk.dr0) < (unsigned)tk.dlen) x -= tk.shift;
+    if (r - tk.dr0 == k - tk.dk0 && (unsigned)(r - tk.dr0) < (unsigned)tk.dlen) x -= shift;
     v[e] = (float)x;
   }
   uint4 hi, lo;
@@ -235,6 +237,25 @@ __global__ __launch_bounds__(256) void diag_sum_kernel(const DiagTask* __restric
   if (threadIdx.x == 0) out[blockIdx.x] = a;
 }
 
+// sig[2p + side] = mean diagonal element of problem p's tasks on that side (if flagged), summed in task
+// order by one thread (the same order on every call); shift[t] = sig of task t.
+__global__ void sigma_kernel(const DiagTask* __restrict__ tasks, int ntask, int nleft,
+                             const double* __restrict__ sums, const int32_t* __restrict__ flags, int P,
+                             double* __restrict__ sig, double* __restrict__ shift) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int q = 0; q < 2 * P; ++q) {
+    const int p = q >> 1, side = q & 1;
+    double sum = 0.0, n = 0.0;
+    for (int t = 0; t < ntask; ++t)
+      if (tasks[t].prob == p && (t < nleft ? 0 : 1) == side) {
+        sum += sums[t];
+        n += tasks[t].len;
+      }
+    sig[q] = (flags[q] && n > 0.0) ? sum / n : 0.0;
+  }
+  for (int t = 0; t < ntask; ++t) shift[t] = sig[2 * tasks[t].prob + (t < nleft ? 0 : 1)];
+}
+
 // The diagonal of an FP32 copy rewritten from its FP64 source minus shift[t],
 // rounded once: d32[i, i] = float(d64[i, i] - shift).
 __global__ __launch_bounds__(256) void diag_shift_kernel(const DiagTask* __restrict__ tasks,
@@ -251,8 +272,9 @@ __global__ __launch_bounds__(256) void diag_shift_kernel(const DiagTask* __restr
   }
 }
 
-__global__ void convert_add_kernel(const float* __restrict__ src, const double* __restrict__ x, double sigma,
-                                   double* __restrict__ dst, int64_t n) {
+__global__ void convert_add_kernel(const float* __restrict__ src, const double* __restrict__ x,
+                                   const double* __restrict__ sig, int prob, double* __restrict__ dst, int64_t n) {
+  const double sigma = sig[2 * prob] + sig[2 * prob + 1];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = (double)src[i] + sigma * x[i];
 }
@@ -318,23 +340,29 @@ void launch_diag_sum(const DiagTask* tasks, int ntask, void* const* bases, doubl
   hipLaunchKernelGGL(diag_sum_kernel, dim3(ntask), dim3(256), 0, s, tasks, bases, out);
 }
 
+void launch_sigma(const DiagTask* tasks, int ntask, int nleft, const double* sums, const int32_t* flags, int P,
+                  double* sig, double* shift, hipStream_t s) {
+  hipLaunchKernelGGL(sigma_kernel, dim3(1), dim3(64), 0, s, tasks, ntask, nleft, sums, flags, P, sig, shift);
+}
+
 void launch_diag_shift_f32(const DiagTask* tasks, int ntask, void* const* src, void* const* dst, const double* shift,
                            hipStream_t s) {
   if (ntask == 0) return;
   hipLaunchKernelGGL(diag_shift_kernel, dim3(ntask), dim3(256), 0, s, tasks, src, dst, shift);
 }
 
-void launch_convert_add(const float* src, const double* x, double sigma, double* dst, int64_t n, hipStream_t s) {
+void launch_convert_add(const float* src, const double* x, const double* sig, int prob, double* dst, int64_t n,
+                        hipStream_t s) {
   if (n <= 0) return;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(convert_add_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, x, sigma, dst, n);
+  hipLaunchKernelGGL(convert_add_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, x, sig, prob, dst, n);
 }
 
 void launch_pack(const PackTask* tasks, int ntask, int ntiles, void* const* sbases, void* const* dbases,
-                 const int32_t* active, hipStream_t s) {
+                 const double* sig, const int32_t* active, hipStream_t s) {
   if (ntask == 0 || ntiles == 0) return;
-  hipLaunchKernelGGL(pack_kernel, dim3(ntiles), dim3(256), 0, s, tasks, ntask, sbases, dbases, active);
+  hipLaunchKernelGGL(pack_kernel, dim3(ntiles), dim3(256), 0, s, tasks, ntask, sbases, dbases, sig, active);
 }
 
 void launch_scale(const ScaleTask* tasks, const int32_t* colmaps, int ntask, int ntiles, double lam_floor,

@@ -284,6 +284,7 @@ static PackTask packtask(int prob, int R, int K, int sbase, int64_t soff, int ld
                          int KB, int kc0, int nch) {
   PackTask p{};
   p.xbase = -1;
+  p.shift_slot = -1;
   p.R = R; p.K = K; p.ld = ld; p.trans = trans;
   p.prob = prob; p.sbase = sbase; p.dbase = dbase;
   p.KB = KB; p.kc0 = kc0; p.nch = nch;
@@ -402,6 +403,7 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
       pt.dr0 = EL.row_off[a][0];
       pt.dk0 = 0;
       pt.dlen = A.dim[a];
+      pt.shift_slot = 2 * prob;
       DiagTask dg{};
       dg.prob = prob; dg.base = 0; dg.len = A.dim[a]; dg.ld = A.dim[a];
       dg.off = EL.stack_off[a] + (int64_t)EL.row_off[a][0] * A.dim[a];
@@ -456,6 +458,7 @@ void build_heff(HeffPlan& p, int prob, const Leg& A, const Leg& B, const Mpo& W1
         pt.dr0 = 0;
         pt.dk0 = 0;
         pt.dlen = du;
+        pt.shift_slot = 2 * prob + 1;
       }
       p.packR.add(pt);
     }

@@ -151,7 +151,22 @@ __global__ __launch_bounds__(ST) void k_select(const SelTask* __restrict__ tasks
   }
 }
 
+// flag[0] = 1 if any of x[0..n) is NaN or infinite (flag cleared by the caller).
+__global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ x, int64_t n, int32_t* flag) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    bad |= !isfinite(x[i]);
+  if (bad) flag[0] = 1;
+}
+
 }  // namespace
+
+void launch_check_finite(const double* x, int64_t n, int32_t* flag, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag);
+}
 
 void launch_select(const SelTask* tasks, int ntask, const SelSector* secs, const double* S, int32_t* kept_per_sec,
                    int32_t* colmap, double* lam_sel, double* scal, hipStream_t s) {

@@ -22,10 +22,12 @@ OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, 1, -1, -2, -3
 PREC = {"f64": 0, "f32": 1, "bf16x3": 2}
 LEFT, RIGHT = 0, 1
 
+OP_HEFF, OP_LANCZOS, OP_TRUNCATE, OP_ENV_LEFT, OP_ENV_RIGHT, OP_PREDICT = range(6)
+
 EXPORTS = ["idmrg_create", "idmrg_destroy", "idmrg_set_stream", "idmrg_last_error", "idmrg_psi_size",
            "idmrg_envL_size", "idmrg_envR_size", "idmrg_U_size", "idmrg_V_size", "idmrg_heff_work",
            "heff_apply", "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction",
-           "idmrg_profile", "idmrg_profile_get"]
+           "idmrg_profile", "idmrg_profile_get", "idmrg_workspace_size", "idmrg_set_workspace", "idmrg_get_stats"]
 PROF_CLASSES = ["heff_gemm1", "heff_gemm2", "heff_mix", "convert", "lanczos_vec", "svd", "trunc_other", "env",
                 "predict", "heff_gemm1_lo", "heff_gemm2_lo", "heff_mix_lo"]
 
@@ -82,6 +84,16 @@ class Predict_t(C.Structure):
                 ("lam_prev", C.c_void_p), ("U_ip1", C.c_void_p), ("lam_ip1", C.c_void_p), ("psi", C.c_void_p)]
 
 
+class WsQuery_t(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("m_max", C.c_int32), ("d", C.c_int32), ("pad", C.c_int32),
+                ("qp", C.POINTER(C.c_int32)), ("opts", C.POINTER(LanczosOpts_t))]
+
+
+class Stats_t(C.Structure):
+    _fields_ = [("device_allocs", C.c_int64), ("stream_syncs", C.c_int64), ("staged_bytes", C.c_int64),
+                ("plan_builds", C.c_int64)]
+
+
 _lib = None
 
 
@@ -119,11 +131,15 @@ def load():
     lib.update_env.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(EnvUpdate_t)]
     lib.predict_wavefunction.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_int32), C.c_double,
                                          C.POINTER(Predict_t)]
+    lib.idmrg_workspace_size.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.POINTER(WsQuery_t),
+                                         C.POINTER(C.c_size_t)]
+    lib.idmrg_set_workspace.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    lib.idmrg_get_stats.argtypes = [C.c_void_p, C.POINTER(Stats_t)]
     lib.idmrg_profile.argtypes = [C.c_void_p, C.c_int]
     lib.idmrg_profile_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
     for name in ["idmrg_profile", "idmrg_profile_get", "idmrg_create", "idmrg_destroy", "idmrg_set_stream",
-                 "idmrg_heff_work", "heff_apply",
+                 "idmrg_heff_work", "heff_apply", "idmrg_workspace_size", "idmrg_set_workspace", "idmrg_get_stats",
                  "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -188,18 +204,58 @@ def _check(ctx, rc):
 
 
 class Context:
-    """Library context bound to a device and PyTorch's current stream on it."""
+    """Library context bound to a device and PyTorch's current stream on it.
 
-    def __init__(self, device=0):
+    The device scratch of every call comes from one workspace that PyTorch
+    allocates: each call is sized first (idmrg_workspace_size) and the
+    workspace grows when a call needs more, so the library itself never
+    allocates device memory.  workspace=False leaves the scratch to the library
+    (its own block, grown with hipMalloc)."""
+
+    def __init__(self, device=0, workspace=True):
         torch = _torch()
         self.device = device
         self.lib = load()
+        self.managed = workspace
+        self.ws, self.ws_bytes = None, 0
         h = C.c_void_p()
         stream = torch.cuda.current_stream(device).cuda_stream
         rc = self.lib.idmrg_create(C.byref(h), device, C.c_void_p(stream))
         if rc != 0:
             raise IdmrgError(rc, "idmrg_create failed")
         self.handle = h
+
+    def workspace_size(self, op, nprob, desc, query):
+        """Bytes of device workspace the call needs (builds and keeps its plan)."""
+        b = C.c_size_t()
+        _check(self, self.lib.idmrg_workspace_size(self.handle, op, nprob, desc, C.byref(query), C.byref(b)))
+        return int(b.value)
+
+    def reserve(self, op, nprob, desc, query):
+        """Size the call and grow the attached workspace if it needs more."""
+        if not self.managed:
+            return
+        need = self.workspace_size(op, nprob, desc, query)
+        if need <= self.ws_bytes:
+            return
+        torch = _torch()
+        new = max(need, self.ws_bytes + self.ws_bytes // 4)
+        new = (new + (1 << 20) - 1) >> 20 << 20
+        if self.ws is not None:
+            # work queued on the stream may still use the old block: PyTorch reuses freed memory only in
+            # stream order, and empty_cache (a hipFree) waits for the device before releasing it
+            self.ws = None
+            self.ws_bytes = 0
+            _check(self, self.lib.idmrg_set_workspace(self.handle, None, 0))
+            torch.cuda.empty_cache()
+        t = torch.empty(new, dtype=torch.uint8, device=torch.device("cuda", self.device))
+        _check(self, self.lib.idmrg_set_workspace(self.handle, C.c_void_p(t.data_ptr()), new))
+        self.ws, self.ws_bytes = t, new
+
+    def stats(self):
+        st = Stats_t()
+        _check(self, self.lib.idmrg_get_stats(self.handle, C.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in Stats_t._fields_}
 
     def sync_stream(self):
         torch = _torch()
@@ -222,6 +278,7 @@ class Context:
         if self.handle:
             self.lib.idmrg_destroy(self.handle)
             self.handle = None
+        self.ws = None
 
     def __del__(self):
         try:
@@ -285,6 +342,7 @@ def heff_apply(ctx, problems, xs, ys, prec="f64"):
     arr = _heff_structs(k, problems)
     xp = (C.c_void_p * len(xs))(*[_ptr(x) for x in xs])
     yp = (C.c_void_p * len(ys))(*[_ptr(y) for y in ys])
+    ctx.reserve(OP_HEFF, len(problems), arr, WsQuery_t(prec=PREC[prec]))
     _check(ctx, ctx.lib.heff_apply(ctx.handle, len(problems), arr, xp, yp, PREC[prec]))
 
 
@@ -299,6 +357,7 @@ def lanczos_solve_batch(ctx, problems, psis, tol_E=1e-12, tol_res=1e-8, k_max=30
     opts = LanczosOpts_t(tol_E, tol_res, k_max, PREC[prec], chunk, 1 if refine else 0, 1 if cgs2 else 0, 1 if graph else 0)
     e = (C.c_double * P)()
     inf = (LanczosInfo_t * P)()
+    ctx.reserve(OP_LANCZOS, P, arr, WsQuery_t(opts=C.pointer(opts)))
     rc = _check(ctx, ctx.lib.lanczos_solve_batch(ctx.handle, P, arr, pp, C.byref(opts), e, inf))
     infos = [dict(iters=x.iters, converged=x.converged, fp64_matvecs=x.fp64_matvecs, flags=x.flags,
                   reorth_passes=x.reorth_passes, residual=x.residual, overlap0=x.overlap0, warn=rc) for x in inf]
@@ -330,7 +389,9 @@ def truncate_twosite(ctx, items, qp, m_max, lam_floor=1e-14, deg_rel=1e-5):
         arr[j] = Trunc_t(k.leg(A), k.leg(B), _ptr(it["psi"]), cap_sec, qo, do, C.c_void_p(U.data_ptr()),
                          C.c_void_p(V.data_ptr()), C.c_void_p(lam.data_ptr()), U.numel(), V.numel(),
                          lam.numel(), 0, 0, 0.0, 0.0, 0.0, 0, 0)
-    rc = _check(ctx, ctx.lib.truncate_twosite(ctx.handle, P, d, k.ints(qp), m_max, lam_floor, deg_rel, arr))
+    qpa = k.ints(qp)
+    ctx.reserve(OP_TRUNCATE, P, arr, WsQuery_t(m_max=m_max, d=d, qp=qpa))
+    rc = _check(ctx, ctx.lib.truncate_twosite(ctx.handle, P, d, qpa, m_max, lam_floor, deg_rel, arr))
     out = []
     for j, it in enumerate(items):
         U, V, lam, qo, do = bufs[j]
@@ -359,6 +420,7 @@ def update_env(ctx, side, items):
         outs.append(o[:n])
         arr[j] = EnvUpdate_t(k.leg(it["old_leg"]), k.leg(it["new_leg"]), k.mpo(W), _ptr(it["env_old"]),
                              _ptr(it["iso"]), C.c_void_p(o.data_ptr()))
+    ctx.reserve(OP_ENV_LEFT if side == LEFT else OP_ENV_RIGHT, P, arr, WsQuery_t())
     _check(ctx, ctx.lib.update_env(ctx.handle, P, side, arr))
     return outs
 
@@ -377,5 +439,7 @@ def predict_wavefunction(ctx, items, qp, lam_floor=1e-14):
         arr[j] = Predict_t(k.leg(it["leg_a"]), k.leg(it["leg_beta"]), k.leg(it["leg_b"]), _ptr(it["lam_i"]),
                            _ptr(it["V_i"]), _ptr(it["lam_prev"]), _ptr(it["U_ip1"]), _ptr(it["lam_ip1"]),
                            C.c_void_p(o.data_ptr()))
-    _check(ctx, ctx.lib.predict_wavefunction(ctx.handle, P, len(qp), k.ints(qp), lam_floor, arr))
+    qpa = k.ints(qp)
+    ctx.reserve(OP_PREDICT, P, arr, WsQuery_t(d=len(qp), qp=qpa))
+    _check(ctx, ctx.lib.predict_wavefunction(ctx.handle, P, len(qp), qpa, lam_floor, arr))
     return outs

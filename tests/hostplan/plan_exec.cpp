@@ -59,7 +59,8 @@ int64_t frag_slot(int64_t word_off, int KB, int r, int k) {
          k % 8;
 }
 
-void run_pack(const PackList& pl, const std::vector<double*>& src, const std::vector<double*>& dst) {
+void run_pack(const PackList& pl, const std::vector<double*>& src, const std::vector<double*>& dst,
+              const double* sig = nullptr) {
   for (const auto& t : pl.t) {
     const double* S = t.K > 0 ? base_ptr(src, t.prob, t.sbase) + t.soff : nullptr;
     double* D = base_ptr(dst, t.prob, t.dbase);
@@ -72,7 +73,7 @@ void run_pack(const PackList& pl, const std::vector<double*>& src, const std::ve
           if (t.trans) Xc[(int64_t)k * t.xld + r] = v;
           else Xc[(int64_t)r * t.xld + k] = v;
         }
-        if (r - t.dr0 == k - t.dk0 && r - t.dr0 >= 0 && r - t.dr0 < t.dlen) v -= t.shift;
+        if (r - t.dr0 == k - t.dk0 && r - t.dr0 >= 0 && r - t.dr0 < t.dlen) v -= sig[t.shift_slot];
         D[i] = v;
         D[i + kFragWords] = 0.0;
       }
@@ -175,9 +176,8 @@ extern "C" int hostplan_heff_frag(const idmrg_heff* H, const double* x, double* 
     sz[5] = p.n_T3f[0]; sz[6] = p.n_Xm[0];
     flags[0] = p.shiftL[0];
     flags[1] = p.shiftR[0];
-    for (auto& t : p.packL.t) t.shift = t.dlen > 0 ? sL : 0.0;
-    for (auto& t : p.packR.t) t.shift = t.dlen > 0 ? sR : 0.0;
-    const double sigma = (p.shiftL[0] ? sL : 0.0) + (p.shiftR[0] ? sR : 0.0);
+    const double sig[2] = {p.shiftL[0] ? sL : 0.0, p.shiftR[0] ? sR : 0.0};   // slots 0 (left), 1 (right)
+    const double sigma = sig[0] + sig[1];
     check_pack(p.packL, ss, sz, "packL");
     check_pack(p.packR, ss, sz, "packR");
     check_pack(p.packX, ss, sz, "packX");
@@ -187,9 +187,9 @@ extern "C" int hostplan_heff_frag(const idmrg_heff* H, const double* x, double* 
     check_mix_frag(p.mixTf, sz, "mixTf");
     check_mix_v4(p.mixTf, sz, "mixTf");
     check_gemm_frag(p.f2, sz, "f2");
-    run_pack(p.packL, src, b);
-    run_pack(p.packR, src, b);
-    run_pack(p.packX, src, b);
+    run_pack(p.packL, src, b, sig);
+    run_pack(p.packR, src, b, sig);
+    run_pack(p.packX, src, b, sig);
     run_gemm_frag(p.f1, b);
     run_mix(p.mixYf, b);
     run_mix_frag(p.mixTf, b);
