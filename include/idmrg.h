@@ -175,6 +175,18 @@ int idmrg_profile_get(idmrg_ctx* ctx, int cls, int64_t* launches, double* ms, do
 int heff_apply(idmrg_ctx* ctx, int nprob, const idmrg_heff* H,
                const double* const* x, double* const* y, int prec);
 
+/* heff_apply for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * plan and kernels as heff_apply, bitwise the same results, but the scratch is
+ * a file-scope device array of 64 MiB (one per GPU, set up by idmrg_create and
+ * held until the process ends) instead of the workspace, and the call makes
+ * no device or pinned allocation.  Calls whose scratch (idmrg_workspace_size
+ * with IDMRG_OP_HEFF) exceeds 64 MiB return IDMRG_EINVAL and launch nothing.
+ * Every call on one GPU, from any context or stream, shares that array: calls
+ * that overlap in time on one GPU race.  Asynchronous like heff_apply. */
+int heff_apply_static(idmrg_ctx* ctx, int nprob, const idmrg_heff* H,
+                      const double* const* x, double* const* y, int prec);
+
 typedef struct {
     double tol_E;       /* stop when |theta_k - theta_{k-1}| <= tol_E ... */
     double tol_res;     /* ... and the residual estimate beta_k |y_k| <= tol_res */

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <mutex>
 #include <tuple>
 
 #include "idmrg.h"
@@ -56,6 +57,15 @@ constexpr size_t kRingChunk = size_t(8) << 20;    // largest single staged copy
 constexpr size_t kRingSlotsMax = 256;             // copies tracked before the oldest is waited for
 constexpr int kOps = 6;
 
+// Scratch of heff_apply_static: a file-scope device array, one copy per GPU,
+// held until the process ends.  Host code never passes its name to a kernel:
+// the address comes from hipGetSymbolAddress on each device (idmrg_create).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 struct CallPlan;
 
 }  // namespace
@@ -82,6 +92,7 @@ struct idmrg_ctx {
   std::deque<RingSlot> ring_busy;
   std::vector<hipEvent_t> ring_events;
   idmrg_stats stats = {};
+  void* static_scratch = nullptr;   // this device's copy of `scratch` (heff_apply_static)
   // GEMM tile autotuner: measured best tiling per (precision, stage, shape bucket)
   std::map<std::tuple<int, int, int, int, int>, int> tune;
   hipEvent_t tev[4][4] = {};   // [variant][stage-1 start, stage-1 end, stage-2 start, stage-2 end]
@@ -179,14 +190,12 @@ char* acquire(idmrg_ctx* c, size_t bytes) {
   return (char*)c->own.p;
 }
 
+// The ring's events are created with the context (kRingSlotsMax of them, as
+// many as copies are ever tracked), so an upload creates nothing.
 hipEvent_t ring_event(idmrg_ctx* c) {
-  if (!c->ring_events.empty()) {
-    hipEvent_t e = c->ring_events.back();
-    c->ring_events.pop_back();
-    return e;
-  }
-  hipEvent_t e;
-  IDMRG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (c->ring_events.empty()) throw HipFailure("internal: staging ring out of events");
+  hipEvent_t e = c->ring_events.back();
+  c->ring_events.pop_back();
   return e;
 }
 
@@ -1107,6 +1116,29 @@ extern "C" int idmrg_create(idmrg_ctx** ctx, int device, void* hip_stream) {
     delete c;
     return IDMRG_ENOMEM;
   }
+  for (size_t i = 0; i < kRingSlotsMax + 1; ++i) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      idmrg_destroy(c);
+      return IDMRG_EHIP;
+    }
+    c->ring_events.push_back(e);
+  }
+  // this device's address of the static scratch array, once per device
+  if (device < kMaxDevices) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        idmrg_destroy(c);
+        return IDMRG_EHIP;
+      }
+      g_scratch_ptr[device] = p;
+    }
+    c->static_scratch = g_scratch_ptr[device];
+  }
   *ctx = c;
   return IDMRG_OK;
 }
@@ -1290,6 +1322,30 @@ extern "C" int heff_apply(idmrg_ctx* ctx, int nprob, const idmrg_heff* H, const 
     }
     auto k = heff_call(ctx, nprob, H, prec);
     char* base = acquire(ctx, k->lay.total);
+    heff_bind(ctx, k->ex, base, H, xs, ys);
+    heff_run(ctx, k->ex, xs, ys, nullptr);
+    return IDMRG_OK;
+  });
+}
+
+extern "C" int heff_apply_static(idmrg_ctx* ctx, int nprob, const idmrg_heff* H, const double* const* x,
+                                 double* const* y, int prec) {
+  return guarded(ctx, [&]() {
+    check_nprob(nprob);
+    if (!H || !x || !y) throw InvalidArg("null argument");
+    if (!ctx->static_scratch) throw InvalidArg("no static scratch on this device");
+    std::vector<double*> xs(nprob), ys(nprob);
+    for (int p = 0; p < nprob; ++p) {
+      if (!x[p] || !y[p] || x[p] == y[p]) throw InvalidArg("x and y must be distinct device pointers");
+      xs[p] = const_cast<double*>(x[p]);
+      ys[p] = y[p];
+    }
+    auto k = heff_call(ctx, nprob, H, prec);
+    if (k->lay.total > kStaticScratchBytes)
+      throw InvalidArg("heff_apply_static: this call needs " + std::to_string(k->lay.total) +
+                       " bytes of scratch; the static scratch holds " + std::to_string(kStaticScratchBytes) +
+                       " (use heff_apply)");
+    char* base = (char*)ctx->static_scratch;
     heff_bind(ctx, k->ex, base, H, xs, ys);
     heff_run(ctx, k->ex, xs, ys, nullptr);
     return IDMRG_OK;

@@ -27,7 +27,8 @@ OP_HEFF, OP_LANCZOS, OP_TRUNCATE, OP_ENV_LEFT, OP_ENV_RIGHT, OP_PREDICT = range(
 EXPORTS = ["idmrg_create", "idmrg_destroy", "idmrg_set_stream", "idmrg_last_error", "idmrg_psi_size",
            "idmrg_envL_size", "idmrg_envR_size", "idmrg_U_size", "idmrg_V_size", "idmrg_heff_work",
            "heff_apply", "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction",
-           "idmrg_profile", "idmrg_profile_get", "idmrg_workspace_size", "idmrg_set_workspace", "idmrg_get_stats"]
+           "idmrg_profile", "idmrg_profile_get", "idmrg_workspace_size", "idmrg_set_workspace", "idmrg_get_stats",
+           "heff_apply_static"]
 PROF_CLASSES = ["heff_gemm1", "heff_gemm2", "heff_mix", "convert", "lanczos_vec", "svd", "trunc_other", "env",
                 "predict", "heff_gemm1_lo", "heff_gemm2_lo", "heff_mix_lo"]
 
@@ -123,6 +124,7 @@ def load():
     lib.idmrg_heff_work.argtypes = [C.POINTER(Heff_t), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.heff_apply.argtypes = [C.c_void_p, C.c_int, C.POINTER(Heff_t), C.POINTER(C.c_void_p),
                                C.POINTER(C.c_void_p), C.c_int]
+    lib.heff_apply_static.argtypes = lib.heff_apply.argtypes
     lib.lanczos_solve_batch.argtypes = [C.c_void_p, C.c_int, C.POINTER(Heff_t), C.POINTER(C.c_void_p),
                                         C.POINTER(LanczosOpts_t), C.POINTER(C.c_double),
                                         C.POINTER(LanczosInfo_t)]
@@ -140,6 +142,7 @@ def load():
                                       C.POINTER(C.c_double)]
     for name in ["idmrg_profile", "idmrg_profile_get", "idmrg_create", "idmrg_destroy", "idmrg_set_stream",
                  "idmrg_heff_work", "heff_apply", "idmrg_workspace_size", "idmrg_set_workspace", "idmrg_get_stats",
+                 "heff_apply_static",
                  "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -344,6 +347,15 @@ def heff_apply(ctx, problems, xs, ys, prec="f64"):
     yp = (C.c_void_p * len(ys))(*[_ptr(y) for y in ys])
     ctx.reserve(OP_HEFF, len(problems), arr, WsQuery_t(prec=PREC[prec]))
     _check(ctx, ctx.lib.heff_apply(ctx.handle, len(problems), arr, xp, yp, PREC[prec]))
+
+
+def heff_apply_static(ctx, problems, xs, ys, prec="f64"):
+    """ys[p] = H_p xs[p] with the library's static scratch (no allocation by the call)."""
+    k = _Keep()
+    arr = _heff_structs(k, problems)
+    xp = (C.c_void_p * len(xs))(*[_ptr(x) for x in xs])
+    yp = (C.c_void_p * len(ys))(*[_ptr(y) for y in ys])
+    _check(ctx, ctx.lib.heff_apply_static(ctx.handle, len(problems), arr, xp, yp, PREC[prec]))
 
 
 def lanczos_solve_batch(ctx, problems, psis, tol_E=1e-12, tol_res=1e-8, k_max=300, prec="f64", chunk=8,
