@@ -402,6 +402,7 @@ def main():
                           "speedup_matvec": round(rmx["matvec_tflops"] / r64["matvec_tflops"], 4),
                           "e_site_diff_max": max(abs(x) for x in de)},
         "prefill_s": round(t_pre, 1),
+        "tile_tuning": d.ctx.tuning(),
     }
     if not a.no_p10:
         out["prediction_effect"] = prediction_effect(d, snap)

@@ -343,6 +343,23 @@ int idmrg_workspace_size(idmrg_ctx* ctx, int op, int nprob, const void* desc, co
  * the work queued on the context stream that uses it has run. */
 int idmrg_set_workspace(idmrg_ctx* ctx, void* ptr, size_t bytes);
 
+/* The GEMM tile autotuner.  The first matvecs of a Lanczos call whose stage
+ * shapes fall in a bucket not yet measured each run one tiling (the results do
+ * not depend on it) and the fastest is kept for that bucket: precision, stage
+ * (0: environment-L GEMM, 1: environment-R GEMM), log2 of the stage's flops and
+ * of its flop-weighted mean N and K.  Tilings: 0 64x64, 1 128x64, 2 64x128,
+ * 3 128x128, 4 256x128 (split-bf16 only, eight waves).  idmrg_tune_get copies up
+ * to cap entries (with the trial times, -1 where a tiling was not tried) and
+ * sets *n to the number of entries; idmrg_tune_set installs entries (a cache
+ * from an earlier process), which are then not measured again. */
+#define IDMRG_TUNE_VARIANTS 8
+typedef struct {
+    int32_t prec, stage, log2_flops, log2_n, log2_k, tiling;
+    float trial_ms[IDMRG_TUNE_VARIANTS];
+} idmrg_tune_entry;
+int idmrg_tune_get(idmrg_ctx* ctx, idmrg_tune_entry* out, int cap, int* n);
+int idmrg_tune_set(idmrg_ctx* ctx, const idmrg_tune_entry* in, int n);
+
 /* Counters of a context since idmrg_create. */
 typedef struct {
     int64_t device_allocs;   /* hipMalloc calls for the library's own scratch block */

@@ -93,9 +93,11 @@ struct idmrg_ctx {
   std::vector<hipEvent_t> ring_events;
   idmrg_stats stats = {};
   void* static_scratch = nullptr;   // this device's copy of `scratch` (heff_apply_static)
-  // GEMM tile autotuner: measured best tiling per (precision, stage, shape bucket)
+  // GEMM tile autotuner: measured best tiling per (precision, stage, shape bucket), and the
+  // trial time of each tiling (ms, -1 if not tried)
   std::map<std::tuple<int, int, int, int, int>, int> tune;
-  hipEvent_t tev[4][4] = {};   // [variant][stage-1 start, stage-1 end, stage-2 start, stage-2 end]
+  std::map<std::tuple<int, int, int, int, int>, std::vector<float>> tune_ms;
+  hipEvent_t tev[5][4] = {};   // [variant][stage-1 start, stage-1 end, stage-2 start, stage-2 end]
   // the plan of the last call of each kind and the hash of its inputs
   uint64_t cache_key[kOps] = {};
   std::shared_ptr<CallPlan> cache[kOps];
@@ -364,8 +366,9 @@ std::shared_ptr<T> plan_of(idmrg_ctx* c, int op, uint64_t key, F&& build) {
 
 // ------------------------------------------------------------------ H_eff execution
 
-// Output tilings of the FP64/FP32 GEMM kernel: code c -> (c & 1 ? 128 : 64) x (c & 2 ? 128 : 64).
-constexpr int kTilings = 4;
+// Output tilings of the GEMM kernels: code c < 4 -> (c & 1 ? 128 : 64) x (c & 2 ? 128 : 64) (four waves);
+// code 4 -> 256 x 128 (split-bf16 only: eight waves, three LDS stages).
+constexpr int kTilings = 5;
 
 struct HeffExec {
   HeffPlan plan;
@@ -434,7 +437,13 @@ void tune_resolve(idmrg_ctx* c, HeffExec& ex, int ntried) {
     }
     ex.sel[st] = best;
     ex.need_tune[st] = false;
-    if (ntried == ex.nvar) c->tune[ex.key[st]] = best;
+    if (ntried == ex.nvar) {
+      c->tune[ex.key[st]] = best;
+      std::vector<float> ms(IDMRG_TUNE_VARIANTS, -1.f);
+      for (int v = 0; v < ntried; ++v)
+        IDMRG_HIP(hipEventElapsedTime(&ms[ex.code[v]], c->tev[v][2 * st], c->tev[v][2 * st + 1]));
+      c->tune_ms[ex.key[st]] = ms;
+    }
   }
 }
 
@@ -468,14 +477,17 @@ void heff_plan(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, int prec,
   ex.npsi = ex.plan.n_psi;
   // Tile variants.  The tile shape does not change the order in which any
   // output element accumulates over k, so all variants give identical results.
-  ex.nvar = kTilings;
-  for (int v = 0; v < kTilings; ++v) ex.code[v] = v;
+  ex.nvar = frag ? 5 : 4;
+  for (int v = 0; v < ex.nvar; ++v) ex.code[v] = v;
   for (int st = 0; st < 2; ++st) {
     const GemmList& base = st == 0 ? (frag ? ex.plan.f1 : ex.plan.g1) : (frag ? ex.plan.f2 : ex.plan.g2);
     ex.var[st].clear();
     for (int v = 0; v < ex.nvar; ++v) {
       ex.var[st].push_back(base);
-      ex.var[st][v].retile(ex.code[v] & 1 ? 128 : 64, ex.code[v] & 2 ? 128 : 64);
+      if (ex.code[v] == 4)
+        ex.var[st][v].retile(256, 128);
+      else
+        ex.var[st][v].retile(ex.code[v] & 1 ? 128 : 64, ex.code[v] & 2 ? 128 : 64);
       ex.tiles[st][v] = ex.var[st][v].tiles;
     }
     ex.key[st] = tune_key(ex.prec, st, base);
@@ -1190,6 +1202,45 @@ extern "C" int idmrg_set_workspace(idmrg_ctx* c, void* ptr, size_t bytes) {
     c->user_ws_n = bytes;
     return IDMRG_OK;
   });
+}
+
+extern "C" int idmrg_tune_get(idmrg_ctx* c, idmrg_tune_entry* out, int cap, int* n) {
+  if (!c || !n || (cap > 0 && !out)) return IDMRG_EINVAL;
+  int k = 0;
+  for (const auto& kv : c->tune) {
+    if (k < cap) {
+      idmrg_tune_entry& e = out[k];
+      e = idmrg_tune_entry{};
+      e.prec = std::get<0>(kv.first);
+      e.stage = std::get<1>(kv.first);
+      e.log2_flops = std::get<2>(kv.first);
+      e.log2_n = std::get<3>(kv.first);
+      e.log2_k = std::get<4>(kv.first);
+      e.tiling = kv.second;
+      auto it = c->tune_ms.find(kv.first);
+      for (int v = 0; v < IDMRG_TUNE_VARIANTS; ++v) e.trial_ms[v] = it != c->tune_ms.end() ? it->second[v] : -1.f;
+    }
+    ++k;
+  }
+  *n = k;
+  return IDMRG_OK;
+}
+
+extern "C" int idmrg_tune_set(idmrg_ctx* c, const idmrg_tune_entry* in, int n) {
+  if (!c || n < 0 || (n > 0 && !in)) return IDMRG_EINVAL;
+  for (int k = 0; k < n; ++k) {
+    const idmrg_tune_entry& e = in[k];
+    if (e.prec < 0 || e.prec > 2 || e.stage < 0 || e.stage > 1 || e.tiling < 0 || e.tiling >= kTilings ||
+        (e.tiling == 4 && e.prec != IDMRG_PREC_BF16X3))
+      return IDMRG_EINVAL;
+  }
+  for (int k = 0; k < n; ++k) {
+    const idmrg_tune_entry& e = in[k];
+    const auto key = std::make_tuple(e.prec, e.stage, e.log2_flops, e.log2_n, e.log2_k);
+    c->tune[key] = e.tiling;
+    c->tune_ms[key] = std::vector<float>(e.trial_ms, e.trial_ms + IDMRG_TUNE_VARIANTS);
+  }
+  return IDMRG_OK;
 }
 
 extern "C" int idmrg_get_stats(idmrg_ctx* c, idmrg_stats* out) {

@@ -258,6 +258,11 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
 // is in flight while slab k is multiplied.  (A third stage does not pay: at
 // 96 KB of LDS only one workgroup fits on a CU.)
 
+// Byte address of an LDS location (the 32-bit offset ds_read takes).
+__device__ __forceinline__ uint32_t lds_addr(const v4u* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) v4u*)(p);
+}
+
 // 16 bytes per lane from global memory straight to LDS: lane l writes dst + 16 l
 // (dst must be the same for the whole wave).
 __device__ __forceinline__ void lds_copy16(gptr<char> src, v4u* dst) {
@@ -370,6 +375,148 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
       }
 }
 
+// The same product with a 256 x 128 tile: 8 waves (4 x 2) of 64 x 64 (the
+// same register footprint per wave as the 128 x 128 tile, so still two waves
+// per SIMD), three LDS stages of 48 KB (144 KB, one workgroup per CU), and the
+// copies of each slab issued two slabs ahead, so that a copy has two slabs of
+// MFMA work (~1500 cycles per SIMD) to land instead of one.  Slab k + 2 goes
+// into the stage that slab k - 1 used; the barrier at the top of slab k, after
+// each thread has waited for its own copies of slab k, makes every copy of
+// slab k visible and ends every read of slab k - 1.  The barrier carries no
+// memory fence (a fence would wait for the copies in flight as well).
+template <int STAGE>
+__global__ __launch_bounds__(512) void gemm_bf16x3_w8_kernel(const GemmTask* __restrict__ tasks, int ntask,
+                                                             void* const* __restrict__ bases,
+                                                             const int32_t* __restrict__ active, int ntiles) {
+  constexpr int BM = 256, BN = 128, NS = 3;
+  constexpr int FA = BM / 16, FB = BN / 16;    // fragments per slab
+  constexpr int UA = FA / 4, UB = FB / 4;      // 16-byte copies per thread per slab (4 fragments per 512 threads)
+  constexpr int NCOPY = UA + UB;
+  constexpr int TI = 4, TJ = 4;                // 16 x 16 MFMA tiles per wave
+  constexpr uint32_t kFragBytes = kFragWords * 4;
+  __shared__ v4u As[NS][FA * 128], Bs[NS][FB * 128];
+  const int tile = xcd_tile(ntiles);
+  if (tile < 0) return;
+  const GemmTask& tk = tasks[find_task(tasks, ntask, tile)];
+  if (active && !active[tk.prob]) return;
+  const int local = tile - tk.tile0;
+  const int m0 = (local / tk.tiles_n) * BM;
+  const int n0 = (local % tk.tiles_n) * BN;
+  const int M = tk.M, N = tk.N;
+  const int KB = (tk.K + kFragK - 1) / kFragK;
+  const int RA = (M + kFragRows - 1) / kFragRows, RB = (N + kFragRows - 1) / kFragRows;
+  const char* A = reinterpret_cast<const char*>(bases[tk.prob * kNumBases + tk.abase]) + tk.aoff * 4;
+  const char* B = reinterpret_cast<const char*>(bases[tk.prob * kNumBases + tk.bbase]) + tk.boff * 4;
+  float* __restrict__ C = reinterpret_cast<float*>(bases[tk.prob * kNumBases + tk.cbase]) + tk.coff;
+  const int ldc = tk.ldc;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  // Copy u of thread t: fragment 4u + t/128 of the slab, chunk t % 128 of it; the
+  // LDS destination of the wave is chunk 64 (wave % 2) of that fragment.
+  const int quarter = t >> 7, within = t & 127;
+  uint32_t ao[UA], bo[UB];
+#pragma unroll
+  for (int u = 0; u < UA; ++u) {
+    const int rb = min(m0 / kFragRows + 4 * u + quarter, RA - 1);
+    ao[u] = (uint32_t)rb * (uint32_t)KB * kFragBytes + within * 16u;
+  }
+#pragma unroll
+  for (int u = 0; u < UB; ++u) {
+    const int rb = min(n0 / kFragRows + 4 * u + quarter, RB - 1);
+    bo[u] = (uint32_t)rb * (uint32_t)KB * kFragBytes + within * 16u;
+  }
+  const int wdst = quarter * 128 + (wave & 1) * 64;
+  auto copy = [&](int kb, int st) {
+    const gptr<char> Ak = as_global(A + (size_t)kb * kFragBytes);
+    const gptr<char> Bk = as_global(B + (size_t)kb * kFragBytes);
+#pragma unroll
+    for (int u = 0; u < UA; ++u) lds_copy16(Ak + ao[u], &As[st][u * 512 + wdst]);
+#pragma unroll
+    for (int u = 0; u < UB; ++u) lds_copy16(Bk + bo[u], &Bs[st][u * 512 + wdst]);
+  };
+
+  v4f acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+
+  if (KB > 0) copy(0, 0);
+  if (KB > 1) copy(1, 1);
+  int cur = 0;
+  for (int kb = 0; kb < KB; ++kb) {
+    // this thread's copies of slab kb have landed (those of slab kb + 1 may still be in flight)
+    if (kb + 1 < KB)
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NCOPY) : "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    if (kb + 2 < KB) copy(kb + 2, cur == 0 ? 2 : cur - 1);
+    // The wave's 16 operand reads in one asm block that ends with their own
+    // wait: the compiler would otherwise make an LDS read that follows the
+    // copies wait for all of them (it cannot tell that they write other
+    // stages), which is the one-slab pipeline again.  Outputs are early-clobber,
+    // so no read lands in an address register that a later read still needs.
+    const uint32_t abase = lds_addr(&As[cur][wr * TI * 128 + lane]);
+    const uint32_t bbase = lds_addr(&Bs[cur][wc * TJ * 128 + lane]);
+    v4u r[16];
+    asm volatile(
+        "ds_read_b128 %0, %16 offset:0\n\t"
+        "ds_read_b128 %1, %16 offset:1024\n\t"
+        "ds_read_b128 %2, %16 offset:2048\n\t"
+        "ds_read_b128 %3, %16 offset:3072\n\t"
+        "ds_read_b128 %4, %16 offset:4096\n\t"
+        "ds_read_b128 %5, %16 offset:5120\n\t"
+        "ds_read_b128 %6, %16 offset:6144\n\t"
+        "ds_read_b128 %7, %16 offset:7168\n\t"
+        "ds_read_b128 %8, %17 offset:0\n\t"
+        "ds_read_b128 %9, %17 offset:1024\n\t"
+        "ds_read_b128 %10, %17 offset:2048\n\t"
+        "ds_read_b128 %11, %17 offset:3072\n\t"
+        "ds_read_b128 %12, %17 offset:4096\n\t"
+        "ds_read_b128 %13, %17 offset:5120\n\t"
+        "ds_read_b128 %14, %17 offset:6144\n\t"
+        "ds_read_b128 %15, %17 offset:7168\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]),
+          "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10]), "=&v"(r[11]), "=&v"(r[12]), "=&v"(r[13]),
+          "=&v"(r[14]), "=&v"(r[15])
+        : "v"(abase), "v"(bbase)
+        : "memory");
+    v8bf ah[TI], al[TI], bh[TJ], bl[TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      ah[i] = __builtin_bit_cast(v8bf, r[2 * i]);
+      al[i] = __builtin_bit_cast(v8bf, r[2 * i + 1]);
+      bh[i] = __builtin_bit_cast(v8bf, r[8 + 2 * i]);
+      bl[i] = __builtin_bit_cast(v8bf, r[8 + 2 * i + 1]);
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+    cur = cur == NS - 1 ? 0 : cur + 1;
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = m0 + wr * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int gn = n0 + wc * 64 + j * 16 + (lane & 15);
+        if (gi < M && gn < N) {
+          float* p = C + (int64_t)gi * ldc + gn;
+          *p = tk.beta ? (*p + acc[i][j][r]) : acc[i][j][r];
+        }
+      }
+}
+
 }  // namespace
 
 template <typename T, int BM, int BN>
@@ -405,6 +552,13 @@ static void launch_b3(int mode, dim3 grid, hipStream_t s, const GemmTask* tasks,
 
 static void launch_bf16x3(int tiling, int mode, dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask,
                           void* const* bases, const int32_t* active, int ntiles) {
+  if (tiling == 4) {   // 256 x 128, eight waves, three stages
+    if (mode == 0)
+      hipLaunchKernelGGL(gemm_bf16x3_w8_kernel<0>, grid, dim3(512), 0, s, tasks, ntask, bases, active, ntiles);
+    else
+      hipLaunchKernelGGL(gemm_bf16x3_w8_kernel<1>, grid, dim3(512), 0, s, tasks, ntask, bases, active, ntiles);
+    return;
+  }
   switch (tiling) {
     case 0: launch_b3<64, 64>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;
     case 1: launch_b3<128, 64>(mode, grid, s, tasks, ntask, bases, active, ntiles); break;

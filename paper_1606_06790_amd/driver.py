@@ -167,6 +167,61 @@ class IDMRG:
         return out
 
 
+def prediction_probe(d):
+    """FP64 Lanczos iterations of iteration d.n + 1 from the current state with the prediction of Eq. (10)
+    and with a random start, each under the full stop rule and under the |dtheta| rule alone (plain Lanczos
+    counts, as the paper's comparison); the state and the precision are restored afterwards.  Returns
+    {label: [iterations per superblock]}."""
+    snap = d.snapshot()
+    keep = (d.predict, dict(d.cfg), d.prec)
+    out = {}
+    d.prec = "f64"
+    for label, predict, dtheta_only in (("with_prediction", True, False), ("with_prediction_dtheta_rule", True, True),
+                                        ("random_start", False, False), ("random_start_dtheta_rule", False, True)):
+        d.restore(snap)
+        d.predict = predict
+        d.cfg = dict(keep[1], tol_res=1e300 if dtheta_only else keep[1]["tol_res"])
+        d.step()
+        out[label] = [s["iters"] for s in d.steps if s["n"] == d.n]
+    d.predict, d.cfg, d.prec = keep
+    d.restore(snap)
+    return out
+
+
+def long_run(d, n_max, out, probe_at=()):
+    """Run to n_max, writing one JSON record per unit-cell period (l iterations) to `out`: the Step 5'
+    energy e_g, e^(n)_1 / (2n + 2), Lanczos iterations, fidelity errors (Eq. (12)), the truncation error
+    eps = max over the period of eps^(n)_1 (Eq. (14)), kept states and seconds per iteration."""
+    import sys
+    period = []
+    t_start = time.perf_counter()
+    while d.n < n_max:
+        if d.n + 1 in probe_at:
+            rec = dict(kind="prediction_probe", iteration=d.n + 1, **prediction_probe(d))
+            out.write(json.dumps(rec) + "\n")
+            out.flush()
+        r = d.step()
+        period.append(r)
+        if (d.n + 1) % d.ell == 0:
+            recs = [s for s in d.steps if s["n"] > d.n - d.ell]
+            first = [s for s in recs if s["i"] == 1]
+            its = [s["iters"] for s in recs]
+            fid = sorted(s["fidelity"] for s in recs)
+            rec = dict(kind="period", n=d.n, e_g=d.e_g[d.n], e_site_1=first[-1]["e_site"],
+                       eps=max(s["eps"] for s in first), m_kept=min(s["m_kept"] for s in recs),
+                       iters_mean=sum(its) / len(its), iters_min=min(its), iters_max=max(its),
+                       fidelity_median=fid[len(fid) // 2], fidelity_max=fid[-1],
+                       unconverged=sum(1 for s in recs if not s["converged"]),
+                       s_per_iteration=sum(p["seconds"] for p in period) / len(period),
+                       elapsed_s=time.perf_counter() - t_start)
+            out.write(json.dumps(rec) + "\n")
+            out.flush()
+            print(f"n={d.n} e_g={rec['e_g']:.10f} iters={rec['iters_mean']:.1f} "
+                  f"fid_med={rec['fidelity_median']:.1e} eps={rec['eps']:.2e} "
+                  f"{rec['s_per_iteration']:.3f} s/it", file=sys.stderr, flush=True)
+            period = []
+
+
 def main():
     import argparse
     ap = argparse.ArgumentParser(description="parallel iDMRG on one GPU")
@@ -175,11 +230,25 @@ def main():
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--prec", default=None)
     ap.add_argument("--dense", action="store_true")
+    ap.add_argument("--periods", default=None,
+                    help="write one record per unit-cell period to this file instead of one per superblock")
+    ap.add_argument("--tol-res", type=float, default=None, help="Lanczos residual tolerance (default: the workload's)")
+    ap.add_argument("--probe-at", type=int, nargs="*", default=[],
+                    help="iterations at which Lanczos counts with and without prediction are compared")
     a = ap.parse_args()
     over = {}
     if a.m:
         over["m"] = a.m
+    if a.tol_res:
+        over["tol_res"] = a.tol_res
     cfg = workloads.workload(a.workload, **over)
+    if a.periods:
+        d = IDMRG(cfg, prec=a.prec, dense=a.dense)
+        with open(a.periods, "w") as f:
+            f.write(json.dumps(dict(kind="config", workload=a.workload, m=cfg["m"], prec=d.prec,
+                                    tol_res=cfg["tol_res"], n_max=a.n or cfg["n_max"])) + "\n")
+            long_run(d, a.n or cfg["n_max"], f, set(a.probe_at))
+        return
     d = IDMRG(cfg, prec=a.prec, dense=a.dense, log=lambda r: print(json.dumps(r), flush=True))
     d.run(a.n or cfg["n_max"])
     print(json.dumps(dict(e_g=d.e_g)))

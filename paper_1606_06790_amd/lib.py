@@ -28,7 +28,7 @@ EXPORTS = ["idmrg_create", "idmrg_destroy", "idmrg_set_stream", "idmrg_last_erro
            "idmrg_envL_size", "idmrg_envR_size", "idmrg_U_size", "idmrg_V_size", "idmrg_heff_work",
            "heff_apply", "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction",
            "idmrg_profile", "idmrg_profile_get", "idmrg_workspace_size", "idmrg_set_workspace", "idmrg_get_stats",
-           "heff_apply_static"]
+           "heff_apply_static", "idmrg_tune_get", "idmrg_tune_set"]
 PROF_CLASSES = ["heff_gemm1", "heff_gemm2", "heff_mix", "convert", "lanczos_vec", "svd", "trunc_other", "env",
                 "predict", "heff_gemm1_lo", "heff_gemm2_lo", "heff_mix_lo"]
 
@@ -90,6 +90,11 @@ class WsQuery_t(C.Structure):
                 ("qp", C.POINTER(C.c_int32)), ("opts", C.POINTER(LanczosOpts_t))]
 
 
+class TuneEntry_t(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("stage", C.c_int32), ("log2_flops", C.c_int32), ("log2_n", C.c_int32),
+                ("log2_k", C.c_int32), ("tiling", C.c_int32), ("trial_ms", C.c_float * 8)]
+
+
 class Stats_t(C.Structure):
     _fields_ = [("device_allocs", C.c_int64), ("stream_syncs", C.c_int64), ("staged_bytes", C.c_int64),
                 ("plan_builds", C.c_int64)]
@@ -137,12 +142,14 @@ def load():
                                          C.POINTER(C.c_size_t)]
     lib.idmrg_set_workspace.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
     lib.idmrg_get_stats.argtypes = [C.c_void_p, C.POINTER(Stats_t)]
+    lib.idmrg_tune_get.argtypes = [C.c_void_p, C.POINTER(TuneEntry_t), C.c_int, C.POINTER(C.c_int)]
+    lib.idmrg_tune_set.argtypes = [C.c_void_p, C.POINTER(TuneEntry_t), C.c_int]
     lib.idmrg_profile.argtypes = [C.c_void_p, C.c_int]
     lib.idmrg_profile_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
     for name in ["idmrg_profile", "idmrg_profile_get", "idmrg_create", "idmrg_destroy", "idmrg_set_stream",
                  "idmrg_heff_work", "heff_apply", "idmrg_workspace_size", "idmrg_set_workspace", "idmrg_get_stats",
-                 "heff_apply_static",
+                 "heff_apply_static", "idmrg_tune_get", "idmrg_tune_set",
                  "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -254,6 +261,28 @@ class Context:
         t = torch.empty(new, dtype=torch.uint8, device=torch.device("cuda", self.device))
         _check(self, self.lib.idmrg_set_workspace(self.handle, C.c_void_p(t.data_ptr()), new))
         self.ws, self.ws_bytes = t, new
+
+    def tuning(self):
+        """The autotuner's table: [{prec, stage, log2_flops, log2_n, log2_k, tiling, trial_ms}]."""
+        n = C.c_int()
+        _check(self, self.lib.idmrg_tune_get(self.handle, None, 0, C.byref(n)))
+        arr = (TuneEntry_t * max(n.value, 1))()
+        _check(self, self.lib.idmrg_tune_get(self.handle, arr, n.value, C.byref(n)))
+        out = []
+        for e in arr[:n.value]:
+            d = {k: int(getattr(e, k)) for k, _ in TuneEntry_t._fields_ if k != "trial_ms"}
+            d["trial_ms"] = [round(float(x), 4) for x in e.trial_ms]
+            out.append(d)
+        return out
+
+    def set_tuning(self, entries):
+        """Install autotuner entries (from tuning(), e.g. a JSON cache of an earlier run)."""
+        arr = (TuneEntry_t * max(len(entries), 1))()
+        for i, d in enumerate(entries):
+            ms = list(d.get("trial_ms", [])) + [-1.0] * 8
+            arr[i] = TuneEntry_t(d["prec"], d["stage"], d["log2_flops"], d["log2_n"], d["log2_k"], d["tiling"],
+                                 (C.c_float * 8)(*ms[:8]))
+        _check(self, self.lib.idmrg_tune_set(self.handle, arr, len(entries)))
 
     def stats(self):
         st = Stats_t()

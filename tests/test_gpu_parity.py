@@ -350,7 +350,7 @@ def test_errors_are_reported(ctx):
 MIXED_TOL = {"f32": 5e-6, "bf16x3": 5e-5}   # max |y - y_64| / max |y_64| of one matvec
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
 def test_lanczos_repeatable_across_tuning(prec):
     """A fresh context tunes the GEMM tiling during its first solve (the first
     matvecs try every tile variant); the second solve uses the chosen variant
@@ -358,6 +358,7 @@ def test_lanczos_repeatable_across_tuning(prec):
     must agree bitwise."""
     c2 = lib.Context(0)
     cfg, r = _oracle_states("random_chain", 32, 7, tol_res=1e-10)
+    # (split-bf16 tries five tilings, the last the eight-wave 256 x 128 kernel)
     sts = [st for st in r["states"] if st["n"] in (6, 7)]
     probs = [_flat_problem(st) for st in sts]
     runs = []
