@@ -235,6 +235,9 @@ def main():
     ap.add_argument("--tol-res", type=float, default=None, help="Lanczos residual tolerance (default: the workload's)")
     ap.add_argument("--probe-at", type=int, nargs="*", default=[],
                     help="iterations at which Lanczos counts with and without prediction are compared")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of GEMM tile choices: read at start (if it matches this device and build), "
+                         "written at the end")
     a = ap.parse_args()
     over = {}
     if a.m:
@@ -244,14 +247,20 @@ def main():
     cfg = workloads.workload(a.workload, **over)
     if a.periods:
         d = IDMRG(cfg, prec=a.prec, dense=a.dense)
+        if a.tune_cache:
+            d.ctx.load_tuning(a.tune_cache)
         with open(a.periods, "w") as f:
             f.write(json.dumps(dict(kind="config", workload=a.workload, m=cfg["m"], prec=d.prec,
                                     tol_res=cfg["tol_res"], n_max=a.n or cfg["n_max"])) + "\n")
             long_run(d, a.n or cfg["n_max"], f, set(a.probe_at))
-        return
-    d = IDMRG(cfg, prec=a.prec, dense=a.dense, log=lambda r: print(json.dumps(r), flush=True))
-    d.run(a.n or cfg["n_max"])
-    print(json.dumps(dict(e_g=d.e_g)))
+    else:
+        d = IDMRG(cfg, prec=a.prec, dense=a.dense, log=lambda r: print(json.dumps(r), flush=True))
+        if a.tune_cache:
+            d.ctx.load_tuning(a.tune_cache)
+        d.run(a.n or cfg["n_max"])
+        print(json.dumps(dict(e_g=d.e_g)))
+    if a.tune_cache:
+        d.ctx.save_tuning(a.tune_cache)
 
 
 if __name__ == "__main__":

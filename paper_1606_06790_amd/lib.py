@@ -11,6 +11,7 @@ raises an error instead of falling back to anything else.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
@@ -283,6 +284,32 @@ class Context:
             arr[i] = TuneEntry_t(d["prec"], d["stage"], d["log2_flops"], d["log2_n"], d["log2_k"], d["tiling"],
                                  (C.c_float * 8)(*ms[:8]))
         _check(self, self.lib.idmrg_tune_set(self.handle, arr, len(entries)))
+
+    def _tuning_key(self):
+        """What a stored tuner table is valid for: the device and this exact build of the library."""
+        import hashlib
+        with open(LIB_PATH, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()[:16]
+        return dict(device=_torch().cuda.get_device_name(self.device), library=digest)
+
+    def load_tuning(self, path):
+        """Install the tuner table of a JSON cache written by save_tuning.  A cache written for another device or
+        another build of the library is ignored (its timings would not hold).  Returns the number of entries."""
+        if not os.path.exists(path):
+            return 0
+        with open(path) as f:
+            doc = json.load(f)
+        if doc.get("key") != self._tuning_key():
+            return 0
+        self.set_tuning(doc["entries"])
+        return len(doc["entries"])
+
+    def save_tuning(self, path):
+        """Write the tuner table, with the device and library it was measured on, as JSON."""
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(dict(key=self._tuning_key(), entries=self.tuning()), f, indent=1)
+        os.replace(tmp, path)
 
     def stats(self):
         st = Stats_t()

@@ -147,3 +147,32 @@ def test_nan_input_is_enumeric(case):
     with pytest.raises(lib.IdmrgError) as e:
         lib.truncate_twosite(ctx, [dict(left=A, right=B, psi=T(xb))], QP, 64)
     assert e.value.code == lib.ENUMERIC
+
+
+def test_tuning_cache_round_trip(case, tmp_path):
+    """A tuner table saved as JSON and loaded into a fresh context gives the same tile choices and bitwise the same
+    solve; a table stored for another build of the library is ignored."""
+    path = str(tmp_path / "tune.json")
+    out = []
+    for k in range(2):
+        ctx = lib.Context(0)
+        if k == 1:
+            assert ctx.load_tuning(path) > 0
+            loaded = {(e["prec"], e["stage"], e["log2_flops"], e["log2_n"], e["log2_k"]): e["tiling"]
+                      for e in ctx.tuning()}
+        psi = T(case["x"] / np.linalg.norm(case["x"]))
+        es, _ = lib.lanczos_solve_batch(ctx, [case["prob"]], [psi], k_max=40, prec="bf16x3")
+        out.append((es[0], H(psi)))
+        if k == 0:
+            ctx.save_tuning(path)
+            saved = {(e["prec"], e["stage"], e["log2_flops"], e["log2_n"], e["log2_k"]): e["tiling"]
+                     for e in ctx.tuning()}
+    assert saved and loaded == saved
+    assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
+    import json
+    with open(path) as f:
+        doc = json.load(f)
+    doc["key"]["library"] = "0" * 16
+    with open(path, "w") as f:
+        json.dump(doc, f)
+    assert lib.Context(0).load_tuning(path) == 0
