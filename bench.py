@@ -141,6 +141,22 @@ def note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+class marker:
+    """A named range on the roctx marker track (rocprofv3 --marker-trace), so that a kernel trace can be cut
+    into the timed regions.  Costs one host call at each end, outside the timed work."""
+
+    def __init__(self, label):
+        self.label = label
+
+    def __enter__(self):
+        import torch
+        torch.cuda.nvtx.range_push(self.label)
+
+    def __exit__(self, *exc):
+        import torch
+        torch.cuda.nvtx.range_pop()
+
+
 def wall(d, steps, warmup, label, profile=False):
     """warmup + timed unit-cell steps from the current state; (seconds per step, step records)."""
     import torch
@@ -150,12 +166,13 @@ def wall(d, steps, warmup, label, profile=False):
     if profile:
         d.ctx.profile(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        d.step()
-        note(f"{label}: timed step {k + 1}/{steps} done (n={d.n})")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with marker(f"timed:{label}"):
+        t0 = time.perf_counter()
+        for k in range(steps):
+            d.step()
+            note(f"{label}: timed step {k + 1}/{steps} done (n={d.n})")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     return (t1 - t0) / steps, [s for s in d.steps if s["n"] > d.n - steps]
 
 
@@ -215,10 +232,19 @@ def microbench(a):
                 prof = ctx.profile_get()
                 ctx.profile(False)
                 ms = sum(prof[k][1] for k in MATVEC) / reps
+                # the same calls as in production (no per-launch events), for a kernel trace of their launch gaps
+                torch.cuda.synchronize()
+                with marker(f"timed:micro_m{m}_{kind}_{prec}"):
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        lib.heff_apply(ctx, [prob], [x], [y], prec)
+                    torch.cuda.synchronize()
+                    wall_ms = (time.perf_counter() - t0) * 1e3 / reps
                 if prec == "f64":
                     y64 = y.clone()
                 err = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
                 rows.append(dict(m=m, blocks=kind, prec=prec, N=nx, flops=flops, kernel_ms=round(ms, 4),
+                                 wall_ms_per_call=round(wall_ms, 4),
                                  tflops=round(flops / (ms * 1e-3) / 1e12, 2), rel_err_vs_f64=err))
                 note(f"microbench m={m} {kind} {prec}: {rows[-1]['tflops']} TFLOP/s")
     print(json.dumps({"microbench": "H_eff matvec, Heisenberg chain MPO D=5, Gaussian environments and state",
@@ -254,6 +280,187 @@ def batching(a):
                       "graph_speedup_vs_direct": round(
                           out["batched_direct"]["ms_per_step"] / out["batched_graph"]["ms_per_step"], 3)}),
           flush=True)
+
+
+def launch_gaps(directory):
+    """Where the GPU idles inside each timed region of a kernel trace.
+
+    Reads the CSV output of `rocprofv3 --kernel-trace --marker-trace --output-format csv` (run on this file) and,
+    for every marker range named "timed:...", takes the kernels that start inside it:
+      busy  = the union of their execution intervals;
+      gaps  = idle time between one kernel's end and the next one's start (launch latency and host work);
+      lead  = from the range start to the first kernel, and tail = from the last kernel to the range end (host
+              work before the first launch and the final synchronisation).
+    Prints one JSON line with, per range, its length, kernel count, busy share and gap statistics."""
+    import csv
+    import glob
+
+    def rows(pattern):
+        out = []
+        for path in glob.glob(os.path.join(directory, "**", pattern), recursive=True):
+            with open(path, newline="") as f:
+                out.extend(csv.DictReader(f))
+        return out
+
+    kern = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows("*kernel_trace.csv"))
+    ranges = []
+    for r in rows("*marker_api_trace.csv"):
+        label = next((v for v in r.values() if isinstance(v, str) and v.startswith("timed:")), None)
+        if label:
+            ranges.append((label[6:], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    out = []
+    for label, t0, t1 in sorted(ranges, key=lambda x: x[1]):
+        ks = [k for k in kern if t0 <= k[0] < t1]
+        if not ks:
+            continue
+        busy, gaps, end = 0, [], ks[0][0]
+        for s, e in ks:
+            if s > end:
+                gaps.append(s - end)
+            busy += max(0, e - max(s, end))
+            end = max(end, e)
+        span = t1 - t0
+        gaps.sort()
+        out.append(dict(range=label, span_ms=round(span * 1e-6, 3), kernels=len(ks),
+                        busy_share=round(busy / span, 4), gap_share=round(sum(gaps) / span, 4),
+                        lead_us=round((ks[0][0] - t0) * 1e-3, 1), tail_us=round((t1 - end) * 1e-3, 1),
+                        gap_median_us=round(gaps[len(gaps) // 2] * 1e-3, 2) if gaps else 0.0,
+                        gap_p90_us=round(gaps[int(len(gaps) * 0.9)] * 1e-3, 2) if gaps else 0.0,
+                        gaps_over_100us_ms=round(sum(g for g in gaps if g > 100_000) * 1e-6, 3)))
+    print(json.dumps({"launch_gaps": directory, "ranges": out}), flush=True)
+
+
+def _csv_rows(directory, pattern):
+    import csv
+    import glob
+    out = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", pattern), recursive=True)):
+        with open(path, newline="") as f:
+            out.extend(csv.DictReader(f))
+    return out
+
+
+def stats_summary(directory, top=24):
+    """Markdown table of a `rocprofv3 --kernel-trace --stats --output-format csv` run under DIR (its
+    kernel_stats.csv): calls, total and average time and share per kernel."""
+    rows = _csv_rows(directory, "*kernel_stats.csv")
+    tot_ns = sum(float(r["TotalDurationNs"]) for r in rows)
+    calls = sum(int(r["Calls"]) for r in rows)
+    print(f"Total kernel time {tot_ns * 1e-9:.2f} s over {calls} dispatches.\n")
+    print("| Kernel | Calls | Total ms | Avg ms | % |\n|---|---|---|---|---|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+        print(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['TotalDurationNs']) * 1e-6:.1f} | "
+              f"{float(r['AverageNs']) * 1e-6:.4f} | {100 * float(r['TotalDurationNs']) / tot_ns:.2f} |")
+
+
+def traffic_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, top=18):
+    """Markdown summary of HBM traffic per kernel from four `rocprofv3 --pmc <counter> --output-format csv` runs:
+    FETCH_SIZE and WRITE_SIZE over the benchmark, and the same two counters over `--copy-calibration` (a plain
+    device copy of known size, which gives the counter's bytes per KiB read).  Ends with the records that
+    measured_traffic() reads for the split-bf16 GEMM stages, stamped with the current sources hash."""
+    import hashlib
+    from collections import defaultdict
+
+    def per_kernel(directory, counter):
+        acc = defaultdict(lambda: [0, 0.0])
+        for r in _csv_rows(directory, "*counter_collection.csv"):
+            if r["Counter_Name"] == counter:
+                a = acc[r["Kernel_Name"]]
+                a[0] += 1
+                a[1] += float(r["Counter_Value"])
+        return {k: (n, v / n) for k, (n, v) in acc.items()}
+
+    copy_bytes = 268435456
+    cf = max(per_kernel(cal_fetch_dir, "FETCH_SIZE").items(), key=lambda kv: kv[1][0] * kv[1][1])
+    cw = max(per_kernel(cal_write_dir, "WRITE_SIZE").items(), key=lambda kv: kv[1][0] * kv[1][1])
+    ff = cf[1][1] * 1024 / copy_bytes
+    fw = cw[1][1] * 1024 / copy_bytes
+    print(f"* FETCH_SIZE read {cf[1][1]:.1f} KiB for {copy_bytes // 1024} KiB moved (`{cf[0][:60]}`): factor {ff:.5f} "
+          f"(bytes = KiB x 1024 / {ff:.5f})")
+    print(f"* WRITE_SIZE read {cw[1][1]:.1f} KiB for {copy_bytes // 1024} KiB moved: factor {fw:.5f}\n")
+    fe, wr = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    rows = []
+    for k in fe:
+        n, f = fe[k]
+        w = wr.get(k, (0, 0.0))[1]
+        rows.append((k, n, f, w, f * 1024 / ff + w * 1024 / fw))
+    rows.sort(key=lambda r: -r[1] * r[4])
+    print("| Kernel | Dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | HBM bytes/dispatch (calibrated) |")
+    print("|---|---|---|---|---|")
+    for k, n, f, w, b in rows[:top]:
+        print(f"| `{k[:90]}` | {n} | {f:.1f} | {w:.1f} | {b:.4e} |")
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    print("\nRecords read by bench.py for the roofline kernel (split-bf16 GEMM stage 1 and stage 2, the tile variant "
+          "with the most dispatches):\n")
+    for cls, tag in (("heff_gemm1_lo", "gemm_bf16x3_kernel<0,"), ("heff_gemm2_lo", "gemm_bf16x3_kernel<1,")):
+        cand = [r for r in rows if tag in r[0].replace(" ", "")]
+        if cand:
+            k, n, f, w, b = max(cand, key=lambda r: r[1])
+            name = k.split("(")[0].replace("void ", "")
+            print(f"traffic-record: class={cls} kernel={name} bytes_per_launch={b:.6e} sources_sha256={h.hexdigest()}\n")
+    print(f"`sources_sha256` is the SHA-256 of {', '.join(TRAFFIC_SOURCES)} (concatenated) when the counters were "
+          "taken; bench.py reports the traffic only while it still matches.")
+
+
+MFMA_PEAK_TFLOPS = {"BF16": 2500.0, "F16": 2500.0, "F32": 157.3, "F64": 78.6}
+
+
+def mfma_counters(directory):
+    """MFMA utilisation per kernel from a `rocprofv3 --pmc ... --kernel-trace --output-format csv` run.
+
+    Per dispatch: MFMA flops executed = 512 x SQ_INSTS_VALU_MFMA_MOPS_<type> (the counter counts units of 512
+    flops, padding of ragged tiles included); rate = flops / kernel duration; share of the type's dense peak.
+    rocprofv3's derived metric MfmaUtil (MFMA-busy SIMD cycles over active cycles x SIMDs, in percent) is
+    averaged weighted by duration.  Per kernel over its dispatches; prints one JSON line."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def rows(pattern):
+        out = []
+        for path in glob.glob(os.path.join(directory, "**", pattern), recursive=True):
+            with open(path, newline="") as f:
+                out.extend(csv.DictReader(f))
+        return out
+
+    dur = {}
+    for r in rows("*kernel_trace.csv"):
+        dur[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    per = defaultdict(lambda: defaultdict(float))
+    name = {}
+    for r in rows("*counter_collection.csv"):
+        did = r["Dispatch_Id"]
+        per[did][r["Counter_Name"]] += float(r["Counter_Value"])
+        name[did] = r["Kernel_Name"]
+        if did not in dur and r.get("Start_Timestamp") and r.get("End_Timestamp"):
+            dur[did] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    agg = defaultdict(lambda: defaultdict(float))
+    for did, c in per.items():
+        if did not in dur or dur[did] <= 0:
+            continue
+        a = agg[name[did]]
+        a["dispatches"] += 1
+        a["ns"] += dur[did]
+        for k, v in c.items():
+            if k == "MfmaUtil":
+                a["MfmaUtil_ns"] += v * dur[did]
+            else:
+                a[k] += v
+    out = []
+    for kname, a in sorted(agg.items(), key=lambda kv: -kv[1]["ns"]):
+        row = dict(kernel=kname[:96], dispatches=int(a["dispatches"]), avg_ms=round(a["ns"] / a["dispatches"] * 1e-6, 4))
+        for typ, peak in MFMA_PEAK_TFLOPS.items():
+            mops = a.get(f"SQ_INSTS_VALU_MFMA_MOPS_{typ}", 0.0)
+            if mops > 0:
+                tf = 512.0 * mops / (a["ns"] * 1e-9) / 1e12
+                row[f"mfma_{typ.lower()}_tflops"] = round(tf, 2)
+                row[f"mfma_{typ.lower()}_peak_share"] = round(tf / peak, 4)
+        if "MfmaUtil_ns" in a:
+            row["mfma_util_pct"] = round(a["MfmaUtil_ns"] / a["ns"], 2)
+        out.append(row)
+    print(json.dumps({"mfma_counters": directory, "kernels": out[:20]}), flush=True)
 
 
 def copy_calibration():
@@ -331,7 +538,30 @@ def main():
                     help="only compare batched (graph / direct) against one call per superblock on --workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (reference for HBM byte counters)")
+    ap.add_argument("--launch-gaps", metavar="DIR", default=None,
+                    help="only summarise the GPU idle time inside the timed regions of a rocprofv3 kernel + marker "
+                         "trace (CSV) found under DIR; runs on the CPU")
+    ap.add_argument("--mfma-counters", metavar="DIR", default=None,
+                    help="only summarise MFMA utilisation per kernel from a rocprofv3 --pmc run (CSV) under DIR; "
+                         "runs on the CPU")
+    ap.add_argument("--stats-summary", metavar="DIR", default=None,
+                    help="only print a markdown table of a rocprofv3 --stats run (CSV) under DIR; runs on the CPU")
+    ap.add_argument("--traffic-summary", metavar="DIR", nargs=4, default=None,
+                    help="only summarise HBM traffic from four rocprofv3 --pmc runs (CSV): FETCH_SIZE and "
+                         "WRITE_SIZE of the benchmark, then of --copy-calibration; runs on the CPU")
     a = ap.parse_args()
+    if a.stats_summary:
+        stats_summary(a.stats_summary)
+        return
+    if a.traffic_summary:
+        traffic_summary(*a.traffic_summary)
+        return
+    if a.launch_gaps:
+        launch_gaps(a.launch_gaps)
+        return
+    if a.mfma_counters:
+        mfma_counters(a.mfma_counters)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU (one process, no collectives); use --gpus 1"}))
         sys.exit(2)

@@ -74,3 +74,69 @@ def test_roofline_entry(tmp_path, monkeypatch, prec):
     else:
         assert out["traffic"] is None
 
+
+
+def test_launch_gaps_from_a_trace(tmp_path, capsys):
+    """The launch-gap summary of a synthetic rocprofv3 CSV pair: two overlapping kernels, a gap, a third kernel,
+    inside one timed range; a kernel outside the range is ignored."""
+    d = tmp_path / "trace" / "host"
+    d.mkdir(parents=True)
+    (d / "x_kernel_trace.csv").write_text(
+        '"Kind","Kernel_Name","Start_Timestamp","End_Timestamp"\n'
+        '"KERNEL_DISPATCH","a",1000,5000\n'
+        '"KERNEL_DISPATCH","b",4000,6000\n'
+        '"KERNEL_DISPATCH","c",8000,9000\n'
+        '"KERNEL_DISPATCH","d",20000,21000\n')
+    (d / "x_marker_api_trace.csv").write_text(
+        '"Domain","Function","Process_Id","Start_Timestamp","End_Timestamp"\n'
+        '"MARKER_CORE_API","timed:f64",1,500,10000\n')
+    bench.launch_gaps(str(tmp_path / "trace"))
+    r = json.loads(capsys.readouterr().out.strip().splitlines()[-1])["ranges"]
+    assert len(r) == 1 and r[0]["range"] == "f64" and r[0]["kernels"] == 3
+    assert r[0]["busy_share"] == round(6000 / 9500, 4)        # [1000, 6000] and [8000, 9000]
+    assert r[0]["gap_share"] == round(2000 / 9500, 4)
+    assert r[0]["lead_us"] == 0.5 and r[0]["tail_us"] == 1.0
+
+
+def test_mfma_counters_from_a_trace(tmp_path, capsys):
+    """The MFMA summary of a synthetic rocprofv3 --pmc CSV: two dispatches of one kernel, 1 ms each."""
+    d = tmp_path / "pmc"
+    d.mkdir()
+    (d / "k_kernel_trace.csv").write_text(
+        '"Dispatch_Id","Kernel_Name","Start_Timestamp","End_Timestamp"\n'
+        '"1","g",0,1000000\n"2","g",2000000,3000000\n')
+    rows = ['"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"']
+    for did in (1, 2):
+        rows += [f'"{did}","g","SQ_INSTS_VALU_MFMA_MOPS_BF16","{1.25e15 * 1e-3 / 512}"',
+                 f'"{did}","g","MfmaUtil","{40.0 + 20 * (did - 1)}"']
+    (d / "k_counter_collection.csv").write_text("\n".join(rows) + "\n")
+    bench.mfma_counters(str(d))
+    k = json.loads(capsys.readouterr().out.strip().splitlines()[-1])["kernels"][0]
+    assert k["dispatches"] == 2 and k["avg_ms"] == 1.0
+    assert k["mfma_bf16_tflops"] == 1250.0 and k["mfma_bf16_peak_share"] == 0.5
+    assert k["mfma_util_pct"] == 50.0
+
+
+def test_traffic_summary_writes_current_records(tmp_path, capsys, monkeypatch):
+    """The traffic summary of synthetic --pmc CSVs calibrates by the copy and stamps the records with the sources
+    hash, so that measured_traffic() reads them back."""
+    def pmc(name, counter, rows):
+        d = tmp_path / name
+        d.mkdir()
+        lines = ['"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"']
+        lines += [f'"{i}","{k}","{counter}","{v}"' for i, (k, v) in enumerate(rows)]
+        (d / "run_counter_collection.csv").write_text("\n".join(lines) + "\n")
+        return str(d)
+    g1, g2 = "void gemm_bf16x3_kernel<0, 128, 128>(int)", "void gemm_bf16x3_kernel<1, 128, 128>(int)"
+    f = pmc("f", "FETCH_SIZE", [(g1, 1000.0), (g1, 1000.0), (g2, 500.0)])
+    w = pmc("w", "WRITE_SIZE", [(g1, 100.0), (g1, 100.0), (g2, 50.0)])
+    cf = pmc("cf", "FETCH_SIZE", [("copy", 131072.0)] * 3)          # factor 0.5
+    cw = pmc("cw", "WRITE_SIZE", [("copy", 262144.0)] * 3)          # factor 1
+    bench.traffic_summary(f, w, cf, cw)
+    out = capsys.readouterr().out
+    rec = tmp_path / "traffic.md"
+    rec.write_text(out)
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(rec))
+    t = bench.measured_traffic()
+    assert t["heff_gemm1_lo"] == ("gemm_bf16x3_kernel<0, 128, 128>", 1000 * 1024 / 0.5 + 100 * 1024)
+    assert t["heff_gemm2_lo"][1] == 500 * 1024 / 0.5 + 50 * 1024
