@@ -348,7 +348,10 @@ int idmrg_set_workspace(idmrg_ctx* ctx, void* ptr, size_t bytes);
  * not depend on it) and the fastest is kept for that bucket: precision, stage
  * (0: environment-L GEMM, 1: environment-R GEMM), log2 of the stage's flops and
  * of its flop-weighted mean N and K.  Tilings: 0 64x64, 1 128x64, 2 64x128,
- * 3 128x128, 4 256x128 (split-bf16 only, eight waves).  idmrg_tune_get copies up
+ * 3 128x128, 4 256x128 (split-bf16 only: eight waves, the operand reads of
+ * each K-slab overlapped with the previous slab's MFMAs), 5 128x128 (split-bf16
+ * only: persistent workgroups that copy the next tile's first K-slab while the
+ * current tile finishes).  idmrg_tune_get copies up
  * to cap entries (with the trial times, -1 where a tiling was not tried) and
  * sets *n to the number of entries; idmrg_tune_set installs entries (a cache
  * from an earlier process), which are then not measured again. */

@@ -97,7 +97,7 @@ struct idmrg_ctx {
   // trial time of each tiling (ms, -1 if not tried)
   std::map<std::tuple<int, int, int, int, int>, int> tune;
   std::map<std::tuple<int, int, int, int, int>, std::vector<float>> tune_ms;
-  hipEvent_t tev[5][4] = {};   // [variant][stage-1 start, stage-1 end, stage-2 start, stage-2 end]
+  hipEvent_t tev[6][4] = {};   // [variant][stage-1 start, stage-1 end, stage-2 start, stage-2 end]
   // the plan of the last call of each kind and the hash of its inputs
   uint64_t cache_key[kOps] = {};
   std::shared_ptr<CallPlan> cache[kOps];
@@ -367,8 +367,12 @@ std::shared_ptr<T> plan_of(idmrg_ctx* c, int op, uint64_t key, F&& build) {
 // ------------------------------------------------------------------ H_eff execution
 
 // Output tilings of the GEMM kernels: code c < 4 -> (c & 1 ? 128 : 64) x (c & 2 ? 128 : 64) (four waves);
-// code 4 -> 256 x 128 (split-bf16 only: eight waves, three LDS stages).
-constexpr int kTilings = 5;
+// code 4 -> 256 x 128 (split-bf16 only: eight waves, three LDS stages, the
+// operand reads of each slab overlapped with the previous slab's MFMAs);
+// code 5 -> 128 x 128 (split-bf16 only: persistent workgroups, the copy
+// pipeline running on across tiles).
+constexpr int kTilings = 6;
+static_assert(sizeof(idmrg_ctx::tev) / sizeof(idmrg_ctx::tev[0]) >= kTilings, "one event row per tiling variant");
 
 struct HeffExec {
   HeffPlan plan;
@@ -477,7 +481,7 @@ void heff_plan(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, int prec,
   ex.npsi = ex.plan.n_psi;
   // Tile variants.  The tile shape does not change the order in which any
   // output element accumulates over k, so all variants give identical results.
-  ex.nvar = frag ? 5 : 4;
+  ex.nvar = frag ? 6 : 4;
   for (int v = 0; v < ex.nvar; ++v) ex.code[v] = v;
   for (int st = 0; st < 2; ++st) {
     const GemmList& base = st == 0 ? (frag ? ex.plan.f1 : ex.plan.g1) : (frag ? ex.plan.f2 : ex.plan.g2);
@@ -486,6 +490,8 @@ void heff_plan(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, int prec,
       ex.var[st].push_back(base);
       if (ex.code[v] == 4)
         ex.var[st][v].retile(256, 128);
+      else if (ex.code[v] == 5)
+        ex.var[st][v].retile(128, 128);
       else
         ex.var[st][v].retile(ex.code[v] & 1 ? 128 : 64, ex.code[v] & 2 ? 128 : 64);
       ex.tiles[st][v] = ex.var[st][v].tiles;
@@ -1231,7 +1237,7 @@ extern "C" int idmrg_tune_set(idmrg_ctx* c, const idmrg_tune_entry* in, int n) {
   for (int k = 0; k < n; ++k) {
     const idmrg_tune_entry& e = in[k];
     if (e.prec < 0 || e.prec > 2 || e.stage < 0 || e.stage > 1 || e.tiling < 0 || e.tiling >= kTilings ||
-        (e.tiling == 4 && e.prec != IDMRG_PREC_BF16X3))
+        (e.tiling >= 4 && e.prec != IDMRG_PREC_BF16X3))
       return IDMRG_EINVAL;
   }
   for (int k = 0; k < n; ++k) {

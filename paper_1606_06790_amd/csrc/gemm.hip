@@ -375,24 +375,227 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
       }
 }
 
-// The same product with a 256 x 128 tile: 8 waves (4 x 2) of 64 x 64 (the
-// same register footprint per wave as the 128 x 128 tile, so still two waves
-// per SIMD), three LDS stages of 48 KB (144 KB, one workgroup per CU), and the
-// copies of each slab issued two slabs ahead, so that a copy has two slabs of
-// MFMA work (~1500 cycles per SIMD) to land instead of one.  Slab k + 2 goes
-// into the stage that slab k - 1 used; the barrier at the top of slab k, after
-// each thread has waited for its own copies of slab k, makes every copy of
-// slab k visible and ends every read of slab k - 1.  The barrier carries no
-// memory fence (a fence would wait for the copies in flight as well).
+// The 128 x 128 tile as a persistent kernel: kPersistPerCu workgroups per CU,
+// each going through a fixed sequence of tiles of its XCD's range, with the
+// copy pipeline running on across tile boundaries.  The first slab of the next
+// tile is copied while the last slab of the current one is multiplied, and its
+// result is stored while that copy is in flight, so a tile costs no pipeline
+// fill (with K of a few hundred, one fill is a sizeable part of a tile).
+// Within a tile everything is as in gemm_bf16x3_kernel<STAGE, 128, 128>: the
+// same slabs, fragments, MFMA order and stores, so the results are identical.
+constexpr int kPersistPerCu = 2, kCus = 256;
+
+// Plan tables read through the constant address space with wave-uniform
+// indices become scalar loads: they then wait on lgkmcnt, not on vmcnt, so
+// looking up the next tile does not wait for the copies in flight.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
+__device__ __forceinline__ int find_task_c(cptr<GemmTask> tasks, int ntask, int tile) {
+  int lo = 0, hi = ntask - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 template <int STAGE>
-__global__ __launch_bounds__(512) void gemm_bf16x3_w8_kernel(const GemmTask* __restrict__ tasks, int ntask,
-                                                             void* const* __restrict__ bases,
-                                                             const int32_t* __restrict__ active, int ntiles) {
+__global__ __launch_bounds__(256) void gemm_bf16x3_persist_kernel(const GemmTask* __restrict__ tasks_, int ntask,
+                                                                  void* const* __restrict__ bases_,
+                                                                  const int32_t* __restrict__ active_, int ntiles) {
+  constexpr int BM = 128, BN = 128;
+  constexpr int FA = BM / 16, FB = BN / 16;
+  constexpr int UA = FA / 2, UB = FB / 2;
+  constexpr int TI = BM / 32, TJ = BN / 32;
+  constexpr uint32_t kFragBytes = kFragWords * 4;
+  __shared__ v4u As[2][FA * 128], Bs[2][FB * 128];
+  const cptr<GemmTask> tasks = as_const(tasks_);
+  const cptr<void*> bases = as_const(bases_);
+  const cptr<int32_t> active = active_ ? as_const(active_) : nullptr;
+  // this workgroup's tiles: start, start + step, ... below t1 (workgroups go round-robin over the XCDs)
+  const int G = (int)gridDim.x, xcd = (int)(blockIdx.x % kXcd), slot = (int)(blockIdx.x / kXcd);
+  const int per = (ntiles + kXcd - 1) / kXcd, step = G / kXcd;
+  const int t1 = min((xcd + 1) * per, ntiles);
+  // a tile's task, looked up once when the copy cursor reaches the tile
+  struct Tile {
+    int t, kb, m0, n0, M, N, K, ldc, beta;
+    int64_t coff;
+    const char *A, *B;
+    float* C;
+  };
+  // next tile at or after t of this workgroup whose problem is active, with its task (t = t1: none left)
+  auto fetch = [&](int t, Tile& x) {
+    for (; t < t1; t += step) {
+      const int ti = __builtin_amdgcn_readfirstlane(find_task_c(tasks, ntask, t));
+      const int prob = tasks[ti].prob;
+      if (active && !active[prob]) continue;
+      const int local = t - tasks[ti].tile0, tiles_n = tasks[ti].tiles_n;
+      x.t = t;
+      x.m0 = (local / tiles_n) * BM;
+      x.n0 = (local % tiles_n) * BN;
+      x.M = tasks[ti].M; x.N = tasks[ti].N; x.K = tasks[ti].K; x.ldc = tasks[ti].ldc; x.beta = tasks[ti].beta;
+      x.kb = (x.K + kFragK - 1) / kFragK;
+      x.A = reinterpret_cast<const char*>(bases[prob * kNumBases + tasks[ti].abase]) + tasks[ti].aoff * 4;
+      x.B = reinterpret_cast<const char*>(bases[prob * kNumBases + tasks[ti].bbase]) + tasks[ti].boff * 4;
+      x.C = reinterpret_cast<float*>(bases[prob * kNumBases + tasks[ti].cbase]) + tasks[ti].coff;
+      return;
+    }
+    x.t = t1;
+  };
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int half = t >> 7, within = t & 127;
+  const int wdst = half * 128 + (wave & 1) * 64;
+
+  v4f acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+  // store the accumulators as tile x (and clear them)
+  auto store_tile = [&](const Tile& x) {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = x.m0 + wr * (BM / 2) + i * 16 + 4 * (lane >> 4) + r;
+          const int gn = x.n0 + wc * (BN / 2) + j * 16 + (lane & 15);
+          if (gi < x.M && gn < x.N) {
+            float* p = x.C + (int64_t)gi * x.ldc + gn;
+            *p = x.beta ? (*p + acc[i][j][r]) : acc[i][j][r];
+          }
+        }
+        acc[i][j] = v4f{0, 0, 0, 0};
+      }
+  };
+  // the result of a tile with K = 0: zero (or C unchanged where the task accumulates)
+  auto zero_tile = [&](const Tile& x) {
+    if (x.beta) return;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = x.m0 + wr * (BM / 2) + i * 16 + 4 * (lane >> 4) + r;
+          const int gn = x.n0 + wc * (BN / 2) + j * 16 + (lane & 15);
+          if (gi < x.M && gn < x.N) x.C[(int64_t)gi * x.ldc + gn] = 0.f;
+        }
+  };
+  // next tile with slabs at or after t (the copy cursor passes over tiles with K = 0; the multiplying side
+  // gives them their result)
+  auto next_copy_tile = [&](int t, Tile& x) {
+    for (fetch(t, x); x.t < t1 && x.kb == 0; fetch(x.t + step, x)) {
+    }
+  };
+  auto next_mul_tile = [&](int t, Tile& x) {
+    for (fetch(t, x); x.t < t1 && x.kb == 0; fetch(x.t + step, x)) zero_tile(x);
+  };
+
+  // copy cursor: tile cx, slab kc
+  Tile cx, mx;
+  int kc = 0;
+  uint32_t ao[UA], bo[UB];
+  auto set_offsets = [&]() {
+    const int RA = (cx.M + kFragRows - 1) / kFragRows, RB = (cx.N + kFragRows - 1) / kFragRows;
+#pragma unroll
+    for (int u = 0; u < UA; ++u)
+      ao[u] = (uint32_t)min(cx.m0 / kFragRows + 2 * u + half, RA - 1) * (uint32_t)cx.kb * kFragBytes + within * 16u;
+#pragma unroll
+    for (int u = 0; u < UB; ++u)
+      bo[u] = (uint32_t)min(cx.n0 / kFragRows + 2 * u + half, RB - 1) * (uint32_t)cx.kb * kFragBytes + within * 16u;
+  };
+  // issue the copy at the cursor into stage st and advance the cursor
+  auto copy_next = [&](int st) {
+    const gptr<char> Ak = as_global(cx.A + (size_t)kc * kFragBytes);
+    const gptr<char> Bk = as_global(cx.B + (size_t)kc * kFragBytes);
+#pragma unroll
+    for (int u = 0; u < UA; ++u) lds_copy16(Ak + ao[u], &As[st][u * 256 + wdst]);
+#pragma unroll
+    for (int u = 0; u < UB; ++u) lds_copy16(Bk + bo[u], &Bs[st][u * 256 + wdst]);
+    if (++kc == cx.kb) {
+      kc = 0;
+      next_copy_tile(cx.t + step, cx);
+      if (cx.t < t1) set_offsets();
+    }
+  };
+
+  next_mul_tile(xcd * per + slot, mx);   // the tile being multiplied, at slab km
+  if (mx.t >= t1) return;
+  cx = mx;
+  set_offsets();
+  copy_next(0);
+  int cur = 0;
+  for (;;) {
+    for (int km = 0; km < mx.kb; ++km, cur ^= 1) {
+      // this slab's copy has landed in every wave; the other stage is free
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      v8bf ah[TI], al[TI], bh[TJ], bl[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        const int f = wr * TI + i;
+        ah[i] = __builtin_bit_cast(v8bf, As[cur][f * 128 + lane]);
+        al[i] = __builtin_bit_cast(v8bf, As[cur][f * 128 + 64 + lane]);
+      }
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        const int f = wc * TJ + j;
+        bh[j] = __builtin_bit_cast(v8bf, Bs[cur][f * 128 + lane]);
+        bl[j] = __builtin_bit_cast(v8bf, Bs[cur][f * 128 + 64 + lane]);
+      }
+      if (cx.t < t1) copy_next(cur ^ 1);
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // the tile is done: store it while the next tile's first slab is in flight
+    store_tile(mx);
+    next_mul_tile(mx.t + step, mx);
+    if (mx.t >= t1) break;
+  }
+}
+
+// The 256 x 128 eight-wave tile with its operand reads software-pipelined:
+// while the MFMAs of slab k run from one register set, the wave reads slab
+// k + 1 from LDS into the other, and the copies of slab k + 3 are in flight
+// into the third LDS stage.  So a wave does not wait for LDS data before its
+// MFMAs, and a copy has two slabs of MFMA work to land.  Step k:
+//   * wait for this thread's copies of slab k + 1 (those of k + 2 may still
+//     be in flight); barrier: every copy of slab k + 1 is visible, and every
+//     wave has finished reading slab k's stage (in step k - 1);
+//   * copy slab k + 3 into slab k's stage;
+//   * one asm block: the 16 reads of slab k + 1 interleaved with the 48 MFMAs
+//     of slab k (one read per three MFMAs), then a wait for the reads.
+// The reads and MFMAs are written out in asm because the compiler treats every
+// LDS read that follows an LDS copy as dependent on it, whichever stage it
+// writes, and would wait for all copies in flight before the first read.  The
+// block waits for its own reads before it ends, so no read is in flight outside
+// it.  The MFMAs of one block go over the 16 tiles of the wave in three passes
+// (lo*hi, hi*lo, hi*hi), so two MFMAs on one accumulator are 16 apart.  The
+// s_nop at the start of each block and after the loop give the wait states
+// between these MFMAs and the vector instructions around them.  The read after
+// the last slab takes a stale stage into registers that nothing uses.
+template <int STAGE>
+__global__ __launch_bounds__(512) void gemm_bf16x3_pipe_kernel(const GemmTask* __restrict__ tasks, int ntask,
+                                                               void* const* __restrict__ bases,
+                                                               const int32_t* __restrict__ active, int ntiles) {
   constexpr int BM = 256, BN = 128, NS = 3;
   constexpr int FA = BM / 16, FB = BN / 16;    // fragments per slab
-  constexpr int UA = FA / 4, UB = FB / 4;      // 16-byte copies per thread per slab (4 fragments per 512 threads)
+  constexpr int UA = FA / 4, UB = FB / 4;      // 16-byte copies per thread per slab
   constexpr int NCOPY = UA + UB;
-  constexpr int TI = 4, TJ = 4;                // 16 x 16 MFMA tiles per wave
+  constexpr int TI = 4, TJ = 4;                // 16 x 16 MFMA tiles per wave (64 x 64)
   constexpr uint32_t kFragBytes = kFragWords * 4;
   __shared__ v4u As[NS][FA * 128], Bs[NS][FB * 128];
   const int tile = xcd_tile(ntiles);
@@ -412,8 +615,8 @@ __global__ __launch_bounds__(512) void gemm_bf16x3_w8_kernel(const GemmTask* __r
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // Copy u of thread t: fragment 4u + t/128 of the slab, chunk t % 128 of it; the
-  // LDS destination of the wave is chunk 64 (wave % 2) of that fragment.
+  // Copy u of thread t: fragment 4u + t/128 of the slab, chunk t % 128 of it;
+  // the LDS destination of the wave is chunk 64 (wave % 2) of that fragment.
   const int quarter = t >> 7, within = t & 127;
   uint32_t ao[UA], bo[UB];
 #pragma unroll
@@ -435,32 +638,29 @@ __global__ __launch_bounds__(512) void gemm_bf16x3_w8_kernel(const GemmTask* __r
 #pragma unroll
     for (int u = 0; u < UB; ++u) lds_copy16(Bk + bo[u], &Bs[st][u * 512 + wdst]);
   };
+  // LDS byte addresses of this wave's operands in stage st
+  auto a_at = [&](int st) { return lds_addr(&As[st][wr * TI * 128 + lane]); };
+  auto b_at = [&](int st) { return lds_addr(&Bs[st][wc * TJ * 128 + lane]); };
 
   v4f acc[TI][TJ];
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+  v4u F0[16], F1[16];
 
   if (KB > 0) copy(0, 0);
   if (KB > 1) copy(1, 1);
-  int cur = 0;
-  for (int kb = 0; kb < KB; ++kb) {
-    // this thread's copies of slab kb have landed (those of slab kb + 1 may still be in flight)
-    if (kb + 1 < KB)
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NCOPY) : "memory");
-    else
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    if (kb + 2 < KB) copy(kb + 2, cur == 0 ? 2 : cur - 1);
-    // The wave's 16 operand reads in one asm block that ends with their own
-    // wait: the compiler would otherwise make an LDS read that follows the
-    // copies wait for all of them (it cannot tell that they write other
-    // stages), which is the one-slab pipeline again.  Outputs are early-clobber,
-    // so no read lands in an address register that a later read still needs.
-    const uint32_t abase = lds_addr(&As[cur][wr * TI * 128 + lane]);
-    const uint32_t bbase = lds_addr(&Bs[cur][wc * TJ * 128 + lane]);
-    v4u r[16];
+  if (KB > 2) copy(2, 2);
+  if (KB > 2)
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * NCOPY) : "memory");
+  else if (KB > 1)
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NCOPY) : "memory");
+  else
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  {
+    const uint32_t abase = a_at(0), bbase = b_at(0);
     asm volatile(
         "ds_read_b128 %0, %16 offset:0\n\t"
         "ds_read_b128 %1, %16 offset:1024\n\t"
@@ -479,29 +679,124 @@ __global__ __launch_bounds__(512) void gemm_bf16x3_w8_kernel(const GemmTask* __r
         "ds_read_b128 %14, %17 offset:6144\n\t"
         "ds_read_b128 %15, %17 offset:7168\n\t"
         "s_waitcnt lgkmcnt(0)"
-        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]),
-          "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10]), "=&v"(r[11]), "=&v"(r[12]), "=&v"(r[13]),
-          "=&v"(r[14]), "=&v"(r[15])
+        : "=&v"(F0[0]), "=&v"(F0[1]), "=&v"(F0[2]), "=&v"(F0[3]), "=&v"(F0[4]), "=&v"(F0[5]), "=&v"(F0[6]),
+          "=&v"(F0[7]), "=&v"(F0[8]), "=&v"(F0[9]), "=&v"(F0[10]), "=&v"(F0[11]), "=&v"(F0[12]),
+          "=&v"(F0[13]), "=&v"(F0[14]), "=&v"(F0[15])
         : "v"(abase), "v"(bbase)
         : "memory");
-    v8bf ah[TI], al[TI], bh[TJ], bl[TJ];
-#pragma unroll
-    for (int i = 0; i < TI; ++i) {
-      ah[i] = __builtin_bit_cast(v8bf, r[2 * i]);
-      al[i] = __builtin_bit_cast(v8bf, r[2 * i + 1]);
-      bh[i] = __builtin_bit_cast(v8bf, r[8 + 2 * i]);
-      bl[i] = __builtin_bit_cast(v8bf, r[8 + 2 * i + 1]);
-    }
-#pragma unroll
-    for (int i = 0; i < TI; ++i)
-#pragma unroll
-      for (int j = 0; j < TJ; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-      }
-    cur = cur == NS - 1 ? 0 : cur + 1;
   }
+
+  // One step k: FC holds slab k, FN receives slab k + 1.
+#define IDMRG_PIPE_STEP(k, FC, FN)                                                                     \
+  do {                                                                                                 \
+    if ((k) + 2 < KB)                                                                                  \
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NCOPY) : "memory");                                     \
+    else                                                                                               \
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");                                                 \
+    __builtin_amdgcn_s_barrier();                                                                      \
+    const int st = (k) % NS;                                                                           \
+    if ((k) + 3 < KB) copy((k) + 3, st);                                                               \
+    const int nx = st == NS - 1 ? 0 : st + 1;                                                          \
+    const uint32_t abase = a_at(nx), bbase = b_at(nx);                                                 \
+    asm volatile(                                                                                      \
+IDMRG_PIPE_ASM                                                                                         \
+        : "=&v"(FN[0]), "=&v"(FN[1]), "=&v"(FN[2]), "=&v"(FN[3]), "=&v"(FN[4]), "=&v"(FN[5]),          \
+          "=&v"(FN[6]), "=&v"(FN[7]), "=&v"(FN[8]), "=&v"(FN[9]), "=&v"(FN[10]), "=&v"(FN[11]),        \
+          "=&v"(FN[12]), "=&v"(FN[13]), "=&v"(FN[14]), "=&v"(FN[15]),                                  \
+          "+v"(acc[0][0]), "+v"(acc[0][1]), "+v"(acc[0][2]), "+v"(acc[0][3]), "+v"(acc[1][0]),         \
+          "+v"(acc[1][1]), "+v"(acc[1][2]), "+v"(acc[1][3]), "+v"(acc[2][0]), "+v"(acc[2][1]),         \
+          "+v"(acc[2][2]), "+v"(acc[2][3]), "+v"(acc[3][0]), "+v"(acc[3][1]), "+v"(acc[3][2]),         \
+          "+v"(acc[3][3])                                                                              \
+        : "v"(FC[0]), "v"(FC[1]), "v"(FC[2]), "v"(FC[3]), "v"(FC[4]), "v"(FC[5]), "v"(FC[6]),          \
+          "v"(FC[7]), "v"(FC[8]), "v"(FC[9]), "v"(FC[10]), "v"(FC[11]), "v"(FC[12]), "v"(FC[13]),      \
+          "v"(FC[14]), "v"(FC[15]), "v"(abase), "v"(bbase)                                             \
+        : "memory");                                                                                   \
+  } while (0)
+#define IDMRG_PIPE_ASM \
+      "s_nop 2\n\t" \
+      "ds_read_b128 %0, %48 offset:0\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %16, %33, %40, %16\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %17, %33, %42, %17\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %18, %33, %44, %18\n\t" \
+      "ds_read_b128 %1, %48 offset:1024\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %19, %33, %46, %19\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %20, %35, %40, %20\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %21, %35, %42, %21\n\t" \
+      "ds_read_b128 %8, %49 offset:0\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %22, %35, %44, %22\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %23, %35, %46, %23\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %24, %37, %40, %24\n\t" \
+      "ds_read_b128 %9, %49 offset:1024\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %25, %37, %42, %25\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %26, %37, %44, %26\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %27, %37, %46, %27\n\t" \
+      "ds_read_b128 %2, %48 offset:2048\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %28, %39, %40, %28\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %29, %39, %42, %29\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %30, %39, %44, %30\n\t" \
+      "ds_read_b128 %3, %48 offset:3072\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %31, %39, %46, %31\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %16, %32, %41, %16\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %17, %32, %43, %17\n\t" \
+      "ds_read_b128 %10, %49 offset:2048\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %18, %32, %45, %18\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %19, %32, %47, %19\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %20, %34, %41, %20\n\t" \
+      "ds_read_b128 %11, %49 offset:3072\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %21, %34, %43, %21\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %22, %34, %45, %22\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %23, %34, %47, %23\n\t" \
+      "ds_read_b128 %4, %48 offset:4096\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %24, %36, %41, %24\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %25, %36, %43, %25\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %26, %36, %45, %26\n\t" \
+      "ds_read_b128 %5, %48 offset:5120\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %27, %36, %47, %27\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %28, %38, %41, %28\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %29, %38, %43, %29\n\t" \
+      "ds_read_b128 %12, %49 offset:4096\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %30, %38, %45, %30\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %31, %38, %47, %31\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %16, %32, %40, %16\n\t" \
+      "ds_read_b128 %13, %49 offset:5120\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %17, %32, %42, %17\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %18, %32, %44, %18\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %19, %32, %46, %19\n\t" \
+      "ds_read_b128 %6, %48 offset:6144\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %20, %34, %40, %20\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %21, %34, %42, %21\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %22, %34, %44, %22\n\t" \
+      "ds_read_b128 %7, %48 offset:7168\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %23, %34, %46, %23\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %24, %36, %40, %24\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %25, %36, %42, %25\n\t" \
+      "ds_read_b128 %14, %49 offset:6144\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %26, %36, %44, %26\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %27, %36, %46, %27\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %28, %38, %40, %28\n\t" \
+      "ds_read_b128 %15, %49 offset:7168\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %29, %38, %42, %29\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %30, %38, %44, %30\n\t" \
+      "v_mfma_f32_16x16x32_bf16 %31, %38, %46, %31\n\t" \
+      "s_waitcnt lgkmcnt(0)\n\t"
+
+  int k = 0;
+  for (; k + 1 < KB; k += 2) {
+    IDMRG_PIPE_STEP(k, F0, F1);
+    IDMRG_PIPE_STEP(k + 1, F1, F0);
+  }
+  if (k < KB) IDMRG_PIPE_STEP(k, F0, F1);
+#undef IDMRG_PIPE_STEP
+#undef IDMRG_PIPE_ASM
+  // wait states between the last MFMAs and the stores that read their results;
+  // the register sets are named here so that every asm output has a use
+  asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7"
+               : "+v"(acc[0][0]), "+v"(acc[0][1]), "+v"(acc[0][2]), "+v"(acc[0][3]), "+v"(acc[1][0]),
+                 "+v"(acc[1][1]), "+v"(acc[1][2]), "+v"(acc[1][3]), "+v"(acc[2][0]), "+v"(acc[2][1]),
+                 "+v"(acc[2][2]), "+v"(acc[2][3]), "+v"(acc[3][0]), "+v"(acc[3][1]), "+v"(acc[3][2]),
+                 "+v"(acc[3][3]));
+#pragma unroll
+  for (int i = 0; i < 16; ++i) asm volatile("" ::"v"(F0[i]), "v"(F1[i]));
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -552,11 +847,20 @@ static void launch_b3(int mode, dim3 grid, hipStream_t s, const GemmTask* tasks,
 
 static void launch_bf16x3(int tiling, int mode, dim3 grid, hipStream_t s, const GemmTask* tasks, int ntask,
                           void* const* bases, const int32_t* active, int ntiles) {
-  if (tiling == 4) {   // 256 x 128, eight waves, three stages
+  if (tiling == 5) {   // 128 x 128, persistent workgroups, pipelined across tiles
+    const int g = std::min(ntiles, kPersistPerCu * kCus);
+    const dim3 pgrid(kXcd * ((g + kXcd - 1) / kXcd));
     if (mode == 0)
-      hipLaunchKernelGGL(gemm_bf16x3_w8_kernel<0>, grid, dim3(512), 0, s, tasks, ntask, bases, active, ntiles);
+      hipLaunchKernelGGL(gemm_bf16x3_persist_kernel<0>, pgrid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
     else
-      hipLaunchKernelGGL(gemm_bf16x3_w8_kernel<1>, grid, dim3(512), 0, s, tasks, ntask, bases, active, ntiles);
+      hipLaunchKernelGGL(gemm_bf16x3_persist_kernel<1>, pgrid, dim3(256), 0, s, tasks, ntask, bases, active, ntiles);
+    return;
+  }
+  if (tiling == 4) {   // 256 x 128, eight waves, three stages, pipelined operand reads
+    if (mode == 0)
+      hipLaunchKernelGGL(gemm_bf16x3_pipe_kernel<0>, grid, dim3(512), 0, s, tasks, ntask, bases, active, ntiles);
+    else
+      hipLaunchKernelGGL(gemm_bf16x3_pipe_kernel<1>, grid, dim3(512), 0, s, tasks, ntask, bases, active, ntiles);
     return;
   }
   switch (tiling) {

@@ -33,6 +33,8 @@ LEGS = {
     "ragged": ([(-3, 20), (-1, 70), (1, 65), (3, 15)], [(-3, 12), (-1, 67), (1, 80), (3, 30)]),
     "wide": ([(-5, 8), (-3, 33), (-1, 66), (1, 70), (3, 40), (5, 9)],
              [(-5, 5), (-3, 41), (-1, 72), (1, 61), (3, 30), (5, 11)]),
+    # sectors of several 256-row tiles and up to 14 K-slabs of 32, none a multiple of a tile
+    "big": ([(-3, 150), (-1, 421), (1, 389), (3, 131)], [(-3, 141), (-1, 397), (1, 410), (3, 127)]),
 }
 
 
@@ -358,7 +360,7 @@ def test_lanczos_repeatable_across_tuning(prec):
     must agree bitwise."""
     c2 = lib.Context(0)
     cfg, r = _oracle_states("random_chain", 32, 7, tol_res=1e-10)
-    # (split-bf16 tries five tilings, the last the eight-wave 256 x 128 kernel)
+    # (split-bf16 tries six tilings, among them the eight-wave and the persistent kernels)
     sts = [st for st in r["states"] if st["n"] in (6, 7)]
     probs = [_flat_problem(st) for st in sts]
     runs = []
@@ -370,6 +372,36 @@ def test_lanczos_repeatable_across_tuning(prec):
     assert runs[0][0] == runs[1][0]
     for a, b in zip(runs[0][1], runs[1][1]):
         assert np.array_equal(a, b)
+
+
+TILINGS = {"f64": range(4), "f32": range(4), "bf16x3": range(6)}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_heff_apply_every_tiling(prec):
+    """Every GEMM tiling of the policy, forced through the tuner table, gives bitwise the same matvec (a tile shape
+    changes no summation order), and that matvec is within the policy's tolerance of the oracle.  The tuner keys of
+    these shapes come from a short solve on the same problems."""
+    cases = [_heff_case("chain", "ragged", 81), _heff_case("yc8", "wide", 82), _heff_case("chain", "big", 83)]
+    probs = [c[0] for c in cases]
+    c2 = lib.Context(0)
+    psis = [T(c[1] / np.linalg.norm(c[1])) for c in cases]
+    lib.lanczos_solve_batch(c2, probs, psis, k_max=12, prec=prec)
+    table = [e for e in c2.tuning() if e["prec"] == {"f64": 0, "f32": 1, "bf16x3": 2}[prec]]
+    assert {e["stage"] for e in table} == {0, 1}
+    outs = []
+    for tiling in TILINGS[prec]:
+        c2.set_tuning([dict(e, tiling=tiling) for e in table])
+        ys = [T(np.full(len(c[2]), np.nan)) for c in cases]
+        lib.heff_apply(c2, probs, [T(c[1]) for c in cases], ys, prec)
+        outs.append([H(y) for y in ys])
+        print(f"[tiling] {prec} tiling {tiling}: max rel err "
+              f"{max(rel_err(o, c[2]) for o, c in zip(outs[-1], cases)):.2e}")
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    for o, c in zip(outs[0], cases):
+        assert rel_err(o, c[2]) <= (1e-13 if prec == "f64" else MIXED_TOL[prec])
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
