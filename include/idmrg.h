@@ -13,6 +13,10 @@
  *   update_env            block-spin transformation of the expanded blocks
  *                         (Step 6, Eqs. (4), (5), with Step 2' folded in)
  *   predict_wavefunction  start vector of the next iteration (Eq. (10))
+ * Two more serve the uniform MPS the iteration converges to (Eq. (11)) and its
+ * observables (Sec. 4): twosite_to_right_iso (a two-site piece as the right
+ * isometry of its fused site) and env_overlap (expectation values as the
+ * contraction of a left and a right environment).
  * Every call is batch-first: it takes nprob >= 1 independent problems and
  * runs them in one set of grouped launches.
  *
@@ -305,6 +309,47 @@ typedef struct {
 int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp, double lam_floor,
                          const idmrg_predict* p);
 
+/* ------------------------------------------------------------------ uniform MPS */
+
+/* Sec. 3, Eq. (11): after iteration n the wavefunction repeats a unit cell of
+ * the two-site pieces B_i = V^(n)dagger_i U~^(n)_{i+1}, which are the Eq. (10)
+ * states of predict_wavefunction with lam_i = 1.  A two-site state in the
+ * Psi layout with legs (A, B) is, unchanged, the left isometry U of one fused
+ * site (s = s1 d + s2, charge qp[s1] + qp[s2]) with new leg B, so update_env
+ * (LEFT) applies the left transfer matrix of a piece, with an MPO of the fused
+ * site carrying operators (Sec. 4: bond strengths, correlations).  The right
+ * transfer matrix needs the piece as the right isometry V of the fused site,
+ * which twosite_to_right_iso writes. */
+typedef struct {
+    idmrg_leg left;            /* A */
+    idmrg_leg right;           /* B */
+    const double* psi;         /* device: Psi layout with legs (A, B) */
+    double* out;               /* device out: V layout of the fused site (B, fused qp, C = A) */
+} idmrg_twosite_item;
+
+/* out = psi read as V[(s, b), a] = psi[a, s1, s2, b], s = s1 d + s2: every
+ * block of psi transposed into its place in the V layout of the fused site
+ * (local charges qp[s1] + qp[s2] for s = s1 d + s2, d = the d of qp).  An
+ * exact copy; asynchronous on the context stream. */
+int twosite_to_right_iso(idmrg_ctx* ctx, int nitem, int32_t d, const int32_t* qp, const idmrg_twosite_item* items);
+
+typedef struct {
+    idmrg_leg leg;             /* the bond both environments live on */
+    int32_t nl;                /* channels of L (its W's columns, incl. the unstored identity) */
+    const int32_t* ql;         /* host [nl]: channel charges of L */
+    const double* L;           /* device: left-environment layout on leg with charges ql */
+    int32_t nr;                /* channels of R (incl. the unstored identity channel 0) */
+    const int32_t* qr;         /* host [nr]: channel charges of R */
+    const double* R;           /* device: right-environment layout on leg with charges qr */
+    int32_t wl, wr;            /* stored channels to contract: 0 <= wl < nl - 1, 1 <= wr < nr, ql[wl] == qr[wr] */
+} idmrg_overlap_item;
+
+/* Sec. 4, expectation values of the uniform MPS: out[k] (host) = sum over a, a'
+ * of L[a, wl, a'] R[a, wr, a'] for item k (the contraction of a left and a
+ * right environment across one bond).  Deterministic order; synchronises the
+ * context stream.  IDMRG_ENUMERIC if a result is not finite. */
+int env_overlap(idmrg_ctx* ctx, int nitem, const idmrg_overlap_item* items, double* out);
+
 /* ------------------------------------------------------------------ workspace */
 
 /* Operations for idmrg_workspace_size. */
@@ -314,6 +359,8 @@ int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const int32_t* qp
 #define IDMRG_OP_ENV_LEFT 3   /* update_env(LEFT);      desc: idmrg_env_update[nprob] */
 #define IDMRG_OP_ENV_RIGHT 4  /* update_env(RIGHT);     desc: idmrg_env_update[nprob] */
 #define IDMRG_OP_PREDICT 5    /* predict_wavefunction;  desc: idmrg_predict[nprob]    */
+#define IDMRG_OP_TWOSITE_V 6  /* twosite_to_right_iso;  desc: idmrg_twosite_item[nprob] */
+#define IDMRG_OP_OVERLAP 7    /* env_overlap;           desc: idmrg_overlap_item[nprob] */
 
 /* The scalar arguments of the call being sized (unused fields are ignored). */
 typedef struct {

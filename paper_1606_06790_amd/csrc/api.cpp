@@ -55,7 +55,8 @@ struct OutOfWorkspace {
 constexpr size_t kRingBytes = size_t(32) << 20;   // pinned staging ring of the plan uploads
 constexpr size_t kRingChunk = size_t(8) << 20;    // largest single staged copy
 constexpr size_t kRingSlotsMax = 256;             // copies tracked before the oldest is waited for
-constexpr int kOps = 6;
+constexpr int kOps = 8;
+constexpr int kPlanWays = 8;   // cached plans per operation (a unit cell's pieces differ in shape)
 
 // Scratch of heff_apply_static: a file-scope device array, one copy per GPU,
 // held until the process ends.  Host code never passes its name to a kernel:
@@ -99,8 +100,10 @@ struct idmrg_ctx {
   std::map<std::tuple<int, int, int, int, int>, std::vector<float>> tune_ms;
   hipEvent_t tev[6][4] = {};   // [variant][stage-1 start, stage-1 end, stage-2 start, stage-2 end]
   // the plan of the last call of each kind and the hash of its inputs
-  uint64_t cache_key[kOps] = {};
-  std::shared_ptr<CallPlan> cache[kOps];
+  uint64_t cache_key[kOps][kPlanWays] = {};
+  uint64_t cache_used[kOps][kPlanWays] = {};
+  uint64_t cache_tick = 0;
+  std::shared_ptr<CallPlan> cache[kOps][kPlanWays];
 };
 
 namespace {
@@ -348,19 +351,28 @@ struct CallPlan {
   Layout lay;
 };
 
-// The cached plan of kind `op` if its key matches, else a new one from build() (cached in its place).
+// The cached plan of kind `op` if one of its entries has this key, else a new
+// one from build(), cached in place of the least recently used entry.
 template <typename T, typename F>
 std::shared_ptr<T> plan_of(idmrg_ctx* c, int op, uint64_t key, F&& build) {
-  if (c->cache[op] && c->cache_key[op] == key) {
-    auto p = std::dynamic_pointer_cast<T>(c->cache[op]);
-    if (p) return p;
+  int victim = 0;
+  for (int w = 0; w < kPlanWays; ++w) {
+    if (c->cache[op][w] && c->cache_key[op][w] == key) {
+      auto p = std::dynamic_pointer_cast<T>(c->cache[op][w]);
+      if (p) {
+        c->cache_used[op][w] = ++c->cache_tick;
+        return p;
+      }
+    }
+    if (c->cache_used[op][w] < c->cache_used[op][victim]) victim = w;
   }
-  c->cache[op].reset();
+  c->cache[op][victim].reset();
   auto p = std::make_shared<T>();
   build(*p);
   ++c->stats.plan_builds;
-  c->cache[op] = p;
-  c->cache_key[op] = key;
+  c->cache[op][victim] = p;
+  c->cache_key[op][victim] = key;
+  c->cache_used[op][victim] = ++c->cache_tick;
   return p;
 }
 
@@ -1115,6 +1127,90 @@ std::shared_ptr<PredictCall> predict_call(idmrg_ctx* c, int P, int d, const int3
   });
 }
 
+// ---- uniform MPS (Eq. (11)): a two-site piece as the fused site's right
+// isometry, and overlaps of left and right environments
+
+struct TwositeCall : CallPlan {
+  MixList mix;
+  std::vector<int64_t> sz;
+  size_t oPlan = 0, a1 = 0, a2 = 0, a3 = 0;
+  Packer pk;
+};
+
+std::shared_ptr<TwositeCall> twosite_call(idmrg_ctx* c, int P, int d, const int32_t* qp_in,
+                                          const idmrg_twosite_item* it) {
+  Hash h;
+  h.val(P);
+  h.arr(qp_in, d);
+  for (int p = 0; p < P; ++p) {
+    h.leg(it[p].left);
+    h.leg(it[p].right);
+  }
+  return plan_of<TwositeCall>(c, IDMRG_OP_TWOSITE_V, h.h, [&](TwositeCall& k) {
+    const std::vector<int> qp = make_qp(d, qp_in);
+    k.sz.assign((size_t)P * kNumBases, -1);
+    for (int p = 0; p < P; ++p) {
+      const Leg A = make_leg(it[p].left, "twosite.left"), B = make_leg(it[p].right, "twosite.right");
+      build_twosite_V(k.mix, p, A, B, qp);
+      k.sz[(size_t)p * kNumBases + 0] = psi_layout(A, B, qp).size;
+      k.sz[(size_t)p * kNumBases + 1] = V_layout(B, fused_qp(qp), A).size;
+    }
+    check_mix(k.mix, k.sz, "twosite_to_right_iso");
+    k.a1 = k.pk.add(k.mix.t);
+    k.a2 = k.pk.add(k.mix.src);
+    k.a3 = k.pk.reserve((size_t)P * kNumBases * sizeof(void*));
+    k.oPlan = k.lay.add(k.pk.host.size());
+  });
+}
+
+struct OverlapCall : CallPlan {
+  std::vector<OverlapSeg> segs;
+  std::vector<int32_t> seg0;
+  std::vector<int64_t> sz;
+  size_t oPartial = 0, oOut = 0, oPlan = 0, a1 = 0, a2 = 0, a3 = 0;
+  Packer pk;
+};
+
+std::shared_ptr<OverlapCall> overlap_call(idmrg_ctx* c, int P, const idmrg_overlap_item* it) {
+  Hash h;
+  h.val(P);
+  for (int p = 0; p < P; ++p) {
+    h.leg(it[p].leg);
+    h.arr(it[p].ql, it[p].nl);
+    h.arr(it[p].qr, it[p].nr);
+    h.val(it[p].wl);
+    h.val(it[p].wr);
+  }
+  return plan_of<OverlapCall>(c, IDMRG_OP_OVERLAP, h.h, [&](OverlapCall& k) {
+    k.sz.assign((size_t)P * kNumBases, -1);
+    k.seg0.assign(P + 1, 0);
+    for (int p = 0; p < P; ++p) {
+      const idmrg_overlap_item& o = it[p];
+      if (!o.ql || !o.qr || o.nl < 2 || o.nr < 2 || o.nl > 4096 || o.nr > 4096)
+        throw InvalidArg("overlap: bad channel lists");
+      const Leg leg = make_leg(o.leg, "overlap.leg");
+      const std::vector<int> ql(o.ql, o.ql + o.nl), qr(o.qr, o.qr + o.nr);
+      k.seg0[p] = (int32_t)k.segs.size();
+      build_overlap(k.segs, p, leg, ql, qr, o.wl, o.wr);
+      k.sz[(size_t)p * kNumBases + 0] = envL_layout(leg, ql).size;
+      k.sz[(size_t)p * kNumBases + 1] = envR_layout(leg, qr).size;
+    }
+    k.seg0[P] = (int32_t)k.segs.size();
+    for (const OverlapSeg& g : k.segs) {
+      const int64_t* z = &k.sz[(size_t)g.item * kNumBases];
+      if (g.aoff < 0 || g.aoff + (int64_t)(g.rows - 1) * g.lda + g.cols > z[0] || g.boff < 0 ||
+          g.boff + (int64_t)(g.rows - 1) * g.ldb + g.cols > z[1])
+        throw InvalidArg("internal: overlap segment out of bounds");
+    }
+    k.oPartial = k.lay.add(std::max<size_t>(k.segs.size(), 1) * 8);
+    k.oOut = k.lay.add((size_t)P * 8);
+    k.a1 = k.pk.add(k.segs);
+    k.a2 = k.pk.add(k.seg0);
+    k.a3 = k.pk.reserve((size_t)P * kNumBases * sizeof(void*));
+    k.oPlan = k.lay.add(k.pk.host.size());
+  });
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ context API
@@ -1165,7 +1261,8 @@ extern "C" int idmrg_destroy(idmrg_ctx* c) {
   if (!c) return IDMRG_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  for (auto& p : c->cache) p.reset();
+  for (auto& row : c->cache)
+    for (auto& p : row) p.reset();
   if (c->own.p) (void)hipFree(c->own.p);
   if (c->ring) (void)hipHostFree(c->ring);
   for (auto& r : c->ring_busy) (void)hipEventDestroy(r.ev);
@@ -1355,6 +1452,12 @@ extern "C" int idmrg_workspace_size(idmrg_ctx* ctx, int op, int nprob, const voi
         break;
       case IDMRG_OP_PREDICT:
         n = predict_call(ctx, nprob, q->d, q->qp, (const idmrg_predict*)desc)->lay.total;
+        break;
+      case IDMRG_OP_TWOSITE_V:
+        n = twosite_call(ctx, nprob, q->d, q->qp, (const idmrg_twosite_item*)desc)->lay.total;
+        break;
+      case IDMRG_OP_OVERLAP:
+        n = overlap_call(ctx, nprob, (const idmrg_overlap_item*)desc)->lay.total;
         break;
       default:
         throw InvalidArg("unknown operation");
@@ -1886,6 +1989,74 @@ extern "C" int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const 
     launch_gemm(Prec::F64, 2, (GemmTask*)(dev + k.a2), (int)k.plan.g.t.size(), k.plan.g.tiles, bases, nullptr,
                 ctx->stream);
     IDMRG_HIP(hipGetLastError());
+    return IDMRG_OK;
+  });
+}
+
+// ------------------------------------------------------------------ uniform MPS
+
+extern "C" int twosite_to_right_iso(idmrg_ctx* ctx, int nitem, int32_t d, const int32_t* qp_in,
+                                    const idmrg_twosite_item* items) {
+  return guarded(ctx, [&]() {
+    check_nprob(nitem);
+    if (!items) throw InvalidArg("null items");
+    for (int p = 0; p < nitem; ++p)
+      if (!items[p].psi || !items[p].out || (const double*)items[p].out == items[p].psi)
+        throw InvalidArg("twosite_to_right_iso: psi and out must be distinct device buffers");
+    auto call = twosite_call(ctx, nitem, d, qp_in, items);
+    TwositeCall& k = *call;
+    for (int p = 0; p < nitem; ++p) {
+      check_dev(items[p].psi, k.sz[(size_t)p * kNumBases + 0], 8, "psi");
+      check_dev(items[p].out, k.sz[(size_t)p * kNumBases + 1], 8, "out");
+    }
+    char* base = acquire(ctx, k.lay.total);
+    std::vector<void*> hb((size_t)nitem * kNumBases, nullptr);
+    for (int p = 0; p < nitem; ++p) {
+      hb[(size_t)p * kNumBases + 0] = (void*)items[p].psi;
+      hb[(size_t)p * kNumBases + 1] = items[p].out;
+    }
+    k.pk.patch(k.a3, hb);
+    char* dev = base + k.oPlan;
+    stage(ctx, dev, k.pk.host.data(), k.pk.host.size());
+    launch_mix(0, 0, (MixTask*)(dev + k.a1), (MixSrc*)(dev + k.a2), (int)k.mix.t.size(), k.mix.tiles,
+               (void* const*)(dev + k.a3), nullptr, ctx->stream);
+    IDMRG_HIP(hipGetLastError());
+    return IDMRG_OK;
+  });
+}
+
+extern "C" int env_overlap(idmrg_ctx* ctx, int nitem, const idmrg_overlap_item* items, double* out) {
+  return guarded(ctx, [&]() {
+    check_nprob(nitem);
+    if (!items || !out) throw InvalidArg("null argument");
+    for (int p = 0; p < nitem; ++p)
+      if (!items[p].L || !items[p].R) throw InvalidArg("env_overlap: null environment");
+    auto call = overlap_call(ctx, nitem, items);
+    OverlapCall& k = *call;
+    for (int p = 0; p < nitem; ++p) {
+      check_dev(items[p].L, k.sz[(size_t)p * kNumBases + 0], 8, "L");
+      check_dev(items[p].R, k.sz[(size_t)p * kNumBases + 1], 8, "R");
+    }
+    char* base = acquire(ctx, k.lay.total);
+    std::vector<void*> hb((size_t)nitem * kNumBases, nullptr);
+    for (int p = 0; p < nitem; ++p) {
+      hb[(size_t)p * kNumBases + 0] = (void*)items[p].L;
+      hb[(size_t)p * kNumBases + 1] = (void*)items[p].R;
+    }
+    k.pk.patch(k.a3, hb);
+    char* dev = base + k.oPlan;
+    stage(ctx, dev, k.pk.host.data(), k.pk.host.size());
+    double* dout = (double*)(base + k.oOut);
+    launch_overlap((const OverlapSeg*)(dev + k.a1), (int)k.segs.size(), (const int32_t*)(dev + k.a2), nitem,
+                   (void* const*)(dev + k.a3), (double*)(base + k.oPartial), dout, ctx->stream);
+    IDMRG_HIP(hipGetLastError());
+    IDMRG_HIP(hipMemcpyAsync(out, dout, (size_t)nitem * 8, hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    for (int p = 0; p < nitem; ++p)
+      if (!std::isfinite(out[p])) {
+        ctx->err = "non-finite overlap (item " + std::to_string(p) + ")";
+        return IDMRG_ENUMERIC;
+      }
     return IDMRG_OK;
   });
 }

@@ -121,6 +121,13 @@ struct SelSector {
   int64_t s_off;            // singular values in the S workspace
 };
 
+// One segment of an environment overlap: sum over i < rows, j < cols of
+// L[aoff + i lda + j] R[boff + i ldb + j], with L and R bases 0 and 1 of its item.
+struct OverlapSeg {
+  int32_t item, rows, cols, lda, ldb, pad;
+  int64_t aoff, boff;
+};
+
 // ---------------------------------------------------------------- host errors
 
 struct Status {
@@ -150,8 +157,9 @@ struct InvalidArg {
 enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
 // Grouped GEMM over `ntask` tasks with `ntiles` total tiles.  tiling selects the
-// output tile: 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 128x128; tile0/tiles_n of
-// the tasks must have been computed for that tile.
+// output tile: 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 128x128, and for BF16X3
+// also 4 = 256x128 (eight waves) and 5 = 128x128 (persistent workgroups);
+// tile0/tiles_n of the tasks must have been computed for that tile.
 // mode: 0 = NN, 1 = NT, 2 = TN.  Element type chosen by prec:
 //   F64: double A, B, C;  F32: float A, B, C;
 //   BF16X3: A and B^T in the fragment layout (aoff, boff in 32-bit words; mode,
@@ -169,6 +177,12 @@ void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int
 
 void launch_scale(const ScaleTask* tasks, const int32_t* colmaps, int ntask, int ntiles,
                   double lam_floor, void* const* bases, hipStream_t s);
+
+// Environment overlaps: partial[g] = the sum of segment g (one workgroup each, a
+// fixed reduction tree); out[k] = the partials of item k (segments
+// [seg0[k], seg0[k + 1])) added in order.
+void launch_overlap(const OverlapSeg* segs, int nseg, const int32_t* seg0, int nitem, void* const* bases,
+                    double* partial, double* out, hipStream_t s);
 
 // element conversions (n elements): kind 0 double -> float, kind 1 float -> double
 void launch_convert(int kind, const void* src, void* dst, int64_t n, hipStream_t s);

@@ -335,6 +335,44 @@ void launch_mix(int tin, int tout, const MixTask* tasks, const MixSrc* srcs, int
     hipLaunchKernelGGL((mix_kernel<double, float>), grid, block, 0, s, tasks, srcs, ntask, bases, active);
 }
 
+__global__ __launch_bounds__(256) void overlap_seg_kernel(const OverlapSeg* __restrict__ segs,
+                                                          void* const* __restrict__ bases,
+                                                          double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const OverlapSeg g = segs[blockIdx.x];
+  const double* L = reinterpret_cast<const double*>(bases[g.item * kNumBases + 0]) + g.aoff;
+  const double* R = reinterpret_cast<const double*>(bases[g.item * kNumBases + 1]) + g.boff;
+  const int64_t n = (int64_t)g.rows * g.cols;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += 256) {
+    const int64_t i = e / g.cols, j = e - i * g.cols;
+    acc += L[i * g.lda + j] * R[i * g.ldb + j];
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void overlap_sum_kernel(const int32_t* __restrict__ seg0, int nitem, const double* __restrict__ partial,
+                                   double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nitem) return;
+  double s = 0.0;
+  for (int g = seg0[k]; g < seg0[k + 1]; ++g) s += partial[g];
+  out[k] = s;
+}
+
+void launch_overlap(const OverlapSeg* segs, int nseg, const int32_t* seg0, int nitem, void* const* bases,
+                    double* partial, double* out, hipStream_t s) {
+  if (nseg > 0) hipLaunchKernelGGL(overlap_seg_kernel, dim3(nseg), dim3(256), 0, s, segs, bases, partial);
+  hipLaunchKernelGGL(overlap_sum_kernel, dim3((nitem + 63) / 64), dim3(64), 0, s, seg0, nitem,
+                     (const double*)partial, out);
+}
+
 void launch_diag_sum(const DiagTask* tasks, int ntask, void* const* bases, double* out, hipStream_t s) {
   if (ntask == 0) return;
   hipLaunchKernelGGL(diag_sum_kernel, dim3(ntask), dim3(256), 0, s, tasks, bases, out);

@@ -567,6 +567,61 @@ void check_gemm(const GemmList& g, int mode, const std::vector<int64_t>& sizes, 
   }
 }
 
+std::vector<int> fused_qp(const std::vector<int>& qp) {
+  const int d = (int)qp.size();
+  std::vector<int> f((size_t)d * d);
+  for (int s1 = 0; s1 < d; ++s1)
+    for (int s2 = 0; s2 < d; ++s2) f[(size_t)s1 * d + s2] = qp[s1] + qp[s2];
+  return f;
+}
+
+void build_twosite_V(MixList& m, int prob, const Leg& A, const Leg& B, const std::vector<int>& qp) {
+  const int d = (int)qp.size();
+  const PsiLayout P = psi_layout(A, B, qp);
+  const IsoLayout V = V_layout(B, fused_qp(qp), A);
+  for (const auto& k : P.blk) {
+    const int r = V.row_of(k.a, k.b, k.s1 * d + k.s2);
+    if (r < 0) throw InvalidArg("internal: a two-site block has no rows in the fused V layout");
+    MixTask t{};
+    t.rows = k.db;                // rows of V: the right sector's states
+    t.cols = k.da;                // columns of V: the left sector's states
+    t.ldd = A.dim[k.a];
+    t.prob = prob;
+    t.dbase = 1;
+    t.doff = V.off[k.a] + (int64_t)r * A.dim[k.a];
+    MixSrc src{};
+    src.coef = 1.0;
+    src.off = k.off;
+    src.ld = k.db;
+    src.base = 0;
+    src.trans = 1;                // V(r, c) = psi block (c, r)
+    m.add(t, {src});
+  }
+}
+
+void build_overlap(std::vector<OverlapSeg>& segs, int item, const Leg& leg, const std::vector<int>& ql,
+                   const std::vector<int>& qr, int wl, int wr) {
+  if (wl < 0 || wl >= (int)ql.size() - 1 || wr < 1 || wr >= (int)qr.size())
+    throw InvalidArg("overlap: channel out of range");
+  if (ql[wl] != qr[wr]) throw InvalidArg("overlap: the two channels carry different charges");
+  const EnvLLayout L = envL_layout(leg, ql);
+  const EnvRLayout R = envR_layout(leg, qr);
+  for (int ac = 0; ac < leg.n(); ++ac) {
+    if (L.row_off[ac][wl] < 0) continue;
+    const int ar = L.a_out[ac][wl];
+    if (R.col_off[ar][wr] < 0 || R.b_in[ar][wr] != ac) throw InvalidArg("internal: overlap blocks do not match");
+    OverlapSeg g{};
+    g.item = item;
+    g.rows = leg.dim[ar];
+    g.cols = leg.dim[ac];
+    g.aoff = L.stack_off[ac] + (int64_t)L.row_off[ac][wl] * leg.dim[ac];
+    g.lda = leg.dim[ac];
+    g.boff = R.off[ar] + R.col_off[ar][wr];
+    g.ldb = R.K[ar];
+    segs.push_back(g);
+  }
+}
+
 void check_mix(const MixList& m, const std::vector<int64_t>& sizes, const char* what) {
   for (const auto& t : m.t) {
     if (t.rows <= 0 || t.cols <= 0) continue;

@@ -173,6 +173,17 @@ struct PredictPlan {
 void build_predict(PredictPlan& p, int prob, const Leg& Aa, const Leg& Bt, const Leg& Bb,
                    const std::vector<int>& qp);
 
+// Charges of the fused site of two sites: qf[s1 d + s2] = qp[s1] + qp[s2].
+std::vector<int> fused_qp(const std::vector<int>& qp);
+// The two-site state psi (legs A, B, local charges qp) read as the right
+// isometry V of the fused site with new leg A: one copy task per block of psi,
+// transposed into its rows of the V layout.  bases: 0 psi, 1 V.
+void build_twosite_V(MixList& m, int prob, const Leg& A, const Leg& B, const std::vector<int>& qp);
+// Segments of sum_{a,a'} L[a, wl, a'] R[a, wr, a'] on one leg (L channel charges
+// ql, R channel charges qr); bases 0 L, 1 R of item `item`.
+void build_overlap(std::vector<OverlapSeg>& segs, int item, const Leg& leg, const std::vector<int>& ql,
+                   const std::vector<int>& qr, int wl, int wr);
+
 // Host-side bounds check of a plan before any launch: every element a task can
 // touch must lie inside its base buffer.  sizes[prob * kNumBases + base] is the
 // element count of that buffer (-1: unused).  Throws InvalidArg on violation.

@@ -23,13 +23,13 @@ OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, 1, -1, -2, -3
 PREC = {"f64": 0, "f32": 1, "bf16x3": 2}
 LEFT, RIGHT = 0, 1
 
-OP_HEFF, OP_LANCZOS, OP_TRUNCATE, OP_ENV_LEFT, OP_ENV_RIGHT, OP_PREDICT = range(6)
+OP_HEFF, OP_LANCZOS, OP_TRUNCATE, OP_ENV_LEFT, OP_ENV_RIGHT, OP_PREDICT, OP_TWOSITE_V, OP_OVERLAP = range(8)
 
 EXPORTS = ["idmrg_create", "idmrg_destroy", "idmrg_set_stream", "idmrg_last_error", "idmrg_psi_size",
            "idmrg_envL_size", "idmrg_envR_size", "idmrg_U_size", "idmrg_V_size", "idmrg_heff_work",
            "heff_apply", "lanczos_solve_batch", "truncate_twosite", "update_env", "predict_wavefunction",
            "idmrg_profile", "idmrg_profile_get", "idmrg_workspace_size", "idmrg_set_workspace", "idmrg_get_stats",
-           "heff_apply_static", "idmrg_tune_get", "idmrg_tune_set"]
+           "heff_apply_static", "idmrg_tune_get", "idmrg_tune_set", "twosite_to_right_iso", "env_overlap"]
 PROF_CLASSES = ["heff_gemm1", "heff_gemm2", "heff_mix", "convert", "lanczos_vec", "svd", "trunc_other", "env",
                 "predict", "heff_gemm1_lo", "heff_gemm2_lo", "heff_mix_lo"]
 
@@ -86,6 +86,16 @@ class Predict_t(C.Structure):
                 ("lam_prev", C.c_void_p), ("U_ip1", C.c_void_p), ("lam_ip1", C.c_void_p), ("psi", C.c_void_p)]
 
 
+class Twosite_t(C.Structure):
+    _fields_ = [("left", Leg_t), ("right", Leg_t), ("psi", C.c_void_p), ("out", C.c_void_p)]
+
+
+class Overlap_t(C.Structure):
+    _fields_ = [("leg", Leg_t), ("nl", C.c_int32), ("ql", C.POINTER(C.c_int32)), ("L", C.c_void_p),
+                ("nr", C.c_int32), ("qr", C.POINTER(C.c_int32)), ("R", C.c_void_p), ("wl", C.c_int32),
+                ("wr", C.c_int32)]
+
+
 class WsQuery_t(C.Structure):
     _fields_ = [("prec", C.c_int32), ("m_max", C.c_int32), ("d", C.c_int32), ("pad", C.c_int32),
                 ("qp", C.POINTER(C.c_int32)), ("opts", C.POINTER(LanczosOpts_t))]
@@ -139,6 +149,8 @@ def load():
     lib.update_env.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(EnvUpdate_t)]
     lib.predict_wavefunction.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_int32), C.c_double,
                                          C.POINTER(Predict_t)]
+    lib.twosite_to_right_iso.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Twosite_t)]
+    lib.env_overlap.argtypes = [C.c_void_p, C.c_int, C.POINTER(Overlap_t), C.POINTER(C.c_double)]
     lib.idmrg_workspace_size.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.POINTER(WsQuery_t),
                                          C.POINTER(C.c_size_t)]
     lib.idmrg_set_workspace.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
@@ -511,3 +523,40 @@ def predict_wavefunction(ctx, items, qp, lam_floor=1e-14):
     ctx.reserve(OP_PREDICT, P, arr, WsQuery_t(d=len(qp), qp=qpa))
     _check(ctx, ctx.lib.predict_wavefunction(ctx.handle, P, len(qp), qpa, lam_floor, arr))
     return outs
+
+
+def fused_qp(qp):
+    """Charges of the fused site of two sites: s = s1 d + s2 has qp[s1] + qp[s2]."""
+    return [a + b for a in qp for b in qp]
+
+
+def twosite_to_right_iso(ctx, items, qp):
+    """items: list of dict(left, right, psi).  Returns each psi as the fused site's right isometry (V layout,
+    new leg = left)."""
+    torch = _torch()
+    k = _Keep()
+    P = len(items)
+    arr = (Twosite_t * P)()
+    outs = []
+    for j, it in enumerate(items):
+        o = torch.empty(V_size(it["right"], fused_qp(qp), it["left"]), dtype=torch.float64, device=it["psi"].device)
+        outs.append(o)
+        arr[j] = Twosite_t(k.leg(it["left"]), k.leg(it["right"]), _ptr(it["psi"]), C.c_void_p(o.data_ptr()))
+    qpa = k.ints(qp)
+    ctx.reserve(OP_TWOSITE_V, P, arr, WsQuery_t(d=len(qp), qp=qpa))
+    _check(ctx, ctx.lib.twosite_to_right_iso(ctx.handle, P, len(qp), qpa, arr))
+    return outs
+
+
+def env_overlap(ctx, items):
+    """items: list of dict(leg, ql, L, qr, R, wl, wr).  Returns [sum_{a,a'} L[a,wl,a'] R[a,wr,a']] as floats."""
+    k = _Keep()
+    P = len(items)
+    arr = (Overlap_t * P)()
+    for j, it in enumerate(items):
+        arr[j] = Overlap_t(k.leg(it["leg"]), len(it["ql"]), k.ints(it["ql"]), _ptr(it["L"]), len(it["qr"]),
+                           k.ints(it["qr"]), _ptr(it["R"]), it["wl"], it["wr"])
+    out = (C.c_double * P)()
+    ctx.reserve(OP_OVERLAP, P, arr, WsQuery_t())
+    _check(ctx, ctx.lib.env_overlap(ctx.handle, P, arr, out))
+    return [float(x) for x in out]

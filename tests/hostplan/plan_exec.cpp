@@ -229,3 +229,43 @@ extern "C" int hostplan_env(int side, const idmrg_env_update* u) {
     return -1;
   }
 }
+
+// A two-site state as the right isometry of its fused site (twosite_to_right_iso's plan).
+extern "C" int hostplan_twosite_V(const idmrg_leg* left, const idmrg_leg* right, int d, const int32_t* qp_in,
+                                  const double* psi, double* out) {
+  try {
+    const Leg A = make_leg(*left, "A"), B = make_leg(*right, "B");
+    const std::vector<int> qp = make_qp(d, qp_in);
+    MixList m;
+    build_twosite_V(m, 0, A, B, qp);
+    std::vector<int64_t> sz(kNumBases, -1);
+    sz[0] = psi_layout(A, B, qp).size;
+    sz[1] = V_layout(B, fused_qp(qp), A).size;
+    check_mix(m, sz, "twosite");
+    std::vector<double*> b(kNumBases, nullptr);
+    b[0] = (double*)psi;
+    b[1] = out;
+    run_mix(m, b);
+    return 0;
+  } catch (...) {
+    return -1;
+  }
+}
+
+// env_overlap's segments, summed with plain loops.
+extern "C" int hostplan_overlap(const idmrg_overlap_item* it, double* out) {
+  try {
+    const Leg leg = make_leg(it->leg, "leg");
+    const std::vector<int> ql(it->ql, it->ql + it->nl), qr(it->qr, it->qr + it->nr);
+    std::vector<OverlapSeg> segs;
+    build_overlap(segs, 0, leg, ql, qr, it->wl, it->wr);
+    double s = 0.0;
+    for (const OverlapSeg& g : segs)
+      for (int i = 0; i < g.rows; ++i)
+        for (int j = 0; j < g.cols; ++j) s += it->L[g.aoff + (int64_t)i * g.lda + j] * it->R[g.boff + (int64_t)i * g.ldb + j];
+    *out = s;
+    return 0;
+  } catch (...) {
+    return -1;
+  }
+}

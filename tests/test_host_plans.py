@@ -137,3 +137,143 @@ def test_env_plan_on_host(lib, hostplan, name, c1, side):
                         C.c_void_p(out.ctypes.data))
     assert hostplan.hostplan_env(sd, C.byref(u)) == 0
     assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ---- the uniform MPS (Eq. (11)): a two-site piece as the fused site's isometries, and environment overlaps
+
+A_OBS = [(-3, 4), (-1, 7), (1, 6), (3, 2)]
+B_OBS = [(-3, 3), (-1, 6), (1, 8), (3, 3)]
+
+
+def test_twosite_V_plan_on_host(lib, hostplan):
+    x = workloads.gaussian(layout.psi_size(A_OBS, B_OBS, QP), 63, 1)
+    psi = layout.flat_to_psi(x, A_OBS, B_OBS, QP)
+    V = {}
+    for (qa, s1, s2), blk in psi.items():
+        V[(2 * s1 + s2, qa + QP[s1] + QP[s2], qa)] = blk.T
+    qf = lib.fused_qp(QP)
+    ref = layout.V_to_flat(V, B_OBS, qf, A_OBS)
+    out = np.full(len(ref), np.nan)
+    k = lib._Keep()
+    assert hostplan.hostplan_twosite_V(C.byref(k.leg(A_OBS)), C.byref(k.leg(B_OBS)), 2, k.ints(QP),
+                                       C.c_void_p(x.ctypes.data), C.c_void_p(out.ctypes.data)) == 0
+    assert np.array_equal(out, ref)
+
+
+def test_overlap_plan_on_host(lib, hostplan):
+    leg = [(-2, 3), (0, 5), (2, 4), (4, 2)]
+    ql, qr = [0, 2, 0, 0], [0, 2, 0, 0]
+    Lf, Rf = workloads.gaussian(layout.envL_size(leg, ql), 64, 1), workloads.gaussian(layout.envR_size(leg, qr), 64, 2)
+    L, R = layout.flat_to_envL(Lf, leg, ql), layout.flat_to_envR(Rf, leg, qr)
+    k = lib._Keep()
+    for wl, wr in ((0, 2), (1, 1), (2, 3)):
+        ref = sum(float(np.sum(b * R[(wr, qa, qa2)])) for (w, qa, qa2), b in L.items()
+                  if w == wl and (wr, qa, qa2) in R)
+        it = lib.Overlap_t(k.leg(leg), 4, k.ints(ql), C.c_void_p(Lf.ctypes.data), 4, k.ints(qr),
+                           C.c_void_p(Rf.ctypes.data), wl, wr)
+        out = C.c_double()
+        assert hostplan.hostplan_overlap(C.byref(it), C.byref(out)) == 0
+        assert abs(out.value - ref) <= 1e-13 * max(1.0, abs(ref))
+    it = lib.Overlap_t(k.leg(leg), 4, k.ints(ql), C.c_void_p(Lf.ctypes.data), 4, k.ints(qr),
+                       C.c_void_p(Rf.ctypes.data), 1, 2)
+    assert hostplan.hostplan_overlap(C.byref(it), C.byref(C.c_double())) == -1    # channel charges differ
+
+
+def _dense(blocks, rows_leg, cols_leg, key):
+    """Dense matrix of the blocks blocks[key(qa, qb)] over two legs (sectors in order)."""
+    ro, co = {}, {}
+    off = 0
+    for q, k in rows_leg:
+        ro[q] = off
+        off += k
+    M = np.zeros((off, sum(k for _, k in cols_leg)))
+    off = 0
+    for q, k in cols_leg:
+        co[q] = off
+        off += k
+    for qa, da in rows_leg:
+        for qb, db in cols_leg:
+            b = blocks.get(key(qa, qb))
+            if b is not None:
+                M[ro[qa]:ro[qa] + da, co[qb]:co[qb] + db] = b
+    return M
+
+
+@pytest.mark.parametrize("ops", [("1", "1"), ("+", "1"), ("1", "-"), ("z", "z")])
+def test_fused_piece_transfer_on_host(lib, hostplan, ops):
+    """update_env(LEFT)'s plan with the piece as the fused site's left isometry and the observables' three-channel
+    MPO equals the oracle's piece transfer with the operators inserted (channel 1) and without (channel 0)."""
+    from oracle import observables as ob
+    from paper_1606_06790_amd.observables import fused_mpo
+    x = workloads.gaussian(layout.psi_size(A_OBS, B_OBS, QP), 65, 1)
+    psi = layout.flat_to_psi(x, A_OBS, B_OBS, QP)
+    W = fused_mpo(ops[0], ops[1], 0, lib.LEFT, QP)
+    # L: channels 0 and 1 the same charge-0 block-diagonal matrix
+    X = {(w, q, q): np.asarray(workloads.gaussian(d * d, 65, 2, q + 100).reshape(d, d)) for q, d in A_OBS
+         for w in (0, 1)}
+    Lf = layout.envL_to_flat(X, A_OBS, W.ql)
+    out = np.full(layout.envL_size(B_OBS, W.qr), np.nan)
+    k = lib._Keep()
+    u = lib.EnvUpdate_t(k.leg(A_OBS), k.leg(B_OBS), k.mpo(W), C.c_void_p(Lf.ctypes.data), C.c_void_p(x.ctypes.data),
+                        C.c_void_p(out.ctypes.data))
+    assert hostplan.hostplan_env(0, C.byref(u)) == 0
+    Lnew = layout.flat_to_envL(out, B_OBS, W.qr)
+    # oracle: dense piece and dense X
+    ma, mb = sum(d for _, d in A_OBS), sum(d for _, d in B_OBS)
+    Bd = np.zeros((ma, 2, 2, mb))
+    ao, bo = {}, {}
+    o = 0
+    for q, d in A_OBS:
+        ao[q] = o
+        o += d
+    o = 0
+    for q, d in B_OBS:
+        bo[q] = o
+        o += d
+    for (qa, s1, s2), blk in psi.items():
+        qb = qa + QP[s1] + QP[s2]
+        Bd[ao[qa]:ao[qa] + blk.shape[0], s1, s2, bo[qb]:bo[qb] + blk.shape[1]] = blk
+    Xd = _dense({(q, q): X[(0, q, q)] for q, _ in A_OBS}, A_OBS, A_OBS, lambda a, b: (a, b))
+    opm = {"1": None, "+": ob.SP, "-": ob.SM, "z": ob.SZ}
+    for ch, (o1, o2) in ((0, (None, None)), (1, (opm[ops[0]], opm[ops[1]]))):
+        ref = ob.apply_piece(Xd, Bd, o1, o2)
+        got = _dense({(qa, qb): v for (w, qa, qb), v in Lnew.items() if w == ch}, B_OBS, B_OBS, lambda a, b: (a, b))
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), ch
+
+
+def test_fused_piece_right_transfer_on_host(lib, hostplan):
+    """update_env(RIGHT)'s plan with the piece rewritten as the fused site's right isometry (twosite plan) and the
+    observables' right MPO equals the right transfer Y'[a, a'] = sum B[a,s,t,b] Y[b,b'] B[a',s,t,b'] in channels 1, 2."""
+    from paper_1606_06790_amd.observables import fused_mpo
+    x = workloads.gaussian(layout.psi_size(A_OBS, B_OBS, QP), 66, 1)
+    qf = lib.fused_qp(QP)
+    Vf = np.full(sum(sum(r[2] for r in layout.V_rows(B_OBS, qf, q)) * d for q, d in A_OBS), np.nan)
+    k = lib._Keep()
+    assert hostplan.hostplan_twosite_V(C.byref(k.leg(A_OBS)), C.byref(k.leg(B_OBS)), 2, k.ints(QP),
+                                       C.c_void_p(x.ctypes.data), C.c_void_p(Vf.ctypes.data)) == 0
+    W = fused_mpo("1", "1", 0, lib.RIGHT, QP)
+    Y = {(w, q, q): np.asarray(workloads.gaussian(d * d, 66, 2, q + 100).reshape(d, d)) for q, d in B_OBS
+         for w in (1, 2)}
+    Rf = layout.envR_to_flat(Y, B_OBS, W.qr)
+    out = np.full(layout.envR_size(A_OBS, W.ql), np.nan)
+    u = lib.EnvUpdate_t(k.leg(B_OBS), k.leg(A_OBS), k.mpo(W), C.c_void_p(Rf.ctypes.data), C.c_void_p(Vf.ctypes.data),
+                        C.c_void_p(out.ctypes.data))
+    assert hostplan.hostplan_env(1, C.byref(u)) == 0
+    Rnew = layout.flat_to_envR(out, A_OBS, W.ql)
+    psi = layout.flat_to_psi(x, A_OBS, B_OBS, QP)
+    ma, mb = sum(d for _, d in A_OBS), sum(d for _, d in B_OBS)
+    ao, bo, o = {}, {}, 0
+    for q, d in A_OBS:
+        ao[q], o = o, o + d
+    o = 0
+    for q, d in B_OBS:
+        bo[q], o = o, o + d
+    Bd = np.zeros((ma, 2, 2, mb))
+    for (qa, s1, s2), blk in psi.items():
+        qb = qa + QP[s1] + QP[s2]
+        Bd[ao[qa]:ao[qa] + blk.shape[0], s1, s2, bo[qb]:bo[qb] + blk.shape[1]] = blk
+    Yd = _dense({(q, q): Y[(2, q, q)] for q, _ in B_OBS}, B_OBS, B_OBS, lambda a, b: (a, b))
+    ref = np.einsum("astb,bB,AstB->aA", Bd, Yd, Bd)
+    for ch in (1, 2):
+        got = _dense({(qa, qb): v for (w, qa, qb), v in Rnew.items() if w == ch}, A_OBS, A_OBS, lambda a, b: (a, b))
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), ch

@@ -108,6 +108,18 @@ def yc8_kagome_bonds(J: float = 1.0):
     return sorted((k, k2, J_) for (k, k2), J_ in bonds.items())
 
 
+def yc8_bond_classes():
+    """The six nearest-neighbour bond classes of the YC8 cylinder whose strengths Sec. 4 reports, each as its four
+    translates by 3 sites around the circumference (site labels; inside a ring the index wraps, a label above 12
+    is a site of the next ring).  Class names are those of the paper: (1,2), (2,3), (3,4), (2,4), (3,13), (3,14)."""
+    def ring(a):
+        return (a - 1) % 12 + 1
+    rules = {"1-2": lambda c: (3 * c + 1, 3 * c + 2), "2-3": lambda c: (3 * c + 2, 3 * c + 3),
+             "3-4": lambda c: (3 * c + 3, ring(3 * c + 4)), "2-4": lambda c: (3 * c + 2, ring(3 * c + 4)),
+             "3-13": lambda c: (3 * c + 3, 3 * c + 13), "3-14": lambda c: (3 * c + 3, 3 * c + 14)}
+    return {name: [tuple(sorted(f(c))) for c in range(4)] for name, f in rules.items()}
+
+
 def segment_bonds(cell_bonds, ell: int, first: int, last: int):
     """All bonds (i, j, J) of the infinite periodic model with first <= i < j <= last."""
     out = {}
