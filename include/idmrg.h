@@ -197,7 +197,10 @@ typedef struct {
     int32_t k_max;      /* at most min(k_max, N) Lanczos vectors */
     int32_t prec;       /* IDMRG_PREC_* of the matvec inside the iteration */
     int32_t chunk;      /* iterations between host checks of the device stop flags */
-    int32_t refine;     /* mixed precision only: FP64 residual refinement after the iteration */
+    int32_t fp32_basis; /* mixed precision only: 1 stores the Krylov vectors of the first pass, after its
+                           start vector, in FP32 (half the bytes of that pass's re-orthogonalisation; every
+                           sum stays FP64, and the refinement passes keep an FP64 basis); 0 keeps every
+                           vector FP64.  Ignored for IDMRG_PREC_F64. */
     int32_t cgs2;       /* 1: second Gram-Schmidt pass in every iteration (classical CGS2);
                            0: only where the first pass removes more than 99 % of |w|^2 */
     int32_t graph;      /* 1: once the GEMM tilings are tuned, every full chunk of iterations

@@ -1547,7 +1547,10 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     for (int p = 0; p < P; ++p) {
       vv[p] = V + k.voff[p];
       ww[p] = V + k.woff[p];
-      probs[p] = LzProblem{k.N[p], k.ld[p], V + k.qoff[p], ww[p], vv[p], psi[p], mixed ? V + k.soff[p] : nullptr};
+      // FP32 basis rows (first pass of a mixed solve) live in the FP64 rows' space after row 0: (kcap - 1) ld
+      // floats fit in (kcap - 1) ld doubles
+      float* qf = mixed && o->fp32_basis ? (float*)(V + k.qoff[p] + k.ld[p]) : nullptr;
+      probs[p] = LzProblem{k.N[p], k.ld[p], V + k.qoff[p], ww[p], vv[p], psi[p], mixed ? V + k.soff[p] : nullptr, qf};
     }
     // The two plans use disjoint scratch regions, so binding the second never
     // touches what the first has uploaded.
@@ -1585,6 +1588,13 @@ extern "C" int lanczos_solve_batch(idmrg_ctx* ctx, int nprob, const idmrg_heff* 
     std::vector<double> ov0(P, 0.0);
     GraphSet graphs(s);
     for (int outer = 0; outer < max_outer; ++outer) {
+      if (outer == 1 && mixed && o->fp32_basis) {
+        // Refinement passes keep an FP64 basis: their Ritz correction must reach the final residual tolerance,
+        // and rounding the basis to FP32 leaves a residual of about |H - theta| u_32 |correction|, which is near
+        // 1e-8 after the first pass.  The first pass stops at a residual far above that.
+        for (auto& pr : probs) pr.Qf = nullptr;
+        stage(ctx, dprobs, probs.data(), P * sizeof(LzProblem));
+      }
       std::vector<LzCtrl> hctrl(P);
       std::vector<int32_t> hact(P);
       int64_t maxk = 0;

@@ -256,6 +256,8 @@ struct LzProblem {
   double* v;        // [ld] current vector (matvec input), zero beyond N
   double* psi;      // [N] caller's vector
   double* s0;       // [ld] normalised start vector (mixed precision only; else null)
+  float* Qf;        // FP32 basis: rows 1.. of the basis, row i at Qf + (i - 1) ld (row 0 stays FP64 in Q);
+                    // null: every row in Q
 };
 
 struct LzCtrl {     // device, one per problem

@@ -31,6 +31,13 @@
 // a 16-byte boundary and the streaming kernels use 16-byte loads.  The
 // dot-product kernel keeps its block's slice of w in LDS and streams the
 // basis rows past it, so the basis is read once per pass and w once.
+//
+// With an FP32 basis (LzProblem::Qf set: the first pass of a mixed solve), rows
+// 1.. are stored rounded to FP32 and v is set to exactly the stored row, so
+// the Lanczos relation holds for the stored vectors up to beta_j times the
+// rounding of q_{j+1}; row 0, the pass's start vector, stays FP64, so the Ritz
+// vector's FP32 part is only the correction the pass adds.  All arithmetic
+// stays FP64.
 #include "internal.h"
 
 namespace idmrg {
@@ -192,13 +199,25 @@ __global__ __launch_bounds__(TB) void k_mdot(const LzProblem* probs, const LzCtr
     }
     __syncthreads();
     for (int i = wave; i <= j; i += TB / 64) {
-      const double* q = pr.Q + (int64_t)i * pr.ld + s0;
       double a = 0.0;
+      if (i == 0 || !pr.Qf) {
+        const double* q = pr.Q + (int64_t)i * pr.ld + s0;
 #pragma unroll 4
-      for (int e = 2 * lane; e < len; e += 128) {
-        const v2d qv = *reinterpret_cast<const v2d*>(&q[e]);
-        const v2d xv = *reinterpret_cast<const v2d*>(&xs[e]);
-        a += qv.x * xv.x + qv.y * xv.y;
+        for (int e = 2 * lane; e < len; e += 128) {
+          const v2d qv = *reinterpret_cast<const v2d*>(&q[e]);
+          const v2d xv = *reinterpret_cast<const v2d*>(&xs[e]);
+          a += qv.x * xv.x + qv.y * xv.y;
+        }
+      } else {
+        // FP32 row: four elements per 16-byte load (len is a multiple of kLzAlign)
+        const float* q = pr.Qf + (int64_t)(i - 1) * pr.ld + s0;
+#pragma unroll 2
+        for (int e = 4 * lane; e < len; e += 256) {
+          const float4 qv = *reinterpret_cast<const float4*>(&q[e]);
+          const v2d x0 = *reinterpret_cast<const v2d*>(&xs[e]);
+          const v2d x1 = *reinterpret_cast<const v2d*>(&xs[e + 2]);
+          a += (double)qv.x * x0.x + (double)qv.y * x0.y + (double)qv.z * x1.x + (double)qv.w * x1.y;
+        }
       }
       a = wave_sum(a);
       if (lane == 0) acc[i] += a;
@@ -248,20 +267,47 @@ __global__ __launch_bounds__(TB) void k_update(const LzProblem* probs, const LzC
   int64_t lo, hi;
   pad_range(pr.ld, b, lo, hi);
   double nrm = 0.0;
-  for (int64_t n = lo + 2 * t; n < hi; n += 2 * TB) {
-    v2d s = {0.0, 0.0};
-    const double* q = pr.Q + n;
+  if (!pr.Qf) {
+    for (int64_t n = lo + 2 * t; n < hi; n += 2 * TB) {
+      v2d s = {0.0, 0.0};
+      const double* q = pr.Q + n;
 #pragma unroll 4
-    for (int i = 0; i <= j; ++i) {
-      const v2d qv = *reinterpret_cast<const v2d*>(&q[(int64_t)i * pr.ld]);
-      s.x += cs[i] * qv.x;
-      s.y += cs[i] * qv.y;
+      for (int i = 0; i <= j; ++i) {
+        const v2d qv = *reinterpret_cast<const v2d*>(&q[(int64_t)i * pr.ld]);
+        s.x += cs[i] * qv.x;
+        s.y += cs[i] * qv.y;
+      }
+      v2d wv = *reinterpret_cast<const v2d*>(&pr.w[n]);
+      wv.x -= s.x;
+      wv.y -= s.y;
+      *reinterpret_cast<v2d*>(&pr.w[n]) = wv;
+      nrm += wv.x * wv.x + wv.y * wv.y;
     }
-    v2d wv = *reinterpret_cast<const v2d*>(&pr.w[n]);
-    wv.x -= s.x;
-    wv.y -= s.y;
-    *reinterpret_cast<v2d*>(&pr.w[n]) = wv;
-    nrm += wv.x * wv.x + wv.y * wv.y;
+  } else {
+    // FP64 row 0, FP32 rows 1..j; four elements per thread (hi - lo is a multiple of kLzAlign)
+    for (int64_t n = lo + 4 * t; n < hi; n += 4 * TB) {
+      const v2d q0a = *reinterpret_cast<const v2d*>(&pr.Q[n]);
+      const v2d q0b = *reinterpret_cast<const v2d*>(&pr.Q[n + 2]);
+      double s0 = cs[0] * q0a.x, s1 = cs[0] * q0a.y, s2 = cs[0] * q0b.x, s3 = cs[0] * q0b.y;
+      const float* q = pr.Qf + n;
+#pragma unroll 4
+      for (int i = 1; i <= j; ++i) {
+        const float4 qv = *reinterpret_cast<const float4*>(&q[(int64_t)(i - 1) * pr.ld]);
+        s0 += cs[i] * (double)qv.x;
+        s1 += cs[i] * (double)qv.y;
+        s2 += cs[i] * (double)qv.z;
+        s3 += cs[i] * (double)qv.w;
+      }
+      v2d wa = *reinterpret_cast<const v2d*>(&pr.w[n]);
+      v2d wb = *reinterpret_cast<const v2d*>(&pr.w[n + 2]);
+      wa.x -= s0;
+      wa.y -= s1;
+      wb.x -= s2;
+      wb.y -= s3;
+      *reinterpret_cast<v2d*>(&pr.w[n]) = wa;
+      *reinterpret_cast<v2d*>(&pr.w[n + 2]) = wb;
+      nrm += wa.x * wa.x + wa.y * wa.y + wb.x * wb.x + wb.y * wb.y;
+    }
   }
   nrm = block_sum(nrm, sh);
   if (t == 0) partial[((int64_t)p * kmax) * kLzBlocks + b] = nrm;
@@ -398,6 +444,16 @@ __global__ __launch_bounds__(TB) void k_next(const LzProblem* probs, const LzCtr
   const LzProblem pr = probs[p];
   const int j = ctrl[p].j;
   const double inv = 1.0 / beta[(int64_t)p * kmax + j - 1];
+  if (pr.Qf) {
+    // the FP32 row, and v = exactly the stored row, so the next matvec acts on the basis vector
+    float* q = pr.Qf + (int64_t)(j - 1) * pr.ld;
+    for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.ld; n += (int64_t)gridDim.x * TB) {
+      const float x = (float)(pr.w[n] * inv);
+      q[n] = x;
+      pr.v[n] = (double)x;
+    }
+    return;
+  }
   double* q = pr.Q + (int64_t)j * pr.ld;
   for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.ld; n += (int64_t)gridDim.x * TB) {
     const double x = pr.w[n] * inv;
@@ -415,7 +471,12 @@ __global__ __launch_bounds__(TB) void k_ritz(const LzProblem* probs, const LzCtr
   const double* y = ritz + (int64_t)p * kmax;
   for (int64_t n = blockIdx.x * (int64_t)TB + threadIdx.x; n < pr.N; n += (int64_t)gridDim.x * TB) {
     double s = 0.0;
-    for (int i = 0; i < k; ++i) s += y[i] * pr.Q[(int64_t)i * pr.ld + n];
+    if (pr.Qf) {
+      s = y[0] * pr.Q[n];
+      for (int i = 1; i < k; ++i) s += y[i] * (double)pr.Qf[(int64_t)(i - 1) * pr.ld + n];
+    } else {
+      for (int i = 0; i < k; ++i) s += y[i] * pr.Q[(int64_t)i * pr.ld + n];
+    }
     pr.psi[n] = s;
   }
 }

@@ -35,6 +35,7 @@ class IDMRG:
         self.predict = predict
         self.chunk = chunk
         self.graph = graph
+        self.fp32_basis = True   # mixed precision: the first pass's Krylov vectors stored in FP32
         self.batched = batched   # False: one library call per superblock (for comparison only)
         self.log = log
         self.W = models.heisenberg_mpo(cfg["bonds"], self.ell, dense=dense)
@@ -105,12 +106,14 @@ class IDMRG:
         t1 = time.perf_counter()
         if self.batched:
             es, infos = lib.lanczos_solve_batch(self.ctx, H, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"],
-                                                self.prec, self.chunk, graph=self.graph)
+                                                self.prec, self.chunk, graph=self.graph,
+                                                fp32_basis=self.fp32_basis)
         else:
             es, infos = [], []
             for h, p in zip(H, psis):
                 e1, i1 = lib.lanczos_solve_batch(self.ctx, [h], [p], cfg["tol_E"], cfg["tol_res"], cfg["k_max"],
-                                                 self.prec, self.chunk, graph=self.graph)
+                                                 self.prec, self.chunk, graph=self.graph,
+                                                 fp32_basis=self.fp32_basis)
                 es += e1
                 infos += i1
         t2 = time.perf_counter()

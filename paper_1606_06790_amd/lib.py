@@ -58,7 +58,7 @@ class Heff_t(C.Structure):
 
 class LanczosOpts_t(C.Structure):
     _fields_ = [("tol_E", C.c_double), ("tol_res", C.c_double), ("k_max", C.c_int32), ("prec", C.c_int32),
-                ("chunk", C.c_int32), ("refine", C.c_int32), ("cgs2", C.c_int32), ("graph", C.c_int32)]
+                ("chunk", C.c_int32), ("fp32_basis", C.c_int32), ("cgs2", C.c_int32), ("graph", C.c_int32)]
 
 
 class LanczosInfo_t(C.Structure):
@@ -427,14 +427,15 @@ def heff_apply_static(ctx, problems, xs, ys, prec="f64"):
 
 
 def lanczos_solve_batch(ctx, problems, psis, tol_E=1e-12, tol_res=1e-8, k_max=300, prec="f64", chunk=8,
-                        refine=True, cgs2=False, graph=False):
+                        fp32_basis=True, cgs2=False, graph=False):
     """Lowest eigenpairs; psis are overwritten with the ground states.  Returns (energies, infos).
-    graph=True replays full chunks of iterations as captured HIP graphs (bitwise the same results)."""
+    graph=True replays full chunks of iterations as captured HIP graphs (bitwise the same results).
+    fp32_basis (mixed precision only): the first pass's Krylov vectors after its start vector stored in FP32."""
     k = _Keep()
     arr = _heff_structs(k, problems)
     P = len(problems)
     pp = (C.c_void_p * P)(*[_ptr(x) for x in psis])
-    opts = LanczosOpts_t(tol_E, tol_res, k_max, PREC[prec], chunk, 1 if refine else 0, 1 if cgs2 else 0, 1 if graph else 0)
+    opts = LanczosOpts_t(tol_E, tol_res, k_max, PREC[prec], chunk, 1 if fp32_basis else 0, 1 if cgs2 else 0, 1 if graph else 0)
     e = (C.c_double * P)()
     inf = (LanczosInfo_t * P)()
     ctx.reserve(OP_LANCZOS, P, arr, WsQuery_t(opts=C.pointer(opts)))

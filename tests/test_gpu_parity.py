@@ -417,14 +417,19 @@ def test_heff_apply_mixed(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
-def test_lanczos_mixed_refined(ctx, prec):
+@pytest.mark.parametrize("fp32_basis", [True, False])
+def test_lanczos_mixed_refined(ctx, prec, fp32_basis):
     """Mixed-precision Lanczos with FP64-anchored refinement: the energy is an FP64
-    Rayleigh quotient with FP64 residual <= tol_res, so it matches the oracle to 1e-12."""
+    Rayleigh quotient with FP64 residual <= tol_res, so it matches the oracle to 1e-12,
+    with the first pass's Krylov vectors stored in FP32 or in FP64."""
     cfg, r = _oracle_states("random_chain", 32, 7, tol_res=1e-10)
     sts = [st for st in r["states"] if st["n"] in (6, 7)]
     probs = [_flat_problem(st) for st in sts]
     psis = [T(st["v0"]) for st in sts]
-    es, infos = lib.lanczos_solve_batch(ctx, probs, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"], prec)
+    es, infos = lib.lanczos_solve_batch(ctx, probs, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"], prec,
+                                        fp32_basis=fp32_basis)
+    print(f"[lanczos mixed] {prec} fp32_basis={fp32_basis}: iterations {[i['iters'] for i in infos]}, "
+          f"FP64 matvecs {[i['fp64_matvecs'] for i in infos]}")
     steps = {(s["n"], s["i"]): s for s in r["steps"]}
     for st, e, inf, p in zip(sts, es, infos, psis):
         assert abs(e - steps[(st["n"], st["i"])]["energy"]) <= 1e-12
