@@ -236,6 +236,14 @@ def correlation_length(corr, r0=2):
     return -1.0 / slope
 
 
+def decay_length(dist, corr, d_min):
+    """Length of the exponential decay |C| ~ exp(-d / xi): least-squares slope of ln|C| against d over d > d_min."""
+    d = np.asarray(dist, dtype=np.float64)
+    y = np.log(np.abs(np.asarray(corr, dtype=np.float64)))
+    keep = d > d_min
+    return -1.0 / np.polyfit(d[keep], y[keep], 1)[0]
+
+
 def main():
     """Run the parallel iDMRG on a workload, then measure the uniform MPS: bond strengths of the bond classes with
     their spread (Eqs. (15), (16)), the correlation function of one site label along the cylinder and its
@@ -280,6 +288,16 @@ def main():
     spread = {name: dict(zip(("average", "delta_plus", "delta_minus"), bond_spread([bs[p] for p in v])))
               for name, v in classes.items()}
     corr = u.correlation_function(a.label, a.rings)
+    axis = None
+    if a.workload == "yc8":
+        # the same correlation along the straight line of the axis (Sec. 4 sweeps i = 2, 14, 35, 47, ...), with
+        # distances in nearest-neighbour units, and its decay length fitted over distances above 5 as in the paper
+        sweep = workloads.yc8_axis_sweep(a.rings, a.label)
+        a0 = u.position(a.label)
+        vals = u.correlations([(a0, a0 + site - a.label) for site, _ in sweep[1:]])
+        dist = [r for _, r in sweep[1:]]
+        axis = dict(sites=[site for site, _ in sweep[1:]], distance=dist, values=vals,
+                    xi=decay_length(dist, vals, 5.0))
     period = [s for s in d.steps if s["n"] > d.n - cfg["ell"] and s["i"] == 1]
     out = dict(workload=a.workload, m=cfg["m"], n=d.n, prec=d.prec, e_g=d.e_g[max(d.e_g)] if d.e_g else None,
                eps=max(s["eps"] for s in period),
@@ -287,7 +305,7 @@ def main():
                if all((i, j) in bs for (i, j, _) in cfg["bonds"]) else None,
                t1=u.t1, cells_left=u.cells_L, cells_right=u.cells_R,
                bonds={f"{i}-{j}": bs[(i, j)] for (i, j) in pairs}, classes=spread,
-               correlation=dict(label=a.label, values=corr, xi_cells=correlation_length(corr)),
+               correlation=dict(label=a.label, values=corr, xi_cells=correlation_length(corr)), axis=axis,
                seconds_run=round(t_run, 1), seconds_observables=round(time.perf_counter() - t0, 2))
     if a.tune_cache:
         d.ctx.save_tuning(a.tune_cache)

@@ -47,3 +47,28 @@ def test_main_leaves_out_runs_below_m_min(tmp_path, capsys):
     assert np.isnan(out[2]["e0_stderr"])          # three points: the quadratic fits exactly, no error estimate
     c, _, _ = extrapolate.fit([8.7e-5, 3.1e-5, 1.3e-5], [-0.43780, -0.43817, -0.43829], 1)
     assert abs(out[1]["e0"] - c[0]) <= 1e-15
+
+
+def test_observables_fit_recovers_known_limits(tmp_path, capsys):
+    """Synthetic observables runs whose class averages, spreads and correlation points are exact quadratics in eps:
+    the fits return the eps -> 0 values, and the correlation length of an exact exponential."""
+    import json
+    xi = 0.7
+    lines = []
+    for m, eps in ((1200, 4.8e-5), (1600, 3.1e-5), (2000, 2.2e-5), (2400, 1.7e-5), (2800, 1.3e-5), (800, 8.7e-5)):
+        cls = {"1-2": dict(average=-0.2158 + 3.0 * eps + 1e3 * eps ** 2, delta_plus=40.0 * eps,
+                           delta_minus=-35.0 * eps - 2e4 * eps ** 2),
+               "3-13": dict(average=-0.2208 - 2.0 * eps, delta_plus=eps, delta_minus=-eps)}
+        vals = [(-1) ** r * 0.05 * np.exp(-r / xi) * (1 + 50 * eps) for r in range(1, 7)]
+        lines.append(json.dumps(dict(m=m, n=239, eps=eps, classes=cls,
+                                     correlation=dict(label=2, values=vals, xi_cells=xi))))
+    p = tmp_path / "obs.jsonl"
+    p.write_text("\n".join(lines) + "\n")
+    out = extrapolate.observables([str(p)], eps_max=6e-5)
+    assert len(out["points"]) == 5 and "left out" in capsys.readouterr().out
+    assert abs(out["classes"]["1-2"]["average"]["value"] + 0.2158) <= 1e-12
+    assert abs(out["classes"]["3-13"]["average"]["value"] + 0.2208) <= 1e-12
+    assert abs(out["classes"]["1-2"]["delta_plus"]["value"]) <= 1e-12
+    assert abs(out["classes"]["1-2"]["delta_minus"]["value"]) <= 1e-12
+    assert abs(out["correlation"]["xi_cells"] - xi) <= 1e-9
+    assert abs(out["correlation"]["values"][0] + 0.05 * np.exp(-1 / xi)) <= 1e-12

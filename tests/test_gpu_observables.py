@@ -135,3 +135,10 @@ def test_uniform_mps_matches_oracle(ctx, name, m, n):
     ref_c = [ob.spin_correlation(Bs, a, a + cfg["ell"] * r, fp) for r in range(1, 5)]
     for x, y in zip(corr, ref_c):
         assert abs(x - y) <= 1e-10 * max(1.0, abs(y)) + 1e-13
+    if name == "yc8":
+        # the sweep along the cylinder's axis: pairs of different labels several cells apart
+        sweep = workloads.yc8_axis_sweep(3, label)
+        got_ax = u.correlations([(a, a + s - label) for s, _ in sweep[1:]])
+        for (s, _), x in zip(sweep[1:], got_ax):
+            y = ob.spin_correlation(Bs, a, a + s - label, fp)
+            assert abs(x - y) <= 1e-10 * max(1.0, abs(y)) + 1e-13, (s, x, y)

@@ -43,3 +43,20 @@ def test_seeded_draws_are_reproducible():
     assert np.array_equal(workloads.gaussian(7, 2, 256, 1, 3), workloads.gaussian(7, 2, 256, 1, 3))
     assert not np.array_equal(workloads.gaussian(7, 2, 256, 1, 3), workloads.gaussian(7, 2, 256, 0, 3))
     assert np.array_equal(workloads.start_vector(5, 1, 2), np.random.default_rng([workloads.SEED, 1, 2]).standard_normal(5))
+
+
+def test_yc8_axis_sweep():
+    """The reconstructed YC8 embedding gives the sweep of sites that Sec. 4 lists for the correlation function
+    (i = 2, 14, 35, 47, ...), every site on it has the start's sublattice, and consecutive sites are joined by the
+    bonds of the lattice's two-step paths (distances 2 and 2 sqrt(3) alternate with the parity of the ring)."""
+    sweep = workloads.yc8_axis_sweep(8, 2)
+    assert [s for s, _ in sweep[:4]] == [2, 14, 35, 47]
+    assert all((s - 1) % 3 == 1 for s, _ in sweep)           # sublattice of label 2
+    assert [s // 12 if s % 12 else s // 12 - 1 for s, _ in sweep] == list(range(9))   # one site per ring
+    for R, (_, d) in enumerate(sweep):
+        assert abs(d - np.sqrt(3 * R * R + R % 2)) <= 1e-12
+    # the even rings lie exactly on the axis: distances R sqrt(3)
+    assert abs(sweep[2][1] - 2 * np.sqrt(3)) <= 1e-12 and abs(sweep[8][1] - 8 * np.sqrt(3)) <= 1e-12
+    # site 14 is a nearest-neighbour two-step path away from 2: 2 - 3 - 14 are both bonds of the cell
+    bonds = {(i, j) for i, j, _ in workloads.yc8_kagome_bonds()}
+    assert (2, 3) in bonds and (3, 14) in bonds

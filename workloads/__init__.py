@@ -120,6 +120,24 @@ def yc8_bond_classes():
     return {name: [tuple(sorted(f(c))) for c in range(4)] for name, f in rules.items()}
 
 
+def yc8_axis_sweep(rings: int, label: int = 2):
+    """Sites on the straight line along the YC8 cylinder's axis through site `label` of ring 0, one per ring
+    R = 0..rings, with their distance from it (nearest-neighbour distance 1).
+
+    Embedding (reconstructed; the paper shows it only in its figure): kagome Bravais vectors of length 2 at 60
+    degrees, a1 wrapped four times around the circumference, a2 from one ring to the next, so a2 moves sqrt(3)
+    along the axis and one unit (half of a1) around.  Site 3c + s + 1 (s = 0, 1, 2) of a ring is sublattice s of
+    the c-th kagome cell around it.  The point of ring R on the line is R a2 - floor(R / 2) a1: cell c - floor(R/2)
+    (mod 4), at distance sqrt(3 R^2 + (R mod 2)^2).  For label 2 this gives the sweep 2, 14, 35, 47, ... of the
+    correlation-length subsection of Sec. 4."""
+    c0, sub = divmod(label - 1, 3)
+    out = []
+    for R in range(rings + 1):
+        c = (c0 - R // 2) % 4
+        out.append((12 * R + 3 * c + sub + 1, math.sqrt(3 * R * R + (R % 2))))
+    return out
+
+
 def segment_bonds(cell_bonds, ell: int, first: int, last: int):
     """All bonds (i, j, J) of the infinite periodic model with first <= i < j <= last."""
     out = {}
