@@ -407,60 +407,77 @@ def traffic_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, top=18):
 MFMA_PEAK_TFLOPS = {"BF16": 2500.0, "F16": 2500.0, "F32": 157.3, "F64": 78.6}
 
 
-def mfma_counters(directory):
-    """MFMA utilisation per kernel from a `rocprofv3 --pmc ... --kernel-trace --output-format csv` run.
+PCT_METRICS = ("MfmaUtil", "LdsUtil", "LDSBankConflict")   # rocprofv3 derived metrics in percent per dispatch
+
+
+def mfma_counters(directories):
+    """MFMA and LDS utilisation per kernel from `rocprofv3 --pmc ... --kernel-trace --output-format csv` runs (one
+    directory per counter pass; the passes are merged by kernel name).
 
     Per dispatch: MFMA flops executed = 512 x SQ_INSTS_VALU_MFMA_MOPS_<type> (the counter counts units of 512
     flops, padding of ragged tiles included); rate = flops / kernel duration; share of the type's dense peak.
-    rocprofv3's derived metric MfmaUtil (MFMA-busy SIMD cycles over active cycles x SIMDs, in percent) is
-    averaged weighted by duration.  Per kernel over its dispatches; prints one JSON line."""
+    The derived metrics MfmaUtil (MFMA-busy SIMD cycles over active cycles x SIMDs), LdsUtil and LDSBankConflict
+    (percent) are averaged weighted by duration; SQ_WAIT_ANY, SQ_WAIT_INST_LDS and SQ_LDS_DATA_FIFO_FULL are
+    reported per wave cycle (over SQ_WAVE_CYCLES of the same pass).  Prints one JSON line."""
     import csv
     import glob
     from collections import defaultdict
 
-    def rows(pattern):
-        out = []
-        for path in glob.glob(os.path.join(directory, "**", pattern), recursive=True):
-            with open(path, newline="") as f:
-                out.extend(csv.DictReader(f))
-        return out
+    if isinstance(directories, str):
+        directories = [directories]
+    merged = {}
+    for directory in directories:
+        def rows(pattern):
+            out = []
+            for path in glob.glob(os.path.join(directory, "**", pattern), recursive=True):
+                with open(path, newline="") as f:
+                    out.extend(csv.DictReader(f))
+            return out
 
-    dur = {}
-    for r in rows("*kernel_trace.csv"):
-        dur[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-    per = defaultdict(lambda: defaultdict(float))
-    name = {}
-    for r in rows("*counter_collection.csv"):
-        did = r["Dispatch_Id"]
-        per[did][r["Counter_Name"]] += float(r["Counter_Value"])
-        name[did] = r["Kernel_Name"]
-        if did not in dur and r.get("Start_Timestamp") and r.get("End_Timestamp"):
-            dur[did] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-    agg = defaultdict(lambda: defaultdict(float))
-    for did, c in per.items():
-        if did not in dur or dur[did] <= 0:
-            continue
-        a = agg[name[did]]
-        a["dispatches"] += 1
-        a["ns"] += dur[did]
-        for k, v in c.items():
-            if k == "MfmaUtil":
-                a["MfmaUtil_ns"] += v * dur[did]
-            else:
-                a[k] += v
-    out = []
-    for kname, a in sorted(agg.items(), key=lambda kv: -kv[1]["ns"]):
-        row = dict(kernel=kname[:96], dispatches=int(a["dispatches"]), avg_ms=round(a["ns"] / a["dispatches"] * 1e-6, 4))
-        for typ, peak in MFMA_PEAK_TFLOPS.items():
-            mops = a.get(f"SQ_INSTS_VALU_MFMA_MOPS_{typ}", 0.0)
-            if mops > 0:
-                tf = 512.0 * mops / (a["ns"] * 1e-9) / 1e12
-                row[f"mfma_{typ.lower()}_tflops"] = round(tf, 2)
-                row[f"mfma_{typ.lower()}_peak_share"] = round(tf / peak, 4)
-        if "MfmaUtil_ns" in a:
-            row["mfma_util_pct"] = round(a["MfmaUtil_ns"] / a["ns"], 2)
-        out.append(row)
-    print(json.dumps({"mfma_counters": directory, "kernels": out[:20]}), flush=True)
+        dur = {}
+        for r in rows("*kernel_trace.csv"):
+            dur[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        per = defaultdict(lambda: defaultdict(float))
+        name = {}
+        for r in rows("*counter_collection.csv"):
+            did = r["Dispatch_Id"]
+            per[did][r["Counter_Name"]] += float(r["Counter_Value"])
+            name[did] = r["Kernel_Name"]
+            if did not in dur and r.get("Start_Timestamp") and r.get("End_Timestamp"):
+                dur[did] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        agg = defaultdict(lambda: defaultdict(float))
+        for did, c in per.items():
+            if did not in dur or dur[did] <= 0:
+                continue
+            a = agg[name[did]]
+            a["dispatches"] += 1
+            a["ns"] += dur[did]
+            for k, v in c.items():
+                if k in PCT_METRICS:
+                    a[k + "_ns"] += v * dur[did]
+                else:
+                    a[k] += v
+        for kname, a in agg.items():
+            row = merged.setdefault(kname, dict(kernel=kname[:96], dispatches=int(a["dispatches"]),
+                                                avg_ms=round(a["ns"] / a["dispatches"] * 1e-6, 4), _ns=a["ns"]))
+            for typ, peak in MFMA_PEAK_TFLOPS.items():
+                mops = a.get(f"SQ_INSTS_VALU_MFMA_MOPS_{typ}", 0.0)
+                if mops > 0:
+                    tf = 512.0 * mops / (a["ns"] * 1e-9) / 1e12
+                    row[f"mfma_{typ.lower()}_tflops"] = round(tf, 2)
+                    row[f"mfma_{typ.lower()}_peak_share"] = round(tf / peak, 4)
+            for k in PCT_METRICS:
+                if k + "_ns" in a:
+                    row[{"MfmaUtil": "mfma_util_pct", "LdsUtil": "lds_util_pct",
+                         "LDSBankConflict": "lds_bank_conflict_pct"}[k]] = round(a[k + "_ns"] / a["ns"], 2)
+            if a.get("SQ_WAVE_CYCLES", 0.0) > 0:
+                for k in ("SQ_WAIT_ANY", "SQ_WAIT_INST_LDS", "SQ_LDS_DATA_FIFO_FULL"):
+                    if k in a:
+                        row[k.lower() + "_per_wave_cycle"] = round(a[k] / a["SQ_WAVE_CYCLES"], 4)
+    out = sorted(merged.values(), key=lambda r: -r["_ns"])
+    for r in out:
+        del r["_ns"]
+    print(json.dumps({"mfma_counters": directories, "kernels": out[:20]}), flush=True)
 
 
 def copy_calibration():
@@ -541,9 +558,9 @@ def main():
     ap.add_argument("--launch-gaps", metavar="DIR", default=None,
                     help="only summarise the GPU idle time inside the timed regions of a rocprofv3 kernel + marker "
                          "trace (CSV) found under DIR; runs on the CPU")
-    ap.add_argument("--mfma-counters", metavar="DIR", default=None,
-                    help="only summarise MFMA utilisation per kernel from a rocprofv3 --pmc run (CSV) under DIR; "
-                         "runs on the CPU")
+    ap.add_argument("--mfma-counters", metavar="DIR", nargs="+", default=None,
+                    help="only summarise MFMA and LDS utilisation per kernel from rocprofv3 --pmc runs (CSV), one "
+                         "directory per counter pass; runs on the CPU")
     ap.add_argument("--stats-summary", metavar="DIR", default=None,
                     help="only print a markdown table of a rocprofv3 --stats run (CSV) under DIR; runs on the CPU")
     ap.add_argument("--traffic-summary", metavar="DIR", nargs=4, default=None,

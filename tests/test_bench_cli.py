@@ -117,6 +117,30 @@ def test_mfma_counters_from_a_trace(tmp_path, capsys):
     assert k["mfma_util_pct"] == 50.0
 
 
+def test_counter_passes_merge_by_kernel(tmp_path, capsys):
+    """Two --pmc passes over the same run (MFMA counters, then LDS counters) merge into one row per kernel; the
+    percent metrics are duration-weighted and the wait counters are taken per wave cycle of their own pass."""
+    def pas(name, counters):
+        d = tmp_path / name
+        d.mkdir()
+        (d / "k_kernel_trace.csv").write_text(
+            '"Dispatch_Id","Kernel_Name","Start_Timestamp","End_Timestamp"\n"1","g",0,1000000\n"2","g",0,3000000\n')
+        rows = ['"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"']
+        for did in (1, 2):
+            rows += [f'"{did}","g","{c}","{v[did - 1]}"' for c, v in counters.items()]
+        (d / "k_counter_collection.csv").write_text("\n".join(rows) + "\n")
+        return str(d)
+    a = pas("a", {"SQ_INSTS_VALU_MFMA_MOPS_F64": [39.3e12 * 1e-3 / 512, 3 * 39.3e12 * 1e-3 / 512],
+                  "MfmaUtil": [10.0, 30.0]})
+    b = pas("b", {"LdsUtil": [20.0, 12.0], "SQ_WAIT_ANY": [10.0, 30.0], "SQ_WAVE_CYCLES": [100.0, 100.0]})
+    bench.mfma_counters([a, b])
+    k = json.loads(capsys.readouterr().out.strip().splitlines()[-1])["kernels"][0]
+    assert k["dispatches"] == 2 and k["avg_ms"] == 2.0
+    assert k["mfma_f64_tflops"] == 39.3 and k["mfma_f64_peak_share"] == 0.5
+    assert k["mfma_util_pct"] == 25.0 and k["lds_util_pct"] == 14.0
+    assert k["sq_wait_any_per_wave_cycle"] == 0.2
+
+
 def test_traffic_summary_writes_current_records(tmp_path, capsys, monkeypatch):
     """The traffic summary of synthetic --pmc CSVs calibrates by the copy and stamps the records with the sources
     hash, so that measured_traffic() reads them back."""
