@@ -23,7 +23,7 @@ from . import lib, models
 
 
 class IDMRG:
-    def __init__(self, cfg, device=0, prec=None, dense=False, predict=True, chunk=8, log=None, graph=True,
+    def __init__(self, cfg, device=0, prec=None, dense=False, predict=True, chunk=8, log=None, graph=False,
                  batched=True):
         import torch
         self.torch = torch
