@@ -964,7 +964,7 @@ std::shared_ptr<TruncCall> trunc_call(idmrg_ctx* c, int P, int d, const int32_t*
         if (n > 4096 || pp > 8192)
           throw InvalidArg("centre sector larger than 4096 x 8192 states is not supported");
         S.m = k.nM; k.nM += (int64_t)S.r * S.c;
-        S.x = k.nX; k.nX += (int64_t)n * pp;
+        S.x = k.nX; k.nX += bj_x_elems(n, pp);
         S.g = k.nG; k.nG += (int64_t)n * n;
         S.u = k.nU; k.nU += (int64_t)S.r * n;
         S.v = k.nV; k.nV += (int64_t)S.c * n;
@@ -986,6 +986,7 @@ std::shared_ptr<TruncCall> trunc_call(idmrg_ctx* c, int P, int d, const int32_t*
         SvdTask sv{};
         sv.r = S.r; sv.c = S.c; sv.prob = p;
         sv.m_off = S.m; sv.x_off = S.x; sv.g_off = S.g; sv.u_off = S.u; sv.v_off = S.v; sv.s_off = S.sv;
+        sv.f_off = S.x + bj_f_rel(n, pp);
         k.svd.push_back(sv);
         SelSector se{};
         se.charge = S.q; se.n = n; se.cand0 = k.ncand_tot; se.s_off = S.sv;

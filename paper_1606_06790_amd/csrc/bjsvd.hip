@@ -17,6 +17,17 @@
 // A pair whose rows are already orthogonal to the relative tolerance is left
 // alone; a sweep in which no pair of a matrix moved ends that matrix.
 //
+// QR preconditioning (Drmac and Veselic's preconditioned one-sided Jacobi,
+// here without column pivoting: the rows are sorted by norm first).  For a
+// matrix of n >= kQrMinN rows, X^T = Q1 R1 and R1^T = Q2 R2 by blocked
+// Householder QR (panels of kQrB reflectors, compact WY form), and the Jacobi
+// sweeps orthogonalise the rows of R2 (n x n) instead of those of X; they need
+// about half as many sweeps.  With G started as Q2^T P (P the norm sort), the
+// accumulated G still satisfies G X_orig = (current rows), and the final rows
+// are mapped back by Q1: F = [R2 rows after Jacobi, 0] Q1^T.  In the row
+// storage used here row j of a factored matrix holds R[0..j][j] in entries
+// 0..j and the reflector v_j (v_j[j] = 1 implicit) in entries j+1..len-1.
+//
 // Null rows: a row whose norm is at most zero_rel * |M|_F carries no
 // trustworthy direction (its singular value is below the truncation floor and
 // at the level of rounding in the other rows), and Jacobi rotations between
@@ -59,6 +70,18 @@ struct BjItem {                 // one column chunk [c0, c1) of a pair: of X (wh
 };
 
 constexpr int kChunk = 256;     // columns per Gram or rotation chunk (four 64-column tiles)
+constexpr int kQrB = 16;        // reflectors per QR panel
+constexpr int kQrMinN = 64;     // matrices with fewer rows are not preconditioned
+constexpr int kQrRows = 32;     // target rows per workgroup of the reflector application
+
+struct QrMat {                  // one matrix of the QR preconditioning (device); offsets in the X base
+  int32_t n, p, prob, qr;
+  int64_t a, f, y, j, k, t1, t2, g;
+};
+
+struct QrItem {                 // target rows [r0, r1) of one matrix
+  int32_t mat, r0, r1, pad;
+};
 
 // Operands are read through global-address-space pointers from clamped
 // (always valid) indices; a tail that must read as zero is cleared with a mask
@@ -390,6 +413,238 @@ __global__ __launch_bounds__(256) void k_bj_apply(const BjItem* __restrict__ ite
 }
 
 // done[m] |= (no pair of m moved in this sweep); changed[m] = 0
+// QR panel k of every preconditioned matrix, one workgroup each: the kQrB
+// Householder reflectors of rows j0 = k kQrB .. j0 + jb - 1 (which = 1: the
+// sorted X, rows of length p; which = 2: R1 in Y, rows of length n), applied
+// within the panel, and the upper triangular T with H_j0 ... H_j0+jb-1 =
+// I - V T V^T (16 x 16, zero padded).  The panel's entries j0 .. len - 1 are
+// worked on in LDS when they fit (kQrVL per row), else in memory.  Reductions
+// in a fixed order.
+constexpr int kQrVLP = 1152;
+
+__global__ __launch_bounds__(1024) void k_qr_panel(const QrMat* __restrict__ qm, void* const* __restrict__ bases,
+                                                  int k, int which) {
+  __shared__ double red[16];
+  __shared__ double s_tau[kQrB];
+  __shared__ double s_gram[kQrB][kQrB];
+  __shared__ double s_T[kQrB * kQrB];
+  __shared__ double Ps[kQrB * kQrVLP];
+  const QrMat m = qm[blockIdx.x];
+  const int n = m.n, j0 = k * kQrB;
+  if (!m.qr || j0 >= n) return;
+  const int jb = min(kQrB, n - j0), len = which == 1 ? m.p : n;
+  const int vl = len - j0;
+  const bool staged = vl <= kQrVLP;
+  double* base = reinterpret_cast<double*>(bases[m.prob * kNumBases + 2]);
+  double* F = base + (which == 1 ? m.a : m.y);
+  double* T = base + (which == 1 ? m.t1 : m.t2) + (int64_t)k * kQrB * kQrB;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // entry e (j0 <= e < len) of panel row i
+  auto at = [&](int i, int e) -> double& { return staged ? Ps[i * vl + (e - j0)] : F[(int64_t)(j0 + i) * len + e]; };
+  if (staged) {
+    for (int x = t; x < jb * vl; x += 1024) Ps[x] = F[(int64_t)(j0 + x / vl) * len + j0 + x % vl];
+    __syncthreads();
+  }
+  for (int jj = 0; jj < jb; ++jj) {
+    const int j = j0 + jj;
+    double a = 0.0;
+    for (int e = j + 1 + t; e < len; e += 1024) {
+      const double v = at(jj, e);
+      a += v * v;
+    }
+    a = wsum(a);
+    if (lane == 0) red[wave] = a;
+    __syncthreads();
+    double sigma = 0.0;
+    for (int w = 0; w < 16; ++w) sigma += red[w];
+    const double alpha = at(jj, j);
+    __syncthreads();   // every thread has read red and the diagonal entry
+    double beta = alpha, tau = 0.0;
+    if (sigma > 0.0) {
+      const double nrm = sqrt(alpha * alpha + sigma);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      const double scale = 1.0 / (alpha - beta);
+      for (int e = j + 1 + t; e < len; e += 1024) at(jj, e) *= scale;
+    }
+    if (t == 0) {
+      at(jj, j) = beta;
+      s_tau[jj] = tau;
+    }
+    __syncthreads();
+    for (int r = jj + 1 + wave; r < jb; r += 16) {
+      const double yj = at(r, j);
+      double w = 0.0;
+      for (int e = j + 1 + lane; e < len; e += 64) w += at(jj, e) * at(r, e);
+      w = wsum(w) + yj;
+      const double tw = tau * w;
+      for (int e = j + 1 + lane; e < len; e += 64) at(r, e) -= tw * at(jj, e);
+      if (lane == 0) at(r, j) = yj - tw;
+    }
+    __syncthreads();
+  }
+  // s_gram[a][b] = v_a . v_b (a < b): v_b starts at its unit entry j0 + b, where v_a holds entry j0 + b of row a
+  for (int pr = wave; pr < jb * jb; pr += 16) {
+    const int ia = pr / jb, ib = pr % jb;
+    if (ia >= ib) continue;
+    double g = 0.0;
+    for (int e = j0 + ib + 1 + lane; e < len; e += 64) g += at(ia, e) * at(ib, e);
+    g = wsum(g) + at(ia, j0 + ib);
+    if (lane == 0) s_gram[ia][ib] = g;
+  }
+  __syncthreads();
+  if (staged)
+    for (int x = t; x < jb * vl; x += 1024) F[(int64_t)(j0 + x / vl) * len + j0 + x % vl] = Ps[x];
+  // T, column by column: T[jj][jj] = tau_jj, T[i][jj] = -tau_jj sum_{i <= l < jj} T[i][l] gram[l][jj]
+  if (t < kQrB * kQrB) s_T[t] = 0.0;
+  __syncthreads();
+  for (int jj = 0; jj < jb; ++jj) {
+    if (t < jj) {
+      double acc = 0.0;
+      for (int l = t; l < jj; ++l) acc += s_T[t * kQrB + l] * s_gram[l][jj];
+      s_T[t * kQrB + jj] = -s_tau[jj] * acc;
+    }
+    if (t == jj) s_T[jj * kQrB + jj] = s_tau[jj];
+    __syncthreads();
+  }
+  if (t < kQrB * kQrB) T[t] = s_T[t];
+}
+
+// Block reflector of panel k applied to rows [r0, r1) (one item per workgroup,
+// eight waves, two rows per wave at a time):
+//   mode 0 (factorisation, which = 1 or 2): rows r >= j0 + jb of the matrix
+//     being factored, x_r <- (I - V T^T V^T) x_r on entries j0 .. len - 1;
+//   mode 1 (Q applied; the panels run in reverse order): rows of the target
+//     (which = 1: F, length p; which = 2: K, length n), x_r <- (I - V T V^T) x_r.
+// The panel's reflectors, entries j0 .. len - 1 with their zeros and unit
+// entries written out, are staged in LDS when they fit (kQrVL entries per
+// reflector); otherwise they are read from memory.
+constexpr int kQrVL = 1152;
+
+__device__ __forceinline__ double qr_v(const double* F, int len, int j0, int jb, int i, int e) {
+  const int ji = j0 + i;
+  return (i >= jb || e < ji) ? 0.0 : (e == ji ? 1.0 : F[(int64_t)ji * len + e]);
+}
+
+template <bool STAGED>
+__global__ __launch_bounds__(512) void k_qr_update(const QrMat* __restrict__ qm, const QrItem* __restrict__ items,
+                                                   void* const* __restrict__ bases, int k, int which, int mode) {
+  __shared__ double Ts[kQrB][kQrB];
+  __shared__ double Vs[STAGED ? kQrB * kQrVL : 1];
+  constexpr int RW = STAGED ? 2 : 1;   // rows per wave at a time
+  const QrItem it = items[blockIdx.x];
+  const QrMat m = qm[it.mat];
+  const int n = m.n, j0 = k * kQrB;
+  const int jb = min(kQrB, n - j0), len = which == 1 ? m.p : n;
+  const int vl = len - j0;
+  double* base = reinterpret_cast<double*>(bases[m.prob * kNumBases + 2]);
+  const double* F = base + (which == 1 ? m.a : m.y);
+  double* C = mode == 0 ? base + (which == 1 ? m.a : m.y) : base + (which == 1 ? m.f : m.k);
+  const double* Tg = base + (which == 1 ? m.t1 : m.t2) + (int64_t)k * kQrB * kQrB;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t < kQrB * kQrB) Ts[t / kQrB][t % kQrB] = Tg[t];
+  if (STAGED)
+    for (int x = t; x < kQrB * vl; x += 512) Vs[x] = qr_v(F, len, j0, jb, x / vl, j0 + x % vl);
+  __syncthreads();
+  for (int r = it.r0 + RW * wave; r < it.r1; r += 8 * RW) {
+    double* y[RW];
+    bool live[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      live[q] = r + q < it.r1;
+      y[q] = C + (int64_t)(live[q] ? r + q : r) * len;
+    }
+    double acc[RW][kQrB];
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+#pragma unroll
+      for (int i = 0; i < kQrB; ++i) acc[q][i] = 0.0;
+    for (int e = j0 + lane; e < len; e += 64) {
+      double ye[RW];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) ye[q] = y[q][e];
+#pragma unroll
+      for (int i = 0; i < kQrB; ++i) {
+        const double v = STAGED ? Vs[i * vl + (e - j0)] : qr_v(F, len, j0, jb, i, e);
+#pragma unroll
+        for (int q = 0; q < RW; ++q) acc[q][i] += v * ye[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+#pragma unroll
+      for (int i = 0; i < kQrB; ++i) acc[q][i] = wsum(acc[q][i]);
+    // u[q][b] = sum_a acc[q][a] T'[a][b] (T' = T or T^T): lane b of every 16 computes column b, then all lanes
+    // take the 16 values (acc is the same in every lane after the reductions)
+    double u[RW][kQrB];
+    const int bl = lane & (kQrB - 1);
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      double s = 0.0;
+      for (int a = 0; a < kQrB; ++a) s += acc[q][a] * (mode == 0 ? Ts[a][bl] : Ts[bl][a]);
+#pragma unroll
+      for (int b = 0; b < kQrB; ++b) u[q][b] = __shfl(s, b, 64);
+    }
+    for (int e = j0 + lane; e < len; e += 64) {
+      double sv[RW];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) sv[q] = 0.0;
+#pragma unroll
+      for (int i = 0; i < kQrB; ++i) {
+        const double v = STAGED ? Vs[i * vl + (e - j0)] : qr_v(F, len, j0, jb, i, e);
+#pragma unroll
+        for (int q = 0; q < RW; ++q) sv[q] += u[q][i] * v;
+      }
+#pragma unroll
+      for (int q = 0; q < RW; ++q)
+        if (live[q]) y[q][e] -= sv[q];
+    }
+  }
+}
+
+// Copies between the stages, rows blockIdx.x, blockIdx.x + gridDim.x, ... of matrix blockIdx.y:
+//   0: Y = R1 (row-major, from the factored sorted X: R1[i][j] = A[j][i] for i <= j)
+//   1: J = R2 (from the factored Y), K = I
+//   2: F = [J, 0] (rows of length p)
+__global__ __launch_bounds__(256) void k_qr_copy(const QrMat* __restrict__ qm, void* const* __restrict__ bases,
+                                                 int stage) {
+  const QrMat m = qm[blockIdx.y];
+  if (!m.qr) return;
+  const int n = m.n, p = m.p;
+  double* base = reinterpret_cast<double*>(bases[m.prob * kNumBases + 2]);
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    if (stage == 0) {
+      double* y = base + m.y + (int64_t)i * n;
+      for (int j = threadIdx.x; j < n; j += 256) y[j] = i <= j ? base[m.a + (int64_t)j * p + i] : 0.0;
+    } else if (stage == 1) {
+      double* jr = base + m.j + (int64_t)i * n;
+      double* kr = base + m.k + (int64_t)i * n;
+      for (int j = threadIdx.x; j < n; j += 256) {
+        jr[j] = i <= j ? base[m.y + (int64_t)j * n + i] : 0.0;
+        kr[j] = i == j ? 1.0 : 0.0;
+      }
+    } else {
+      double* fr = base + m.f + (int64_t)i * p;
+      const double* jr = base + m.j + (int64_t)i * n;
+      for (int e = threadIdx.x; e < p; e += 256) fr[e] = e < n ? jr[e] : 0.0;
+    }
+  }
+}
+
+// G (the sort permutation P, G[i][idx[i]] = 1, idx also in S) <- K P with K = Q2^T:  G[i][idx[l]] = K[i][l].
+// Rows blockIdx.y, blockIdx.y + gridDim.y, ... of matrix blockIdx.x.
+__global__ __launch_bounds__(256) void k_qr_g0(const QrMat* __restrict__ qm, const SvdTask* __restrict__ tasks,
+                                               void* const* __restrict__ bases) {
+  const QrMat m = qm[blockIdx.x];
+  if (!m.qr) return;
+  const int n = m.n;
+  double* G = reinterpret_cast<double*>(bases[m.prob * kNumBases + 3]) + m.g;
+  const double* K = reinterpret_cast<double*>(bases[m.prob * kNumBases + 2]) + m.k;
+  const double* S = reinterpret_cast<double*>(bases[m.prob * kNumBases + 6]) + tasks[blockIdx.x].s_off;
+  for (int i = blockIdx.y; i < n; i += gridDim.y)
+    for (int l = threadIdx.x; l < n; l += 256) G[(int64_t)i * n + (int)S[l]] = K[(int64_t)i * n + l];
+}
+
 __global__ void k_bj_sweep_end(int nm, int32_t* done, int32_t* changed) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= nm) return;
@@ -473,6 +728,9 @@ __global__ __launch_bounds__(256) void k_bj_init(const SvdTask* __restrict__ tas
     X[e] = tr ? M[(int64_t)k * tk.c + src] : M[(int64_t)src * p + k];
   }
   for (int64_t e = t; e < (int64_t)n * n; e += 256) G[e] = (e % n == idx[e / n]) ? 1.0 : 0.0;
+  // the permutation also goes to S (free until the singular values are written) for the QR preconditioning
+  double* S = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 6]) + tk.s_off;
+  for (int i = t; i < n; i += 256) S[i] = (double)idx[i];
   if (t == 0) thr2[blockIdx.x] = zero_rel * zero_rel * (((red[0] + red[1]) + red[2]) + red[3]);
 }
 
@@ -494,7 +752,7 @@ __global__ __launch_bounds__(1024) void k_bj_sigma(const SvdTask* __restrict__ t
   const SvdTask tk = tasks[blockIdx.x];
   const bool tr = tk.r > tk.c;
   const int n = tr ? tk.c : tk.r, p = tr ? tk.r : tk.c;
-  const double* X = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 2]) + tk.x_off;
+  const double* X = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 2]) + tk.f_off;
   double* S = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 6]) + tk.s_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   for (int i = wave; i < n; i += 16) {
@@ -526,7 +784,7 @@ __global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ 
   const int r = tk.r, c = tk.c;
   const bool tr = r > c;
   const int n = tr ? c : r, p = tr ? r : c;
-  double* X = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 2]) + tk.x_off;
+  double* X = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 2]) + tk.f_off;
   double* G = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 3]) + tk.g_off;
   double* Uf = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 4]) + tk.u_off;
   double* Vf = reinterpret_cast<double*>(bases[tk.prob * kNumBases + 5]) + tk.v_off;
@@ -640,7 +898,19 @@ __global__ __launch_bounds__(1024) void k_bj_finish(const SvdTask* __restrict__ 
   }
 }
 
+int64_t qr_panels(int n) { return (n + kQrB - 1) / kQrB; }
+
 }  // namespace
+
+// Per matrix in the X base: the sorted rows A (n x p; with preconditioning, then its QR factorisation); with
+// preconditioning also the final rows F (n x p), Y (R1, then its factorisation), J (R2, the Jacobi rows), K (Q2^T),
+// each n x n, and the T matrices of both factorisations.
+int64_t bj_x_elems(int n, int p) {
+  if (n < kQrMinN) return (int64_t)n * p;
+  return 2 * (int64_t)n * p + 3 * (int64_t)n * n + 2 * qr_panels(n) * kQrB * kQrB;
+}
+
+int64_t bj_f_rel(int n, int p) { return n < kQrMinN ? 0 : (int64_t)n * p; }
 
 void bj_prepare(const std::vector<SvdTask>& svd, BjPlan& plan) {
   const int nm = (int)svd.size();
@@ -648,16 +918,31 @@ void bj_prepare(const std::vector<SvdTask>& svd, BjPlan& plan) {
   plan.nm = nm;
   if (nm == 0) return;
   std::vector<BjMat> mats(nm);
+  std::vector<QrMat> qm(nm);
   struct Round {
     std::vector<BjPair> pairs;
     std::vector<BjItem> gram, apply;
   };
   std::vector<Round> rounds;
+  int npanel = 0;
   for (int m = 0; m < nm; ++m) {
     const SvdTask& t = svd[m];
     const bool tr = t.r > t.c;
-    const int n = tr ? t.c : t.r, p = tr ? t.r : t.c;
-    mats[m] = BjMat{n, p, t.prob, 0, t.x_off, t.g_off};
+    const int n = tr ? t.c : t.r, p0 = tr ? t.r : t.c;
+    const bool qr = n >= kQrMinN;
+    QrMat& q = qm[m];
+    q.n = n; q.p = p0; q.prob = t.prob; q.qr = qr ? 1 : 0;
+    q.a = t.x_off; q.f = t.f_off; q.g = t.g_off;
+    q.y = q.f + (int64_t)n * p0; q.j = q.y + (int64_t)n * n; q.k = q.j + (int64_t)n * n;
+    q.t1 = q.k + (int64_t)n * n; q.t2 = q.t1 + qr_panels(n) * kQrB * kQrB;
+    if (qr) {
+      if (t.f_off != t.x_off + bj_f_rel(n, p0)) throw std::runtime_error("internal: SVD task layout");
+      ++plan.nqr;
+      npanel = std::max<int>(npanel, (int)qr_panels(n));
+    }
+    // the Jacobi sweeps run on R2 (n x n) where preconditioned
+    const int p = qr ? n : p0;
+    mats[m] = BjMat{n, p, t.prob, 0, qr ? q.j : t.x_off, t.g_off};
     const int nb = (n + BB - 1) / BB;
     const int nbe = nb + (nb & 1);
     for (int rd = 0; rd < nbe - 1; ++rd) {
@@ -685,6 +970,29 @@ void bj_prepare(const std::vector<SvdTask>& svd, BjPlan& plan) {
     return off;
   };
   plan.omats = put(mats.data(), mats.size() * sizeof(BjMat));
+  plan.oqr = put(qm.data(), qm.size() * sizeof(QrMat));
+  plan.npanel = npanel;
+  plan.otrail.assign(npanel, 0);
+  plan.ofull.assign(npanel, 0);
+  plan.ntrail.assign(npanel, 0);
+  plan.nfull.assign(npanel, 0);
+  plan.vl1.assign(npanel, 0);
+  plan.vl2.assign(npanel, 0);
+  for (int k = 0; k < npanel; ++k) {
+    std::vector<QrItem> trail, full;
+    for (int m = 0; m < nm; ++m) {
+      const QrMat& q = qm[m];
+      if (!q.qr || k * kQrB >= q.n) continue;
+      plan.vl1[k] = std::max(plan.vl1[k], q.p - k * kQrB);
+      plan.vl2[k] = std::max(plan.vl2[k], q.n - k * kQrB);
+      for (int r0 = (k + 1) * kQrB; r0 < q.n; r0 += kQrRows) trail.push_back(QrItem{m, r0, std::min(q.n, r0 + kQrRows), 0});
+      for (int r0 = 0; r0 < q.n; r0 += kQrRows) full.push_back(QrItem{m, r0, std::min(q.n, r0 + kQrRows), 0});
+    }
+    plan.otrail[k] = put(trail.data(), trail.size() * sizeof(QrItem));
+    plan.ofull[k] = put(full.data(), full.size() * sizeof(QrItem));
+    plan.ntrail[k] = (int)trail.size();
+    plan.nfull[k] = (int)full.size();
+  }
   const size_t nr = rounds.size();
   plan.opair.resize(nr);
   plan.ogram.resize(nr);
@@ -728,6 +1036,29 @@ void bj_svd(const BjPlan& plan, void* const* dbases, const SvdTask* dtasks, BjSc
   int32_t* changed = done + nm;
   double* thr2 = (double*)(dev + plan.othr);
   hipLaunchKernelGGL(k_bj_init, dim3(nm), dim3(256), 0, s, dtasks, dbases, thr2, scr.zero_rel);
+  const QrMat* dqr = (const QrMat*)(dev + plan.oqr);
+  auto apply_panels = [&](int which, int mode, bool reverse) {
+    for (int kk = 0; kk < plan.npanel; ++kk) {
+      const int k = reverse ? plan.npanel - 1 - kk : kk;
+      const int nit = mode == 0 ? plan.ntrail[k] : plan.nfull[k];
+      const QrItem* it = (const QrItem*)(dev + (mode == 0 ? plan.otrail[k] : plan.ofull[k]));
+      if (mode == 0) hipLaunchKernelGGL(k_qr_panel, dim3(nm), dim3(1024), 0, s, dqr, dbases, k, which);
+      if (nit == 0) continue;
+      // reflectors staged in LDS when every matrix's panel fits
+      if ((which == 1 ? plan.vl1[k] : plan.vl2[k]) <= kQrVL)
+        hipLaunchKernelGGL(k_qr_update<true>, dim3(nit), dim3(512), 0, s, dqr, it, dbases, k, which, mode);
+      else
+        hipLaunchKernelGGL(k_qr_update<false>, dim3(nit), dim3(512), 0, s, dqr, it, dbases, k, which, mode);
+    }
+  };
+  if (plan.nqr > 0) {
+    apply_panels(1, 0, false);                                                       // sorted X^T = Q1 R1
+    hipLaunchKernelGGL(k_qr_copy, dim3(64, nm), dim3(256), 0, s, dqr, dbases, 0);   // Y = R1
+    apply_panels(2, 0, false);                                                       // R1^T = Q2 R2
+    hipLaunchKernelGGL(k_qr_copy, dim3(64, nm), dim3(256), 0, s, dqr, dbases, 1);   // J = R2, K = I
+    apply_panels(2, 1, true);                                                        // K = Q2^T
+    hipLaunchKernelGGL(k_qr_g0, dim3(nm, 64), dim3(256), 0, s, dqr, dtasks, dbases);  // G = Q2^T P
+  }
   std::vector<int32_t> hdone(nm);
   int sweeps = 0;
   scr.converged = 0;
@@ -757,6 +1088,10 @@ void bj_svd(const BjPlan& plan, void* const* dbases, const SvdTask* dtasks, BjSc
     }
   }
   scr.sweeps = std::min(sweeps + 1, scr.max_sweeps);
+  if (plan.nqr > 0) {
+    hipLaunchKernelGGL(k_qr_copy, dim3(64, nm), dim3(256), 0, s, dqr, dbases, 2);   // F = [J, 0]
+    apply_panels(1, 1, true);                                                        // F = [J, 0] Q1^T
+  }
   int32_t* dcomp = (int32_t*)(dev + plan.ocomp);
   std::vector<int32_t> complete(nm, 1);
   if (scr.need_completion) {

@@ -104,7 +104,12 @@ struct DiagTask {
 struct SvdTask {
   int32_t r, c, prob, pad;
   int64_t m_off, x_off, g_off, u_off, v_off, s_off;
+  int64_t f_off;   // rows read by the singular-value and output kernels (= x_off unless QR-preconditioned)
 };
+// Elements of the X base that one matrix of min(r, c) = n rows of length p = max(r, c) needs, and where its
+// final rows start (relative to its x_off); see bjsvd.hip.
+int64_t bj_x_elems(int n, int p);
+int64_t bj_f_rel(int n, int p);
 
 // Selection of kept singular values for one problem (all its centre sectors).
 struct SelTask {
@@ -236,6 +241,12 @@ struct BjPlan {
   size_t omats = 0, oflags = 0, othr = 0, ocomp = 0, b_partial = 0, b_q = 0;
   std::vector<size_t> opair, ogram, oapply;
   std::vector<int> npair, ngram, napply;
+  // QR preconditioning: per-matrix table, and per panel the row chunks of the trailing update and of the
+  // application of the reflectors to all rows
+  int nqr = 0, npanel = 0;
+  size_t oqr = 0;
+  std::vector<size_t> otrail, ofull;
+  std::vector<int> ntrail, nfull, vl1, vl2;   // vl: the longest reflector of panel k (which = 1, 2)
 };
 void bj_prepare(const std::vector<SvdTask>& svd, BjPlan& plan);
 // dev: plan.host on the device; work: plan.scratch bytes of device memory.
