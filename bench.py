@@ -392,13 +392,15 @@ def traffic_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, top=18):
     h = hashlib.sha256()
     for src in TRAFFIC_SOURCES:
         h.update(open(os.path.join(ROOT, src), "rb").read())
-    print("\nRecords read by bench.py for the roofline kernel (split-bf16 GEMM stage 1 and stage 2, the tile variant "
+    print("\nRecords read by bench.py for the roofline kernel (split-bf16 GEMM stage 1 and stage 2, the kernel variant "
           "with the most dispatches):\n")
-    for cls, tag in (("heff_gemm1_lo", "gemm_bf16x3_kernel<0,"), ("heff_gemm2_lo", "gemm_bf16x3_kernel<1,")):
-        cand = [r for r in rows if tag in r[0].replace(" ", "")]
+    import re
+    for cls, stage in (("heff_gemm1_lo", "0"), ("heff_gemm2_lo", "1")):
+        pat = re.compile(r"gemm_bf16x3(_\w+)?_kernel<" + stage + r"[,>]")
+        cand = [r for r in rows if pat.search(r[0].replace(" ", ""))]
         if cand:
             k, n, f, w, b = max(cand, key=lambda r: r[1])
-            name = k.split("(")[0].replace("void ", "")
+            name = k.replace("void ", "").replace("idmrg::(anonymous namespace)::", "").split("(")[0]
             print(f"traffic-record: class={cls} kernel={name} bytes_per_launch={b:.6e} sources_sha256={h.hexdigest()}\n")
     print(f"`sources_sha256` is the SHA-256 of {', '.join(TRAFFIC_SOURCES)} (concatenated) when the counters were "
           "taken; bench.py reports the traffic only while it still matches.")

@@ -152,8 +152,10 @@ def test_traffic_summary_writes_current_records(tmp_path, capsys, monkeypatch):
         (d / "run_counter_collection.csv").write_text("\n".join(lines) + "\n")
         return str(d)
     g1, g2 = "void gemm_bf16x3_kernel<0, 128, 128>(int)", "void gemm_bf16x3_kernel<1, 128, 128>(int)"
-    f = pmc("f", "FETCH_SIZE", [(g1, 1000.0), (g1, 1000.0), (g2, 500.0)])
-    w = pmc("w", "WRITE_SIZE", [(g1, 100.0), (g1, 100.0), (g2, 50.0)])
+    # the tuner's variant: the stage-1 record must come from the variant with the most dispatches
+    g1p = "void idmrg::(anonymous namespace)::gemm_bf16x3_persist_kernel<0>(idmrg::GemmTask const*, int)"
+    f = pmc("f", "FETCH_SIZE", [(g1, 1000.0), (g1, 1000.0), (g2, 500.0)] + [(g1p, 800.0)] * 3)
+    w = pmc("w", "WRITE_SIZE", [(g1, 100.0), (g1, 100.0), (g2, 50.0)] + [(g1p, 900.0)] * 3)
     cf = pmc("cf", "FETCH_SIZE", [("copy", 131072.0)] * 3)          # factor 0.5
     cw = pmc("cw", "WRITE_SIZE", [("copy", 262144.0)] * 3)          # factor 1
     bench.traffic_summary(f, w, cf, cw)
@@ -162,5 +164,5 @@ def test_traffic_summary_writes_current_records(tmp_path, capsys, monkeypatch):
     rec.write_text(out)
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(rec))
     t = bench.measured_traffic()
-    assert t["heff_gemm1_lo"] == ("gemm_bf16x3_kernel<0, 128, 128>", 1000 * 1024 / 0.5 + 100 * 1024)
+    assert t["heff_gemm1_lo"] == ("gemm_bf16x3_persist_kernel<0>", 800 * 1024 / 0.5 + 900 * 1024)
     assert t["heff_gemm2_lo"][1] == 500 * 1024 / 0.5 + 50 * 1024
