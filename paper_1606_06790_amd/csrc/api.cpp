@@ -608,7 +608,7 @@ void heff_plan(idmrg_ctx* c, HeffExec& ex, int P, const idmrg_heff* H, int prec,
   Packer& pk = ex.pk;
   pk.host.clear();
   for (int st = 0; st < 2; ++st)
-    for (int v = 0; v < ex.nvar; ++v) ex.av[st][v] = pk.add(ex.var[st][v].t);
+    for (int v = 0; v < ex.nvar; ++v) ex.av[st][v] = pk.add(ex.var[st][v].upload());
   const MixList& mY = frag ? ex.plan.mixYf : ex.plan.mixY;
   const MixList& mT = frag ? ex.plan.mixTf : ex.plan.mixT;
   ex.aMY = pk.add(mY.t);
@@ -750,7 +750,8 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   {
     Prof pr(c, lo + 0, ex.flops_g1);
     if (trial >= 0) IDMRG_HIP(hipEventRecord(c->tev[trial][0], s));
-    launch_gemm(ex.prec, 0, ex.gv[0][v1], (int)ex.plan.g1.t.size(), ex.tiles[0][v1], ex.bases, active, s,
+    launch_gemm(ex.prec, 0, ex.gv[0][v1], (int)ex.plan.g1.t.size(), ex.tiles[0][v1], ex.var[0][v1].xmax, ex.bases,
+                active, s,
                 ex.code[v1]);
     if (trial >= 0) IDMRG_HIP(hipEventRecord(c->tev[trial][1], s));
   }
@@ -764,7 +765,8 @@ void heff_run(idmrg_ctx* c, HeffExec& ex, const std::vector<double*>& x, const s
   {
     Prof pr(c, lo + 1, ex.flops_g2);
     if (trial >= 0) IDMRG_HIP(hipEventRecord(c->tev[trial][2], s));
-    launch_gemm(ex.prec, 1, ex.gv[1][v2], (int)ex.plan.g2.t.size(), ex.tiles[1][v2], ex.bases, active, s,
+    launch_gemm(ex.prec, 1, ex.gv[1][v2], (int)ex.plan.g2.t.size(), ex.tiles[1][v2], ex.var[1][v2].xmax, ex.bases,
+                active, s,
                 ex.code[v2]);
     if (trial >= 0) IDMRG_HIP(hipEventRecord(c->tev[trial][3], s));
   }
@@ -1075,10 +1077,10 @@ std::shared_ptr<EnvCall> env_call(idmrg_ctx* c, int P, int side, const idmrg_env
     }
     k.n1 = n1;
     k.oT = k.lay.add((n1 + n2) * 8);
-    k.a1 = k.pk.add(k.plan.ga.t);
+    k.a1 = k.pk.add(k.plan.ga.upload());
     k.a2 = k.pk.add(k.plan.mix.t);
     k.a3 = k.pk.add(k.plan.mix.src);
-    k.a4 = k.pk.add(k.plan.gc.t);
+    k.a4 = k.pk.add(k.plan.gc.upload());
     k.a5 = k.pk.reserve((size_t)P * kNumBases * sizeof(void*));
     k.oPlan = k.lay.add(k.pk.host.size());
   });
@@ -1122,7 +1124,7 @@ std::shared_ptr<PredictCall> predict_call(idmrg_ctx* c, int P, int d, const int3
     }
     k.oW = k.lay.add(n * 8);
     k.a1 = k.pk.add(k.plan.scale.t);
-    k.a2 = k.pk.add(k.plan.g.t);
+    k.a2 = k.pk.add(k.plan.g.upload());
     k.a3 = k.pk.reserve((size_t)P * kNumBases * sizeof(void*));
     k.oPlan = k.lay.add(k.pk.host.size());
   });
@@ -1950,11 +1952,11 @@ extern "C" int update_env(idmrg_ctx* ctx, int nprob, int side, const idmrg_env_u
     hipStream_t s = ctx->stream;
     Prof pr(ctx, 7, k.plan.ga.flops() + k.plan.gc.flops() + k.plan.mix.flops());
     launch_gemm(Prec::F64, side == IDMRG_LEFT ? 0 : 2, (GemmTask*)(dev + k.a1), (int)k.plan.ga.t.size(),
-                k.plan.ga.tiles, bases, nullptr, s);
+                k.plan.ga.tiles, k.plan.ga.xmax, bases, nullptr, s);
     launch_mix(0, 0, (MixTask*)(dev + k.a2), (MixSrc*)(dev + k.a3), (int)k.plan.mix.t.size(), k.plan.mix.tiles,
                bases, nullptr, s);
     launch_gemm(Prec::F64, side == IDMRG_LEFT ? 2 : 0, (GemmTask*)(dev + k.a4), (int)k.plan.gc.t.size(),
-                k.plan.gc.tiles, bases, nullptr, s);
+                k.plan.gc.tiles, k.plan.gc.xmax, bases, nullptr, s);
     IDMRG_HIP(hipGetLastError());
     return IDMRG_OK;
   });
@@ -1997,8 +1999,8 @@ extern "C" int predict_wavefunction(idmrg_ctx* ctx, int nprob, int32_t d, const 
     Prof prf(ctx, 8, k.plan.g.flops());
     launch_scale((ScaleTask*)(dev + k.a1), nullptr, (int)k.plan.scale.t.size(), k.plan.scale.tiles, lam_floor, bases,
                  ctx->stream);
-    launch_gemm(Prec::F64, 2, (GemmTask*)(dev + k.a2), (int)k.plan.g.t.size(), k.plan.g.tiles, bases, nullptr,
-                ctx->stream);
+    launch_gemm(Prec::F64, 2, (GemmTask*)(dev + k.a2), (int)k.plan.g.t.size(), k.plan.g.tiles, k.plan.g.xmax, bases,
+                nullptr, ctx->stream);
     IDMRG_HIP(hipGetLastError());
     return IDMRG_OK;
   });

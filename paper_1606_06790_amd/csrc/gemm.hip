@@ -15,7 +15,9 @@
 //
 // Workgroups are dispatched round-robin over the 8 XCDs; xcd_tile() renumbers
 // them so that each XCD receives a contiguous range of tiles, and the tiles of
-// one output row band (which share their A operand) meet in one L2.
+// one output row band (which share their A operand) meet in one L2.  The
+// ranges, stored after the task table, split the tiles at equal estimated work
+// (K + 64 per tile), so that no XCD gets more than its share of long-K tasks.
 #include "internal.h"
 
 namespace idmrg {
@@ -28,11 +30,14 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kXcd = 8;
 
-// Logical tile of this workgroup (grid = kXcd * ceil(ntiles / kXcd)), or -1.
-__device__ __forceinline__ int xcd_tile(int ntiles) {
-  const int per = (ntiles + kXcd - 1) / kXcd;
-  const int t = (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
-  return t < ntiles ? t : -1;
+static_assert(kXcd + 1 == kXcdRanges, "one range per XCD");
+
+// Logical tile of this workgroup (grid = kXcd * the largest range), or -1.
+__device__ __forceinline__ int xcd_tile(const GemmTask* tasks, int ntask) {
+  const int32_t* xr = reinterpret_cast<const int32_t*>(tasks + ntask);
+  const int x = (int)(blockIdx.x % kXcd);
+  const int t = xr[x] + (int)(blockIdx.x / kXcd);
+  return t < xr[x + 1] ? t : -1;
 }
 
 // Operands are read through global-address-space pointers (global_load, not
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmTask* __restri
   __shared__ T As[2][BK][BM + 1];
   __shared__ T Bs[2][BK][BN + 1];
 
-  const int tile = xcd_tile(ntiles);
+  const int tile = xcd_tile(tasks, ntask);
   if (tile < 0) return;
   const GemmTask& tk = tasks[find_task(tasks, ntask, tile)];
   if (active && !active[tk.prob]) return;
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const GemmTask* __rest
   constexpr int TI = BM / 32, TJ = BN / 32;    // 16 x 16 MFMA tiles per wave
   constexpr uint32_t kFragBytes = kFragWords * 4;
   __shared__ v4u As[2][FA * 128], Bs[2][FB * 128];
-  const int tile = xcd_tile(ntiles);
+  const int tile = xcd_tile(tasks, ntask);
   if (tile < 0) return;
   const GemmTask& tk = tasks[find_task(tasks, ntask, tile)];
   if (active && !active[tk.prob]) return;
@@ -418,8 +423,8 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_persist_kernel(const GemmTask
   const cptr<int32_t> active = active_ ? as_const(active_) : nullptr;
   // this workgroup's tiles: start, start + step, ... below t1 (workgroups go round-robin over the XCDs)
   const int G = (int)gridDim.x, xcd = (int)(blockIdx.x % kXcd), slot = (int)(blockIdx.x / kXcd);
-  const int per = (ntiles + kXcd - 1) / kXcd, step = G / kXcd;
-  const int t1 = min((xcd + 1) * per, ntiles);
+  const cptr<int32_t> xr = as_const(reinterpret_cast<const int32_t*>(tasks_ + ntask));
+  const int t0 = xr[xcd], t1 = xr[xcd + 1], step = G / kXcd;
   // a tile's task, looked up once when the copy cursor reaches the tile
   struct Tile {
     int t, kb, m0, n0, M, N, K, ldc, beta;
@@ -526,7 +531,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_persist_kernel(const GemmTask
     }
   };
 
-  next_mul_tile(xcd * per + slot, mx);   // the tile being multiplied, at slab km
+  next_mul_tile(t0 + slot, mx);   // the tile being multiplied, at slab km
   if (mx.t >= t1) return;
   cx = mx;
   set_offsets();
@@ -598,7 +603,7 @@ __global__ __launch_bounds__(512) void gemm_bf16x3_pipe_kernel(const GemmTask* _
   constexpr int TI = 4, TJ = 4;                // 16 x 16 MFMA tiles per wave (64 x 64)
   constexpr uint32_t kFragBytes = kFragWords * 4;
   __shared__ v4u As[NS][FA * 128], Bs[NS][FB * 128];
-  const int tile = xcd_tile(ntiles);
+  const int tile = xcd_tile(tasks, ntask);
   if (tile < 0) return;
   const GemmTask& tk = tasks[find_task(tasks, ntask, tile)];
   if (active && !active[tk.prob]) return;
@@ -871,10 +876,11 @@ static void launch_bf16x3(int tiling, int mode, dim3 grid, hipStream_t s, const 
   }
 }
 
-void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntiles, void* const* bases,
+void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntiles, int xmax, void* const* bases,
                  const int32_t* active, hipStream_t s, int tiling) {
   if (ntask == 0 || ntiles == 0) return;
-  dim3 grid(kXcd * ((ntiles + kXcd - 1) / kXcd)), block(256);
+  if (xmax <= 0 || xmax > ntiles) throw InvalidArg("internal: GEMM tile ranges");
+  dim3 grid(kXcd * xmax), block(256);
   switch (prec) {
     case Prec::F64: launch_t<double>(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;
     case Prec::F32: launch_t<float>(tiling, mode, grid, s, tasks, ntask, bases, active, ntiles); break;

@@ -29,6 +29,10 @@ struct GemmTask {
   int32_t pad;
   int64_t aoff, boff, coff;
 };
+// Workgroups are dispatched round-robin over the 8 XCDs.  A GEMM's device task table ends with one more record
+// whose first kXcdRanges int32 fields hold s_0 = 0 <= s_1 <= ... <= s_8 = ntiles: XCD x runs tiles [s_x, s_x+1).
+constexpr int kXcdRanges = 9;
+static_assert(sizeof(GemmTask) >= kXcdRanges * sizeof(int32_t), "XCD ranges must fit in one task record");
 
 // D[rows x cols] = sum_k coef_k * S_k   (S_k[r][c] at off + r*ld + c, or off + c*ld + r if trans)
 // In fragment output mode (split-bf16 T3) output (r, c) is element (r0 + r, c0 + c)
@@ -170,7 +174,7 @@ enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 //   BF16X3: A and B^T in the fragment layout (aoff, boff in 32-bit words; mode,
 //   lda and ldb are ignored), float C.
 // `active` (nullable) holds one flag per problem; tasks of inactive problems exit at once.
-void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntiles,
+void launch_gemm(Prec prec, int mode, const GemmTask* tasks, int ntask, int ntiles, int xmax,
                  void* const* bases, const int32_t* active, hipStream_t s, int tiling = 0);
 
 // Mix over tasks; tin/tout element types: 0 = double, 1 = float, 3 = split-bf16 pairs in the fragment

@@ -5,6 +5,7 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 
 namespace idmrg {
@@ -204,6 +205,32 @@ void GemmList::retile(int tm_, int tn_) {
     g.tile0 = tiles;
     tiles += ((g.M + tm - 1) / tm) * g.tiles_n;
   }
+}
+
+std::vector<GemmTask> GemmList::upload() {
+  std::vector<GemmTask> out = t;
+  GemmTask rec{};
+  int32_t s[kXcdRanges] = {};
+  double total = 0.0;
+  for (const auto& g : t) total += (double)((g.M + tm - 1) / tm) * g.tiles_n * (std::max(g.K, 0) + 64);
+  // cut x at the first tile whose cumulative cost reaches x / 8 of the total
+  int x = 1;
+  double cum = 0.0;
+  for (const auto& g : t) {
+    const int nt = ((g.M + tm - 1) / tm) * g.tiles_n;
+    const double c = std::max(g.K, 0) + 64;
+    for (int i = 0; i < nt; ++i) {
+      while (x < kXcdRanges - 1 && cum >= total * x / (kXcdRanges - 1)) s[x++] = g.tile0 + i;
+      cum += c;
+    }
+  }
+  while (x < kXcdRanges - 1) s[x++] = tiles;
+  s[kXcdRanges - 1] = tiles;
+  xmax = 0;
+  for (int i = 0; i + 1 < kXcdRanges; ++i) xmax = std::max(xmax, s[i + 1] - s[i]);
+  std::memcpy(&rec, s, sizeof(s));
+  out.push_back(rec);
+  return out;
 }
 
 double GemmList::efficiency(int tm_, int tn_) const {

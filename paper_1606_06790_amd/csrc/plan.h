@@ -93,6 +93,11 @@ struct GemmList {
   // fraction of MFMA work that is not padding, for tile tm_ x tn_
   double efficiency(int tm_, int tn_) const;
   void choose_tile(bool allow_large);  // picks the largest tile whose padding costs little
+  // The device table of the list: the tasks, then one record whose first kXcdRanges int32 fields are the
+  // per-XCD tile ranges [s_x, s_x+1) (contiguous, of about equal work: a tile costs K + 64); sets xmax, the
+  // largest number of tiles of one XCD.
+  std::vector<GemmTask> upload();
+  int xmax = 0;
 };
 
 struct MixList {
