@@ -269,3 +269,39 @@ extern "C" int hostplan_overlap(const idmrg_overlap_item* it, double* out) {
     return -1;
   }
 }
+
+// The per-XCD tile ranges stored after a GEMM task table (stage 1 and 2 of the split-bf16 plan, 128 x 128 tiles):
+// out[0..8] the ranges, out[9] the largest range, out[10] the tile count, out[11..18] each XCD's work (K + 64 per
+// tile) in units of the largest single tile's work.
+extern "C" int hostplan_xcd_ranges(const idmrg_heff* H, int nprob, int stage, double* out) {
+  try {
+    HeffPlan p;
+    for (int i = 0; i < nprob; ++i)
+      build_heff(p, i, make_leg(H[i].left, "A"), make_leg(H[i].right, "B"), make_mpo(H[i].w1, "w1"),
+                 make_mpo(H[i].w2, "w2"));
+    GemmList g = stage == 1 ? p.f1 : p.f2;
+    g.retile(128, 128);
+    const std::vector<GemmTask> up = g.upload();
+    if (up.size() != g.t.size() + 1) return -2;
+    int32_t s[kXcdRanges];
+    std::memcpy(s, &up.back(), sizeof(s));
+    for (int i = 0; i < kXcdRanges; ++i) out[i] = s[i];
+    out[kXcdRanges] = g.xmax;
+    out[kXcdRanges + 1] = g.tiles;
+    double big = 0.0;
+    std::vector<double> cost(g.tiles, 0.0);
+    for (const auto& t : g.t) {
+      const int nt = ((t.M + 127) / 128) * t.tiles_n;
+      for (int i = 0; i < nt; ++i) cost[t.tile0 + i] = std::max(t.K, 0) + 64;
+      big = std::max(big, (double)std::max(t.K, 0) + 64);
+    }
+    for (int x = 0; x + 1 < kXcdRanges; ++x) {
+      double w = 0.0;
+      for (int i = s[x]; i < s[x + 1]; ++i) w += cost[i];
+      out[kXcdRanges + 2 + x] = w / big;
+    }
+    return 0;
+  } catch (...) {
+    return -1;
+  }
+}

@@ -277,3 +277,26 @@ def test_fused_piece_right_transfer_on_host(lib, hostplan):
     for ch in (1, 2):
         got = _dense({(qa, qb): v for (w, qa, qb), v in Rnew.items() if w == ch}, A_OBS, A_OBS, lambda a, b: (a, b))
         assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), ch
+
+
+@pytest.mark.parametrize("stage", [1, 2])
+def test_gemm_xcd_ranges(lib, hostplan, stage):
+    """The per-XCD tile ranges after a GEMM task table cover every tile once, in order, and split the work (K + 64 per
+    tile) so that no XCD's share exceeds the mean by more than one tile: three YC8 superblocks on the legs of the
+    host tests, in the split-bf16 plan."""
+    k = lib._Keep()
+    hs = []
+    for li, c1 in ((3, 4), (2, 9), (3, 7)):
+        (_, _, _, _, _), (M1, M2) = _mpo_pair("yc8", c1)
+        A, B = LEGS[li]
+        hs.append(lib.Heff_t(k.leg(A), k.leg(B), k.mpo(M1), k.mpo(M2), None, None))
+    arr = (lib.Heff_t * len(hs))(*hs)
+    out = (C.c_double * 19)()
+    assert hostplan.hostplan_xcd_ranges(arr, len(hs), stage, out) == 0
+    s = [int(v) for v in out[:9]]
+    xmax, tiles = int(out[9]), int(out[10])
+    work = list(out[11:19])
+    assert s[0] == 0 and s[8] == tiles and all(a <= b for a, b in zip(s, s[1:]))
+    assert xmax == max(b - a for a, b in zip(s, s[1:]))
+    mean = sum(work) / 8
+    assert max(work) <= mean + 1.0 + 1e-9
