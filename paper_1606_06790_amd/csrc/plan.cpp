@@ -208,15 +208,23 @@ void GemmList::retile(int tm_, int tn_) {
 }
 
 std::vector<GemmTask> GemmList::upload() {
+  // Tasks in order of decreasing K (stable, so tasks of equal K keep their order and those sharing an operand stay
+  // together): each XCD then starts its longest tiles first, and its last wave of workgroups holds the shortest.
   std::vector<GemmTask> out = t;
+  std::stable_sort(out.begin(), out.end(), [](const GemmTask& a, const GemmTask& b) { return a.K > b.K; });
+  int nt0 = 0;
+  for (auto& g : out) {
+    g.tile0 = nt0;
+    nt0 += ((g.M + tm - 1) / tm) * g.tiles_n;
+  }
   GemmTask rec{};
   int32_t s[kXcdRanges] = {};
   double total = 0.0;
-  for (const auto& g : t) total += (double)((g.M + tm - 1) / tm) * g.tiles_n * (std::max(g.K, 0) + 64);
+  for (const auto& g : out) total += (double)((g.M + tm - 1) / tm) * g.tiles_n * (std::max(g.K, 0) + 64);
   // cut x at the first tile whose cumulative cost reaches x / 8 of the total
   int x = 1;
   double cum = 0.0;
-  for (const auto& g : t) {
+  for (const auto& g : out) {
     const int nt = ((g.M + tm - 1) / tm) * g.tiles_n;
     const double c = std::max(g.K, 0) + 64;
     for (int i = 0; i < nt; ++i) {

@@ -290,7 +290,9 @@ extern "C" int hostplan_xcd_ranges(const idmrg_heff* H, int nprob, int stage, do
     out[kXcdRanges + 1] = g.tiles;
     double big = 0.0;
     std::vector<double> cost(g.tiles, 0.0);
-    for (const auto& t : g.t) {
+    for (size_t k = 0; k + 1 < up.size(); ++k) {   // the uploaded order, whose tile0 the ranges refer to
+      const GemmTask& t = up[k];
+      if (k > 0 && t.tile0 < up[k - 1].tile0) return -3;
       const int nt = ((t.M + 127) / 128) * t.tiles_n;
       for (int i = 0; i < nt; ++i) cost[t.tile0 + i] = std::max(t.K, 0) + 64;
       big = std::max(big, (double)std::max(t.K, 0) + 64);
