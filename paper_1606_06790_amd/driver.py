@@ -13,6 +13,7 @@ e_g = (e^(n)_1 - e^(n-l)_1) / (2l) whenever mod(n+1, l) = 0.
 from __future__ import annotations
 
 import json
+import os
 import time
 
 import numpy as np
@@ -20,6 +21,9 @@ import numpy as np
 import workloads
 
 from . import lib, models
+
+
+CHECKPOINT_VERSION = 1
 
 
 class IDMRG:
@@ -33,6 +37,7 @@ class IDMRG:
         self.dev = torch.device("cuda", device)
         self.prec = prec or cfg.get("prec", "f64")
         self.predict = predict
+        self.dense = dense
         self.chunk = chunk
         self.graph = graph
         self.fp32_basis = True   # mixed precision: the first pass's Krylov vectors stored in FP32
@@ -163,6 +168,73 @@ class IDMRG:
         self.prev, self.lam2 = dict(snap["prev"]), dict(snap["lam2"])
         self.energies, self.e_g, self.steps = dict(snap["energies"]), dict(snap["e_g"]), list(snap["steps"])
 
+    def save(self, path):
+        """Write the state after the last iteration to `path` (an uncompressed .npz; the file is replaced only
+        once it is complete).  It holds what the next iteration reads: L^(n)_{2i-1} and R^(n)_{2i} of every
+        superblock, the decomposition U, Lambda, V of iteration n and Lambda^(n-1) (both enter Eq. (10)),
+        each with its quantum-number leg, and the energy history for Step 5'.  Arrays are float64; the rest
+        (configuration, legs, records) is one JSON string, so reading it back unpickles nothing."""
+        arrays, legs = {}, {}
+
+        def put(key, leg, t):
+            legs[key] = [[int(q), int(x)] for q, x in leg]
+            arrays[key] = t.detach().to("cpu").numpy()
+
+        for i, (leg, t) in self.L.items():
+            put(f"L{i}", leg, t)
+        for i, (leg, t) in self.R.items():
+            put(f"R{i}", leg, t)
+        prev = {}
+        for i, tr in self.prev.items():
+            put(f"U{i}", tr["C"], tr["U"])
+            put(f"V{i}", tr["C"], tr["V"])
+            put(f"lam{i}", tr["C"], tr["lam"])
+            prev[str(i)] = {k: v for k, v in tr.items() if k not in ("C", "U", "V", "lam")}
+        for i, (leg, lam) in self.lam2.items():
+            put(f"lam2_{i}", leg, lam)
+        header = dict(version=CHECKPOINT_VERSION, cfg=self.cfg, prec=self.prec, dense=self.dense,
+                      predict=self.predict, chunk=self.chunk, fp32_basis=self.fp32_basis, batched=self.batched,
+                      n=self.n, superblocks=sorted(self.L), prev=prev, lam2=sorted(self.lam2), legs=legs,
+                      energies=[[n, i, e] for (n, i), e in sorted(self.energies.items())],
+                      e_g=[[n, e] for n, e in sorted(self.e_g.items())], steps=self.steps)
+        tmp = path + ".partial"
+        with open(tmp, "wb") as f:
+            np.savez(f, header=np.array(json.dumps(header)), **arrays)
+        os.replace(tmp, path)
+
+    @classmethod
+    def resume(cls, path, device=0, log=None, graph=False):
+        """A driver in the state `save` wrote, on `device`, ready to continue with iteration n + 1.  The run
+        then continues bitwise as it would have without the interruption: every step is deterministic given
+        this state (the GEMM tile variants a fresh tuner may choose give identical results)."""
+        import torch
+        with np.load(path, allow_pickle=False) as z:
+            h = json.loads(str(z["header"]))
+            arrays = {k: z[k] for k in z.files if k != "header"}
+        if h.get("version") != CHECKPOINT_VERSION:
+            raise ValueError(f"{path}: checkpoint version {h.get('version')}, expected {CHECKPOINT_VERSION}")
+        cfg = dict(h["cfg"], bonds=[tuple(b) for b in h["cfg"]["bonds"]])
+        d = cls(cfg, device=device, prec=h["prec"], dense=h["dense"], predict=h["predict"], chunk=h["chunk"],
+                log=log, graph=graph, batched=h["batched"])
+        d.fp32_basis = h["fp32_basis"]
+
+        def leg(key):
+            return [(int(q), int(x)) for q, x in h["legs"][key]]
+
+        def dev(key):
+            return torch.from_numpy(arrays[key]).to(d.dev)
+
+        d.n = int(h["n"])
+        d.L = {i: (leg(f"L{i}"), dev(f"L{i}")) for i in h["superblocks"]}
+        d.R = {i: (leg(f"R{i}"), dev(f"R{i}")) for i in h["superblocks"]}
+        d.prev = {int(i): dict(meta, C=leg(f"U{i}"), U=dev(f"U{i}"), V=dev(f"V{i}"), lam=dev(f"lam{i}"))
+                  for i, meta in h["prev"].items()}
+        d.lam2 = {i: (leg(f"lam2_{i}"), dev(f"lam2_{i}")) for i in h["lam2"]}
+        d.energies = {(int(n), int(i)): e for n, i, e in h["energies"]}
+        d.e_g = {int(n): e for n, e in h["e_g"]}
+        d.steps = list(h["steps"])
+        return d
+
     def run(self, n_max):
         out = []
         while self.n < n_max:
@@ -191,10 +263,11 @@ def prediction_probe(d):
     return out
 
 
-def long_run(d, n_max, out, probe_at=()):
+def long_run(d, n_max, out, probe_at=(), checkpoint=None):
     """Run to n_max, writing one JSON record per unit-cell period (l iterations) to `out`: the Step 5'
     energy e_g, e^(n)_1 / (2n + 2), Lanczos iterations, fidelity errors (Eq. (12)), the truncation error
-    eps = max over the period of eps^(n)_1 (Eq. (14)), kept states and seconds per iteration."""
+    eps = max over the period of eps^(n)_1 (Eq. (14)), kept states and seconds per iteration.  With
+    `checkpoint`, the state is saved there after each period's record."""
     import sys
     period = []
     t_start = time.perf_counter()
@@ -219,6 +292,8 @@ def long_run(d, n_max, out, probe_at=()):
                        elapsed_s=time.perf_counter() - t_start)
             out.write(json.dumps(rec) + "\n")
             out.flush()
+            if checkpoint:
+                d.save(checkpoint)
             print(f"n={d.n} e_g={rec['e_g']:.10f} iters={rec['iters_mean']:.1f} "
                   f"fid_med={rec['fidelity_median']:.1e} eps={rec['eps']:.2e} "
                   f"{rec['s_per_iteration']:.3f} s/it", file=sys.stderr, flush=True)
@@ -238,6 +313,11 @@ def main():
     ap.add_argument("--tol-res", type=float, default=None, help="Lanczos residual tolerance (default: the workload's)")
     ap.add_argument("--probe-at", type=int, nargs="*", default=[],
                     help="iterations at which Lanczos counts with and without prediction are compared")
+    ap.add_argument("--checkpoint", default=None,
+                    help="save the state to this .npz after every unit-cell period (with --periods), else at the end")
+    ap.add_argument("--resume", default=None,
+                    help="continue from a state saved with --checkpoint (its workload, m and precision apply; "
+                         "with --periods the records are appended)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of GEMM tile choices: read at start (if it matches this device and build), "
                          "written at the end")
@@ -247,20 +327,29 @@ def main():
         over["m"] = a.m
     if a.tol_res:
         over["tol_res"] = a.tol_res
-    cfg = workloads.workload(a.workload, **over)
+
+    def make(log=None):
+        if a.resume:
+            return IDMRG.resume(a.resume, log=log)
+        return IDMRG(workloads.workload(a.workload, **over), prec=a.prec, dense=a.dense, log=log)
+
     if a.periods:
-        d = IDMRG(cfg, prec=a.prec, dense=a.dense)
+        d = make()
+        n_max = a.n or d.cfg["n_max"]
         if a.tune_cache:
             d.ctx.load_tuning(a.tune_cache)
-        with open(a.periods, "w") as f:
-            f.write(json.dumps(dict(kind="config", workload=a.workload, m=cfg["m"], prec=d.prec,
-                                    tol_res=cfg["tol_res"], n_max=a.n or cfg["n_max"])) + "\n")
-            long_run(d, a.n or cfg["n_max"], f, set(a.probe_at))
+        with open(a.periods, "a" if a.resume else "w") as f:
+            head = dict(kind="resume", workload=d.cfg["name"]) if a.resume else dict(kind="config", workload=a.workload)
+            f.write(json.dumps(dict(head, m=d.cfg["m"], prec=d.prec, tol_res=d.cfg["tol_res"], n_max=n_max,
+                                    n=d.n)) + "\n")
+            long_run(d, n_max, f, set(a.probe_at), a.checkpoint)
     else:
-        d = IDMRG(cfg, prec=a.prec, dense=a.dense, log=lambda r: print(json.dumps(r), flush=True))
+        d = make(log=lambda r: print(json.dumps(r), flush=True))
         if a.tune_cache:
             d.ctx.load_tuning(a.tune_cache)
-        d.run(a.n or cfg["n_max"])
+        d.run(a.n or d.cfg["n_max"])
+        if a.checkpoint:
+            d.save(a.checkpoint)
         print(json.dumps(dict(e_g=d.e_g)))
     if a.tune_cache:
         d.ctx.save_tuning(a.tune_cache)
