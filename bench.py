@@ -22,7 +22,7 @@ divided by their summed kernel time in that run.
 Prints one JSON line on stdout (value = matvec TFLOP/s of the mixed path,
 ms_per_step = its seconds per unit-cell step; the FP64 figures sit under
 "fp64"), and one progress line per unit-cell step on stderr.
---gpus N with N > 1 exits: this build runs on one GPU.
+--gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -582,7 +582,7 @@ def main():
         mfma_counters(a.mfma_counters)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU (one process, no collectives); use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (one process, no collectives); use --gpus 1"}))
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration()
