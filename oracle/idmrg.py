@@ -109,12 +109,16 @@ def superblock_sites(n, i):
     return 2 * i - 1, 2 * i + 2 * n, 2 * i + n - 1, 2 * i + n
 
 
-def run(cfg, mode="u1", n_max=None, predict=True, seed=workloads.SEED, keep_states=False, log=None):
+def run(cfg, mode="u1", n_max=None, predict=True, seed=None, keep_states=False, log=None):
     """Run the parallel iDMRG on the workload ``cfg`` (see ``workloads.workload``).
 
     Returns a dict with ``steps`` (one record per (n, i)), ``e_g`` ({n: value})
     and, if ``keep_states``, the per-iteration environments and decompositions.
+    The random start vectors of iterations 1 and 2 are drawn with ``seed``, else
+    the configuration's own ``seed``, else ``workloads.SEED``.
     """
+    if seed is None:
+        seed = cfg.get("seed", workloads.SEED)
     ell = cfg["ell"]
     half = ell // 2
     n_max = cfg["n_max"] if n_max is None else n_max

@@ -36,6 +36,7 @@ class IDMRG:
         self.half = self.ell // 2
         self.dev = torch.device("cuda", device)
         self.prec = prec or cfg.get("prec", "f64")
+        self.seed = cfg.get("seed", workloads.SEED)   # random start vectors of iterations 1 and 2
         self.predict = predict
         self.dense = dense
         self.chunk = chunk
@@ -78,8 +79,8 @@ class IDMRG:
     def start_vectors(self, n, H):
         """Step 3': random for n <= 2 (seeded, drawn on the host), Eq. (10) otherwise."""
         if n <= 2 or not self.predict:
-            return [self._dev(workloads.start_vector(lib.psi_size(h["left"], h["right"], self.qp), n, h["i"]))
-                    for h in H]
+            return [self._dev(workloads.start_vector(lib.psi_size(h["left"], h["right"], self.qp), n, h["i"],
+                                                     self.seed)) for h in H]
         items = []
         for h in H:
             i, ip1 = h["i"], h["ip1"]
@@ -107,7 +108,7 @@ class IDMRG:
             norms = [float(torch.linalg.vector_norm(p)) for p in psis]
             for j, nr in enumerate(norms):
                 if nr == 0.0:
-                    psis[j] = self._dev(workloads.start_vector(psis[j].numel(), n, H[j]["i"]))
+                    psis[j] = self._dev(workloads.start_vector(psis[j].numel(), n, H[j]["i"], self.seed))
         t1 = time.perf_counter()
         if self.batched:
             es, infos = lib.lanczos_solve_batch(self.ctx, H, psis, cfg["tol_E"], cfg["tol_res"], cfg["k_max"],
@@ -313,6 +314,11 @@ def main():
     ap.add_argument("--tol-res", type=float, default=None, help="Lanczos residual tolerance (default: the workload's)")
     ap.add_argument("--probe-at", type=int, nargs="*", default=[],
                     help="iterations at which Lanczos counts with and without prediction are compared")
+    ap.add_argument("--config", default=None,
+                    help="run configuration as a JSON file (the format of --dump-config); replaces --workload")
+    ap.add_argument("--dump-config", action="store_true",
+                    help="print the run configuration (workload or --config, with --m / --tol-res applied) as JSON "
+                         "and exit")
     ap.add_argument("--checkpoint", default=None,
                     help="save the state to this .npz after every unit-cell period (with --periods), else at the end")
     ap.add_argument("--resume", default=None,
@@ -327,11 +333,20 @@ def main():
         over["m"] = a.m
     if a.tol_res:
         over["tol_res"] = a.tol_res
+    cfg = None
+    if not a.resume:
+        cfg = workloads.load_config(a.config) if a.config else workloads.workload(a.workload)
+        cfg = workloads.check_config(dict(cfg, **over))
+    if a.dump_config:
+        if cfg is None:
+            ap.error("--dump-config needs a workload or --config, not --resume")
+        print(json.dumps(dict(cfg, bonds=[list(b) for b in cfg["bonds"]]), indent=1))
+        return
 
     def make(log=None):
         if a.resume:
             return IDMRG.resume(a.resume, log=log)
-        return IDMRG(workloads.workload(a.workload, **over), prec=a.prec, dense=a.dense, log=log)
+        return IDMRG(cfg, prec=a.prec, dense=a.dense, log=log)
 
     if a.periods:
         d = make()
@@ -339,7 +354,7 @@ def main():
         if a.tune_cache:
             d.ctx.load_tuning(a.tune_cache)
         with open(a.periods, "a" if a.resume else "w") as f:
-            head = dict(kind="resume", workload=d.cfg["name"]) if a.resume else dict(kind="config", workload=a.workload)
+            head = dict(kind="resume" if a.resume else "config", workload=d.cfg["name"])
             f.write(json.dumps(dict(head, m=d.cfg["m"], prec=d.prec, tol_res=d.cfg["tol_res"], n_max=n_max,
                                     n=d.n)) + "\n")
             long_run(d, n_max, f, set(a.probe_at), a.checkpoint)

@@ -60,3 +60,72 @@ def test_yc8_axis_sweep():
     # site 14 is a nearest-neighbour two-step path away from 2: 2 - 3 - 14 are both bonds of the cell
     bonds = {(i, j) for i, j, _ in workloads.yc8_kagome_bonds()}
     assert (2, 3) in bonds and (3, 14) in bonds
+
+
+# ---------------------------------------------------------------- run configurations as JSON
+
+
+@pytest.mark.parametrize("name", ["chain", "random_chain", "yc4", "yc8", "dimer"])
+def test_config_json_round_trip(tmp_path, name):
+    cfg = workloads.workload(name)
+    path = str(tmp_path / f"{name}.json")
+    workloads.save_config(cfg, path)
+    assert workloads.load_config(path) == cfg
+    cfg7 = dict(cfg, seed=7, m=48)
+    workloads.save_config(cfg7, path)
+    assert workloads.load_config(path) == cfg7
+
+
+@pytest.mark.parametrize("change, match", [
+    (dict(colour="red"), "unknown"),
+    (dict(ell=5), "even"),
+    (dict(bonds=[(2, 1, 1.0)]), "k2 > k"),
+    (dict(bonds=[(1, 2)]), "not"),
+    (dict(bonds=[]), "no bonds"),
+    (dict(prec="f16"), "prec"),
+    (dict(m=True), "int"),
+    (dict(m=0), "positive"),
+    (dict(tol_res="1e-8"), "float"),
+])
+def test_config_rejects_bad_entries(change, match):
+    with pytest.raises(ValueError, match=match):
+        workloads.check_config(dict(workloads.workload("chain"), **change))
+
+
+def test_config_needs_every_key():
+    cfg = workloads.workload("chain")
+    del cfg["k_max"]
+    with pytest.raises(ValueError, match="missing"):
+        workloads.check_config(cfg)
+
+
+def test_oracle_draws_start_vectors_with_the_config_seed():
+    """The configuration's seed reaches the random start vectors of iterations 1 and 2 (Step 3')."""
+    from oracle import idmrg
+    cfg = dict(workloads.workload("chain"), seed=7)
+    r = idmrg.run(cfg, n_max=2, keep_states=True)
+    for st in r["states"]:
+        n_elem = st["v0"].size
+        assert np.array_equal(st["v0"], workloads.start_vector(n_elem, st["n"], st["i"], 7))
+        assert not np.array_equal(st["v0"], workloads.start_vector(n_elem, st["n"], st["i"]))
+    # an explicit seed argument still wins
+    r2 = idmrg.run(cfg, n_max=1, keep_states=True, seed=workloads.SEED)
+    st = r2["states"][0]
+    assert np.array_equal(st["v0"], workloads.start_vector(st["v0"].size, 1, st["i"]))
+
+
+def test_driver_dumps_and_reads_configurations(tmp_path):
+    import json
+    import subprocess
+    import sys
+    root = str(__import__("pathlib").Path(__file__).resolve().parents[1])
+    out = subprocess.run([sys.executable, "-m", "paper_1606_06790_amd.driver", "--workload", "yc4", "--m", "96",
+                          "--dump-config"], cwd=root, capture_output=True, text=True, check=True).stdout
+    cfg = workloads.check_config(json.loads(out))
+    assert cfg == workloads.workload("yc4", m=96)
+    path = tmp_path / "yc4.json"
+    path.write_text(out)
+    again = subprocess.run([sys.executable, "-m", "paper_1606_06790_amd.driver", "--config", str(path),
+                            "--tol-res", "1e-9", "--dump-config"], cwd=root, capture_output=True, text=True,
+                           check=True).stdout
+    assert workloads.check_config(json.loads(again)) == dict(cfg, tol_res=1e-9)

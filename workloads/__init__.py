@@ -19,6 +19,7 @@ Conventions used by every consumer:
 """
 from __future__ import annotations
 
+import json
 import math
 
 import numpy as np
@@ -184,6 +185,63 @@ def workload(name: str, **over):
     out.update(cfg)
     out.update(over)
     return out
+
+
+# Keys of a run configuration, with their types.  `seed` (optional) seeds the random start vectors of the first
+# two iterations; without it they come from SEED.
+CONFIG_KEYS = dict(name=str, ell=int, bonds=list, m=int, n_max=int, prec=str, tol_E=float, tol_res=float, k_max=int,
+                   lam_floor=float, deg_rel=float, u1=bool, seed=int)
+PRECISIONS = ("f64", "f32", "bf16x3")
+
+
+def check_config(cfg: dict) -> dict:
+    """The configuration with its bonds as (k, k2, J) tuples, after checking its keys, types and values; raises
+    ValueError on anything else."""
+    missing = [k for k in CONFIG_KEYS if k != "seed" and k not in cfg]
+    unknown = [k for k in cfg if k not in CONFIG_KEYS]
+    if missing or unknown:
+        raise ValueError(f"configuration: missing {missing}, unknown {unknown}")
+    out = {}
+    for k, v in cfg.items():
+        t = CONFIG_KEYS[k]
+        if t is float and isinstance(v, int) and not isinstance(v, bool):
+            v = float(v)
+        if not isinstance(v, t) or (t is int and isinstance(v, bool)):
+            raise ValueError(f"configuration: {k} must be {t.__name__}, not {type(v).__name__}")
+        out[k] = v
+    ell = out["ell"]
+    if ell < 2 or ell % 2:
+        raise ValueError("configuration: ell must be even and at least 2")
+    bonds = []
+    for b in out["bonds"]:
+        if len(b) != 3:
+            raise ValueError(f"configuration: bond {b} is not (k, k2, J)")
+        k, k2, J = int(b[0]), int(b[1]), float(b[2])
+        if k != b[0] or k2 != b[1] or not 1 <= k <= ell or k2 <= k:
+            raise ValueError(f"configuration: bond {b} needs integer sites with 1 <= k <= ell and k2 > k")
+        bonds.append((k, k2, J))
+    if not bonds:
+        raise ValueError("configuration: no bonds")
+    out["bonds"] = bonds
+    if out["prec"] not in PRECISIONS:
+        raise ValueError(f"configuration: prec must be one of {PRECISIONS}")
+    if out["m"] < 1 or out["n_max"] < 1 or out["k_max"] < 1:
+        raise ValueError("configuration: m, n_max and k_max must be positive")
+    return out
+
+
+def save_config(cfg: dict, path: str) -> None:
+    """Write a run configuration as one JSON object (bonds as [k, k2, J] lists)."""
+    c = check_config(dict(cfg))
+    with open(path, "w") as f:
+        json.dump(dict(c, bonds=[list(b) for b in c["bonds"]]), f, indent=1)
+        f.write("\n")
+
+
+def load_config(path: str) -> dict:
+    """A run configuration from a JSON file written by save_config (or by hand, with the same keys)."""
+    with open(path) as f:
+        return check_config(json.load(f))
 
 
 # --------------------------------------------------------------------------
