@@ -134,15 +134,23 @@ class IDMRG:
                             for h, tr in zip(H, trs)])
         torch.cuda.synchronize(self.dev)
         t4 = time.perf_counter()
+        for h, e in zip(H, es):
+            self.energies[(n, h["i"])] = e
+        if (n + 1) % self.ell == 0:       # Step 5'
+            e_old = self.energies[(n - self.ell, 1)] if n - self.ell >= 1 else 0.0
+            self.e_g[n] = (self.energies[(n, 1)] - e_old) / (2 * self.ell)
+        # seconds of the whole batched step (all superblocks together) by stage
+        secs = dict(predict=t1 - t0, lanczos=t2 - t1, truncate=t3 - t2, env=t4 - t3)
         for h, e, inf, tr, Ln, Rn in zip(H, es, infos, trs, newL, newR):
             i = h["i"]
-            self.energies[(n, i)] = e
             rec = dict(n=n, i=i, energy=e, e_site=e / (2 * n + 2), iters=inf["iters"], residual=inf["residual"],
                        fidelity=1.0 - inf["overlap0"], eps=tr["eps"], eps_prime=tr["eps_prime"],
                        m_kept=tr["m_kept"], cut_gap=tr["cut_gap"], svd_sweeps=tr["svd_sweeps"],
                        fp64_matvecs=inf["fp64_matvecs"], reorth_passes=inf["reorth_passes"],
                        converged=bool(inf["converged"]), svd_converged=bool(tr["svd_converged"]),
-                       N=int(psis[h["i"] - 1].numel()))
+                       N=int(psis[h["i"] - 1].numel()), step_seconds=secs)
+            if i == 1 and n in self.e_g:
+                rec["e_g"] = self.e_g[n]
             self.steps.append(rec)
             if self.log:
                 self.log(rec)
@@ -152,9 +160,6 @@ class IDMRG:
         self.L = {h["i"]: (tr["C"], Ln) for h, tr, Ln in zip(H, trs, newL)}
         self.R = {h["i"]: (tr["C"], Rn) for h, tr, Rn in zip(H, trs, newR)}
         self.n = n
-        if (n + 1) % self.ell == 0:       # Step 5'
-            e_old = self.energies[(n - self.ell, 1)] if n - self.ell >= 1 else 0.0
-            self.e_g[n] = (self.energies[(n, 1)] - e_old) / (2 * self.ell)
         return dict(n=n, seconds=t4 - t0, t_predict=t1 - t0, t_lanczos=t2 - t1, t_truncate=t3 - t2,
                     t_env=t4 - t3, iters=[inf["iters"] for inf in infos])
 

@@ -1,6 +1,6 @@
 """Resume from a checkpoint on the GPU (needs an MI355X): a run interrupted after iteration n_save and
 resumed in a new driver (new library context, so a fresh tile tuner) reproduces the uninterrupted run
-bit for bit: every superblock energy, every record and the final environments.
+bit for bit: every superblock energy, every record (apart from its timings) and the final environments.
 
 Cases: the Heisenberg chain (l = 4, m = 32) in FP64, saved before truncation starts, and the YC8 kagome
 cylinder (l = 12, m = 64) with the split-bf16 matvec and FP64 refinement, saved after one unit-cell period,
@@ -35,7 +35,9 @@ def test_resume_matches_uninterrupted_run(tmp_path, wl, m, prec, n_save, n_max):
     b.run(n_max)
     assert b.energies == a.energies
     assert b.e_g == a.e_g
-    assert b.steps == a.steps
+    # the records match except for their wall-clock timings
+    strip = lambda steps: [{k: v for k, v in r.items() if k != "step_seconds"} for r in steps]
+    assert strip(b.steps) == strip(a.steps)
     assert all(s["converged"] and s["svd_converged"] for s in b.steps)
     for i in a.L:
         assert a.L[i][0] == b.L[i][0] and torch.equal(a.L[i][1], b.L[i][1])

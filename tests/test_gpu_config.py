@@ -32,6 +32,10 @@ def test_seeded_json_config_matches_the_oracle(tmp_path):
     d = IDMRG(cfg)
     d.run(6)
     assert [(s["n"], s["i"]) for s in d.steps] == [(s["n"], s["i"]) for s in ref["steps"]]
+    # the log records carry the stage timings of their step and, on superblock 1, the Step 5' energy
+    assert all(set(s["step_seconds"]) == {"predict", "lanczos", "truncate", "env"} for s in d.steps)
+    assert [s["n"] for s in d.steps if "e_g" in s] == [3]
+    assert d.steps[4]["e_g"] == d.e_g[3]
     for g, o in zip(d.steps, ref["steps"]):
         assert abs(g["e_site"] - o["e_site"]) <= 1e-10, (g["n"], g["i"])
         assert g["m_kept"] == o["m_kept"]
